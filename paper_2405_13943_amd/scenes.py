@@ -1,0 +1,240 @@
+"""Seeded synthetic scenes, cameras and targets.
+
+This module only draws inputs: Gaussian parameter planes, pinhole cameras and
+target images. It contains none of the rasterizer, optimiser or consensus
+arithmetic, so that the FP64 oracle and the HIP path can both be fed from it
+without sharing any method code.
+
+Parameter layout (one FP32 plane per scalar attribute, ``[A][N]``), following
+the attribute list x = {u, q, s, f, o} of the Gaussian-splatting preliminaries
+(Sec. 3.1, Eq. 1-3):
+
+    planes 0..2    mean u (x, y, z)
+    planes 3..6    rotation quaternion q (w, x, y, z), unnormalised
+    planes 7..9    log of the scale s
+    plane  10      opacity logit (opacity = sigmoid(logit))
+    planes 11..    SH coefficients f: plane 11 + 3*k + channel, k = l*l + l + m
+
+so A = 11 + 3 (d + 1)^2 (14 at degree 0, 59 at degree 3).
+
+Cameras are world-to-camera rigid transforms with OpenCV axes (x right,
+y down, z forward), fx/fy/cx/cy in pixels.  Random draws use
+``numpy.random.Generator(PCG64(seed))`` in FP64 and are cast to FP32 once.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# plane offsets of the attribute groups (see module docstring)
+MEAN, QUAT, LOGSCALE, OPACITY, SH = 0, 3, 7, 10, 11
+# 1/(2 sqrt(pi)): value of the constant real spherical harmonic.  Used only to
+# draw degree-0 colour coefficients whose rendered colour is a given U(0,1)
+# sample (the configuration states colours, not coefficients).
+_SH_DC_VALUE = 0.28209479177387814
+
+
+def n_attr(sh_degree: int) -> int:
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+@dataclass
+class Camera:
+    R: np.ndarray            # [3,3] world -> camera rotation (rows: right, down, forward)
+    t: np.ndarray            # [3]   world -> camera translation
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+
+    @property
+    def center(self) -> np.ndarray:
+        return -self.R.T @ self.t
+
+
+def look_at(eye, target, width, height, fx=None, fy=None, up=(0.0, 1.0, 0.0)) -> Camera:
+    """Pinhole camera at ``eye`` looking at ``target`` with world-up +y.
+
+    Rows of R are [right; down; forward] with forward = normalise(target-eye),
+    right = normalise(forward x up), down = forward x right.  Focal length
+    defaults to a 60 degree horizontal field of view; principal point is the
+    image centre."""
+    eye = np.asarray(eye, np.float64)
+    fwd = np.asarray(target, np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, np.asarray(up, np.float64))
+    right /= np.linalg.norm(right)
+    down = np.cross(fwd, right)
+    R = np.stack([right, down, fwd]).astype(np.float32).astype(np.float64)
+    t = (-R @ eye).astype(np.float32).astype(np.float64)
+    if fx is None:
+        fx = width / (2.0 * math.tan(math.radians(30.0)))
+    if fy is None:
+        fy = fx
+    return Camera(R, t, float(np.float32(fx)), float(np.float32(fy)),
+                  width / 2.0, height / 2.0, int(width), int(height))
+
+
+def gaussians(n, sh_degree, seed, lo, hi, logscale_mu, logscale_sigma,
+              dc="uniform_coef", rest_sigma=0.05) -> np.ndarray:
+    """Draw ``n`` Gaussians as a ``[A][n]`` FP32 plane array.
+
+    Draw order: means, log-scales, quaternions, opacity logits, SH DC, SH rest.
+    ``dc='colour'`` draws the rendered degree-0 colour c ~ U(0,1) and stores the
+    coefficient whose value is c (coefficient = (c - 0.5) / Y00);
+    ``dc='uniform_coef'`` draws the DC coefficients themselves from U(0,1).
+    """
+    g = rng(seed)
+    A = n_attr(sh_degree)
+    out = np.zeros((A, n), np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    out[MEAN:MEAN + 3] = (lo[:, None] + (hi - lo)[:, None] * g.random((3, n)))
+    out[LOGSCALE:LOGSCALE + 3] = g.normal(logscale_mu, logscale_sigma, (3, n))
+    q = g.normal(0.0, 1.0, (4, n))
+    out[QUAT:QUAT + 4] = q / np.linalg.norm(q, axis=0, keepdims=True)
+    out[OPACITY] = g.normal(0.0, 1.0, n)
+    dcv = g.random((3, n))
+    if dc == "colour":
+        dcv = (dcv - 0.5) / _SH_DC_VALUE
+    out[SH:SH + 3] = dcv
+    nrest = 3 * ((sh_degree + 1) ** 2 - 1)
+    if nrest:
+        out[SH + 3:] = g.normal(0.0, rest_sigma, (nrest, n))
+    return out.astype(np.float32)
+
+
+def target_images(seed, cams) -> list:
+    """One U(0,1) target [3][H][W] per camera; camera v uses seed + 1 + v."""
+    return [rng(seed + 1 + v).random((3, c.height, c.width)).astype(np.float32)
+            for v, c in enumerate(cams)]
+
+
+def ring_cameras(n, radius, height, width, img_h, center=(0.0, 0.0, 0.0), fx=None):
+    c = np.asarray(center, np.float64)
+    cams = []
+    for k in range(n):
+        th = 2.0 * math.pi * k / n
+        eye = c + np.array([radius * math.cos(th), height, radius * math.sin(th)])
+        cams.append(look_at(eye, c, width, img_h, fx, fx))
+    return cams
+
+
+@dataclass
+class Scene:
+    name: str
+    params: np.ndarray               # [A][N] FP32
+    sh_degree: int
+    cams: list
+    targets: list = field(default_factory=list)
+    seed: int = 0
+
+
+def config1() -> Scene:
+    """Parity case: 2,000 Gaussians, SH degree 0, four 128x128 views at radius 3."""
+    seed = 1001
+    p = gaussians(2000, 0, seed, [-1, -1, -1], [1, 1, 1], -4.0, 0.5, dc="colour")
+    cams = []
+    for k in range(4):
+        a = k * math.pi / 2
+        cams.append(look_at([3 * math.sin(a), 0.0, 3 * math.cos(a)], [0, 0, 0], 128, 128, 150.0, 150.0))
+    return Scene("plain-2k-sh0-4x128", p, 0, cams, target_images(seed, cams), seed)
+
+
+def config2(n=500_000, n_cams=64, width=1600, height=1066) -> Scene:
+    """Scale case: 500k Gaussians, SH degree 3, 1600x1066 views on a 40 m ring."""
+    seed = 1002
+    p = gaussians(n, 3, seed, [-50, -10, -50], [50, 10, 50], -3.0, 0.7)
+    cams = ring_cameras(n_cams, 40.0, 10.0, width, height)
+    return Scene(f"plain-{n // 1000}k-sh3-{width}x{height}", p, 3, cams, [], seed)
+
+
+def config2_targets(scene: Scene, views) -> list:
+    return [rng(scene.seed + 1 + v).random((3, scene.cams[v].height, scene.cams[v].width)).astype(np.float32)
+            for v in views]
+
+
+def config4a() -> Scene:
+    """Adjoint case: 200 Gaussians, SH degree 3, one 64x64 view (fx = 75)."""
+    seed = 1004
+    p = gaussians(200, 3, seed, [-0.5] * 3, [0.5] * 3, -2.5, 0.3)
+    cams = [look_at([0.0, 0.0, 3.0], [0, 0, 0], 64, 64, 75.0, 75.0)]
+    return Scene("adjoint-200-sh3-64x64", p, 3, cams, [], seed)
+
+
+SLAB_BOUNDS = (-50.0, -39.333, -19.333, 10.0, 50.0)
+BLOCK_COUNTS = (800_000, 1_500_000, 2_200_000, 3_000_000)
+
+
+@dataclass
+class BlockScene:
+    """K spatial blocks sharing boundary Gaussians (global ids)."""
+    params_global: np.ndarray        # [A][N_global]
+    sh_degree: int
+    local_gid: list                  # per block: int64 global ids of its local copies
+    own: list                        # per block: number of own Gaussians (first entries)
+    cams: list                       # per block: list of cameras
+    seed: int
+
+
+def block_scene(counts=BLOCK_COUNTS, bounds=SLAB_BOUNDS, share=0.10, n_cams=32,
+                width=1600, height=1066, sh_degree=3, seed=1003) -> BlockScene:
+    """Blocks as x-slabs of uniform density; the ``share`` fraction of each
+    block's own Gaussians nearest the plane it shares with neighbour
+    n(k) = k + 1 (n(K-1) = K-2) is copied into n(k) under the same global id."""
+    K = len(counts)
+    parts, gids, base = [], [], 0
+    for k in range(K):
+        lo = [bounds[k], -10.0, -50.0]
+        hi = [bounds[k + 1], 10.0, 50.0]
+        parts.append(gaussians(counts[k], sh_degree, seed * 100 + k, lo, hi, -3.0, 0.7))
+        gids.append(np.arange(base, base + counts[k], dtype=np.int64))
+        base += counts[k]
+    params_global = np.concatenate(parts, axis=1)
+    received = [[] for _ in range(K)]
+    for k in range(K):
+        nb = k + 1 if k + 1 < K else K - 2
+        plane = bounds[k + 1] if nb > k else bounds[k]
+        xs = parts[k][MEAN]
+        m = int(round(share * counts[k]))
+        near = np.argsort(np.abs(xs.astype(np.float64) - plane), kind="stable")[:m]
+        received[nb].append(np.sort(gids[k][near]))
+    local_gid = [np.concatenate([gids[k]] + received[k]) for k in range(K)]
+    cams = []
+    for k in range(K):
+        cx = 0.5 * (bounds[k] + bounds[k + 1])
+        cams.append(ring_cameras(n_cams, 40.0, 10.0, width, height, center=(cx, 0.0, 0.0)))
+    return BlockScene(params_global, sh_degree, local_gid, list(counts), cams, seed)
+
+
+def poisson_arrivals(rate, duration, seed):
+    g = rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t >= duration:
+            return np.asarray(out)
+        out.append(t)
+
+
+SERVE_RESOLUTIONS = ((800, 600), (1280, 720), (1600, 1066), (1920, 1080))
+
+
+def serve_requests(n, seed, radius=40.0, height=10.0):
+    """Random render requests: resolution uniform over SERVE_RESOLUTIONS, pose
+    azimuth U[0, 2 pi) on a ring looking at the origin."""
+    g = rng(seed)
+    cams = []
+    for _ in range(n):
+        w, h = SERVE_RESOLUTIONS[int(g.integers(0, len(SERVE_RESOLUTIONS)))]
+        th = g.random() * 2.0 * math.pi
+        cams.append(look_at([radius * math.cos(th), height, radius * math.sin(th)], [0, 0, 0], w, h))
+    return cams

@@ -1,0 +1,343 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, invariants, library routines and finite differences.
+
+Each test names the part of the oracle it pins; a plausible slip in that part
+(a dropped term, a wrong sign or index, a transposed operand) fails it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13943_amd import scenes
+
+Y00 = 0.5 / math.sqrt(math.pi)
+CFG = oracle.RasterConfig()
+
+
+def one_gaussian(mean, log_scale, quat, logit, colour, deg=0):
+    A = scenes.n_attr(deg)
+    p = np.zeros((A, 1))
+    p[0:3, 0] = mean
+    p[3:7, 0] = quat
+    p[7:10, 0] = log_scale
+    p[10, 0] = logit
+    p[11:14, 0] = (np.asarray(colour) - 0.5) / Y00
+    return p
+
+
+def stack(*ps):
+    return np.concatenate(ps, axis=1)
+
+
+def axis_cam(W=128, H=128, f=150.0, dist=3.0):
+    return scenes.look_at([0.0, 0.0, dist], [0, 0, 0], W, H, f, f)
+
+
+# --------------------------------------------------------------------------
+# P1: integral of one isolated Gaussian (Eq. 1-2, dilation, alpha_min cut-off)
+
+def test_isolated_gaussian_integral_closed_form():
+    """Sum_p C(p)/c = 2 pi o sqrt(det S') (1 - 1/(255 o)) for a Gaussian on the
+    optical axis, with S' = ((f s / z)^2 + 0.3) I."""
+    f, s, z, c = 150.0, 0.1, 3.0, 0.8
+    for o in (0.5, 0.7, 0.9):
+        p = one_gaussian([0, 0, 0], [math.log(s)] * 3, [1, 0, 0, 0], math.log(o / (1 - o)), [c] * 3)
+        r = oracle.render(p, axis_cam(f=f, dist=z))
+        var = (f * s / z) ** 2 + 0.3
+        expect = 2 * math.pi * o * var * (1 - 1 / (255 * o))
+        got = r["rgb"][0].sum() / c
+        assert abs(got / expect - 1) < 5e-4, (o, got, expect)
+
+
+def test_isolated_gaussian_moments():
+    """Image centroid equals the pinhole projection of the mean (pixel centres
+    at +1/2), and the normalised second moment of the truncated Gaussian is
+    S' (1 - (a e^-a)/(1 - e^-a)), a = ln(255 o), for a rotated anisotropic
+    Gaussian (P2)."""
+    f = 150.0
+    mean = np.array([0.11, -0.07, 0.0])
+    q = np.array([0.8, 0.3, -0.4, 0.33])
+    ls = np.log([0.25, 0.12, 0.05])
+    o = 0.8
+    p = one_gaussian(mean, ls, q, math.log(o / (1 - o)), [1.0] * 3)
+    cam = axis_cam(W=256, H=256, f=f)
+    r = oracle.render(p, cam)
+    w = r["rgb"][0]
+    ys, xs = np.mgrid[0:256, 0:256] + 0.5
+    tot = w.sum()
+    cx, cy = (w * xs).sum() / tot, (w * ys).sum() / tot
+    # camera at +3 z looking at the origin: camera x = world x, camera y = -world y
+    assert abs(cx - (f * mean[0] / 3 + 128)) < 2e-3
+    assert abs(cy - (f * -mean[1] / 3 + 128)) < 2e-3
+    dx, dy = xs - cx, ys - cy
+    M = np.array([[(w * dx * dx).sum(), (w * dx * dy).sum()], [(w * dx * dy).sum(), (w * dy * dy).sum()]]) / tot
+    pr = oracle.project(p, cam)
+    S = np.array([[pr["cov2d"][0, 0], pr["cov2d"][0, 1]], [pr["cov2d"][0, 1], pr["cov2d"][0, 2]]])
+    a = math.log(255 * o)
+    kappa = 1 - a * math.exp(-a) / (1 - math.exp(-a))
+    np.testing.assert_allclose(M, S * kappa, rtol=0, atol=2e-3 * np.abs(S).max())
+
+
+def test_ewa_covariance_matches_sampled_projection():
+    """EWA covariance (J W Sigma W^T J^T) equals the covariance of 3D samples
+    of N(u, R S S^T R^T) pushed through the exact pinhole projection, for a
+    small, off-axis, rotated Gaussian (pins R(q), S, W and J with its
+    off-axis terms; the linearisation error is O((s/z)^2))."""
+    rng = np.random.default_rng(7)
+    cam = scenes.look_at([0.5, 1.0, 9.0], [0.2, -0.3, 0.0], 200, 160, 180.0, 170.0)
+    mean = np.array([1.2, -0.6, -0.8])
+    q = np.array([0.3, -0.7, 0.2, 0.6])
+    s = np.array([0.09, 0.03, 0.05])
+    p = one_gaussian(mean, np.log(s), q, 2.0, [0.5] * 3)
+    pr = oracle.project(p, cam, oracle.RasterConfig(dilation=0.0))
+    from scipy.spatial.transform import Rotation
+    Rq = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    L = Rq @ np.diag(s)
+    X = mean[None, :] + rng.standard_normal((4_000_000, 3)) @ L.T
+    Xc = X @ cam.R.T + cam.t[None, :]
+    u = cam.fx * Xc[:, 0] / Xc[:, 2] + cam.cx
+    v = cam.fy * Xc[:, 1] / Xc[:, 2] + cam.cy
+    C = np.cov(np.stack([u, v]))
+    S = np.array([[pr["cov2d"][0, 0], pr["cov2d"][0, 1]], [pr["cov2d"][0, 1], pr["cov2d"][0, 2]]])
+    np.testing.assert_allclose(S, C, atol=4e-3 * np.abs(C).max())
+    # the sample mean carries a second-order perspective bias of ~f s^2 / z^2
+    np.testing.assert_allclose(pr["mean2d"][0], [u.mean(), v.mean()], atol=1e-2)
+
+
+def test_conic_is_inverse_covariance():
+    s = scenes.config1()
+    pr = oracle.project(s.params, s.cams[1])
+    a, b, c = pr["conic"].T
+    sxx, sxy, syy = pr["cov2d"].T
+    np.testing.assert_allclose(a * sxx + b * sxy, 1, atol=1e-10)
+    np.testing.assert_allclose(b * sxx + c * sxy, 0, atol=1e-10)
+    np.testing.assert_allclose(b * sxy + c * syy, 1, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# P3/P4: compositing (Eq. 2) closed forms and invariants
+
+def _centre_gaussian(depth_offset, o, colour, cam, px=(40, 30)):
+    """A Gaussian whose mean projects exactly onto the centre of pixel px."""
+    f, d = cam.fx, 3.0 - depth_offset
+    x = (px[0] + 0.5 - cam.cx) * d / f
+    y = -(px[1] + 0.5 - cam.cy) * d / f
+    return one_gaussian([x, y, depth_offset], np.log([0.02] * 3), [1, 0, 0, 0], math.log(o / (1 - o)), colour)
+
+
+def test_two_gaussians_front_to_back():
+    """C = c1 a1 + c2 a2 (1 - a1) at a pixel on both centres (P3); the result
+    does not depend on the input order, only on depth."""
+    cam = axis_cam()
+    near = _centre_gaussian(0.5, 0.6, [0.9, 0.2, 0.1], cam)
+    far = _centre_gaussian(-0.5, 0.7, [0.1, 0.3, 0.8], cam)
+    pix = [30 * 128 + 40]
+    for p in (stack(near, far), stack(far, near)):
+        r = oracle.render(p, cam, pixels=pix)
+        c1, c2 = np.array([0.9, 0.2, 0.1]), np.array([0.1, 0.3, 0.8])
+        np.testing.assert_allclose(r["rgb"][:, 0], c1 * 0.6 + c2 * 0.7 * 0.4, rtol=1e-6)
+        assert abs(r["T"][0] - 0.4 * 0.3) < 1e-6
+        assert r["n"][0] == 2
+
+
+def test_alpha_clamp_and_stop_rule():
+    """alpha = min(0.99, o G); stop before the Gaussian that takes T below
+    1e-4 (that Gaussian excluded).  With alpha 0.95 per layer the transmittance
+    runs 0.05, 0.0025, 1.25e-4, then 6.25e-6 < 1e-4: three contributors."""
+    cam = axis_cam()
+    pix = [30 * 128 + 40]
+    o = 0.995
+    r = oracle.render(_centre_gaussian(0.0, o, [1, 1, 1], cam), cam, pixels=pix)
+    # alpha_max is held as the FP32 value nearest 0.99
+    np.testing.assert_allclose(r["rgb"][:, 0], float(np.float32(0.99)), rtol=1e-12)
+    layers = stack(*[_centre_gaussian(0.1 * k, 0.95, [0.5, 0.5, 0.5], cam) for k in range(5)])
+    r = oracle.render(layers, cam, pixels=pix)
+    assert r["n"][0] == 3
+    np.testing.assert_allclose(r["T"][0], 0.05 ** 3, rtol=1e-9)
+    np.testing.assert_allclose(r["rgb"][:, 0], 0.5 * (1 - 0.05 ** 3), rtol=1e-9)
+
+
+def test_compositing_invariants_config1():
+    """T_final in [T_min, 1]; with unit colours and black background the pixel
+    value equals the total weight sum_i alpha_i T_i = 1 - T_final <= 1 (P4);
+    with a white background it is exactly 1; colours stay within [0, max c]."""
+    s = scenes.config1()
+    p = s.params.astype(np.float64).copy()
+    r = oracle.render(p, s.cams[0])
+    assert r["T"].min() >= 1e-4 and r["T"].max() <= 1
+    assert r["rgb"].min() >= 0
+    cmax = oracle.project(p, s.cams[0])["rgb"].max()
+    assert r["rgb"].max() <= cmax + 1e-12
+    p[11:14] = 0.5 / Y00                                  # colour exactly 1
+    r1 = oracle.render(p, s.cams[0])
+    np.testing.assert_allclose(r1["rgb"][0], 1 - r1["T"], atol=1e-12)
+    r2 = oracle.render(p, s.cams[0], oracle.RasterConfig(bg=(1.0, 1.0, 1.0)))
+    np.testing.assert_allclose(r2["rgb"], 1.0, atol=1e-12)
+
+
+def test_order_and_quaternion_scale_invariance():
+    """The image depends on depth order only, not on the input order, and a
+    quaternion scaled by any lambda != 0 gives the same rotation."""
+    s = scenes.config1()
+    p = s.params.astype(np.float64)
+    r0 = oracle.render(p, s.cams[2])
+    perm = np.random.default_rng(3).permutation(p.shape[1])
+    r1 = oracle.render(p[:, perm], s.cams[2])
+    flagged = (r0["flags"] & 4) != 0
+    np.testing.assert_allclose(r1["rgb"][:, ~flagged], r0["rgb"][:, ~flagged], atol=1e-13)
+    q = p.copy()
+    q[3:7] *= np.random.default_rng(4).uniform(0.3, 3.0, p.shape[1])[None, :] * np.where(
+        np.arange(p.shape[1]) % 2, -1, 1)[None, :]
+    r2 = oracle.render(q, s.cams[2])
+    np.testing.assert_allclose(r2["rgb"], r0["rgb"], atol=1e-12)
+
+
+def test_near_plane_and_opacity_culls():
+    cam = axis_cam()
+    pix = [30 * 128 + 40]
+    g = _centre_gaussian(0.0, 0.8, [1, 1, 1], cam)
+    g[0:3, 0] = [0.0, 0.0, 3.0 - 0.19]          # depth 0.19 < near 0.2
+    assert oracle.project(g, cam)["valid"][0] == False  # noqa: E712
+    g2 = _centre_gaussian(0.0, 0.003, [1, 1, 1], cam)     # opacity < 1/255
+    assert oracle.project(g2, cam)["valid"][0] == False  # noqa: E712
+    assert oracle.render(g2, cam, pixels=pix)["n"][0] == 0
+
+
+# --------------------------------------------------------------------------
+# P5: spherical harmonics against SciPy's complex harmonics
+
+def test_sh_matches_scipy():
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal((500, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = oracle.sh_basis(3, d)
+    polar = np.arccos(np.clip(d[:, 2], -1, 1))
+    azim = np.arctan2(d[:, 1], d[:, 0])
+    for l in range(4):
+        for m in range(-l, l + 1):
+            k = l * l + l + m
+            c = sph_harm_y(l, abs(m), polar, azim)
+            if m > 0:
+                ref = math.sqrt(2) * c.real
+            elif m < 0:
+                ref = math.sqrt(2) * c.imag
+            else:
+                ref = c.real
+            np.testing.assert_allclose(Y[:, k], ref, atol=1e-12, err_msg=f"l={l} m={m}")
+
+
+def test_sh_orthonormal_by_quadrature():
+    x, w = np.polynomial.legendre.leggauss(24)
+    phi = (np.arange(48) + 0.5) * 2 * math.pi / 48
+    Z, P = np.meshgrid(x, phi, indexing="ij")
+    W = np.outer(w, np.full(48, 2 * math.pi / 48)).ravel()
+    r = np.sqrt(1 - Z ** 2)
+    d = np.stack([(r * np.cos(P)).ravel(), (r * np.sin(P)).ravel(), Z.ravel()], axis=1)
+    Y = oracle.sh_basis(3, d)
+    G = (Y * W[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_gradient_finite_difference():
+    rng = np.random.default_rng(12)
+    d = rng.standard_normal((50, 3))
+    Y, dY = oracle.sh_basis(3, d, with_grad=True)
+    h = 1e-6
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd = (oracle.sh_basis(3, d + e) - oracle.sh_basis(3, d - e)) / (2 * h)
+        np.testing.assert_allclose(dY[:, :, a], fd, atol=1e-7)
+
+
+def test_quaternion_rotation_matches_scipy():
+    from scipy.spatial.transform import Rotation
+    q = np.random.default_rng(5).standard_normal((100, 4))
+    R = oracle.quat_rotation(q)
+    ref = Rotation.from_quat(np.concatenate([q[:, 1:], q[:, :1]], axis=1)).as_matrix()
+    np.testing.assert_allclose(R, ref, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# P6: reverse mode against central finite differences in FP64
+
+def _fd_scene():
+    s = scenes.config4a()
+    p = s.params[:, :40].astype(np.float64)
+    cam = scenes.look_at([0.0, 0.0, 3.0], [0, 0, 0], 40, 40, 47.0, 47.0)
+    return p, cam
+
+
+def _fd_check(p, cam, coords, cfg=oracle.RasterConfig(), h=1e-6, tol=2e-5):
+    rng = np.random.default_rng(21)
+    Wt = rng.standard_normal((3, cam.height, cam.width))
+    base = oracle.render(p, cam, cfg)
+    Wt[:, base["flags"] != 0] = 0.0
+    g = oracle.backward(p, cam, Wt, cfg)
+    bad, used = [], 0
+    for (a, i) in coords:
+        pp, pm = p.copy(), p.copy()
+        pp[a, i] += h
+        pm[a, i] -= h
+        rp, rm = oracle.render(pp, cam, cfg), oracle.render(pm, cam, cfg)
+        if not (np.array_equal(rp["n"], base["n"]) and np.array_equal(rm["n"], base["n"])):
+            continue                    # a keep/stop decision flips inside [-h, h]
+        used += 1
+        fd = ((Wt * rp["rgb"]).sum() - (Wt * rm["rgb"]).sum()) / (2 * h)
+        scale = max(1e-3, np.abs(g[a]).max())
+        if abs(fd - g[a, i]) > tol * scale + 1e-5 * abs(fd):
+            bad.append((a, i, fd, g[a, i]))
+    return bad, used
+
+
+def test_backward_matches_finite_differences_all_planes():
+    p, cam = _fd_scene()
+    pr = oracle.project(p, cam)
+    vis = np.nonzero(pr["valid"])[0]
+    rng = np.random.default_rng(22)
+    coords = [(a, int(i)) for a in range(p.shape[0]) for i in rng.choice(vis, 3, replace=False)]
+    bad, used = _fd_check(p, cam, coords)
+    assert used >= 0.9 * len(coords)
+    assert not bad, bad[:10]
+
+
+def test_backward_finite_differences_with_clamps_active():
+    """Jacobian clamp (Gaussians outside 1.3x the field of view), colour clamp
+    and background colour all exercised."""
+    p, cam = _fd_scene()
+    p = p.copy()
+    p[0, :10] += 2.5                       # push some Gaussians far off to the side
+    p[11:14, 10:20] = -3.0                 # negative DC: colour clamped at zero
+    cfg = oracle.RasterConfig(bg=(0.2, 0.5, 0.9))
+    pr = oracle.project(p, cam, cfg)
+    assert (np.abs(pr["tcam"][:, 0] / pr["tcam"][:, 2]) > 1.3 * 20 / 47).any()
+    coords = [(a, i) for a in (0, 1, 2, 3, 5, 7, 9, 10, 11, 20, 40) for i in (0, 3, 12, 25, 33)]
+    bad, _ = _fd_check(p, cam, coords, cfg)
+    assert not bad, bad[:10]
+
+
+def test_backward_is_linear_in_dLdC():
+    """<J v, w> = <v, J^T w>: the gradient for dLdC = a W1 + b W2 is the same
+    combination of the two gradients."""
+    p, cam = _fd_scene()
+    rng = np.random.default_rng(23)
+    W1 = rng.standard_normal((3, cam.height, cam.width))
+    W2 = rng.standard_normal((3, cam.height, cam.width))
+    g1, g2 = oracle.backward(p, cam, W1), oracle.backward(p, cam, W2)
+    g3 = oracle.backward(p, cam, 2.0 * W1 - 0.5 * W2)
+    np.testing.assert_allclose(g3, 2 * g1 - 0.5 * g2, atol=1e-12 * max(1, np.abs(g3).max()))
+
+
+# --------------------------------------------------------------------------
+# Crops and listed pixels give the same values as the full image
+
+def test_listed_pixels_equal_full_render():
+    s = scenes.config1()
+    full = oracle.render(s.params, s.cams[3])
+    pix = np.random.default_rng(1).choice(128 * 128, 300, replace=False)
+    part = oracle.render(s.params, s.cams[3], pixels=pix)
+    np.testing.assert_array_equal(part["rgb"], full["rgb"].reshape(3, -1)[:, pix])
+    np.testing.assert_array_equal(part["n"], full["n"].ravel()[pix])
