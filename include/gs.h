@@ -1,0 +1,253 @@
+/*
+ * gs.h -- C ABI of libgs: the per-block training step of ADMM-consensus
+ * Gaussian splatting on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the paper's statement of the problem (DOGS,
+ * "Distributed-Oriented Gaussian Splatting ... via Gaussian Consensus"):
+ *   - Gaussians x = {u, q, s, f, o} (Sec. 3.1, Eq. 1-3 and the attribute list
+ *     that follows Eq. 3);
+ *   - rendering by projection and front-to-back alpha compositing (Eq. 2);
+ *   - the block x-update with the scaled ADMM penalty, per-attribute rho
+ *     (Eq. 8a; supplementary Sec. C);
+ *   - the consensus z = mean of the local copies and the dual update
+ *     u += x - z (Eq. 8b-c; Alg. 2), duals initialised to zero.
+ * Where the paper is silent (projection, tiling, thresholds) the readings are
+ * the constants of gs_raster_cfg, documented field by field below.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named *_dev or stored in gs_params / gs_bins are DEVICE
+ *     pointers; the structs themselves (gs_params, gs_frame, gs_raster_cfg,
+ *     gs_adam_cfg, gs_bins) are read on the host and passed by value to the
+ *     kernels.  gs_frame.cams and gs_frame.jobs point to device copies.
+ *   - The caller owns every buffer, including workspaces; libgs allocates no
+ *     device memory and keeps no per-call state.
+ *   - Calls are asynchronous on the given HIP stream (NULL = default stream)
+ *     and re-entrant.
+ *   - A call returns GS_OK or an error code; on error nothing was launched
+ *     (GS_E_INVALID, GS_E_UNSUPPORTED) or a launch failed (GS_E_DEVICE).
+ *     gs_last_error() returns a thread-local description.  No C++ exception
+ *     crosses this interface.
+ *   - Conditions only known on the device (pair-capacity overflow) are
+ *     reported through gs_bins.counters; check them after the stream work is
+ *     done, grow the buffers and run again.
+ *   - FP32 entry points take float planes; the *_f64 variants are the same
+ *     kernels instantiated for double (for adjoint checks).
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_ABI_VERSION 1
+
+typedef enum {
+    GS_OK = 0,
+    GS_E_INVALID = 1,      /* null pointer, negative size, SH degree > 3, bad tile shape */
+    GS_E_CAPACITY = 2,     /* a host-visible size exceeds a buffer */
+    GS_E_DEVICE = 3,       /* a HIP call or kernel launch failed */
+    GS_E_UNSUPPORTED = 4   /* valid request this build does not implement */
+} gs_status;
+
+/* status bits OR-ed into gs_bins.counters[GS_CTR_STATUS]; sticky: gs_bin_sort
+ * never clears them, so one check after many steps covers all of them */
+#define GS_STATUS_PAIR_OVERFLOW 1u
+
+/* indices into gs_bins.counters (device, uint32[GS_N_COUNTERS]) */
+#define GS_CTR_VISIBLE 0   /* records with at least one covered tile */
+#define GS_CTR_PAIRS 1     /* (tile, record) pairs required (may exceed capacity) */
+#define GS_CTR_STATUS 2
+#define GS_N_COUNTERS 4
+
+typedef void *gs_stream;   /* hipStream_t */
+
+/* Parameter planes (Sec. 3.1): one plane per scalar attribute, plane a at
+ * data + a * stride elements:
+ *   0..2  mean u;  3..6 quaternion q (w, x, y, z), unnormalised;
+ *   7..9  log scale;  10 opacity logit;
+ *   11 + 3k + c  SH coefficient k = l*l + l + m of colour channel c.
+ * A = 11 + 3 (sh_degree + 1)^2 planes.  The same layout holds Adam moments,
+ * duals u, consensus targets w = z - u, gradients and the global model z. */
+typedef struct {
+    void *data;          /* device, float (or double for *_f64) */
+    int64_t n;           /* number of Gaussians */
+    int64_t stride;      /* elements between planes, >= n */
+    int32_t sh_degree;   /* 0..3 */
+    int32_t reserved;
+} gs_params;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point X
+ * maps to camera point R X + t and to pixel (fx x/z + cx, fy y/z + cy);
+ * pixel (i, j) samples the point (i + 1/2, j + 1/2). */
+typedef struct {
+    float R[9];          /* world -> camera rotation, row major */
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+} gs_camera;
+
+/* One render job: the Gaussians [g0, g1) seen through camera `cam`.  The
+ * fields marked (plan) are filled by gs_frame_plan. */
+typedef struct {
+    int32_t cam;
+    int32_t tiles_x;     /* (plan) */
+    int32_t tiles_y;     /* (plan) */
+    int32_t tile0;       /* (plan) first global tile id */
+    int64_t g0, g1;
+    int64_t rec0;        /* (plan) first projected-record slot */
+    int64_t px0;         /* (plan) first pixel; the job's image is [3][H][W] at 3*px0 */
+    float loss_weight;   /* weight of this job's L1 loss term */
+    int32_t reserved;
+} gs_job;
+
+typedef struct {
+    const gs_camera *cams;   /* device */
+    const gs_job *jobs;      /* device, planned */
+    int32_t n_jobs;
+    int32_t n_tiles;         /* total tiles over all jobs */
+    int64_t n_records;       /* sum of (g1 - g0) */
+    int64_t n_pixels;        /* sum of W * H */
+    int64_t g_max;           /* max g1 over jobs; must not exceed the parameter count */
+} gs_frame;
+
+/* Rasterizer constants.  The paper writes alpha = o X^proj(p) (Eq. 2) without
+ * defining X^proj; the readings: EWA local-affine projection with `dilation`
+ * px^2 added to the screen covariance, x/z and y/z clamped to `jac_clip`
+ * times the half field of view inside the Jacobian, cull at depth <=
+ * `near_z`, alpha = min(alpha_max, o G), keep when alpha >= alpha_min, stop
+ * before the Gaussian that takes T below T_min, background bg. */
+typedef struct {
+    int32_t tile_w, tile_h;  /* 8x8, 16x8 or 16x16 */
+    float near_z;            /* 0.2 */
+    float alpha_min;         /* 1/255 */
+    float alpha_max;         /* 0.99 */
+    float T_min;             /* 1e-4 */
+    float dilation;          /* 0.3 */
+    float jac_clip;          /* 1.3 */
+    float bg[3];             /* 0, 0, 0 */
+    int32_t reserved;
+} gs_raster_cfg;
+
+/* Tile bins produced by gs_bin_sort. */
+typedef struct {
+    uint32_t *vals;          /* device [capacity]: record ids in (tile, depth, record) order */
+    uint32_t *ranges;        /* device [n_tiles][2]: [start, end) into vals */
+    uint32_t *pair_off;      /* device [n_records]: first pair of each visible record */
+    uint32_t *counters;      /* device [GS_N_COUNTERS] */
+    uint64_t capacity;       /* pairs vals can hold */
+} gs_bins;
+
+/* Adam with the ADMM penalty (Eq. 8a, supplementary Sec. C).  Groups in the
+ * paper's order: 0 p (mean), 1 q (rotation), 2 s (scale), 3 f (SH), 4 o. */
+typedef struct {
+    float lr[5];
+    float rho[5];
+    float beta1, beta2, eps;
+    int32_t reserved;
+    int64_t step;            /* 1-based, for bias correction */
+} gs_adam_cfg;
+
+typedef enum { GS_LOSS_L1 = 0, GS_LOSS_EXTERNAL = 1 } gs_loss_mode;
+
+/* Records written by gs_project, per (job, Gaussian) slot: */
+#define GS_REC_WORDS 12      /* T-typed words per record */
+#define GS_META_WORDS 4      /* uint32 words per record: depth bits, n_tiles, rect lo, rect hi */
+
+/* ------------------------------------------------------------------ */
+
+int32_t gs_abi_version(void);
+const char *gs_last_error(void);
+
+/* Defaults of gs_raster_cfg (16x16 tiles and the constants listed above). */
+void gs_raster_cfg_default(gs_raster_cfg *cfg);
+
+/* Host-side planning of a frame: fills tiles_x/tiles_y/tile0/rec0/px0 of each
+ * job from the host copy of the cameras, and the totals of gs_frame (n_tiles,
+ * n_records, n_pixels, g_max).  No device work.  The device job table handed
+ * to the other calls must be a copy of the planned jobs. */
+gs_status gs_frame_plan(const gs_camera *cams_host, int32_t n_cams, gs_job *jobs_host, int32_t n_jobs,
+                        const gs_raster_cfg *cfg, int64_t *n_records, int64_t *n_pixels, int32_t *n_tiles,
+                        int64_t *g_max);
+
+/* Projection (Sec. 3.1: Eq. 1, Sigma = R S S^T R^T, alpha = o X^proj(p), SH
+ * colour).  For every (job, Gaussian) slot r = rec0 + g - g0 writes
+ *   rec [r][12]: mean2d x, y; the conic scaled for exp2 (-a/2, -b, -c/2
+ *                times log2 e); log2 opacity; colour r, g, b; depth; 2 spare
+ *   meta[r][4]:  FP32 bits of the depth, number of covered tiles (0 = culled),
+ *                tile rectangle lo (x | y << 16) and hi (inclusive).
+ * The rectangle is conservative: every pixel where alpha >= alpha_min lies
+ * inside it. */
+gs_status gs_project(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
+                     void *rec_dev, uint32_t *meta_dev, gs_stream stream);
+gs_status gs_project_f64(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
+                         void *rec_dev, uint32_t *meta_dev, gs_stream stream);
+
+/* Tile binning (no counterpart in the paper; an exact acceleration of the
+ * per-pixel definition).  Emits one pair per (covered tile, record) in
+ * ascending (depth bits, record) order and sorts the pairs stably by global
+ * tile id with an LSD radix sort, so each tile's list is ordered by
+ * (depth, record).  Writes vals, ranges, pair_off and counters.  When the
+ * pairs exceed bins->capacity, sets GS_STATUS_PAIR_OVERFLOW, stores the
+ * needed count in counters[GS_CTR_PAIRS] and leaves vals/ranges invalid. */
+size_t gs_bin_sort_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles);
+gs_status gs_bin_sort(const gs_frame *frame, const gs_raster_cfg *cfg, const uint32_t *meta_dev,
+                      const gs_bins *bins, void *ws_dev, size_t ws_bytes, gs_stream stream);
+
+/* Forward compositing (Eq. 2) per pixel over its tile's list.  Writes
+ * rgb [3][H][W] per job at 3*px0 (C + T bg), T_final [H][W] at px0 and
+ * n_contrib (list position after the last contributor) at px0. */
+gs_status gs_render_fwd(const gs_frame *frame, const gs_raster_cfg *cfg, const void *rec_dev,
+                        const gs_bins *bins, void *rgb_dev, void *T_dev, uint32_t *n_contrib_dev,
+                        gs_stream stream);
+gs_status gs_render_fwd_f64(const gs_frame *frame, const gs_raster_cfg *cfg, const void *rec_dev,
+                            const gs_bins *bins, void *rgb_dev, void *T_dev, uint32_t *n_contrib_dev,
+                            gs_stream stream);
+
+/* Backward of the loss through compositing and projection to the raw
+ * parameter planes.  GS_LOSS_L1: L = sum_jobs loss_weight * mean |C - target|
+ * over 3HW (the L1 part of Eq. 3), target laid out like rgb; the per-job
+ * loss is added to loss_out[job] (may be NULL).  GS_LOSS_EXTERNAL: grad_in is
+ * dL/dC laid out like rgb.  The transmittance is recomputed front to back
+ * (never stored per pair).  grad->data receives dense gradient planes
+ * (zero for Gaussians in no job or culled); grad must cover params->n.
+ * Workspace: gs_render_bwd_workspace_size bytes. */
+size_t gs_render_bwd_workspace_size(uint64_t capacity, int32_t f64);
+gs_status gs_render_bwd(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
+                        const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,
+                        const void *rgb_dev, gs_loss_mode mode, const void *grad_in_dev,
+                        float *loss_out_dev, gs_params *grad, void *ws_dev, size_t ws_bytes,
+                        gs_stream stream);
+gs_status gs_render_bwd_f64(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
+                            const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,
+                            const void *rgb_dev, gs_loss_mode mode, const void *grad_in_dev,
+                            double *loss_out_dev, gs_params *grad, void *ws_dev, size_t ws_bytes,
+                            gs_stream stream);
+
+/* x-update step of Eq. 8a: Adam (bias-corrected) on g + rho_a (x - w), where
+ * w = z - u is the consensus target and rho_a the per-attribute penalty
+ * (supplementary Sec. C).  w == NULL: no penalty.  mask (device float [n],
+ * may be NULL): per-Gaussian penalty weight.  Updates x, m, v in place over
+ * all x->n Gaussians; all five gs_params must share n and sh_degree. */
+gs_status gs_adam_admm(gs_params *x, const gs_params *g, gs_params *m, gs_params *v, const gs_params *w,
+                       const float *mask_dev, const gs_adam_cfg *cfg, gs_stream stream);
+
+/* Consensus step (Eq. 8b-c, Alg. 2) over K blocks held in one parameter
+ * store.  For each global id gid with local holders
+ * holder_idx[holder_ptr[gid] .. holder_ptr[gid+1]) (ascending block order):
+ *   xh_k = relax * x_k + (1 - relax) * z_gid   (over-relaxation; relax = 1: none)
+ *   z_gid = mean_k xh_k;  u_k += xh_k - z_gid;  w_k = z_gid - u_k.
+ * z_global is read (previous z) and overwritten.  resid_out (device float[10],
+ * may be NULL) accumulates per group the squared primal residual
+ * sum (x_k - z)^2 (0..4) and sum (z - z_prev)^2 (5..9); the caller zeroes it. */
+gs_status gs_consensus(const gs_params *x_local, gs_params *u_local, gs_params *w_local, gs_params *z_global,
+                       const int64_t *holder_ptr_dev, const int64_t *holder_idx_dev, float relax,
+                       float *resid_out_dev, gs_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

@@ -1,0 +1,261 @@
+// C ABI of libgs (declared in include/gs.h): argument validation, workspace
+// sizing and kernel launches.  No device memory is allocated here.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gs_internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+gs_status fail(gs_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+gs_status check_hip(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(GS_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    g_err[0] = 0;
+    return GS_OK;
+}
+
+gs_status check_params(const gs_params* p, const char* name, bool allow_null_data = false) {
+    if (!p) return fail(GS_E_INVALID, "%s: null gs_params", name);
+    if (p->n < 0) return fail(GS_E_INVALID, "%s: negative n", name);
+    if (p->stride < p->n) return fail(GS_E_INVALID, "%s: stride %lld < n %lld", name, (long long)p->stride, (long long)p->n);
+    if (p->sh_degree < 0 || p->sh_degree > 3) return fail(GS_E_INVALID, "%s: sh_degree %d outside 0..3", name, p->sh_degree);
+    if (!p->data && !(allow_null_data || p->n == 0)) return fail(GS_E_INVALID, "%s: null data", name);
+    return GS_OK;
+}
+
+bool tile_ok(const gs_raster_cfg* c) {
+    return (c->tile_w == 8 && c->tile_h == 8) || (c->tile_w == 16 && c->tile_h == 8) ||
+           (c->tile_w == 16 && c->tile_h == 16) || (c->tile_w == 32 && c->tile_h == 8);
+}
+
+gs_status check_frame(const gs_frame* f, const gs_raster_cfg* cfg) {
+    if (!f || !cfg) return fail(GS_E_INVALID, "null frame or raster config");
+    if (f->n_jobs < 0 || f->n_tiles < 0 || f->n_records < 0 || f->n_pixels < 0 || f->g_max < 0)
+        return fail(GS_E_INVALID, "negative frame totals");
+    if (f->n_jobs > 0 && (!f->cams || !f->jobs)) return fail(GS_E_INVALID, "null cams/jobs");
+    if (f->n_records >= (int64_t(1) << 32)) return fail(GS_E_UNSUPPORTED, "more than 2^32 - 1 records");
+    if (!tile_ok(cfg)) return fail(GS_E_INVALID, "tile %dx%d not one of 8x8, 16x8, 16x16, 32x8", cfg->tile_w, cfg->tile_h);
+    if (!(cfg->alpha_min > 0.f) || !(cfg->alpha_max > cfg->alpha_min) || !(cfg->alpha_max < 1.f) ||
+        !(cfg->T_min > 0.f) || !(cfg->near_z > 0.f) || !(cfg->dilation >= 0.f) || !(cfg->jac_clip > 0.f))
+        return fail(GS_E_INVALID, "raster constants out of range");
+    return GS_OK;
+}
+
+gs_status check_bins(const gs_bins* b, const gs_frame* f) {
+    if (!b) return fail(GS_E_INVALID, "null gs_bins");
+    if (!b->counters || !b->ranges || (!b->pair_off && f->n_records > 0) || (!b->vals && b->capacity > 0))
+        return fail(GS_E_INVALID, "null gs_bins buffer");
+    if (b->capacity >= (uint64_t(1) << 32)) return fail(GS_E_UNSUPPORTED, "pair capacity must be below 2^32");
+    return GS_OK;
+}
+
+template <typename T>
+gs_status project_impl(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, void* rec,
+                       uint32_t* meta, gs_stream stream) {
+    gs_status st;
+    if ((st = check_params(params, "params")) != GS_OK) return st;
+    if ((st = check_frame(frame, cfg)) != GS_OK) return st;
+    if (frame->g_max > params->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
+                                              (long long)frame->g_max, (long long)params->n);
+    if (frame->n_records > 0 && (!rec || !meta)) return fail(GS_E_INVALID, "null record buffers");
+    return check_hip(gs::launch_project<T>(*params, *frame, *cfg, static_cast<T*>(rec), meta, (hipStream_t)stream),
+                     "gs_project");
+}
+
+template <typename T>
+gs_status render_fwd_impl(const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec, const gs_bins* bins,
+                          void* rgb, void* Tf, uint32_t* nc, gs_stream stream) {
+    gs_status st;
+    if ((st = check_frame(frame, cfg)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if (frame->n_pixels > 0 && (!rgb || !Tf || !nc)) return fail(GS_E_INVALID, "null image buffers");
+    if (frame->n_records > 0 && !rec) return fail(GS_E_INVALID, "null record buffer");
+    return check_hip(gs::launch_render_fwd<T>(*frame, *cfg, static_cast<const T*>(rec), *bins, static_cast<T*>(rgb),
+                                              static_cast<T*>(Tf), nc, (hipStream_t)stream),
+                     "gs_render_fwd");
+}
+
+size_t bwd_ws(uint64_t capacity, int f64) {
+    const size_t e = f64 ? sizeof(double) : sizeof(float);
+    return size_t(capacity > 0 ? capacity : 1) * 9 * e;
+}
+
+template <typename T>
+gs_status render_bwd_impl(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
+                          const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
+                          const void* gin, T* loss, gs_params* grad, void* ws, size_t ws_bytes, gs_stream stream) {
+    gs_status st;
+    if ((st = check_params(params, "params")) != GS_OK) return st;
+    if ((st = check_params(grad, "grad")) != GS_OK) return st;
+    if ((st = check_frame(frame, cfg)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if (grad->n != params->n || grad->sh_degree != params->sh_degree)
+        return fail(GS_E_INVALID, "grad planes do not match params");
+    if (frame->g_max > params->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
+                                              (long long)frame->g_max, (long long)params->n);
+    if (mode != GS_LOSS_L1 && mode != GS_LOSS_EXTERNAL) return fail(GS_E_INVALID, "unknown loss mode");
+    if (frame->n_pixels > 0 && (!rgb || !gin)) return fail(GS_E_INVALID, "null image or gradient input");
+    if (frame->n_records > 0 && (!rec || !meta)) return fail(GS_E_INVALID, "null record buffers");
+    if (!ws || ws_bytes < bwd_ws(bins->capacity, sizeof(T) == 8))
+        return fail(GS_E_CAPACITY, "backward workspace too small (%zu < %zu)", ws_bytes,
+                    bwd_ws(bins->capacity, sizeof(T) == 8));
+    T* pg = static_cast<T*>(ws);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = gs::launch_render_bwd<T>(*frame, *cfg, static_cast<const T*>(rec), meta, *bins,
+                                            static_cast<const T*>(rgb), mode, static_cast<const T*>(gin), loss, pg, s);
+    if (e != hipSuccess) return check_hip(e, "gs_render_bwd (composite)");
+    return check_hip(gs::launch_project_bwd<T>(*params, *frame, *cfg, meta, bins->pair_off, bins->capacity, pg, *grad, s),
+                     "gs_render_bwd (projection)");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gs_abi_version(void) { return GS_ABI_VERSION; }
+
+const char* gs_last_error(void) { return g_err; }
+
+void gs_raster_cfg_default(gs_raster_cfg* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->tile_w = 16;
+    cfg->tile_h = 16;
+    cfg->near_z = 0.2f;
+    cfg->alpha_min = 1.0f / 255.0f;
+    cfg->alpha_max = 0.99f;
+    cfg->T_min = 1e-4f;
+    cfg->dilation = 0.3f;
+    cfg->jac_clip = 1.3f;
+}
+
+gs_status gs_frame_plan(const gs_camera* cams, int32_t n_cams, gs_job* jobs, int32_t n_jobs, const gs_raster_cfg* cfg,
+                        int64_t* n_records, int64_t* n_pixels, int32_t* n_tiles, int64_t* g_max) {
+    if (!cfg || !tile_ok(cfg)) return fail(GS_E_INVALID, "bad raster config / tile shape");
+    if (n_jobs < 0 || n_cams < 0 || (n_jobs > 0 && (!jobs || !cams))) return fail(GS_E_INVALID, "bad job list");
+    int64_t rec = 0, px = 0, tiles = 0, gmax = 0;
+    for (int32_t j = 0; j < n_jobs; j++) {
+        gs_job& J = jobs[j];
+        if (J.cam < 0 || J.cam >= n_cams) return fail(GS_E_INVALID, "job %d: camera %d out of range", j, J.cam);
+        if (J.g0 < 0 || J.g1 < J.g0) return fail(GS_E_INVALID, "job %d: bad Gaussian range", j);
+        const gs_camera& c = cams[J.cam];
+        if (c.width <= 0 || c.height <= 0 || c.width > 65535 * 8 || c.height > 65535 * 8)
+            return fail(GS_E_INVALID, "job %d: bad image size", j);
+        if (!(c.fx > 0.f) || !(c.fy > 0.f)) return fail(GS_E_INVALID, "job %d: bad focal length", j);
+        J.tiles_x = (c.width + cfg->tile_w - 1) / cfg->tile_w;
+        J.tiles_y = (c.height + cfg->tile_h - 1) / cfg->tile_h;
+        J.tile0 = int32_t(tiles);
+        J.rec0 = rec;
+        J.px0 = px;
+        tiles += int64_t(J.tiles_x) * J.tiles_y;
+        rec += J.g1 - J.g0;
+        if (J.g1 > gmax) gmax = J.g1;
+        px += int64_t(c.width) * c.height;
+        if (tiles >= (int64_t(1) << 31)) return fail(GS_E_UNSUPPORTED, "too many tiles");
+    }
+    if (n_records) *n_records = rec;
+    if (n_pixels) *n_pixels = px;
+    if (n_tiles) *n_tiles = int32_t(tiles);
+    if (g_max) *g_max = gmax;
+    g_err[0] = 0;
+    return GS_OK;
+}
+
+gs_status gs_project(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, void* rec,
+                     uint32_t* meta, gs_stream stream) {
+    return project_impl<float>(params, frame, cfg, rec, meta, stream);
+}
+
+gs_status gs_project_f64(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, void* rec,
+                         uint32_t* meta, gs_stream stream) {
+    return project_impl<double>(params, frame, cfg, rec, meta, stream);
+}
+
+size_t gs_bin_sort_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles) {
+    return gs::bin_workspace_size(n_records, capacity, n_tiles);
+}
+
+gs_status gs_bin_sort(const gs_frame* frame, const gs_raster_cfg* cfg, const uint32_t* meta, const gs_bins* bins,
+                      void* ws, size_t ws_bytes, gs_stream stream) {
+    gs_status st;
+    if ((st = check_frame(frame, cfg)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if (frame->n_records > 0 && !meta) return fail(GS_E_INVALID, "null meta");
+    const size_t need = gs::bin_workspace_size(frame->n_records, bins->capacity, frame->n_tiles);
+    if (!ws || ws_bytes < need) return fail(GS_E_CAPACITY, "binning workspace too small (%zu < %zu)", ws_bytes, need);
+    return check_hip(gs::launch_bin_sort(*frame, *cfg, meta, *bins, ws, ws_bytes, (hipStream_t)stream), "gs_bin_sort");
+}
+
+gs_status gs_render_fwd(const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec, const gs_bins* bins, void* rgb,
+                        void* T, uint32_t* nc, gs_stream stream) {
+    return render_fwd_impl<float>(frame, cfg, rec, bins, rgb, T, nc, stream);
+}
+
+gs_status gs_render_fwd_f64(const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec, const gs_bins* bins,
+                            void* rgb, void* T, uint32_t* nc, gs_stream stream) {
+    return render_fwd_impl<double>(frame, cfg, rec, bins, rgb, T, nc, stream);
+}
+
+size_t gs_render_bwd_workspace_size(uint64_t capacity, int32_t f64) { return bwd_ws(capacity, f64); }
+
+gs_status gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
+                        const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
+                        const void* gin, float* loss, gs_params* grad, void* ws, size_t ws_bytes, gs_stream stream) {
+    return render_bwd_impl<float>(params, frame, cfg, rec, meta, bins, rgb, mode, gin, loss, grad, ws, ws_bytes, stream);
+}
+
+gs_status gs_render_bwd_f64(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
+                            const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
+                            const void* gin, double* loss, gs_params* grad, void* ws, size_t ws_bytes,
+                            gs_stream stream) {
+    return render_bwd_impl<double>(params, frame, cfg, rec, meta, bins, rgb, mode, gin, loss, grad, ws, ws_bytes,
+                                   stream);
+}
+
+gs_status gs_adam_admm(gs_params* x, const gs_params* g, gs_params* m, gs_params* v, const gs_params* w,
+                       const float* mask, const gs_adam_cfg* cfg, gs_stream stream) {
+    gs_status st;
+    if ((st = check_params(x, "x")) != GS_OK) return st;
+    if ((st = check_params(g, "g")) != GS_OK) return st;
+    if ((st = check_params(m, "m")) != GS_OK) return st;
+    if ((st = check_params(v, "v")) != GS_OK) return st;
+    if (w && (st = check_params(w, "w")) != GS_OK) return st;
+    if (!cfg) return fail(GS_E_INVALID, "null adam config");
+    const gs_params* all[4] = {g, m, v, w};
+    for (const gs_params* p : all)
+        if (p && (p->n != x->n || p->sh_degree != x->sh_degree))
+            return fail(GS_E_INVALID, "adam planes disagree in n or sh_degree");
+    if (cfg->step < 1) return fail(GS_E_INVALID, "adam step must be >= 1");
+    if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) || !(cfg->eps >= 0.f))
+        return fail(GS_E_INVALID, "adam betas/eps out of range");
+    if (mask && !w) return fail(GS_E_INVALID, "mask given without a consensus target");
+    return check_hip(gs::launch_adam_admm(*x, *g, *m, *v, w, mask, *cfg, (hipStream_t)stream), "gs_adam_admm");
+}
+
+gs_status gs_consensus(const gs_params* x, gs_params* u, gs_params* w, gs_params* z, const int64_t* hptr,
+                       const int64_t* hidx, float relax, float* resid, gs_stream stream) {
+    gs_status st;
+    if ((st = check_params(x, "x_local")) != GS_OK) return st;
+    if ((st = check_params(u, "u_local")) != GS_OK) return st;
+    if ((st = check_params(w, "w_local")) != GS_OK) return st;
+    if ((st = check_params(z, "z_global")) != GS_OK) return st;
+    if (u->n != x->n || w->n != x->n) return fail(GS_E_INVALID, "local planes disagree in n");
+    if (u->sh_degree != x->sh_degree || w->sh_degree != x->sh_degree || z->sh_degree != x->sh_degree)
+        return fail(GS_E_INVALID, "planes disagree in sh_degree");
+    if (z->n > 0 && (!hptr || !hidx)) return fail(GS_E_INVALID, "null holder CSR");
+    if (!(relax > 0.f && relax < 2.f)) return fail(GS_E_INVALID, "relaxation %g outside (0, 2)", double(relax));
+    return check_hip(gs::launch_consensus(*x, *u, *w, *z, hptr, hidx, relax, resid, (hipStream_t)stream),
+                     "gs_consensus");
+}
+
+}  // extern "C"

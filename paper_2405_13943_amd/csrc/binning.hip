@@ -1,0 +1,420 @@
+// Tile binning: turns per-record tile rectangles into per-tile lists of
+// record ids ordered by (depth, record).  The paper does not describe tiling
+// (its rasterizer is cited, not specified); this is an exact acceleration of
+// the per-pixel compositing order (depth, index).
+//
+// Two stable LSD radix sorts instead of one sort of 64-bit (tile, depth) keys:
+//   1. compact the visible records (scan of n_tiles > 0) and sort them by the
+//      FP32 bits of their depth (positive floats order like their bits);
+//   2. emit one (tile id, record) pair per covered tile in that depth order
+//      and sort the pairs by tile id only (ceil(log2 tiles) bits).
+// Stability makes each tile's list come out in (depth bits, record) order,
+// exactly what one stable sort of (tile, depth) keys on record-ordered
+// emission gives, while moving 32-bit keys over far fewer passes.
+//
+// Every count that depends on the data (visible records V, pairs P) stays on
+// the device: kernels read it from the counters and size their loops from
+// it, so the whole chain runs without a host round trip.
+#include "gs_device.hpp"
+#include "gs_internal.hpp"
+
+#include <algorithm>
+
+namespace gs {
+
+constexpr int kScanBlock = 256;
+constexpr int kRsBlock = 256;
+constexpr int kRsItems = 4;
+constexpr int kRsTile = kRsBlock * kRsItems;
+constexpr int kMaxGrid = 1024;
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BinWs {
+    uint32_t* dkey[2];    // depth keys, [n_records] each
+    uint32_t* dval[2];    // record ids, [n_records] each
+    uint32_t* tkey[2];    // tile keys, [capacity] each
+    uint32_t* tval;       // alternate record-id buffer, [capacity]
+    uint32_t* part;       // scan partials, [kMaxGrid + 1]
+    uint32_t* hist;       // radix histograms, [256 * kMaxGrid]
+    size_t bytes;
+};
+
+static BinWs carve(void* base, int64_t n_records, uint64_t capacity) {
+    BinWs w;
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return reinterpret_cast<uint32_t*>(q); };
+    const size_t nr = size_t(n_records > 0 ? n_records : 1) * 4, nc = size_t(capacity > 0 ? capacity : 1) * 4;
+    w.dkey[0] = take(nr); w.dkey[1] = take(nr);
+    w.dval[0] = take(nr); w.dval[1] = take(nr);
+    w.tkey[0] = take(nc); w.tkey[1] = take(nc);
+    w.tval = take(nc);
+    w.part = take(size_t(kMaxGrid + 1) * 4);
+    w.hist = take(size_t(256) * kMaxGrid * 4);
+    w.bytes = off;
+    return w;
+}
+
+size_t bin_workspace_size(int64_t n_records, uint64_t capacity, int32_t) {
+    return carve(nullptr, n_records, capacity).bytes;
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+// exclusive scan of one value per thread over a 256-thread block
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+    const int lane = lane_id(), wave = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) s_wave[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kScanBlock / kWave; w++) {
+        const uint32_t s = s_wave[w];
+        if (w < wave) before += s;
+        total += s;
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+// chunk of items [lo, hi) that block b of G handles when n items are split
+__device__ inline void block_range(uint32_t n, int G, int b, uint32_t granule, uint32_t& lo, uint32_t& hi) {
+    uint32_t chunk = (n + G - 1) / G;
+    chunk = (chunk + granule - 1) / granule * granule;
+    lo = min(n, uint32_t(b) * chunk);
+    hi = min(n, lo + chunk);
+}
+
+// ---------------------------------------------------------------------------
+// reduce-then-scan over a device-sized sequence; two flavours of input/output
+
+struct VisibleFlag {      // item i: record i is visible; output: compact (depth key, record)
+    const uint4* meta;
+    uint32_t* key_out;
+    uint32_t* val_out;
+    __device__ uint32_t value(uint32_t i) const { return meta[i].y > 0 ? 1u : 0u; }
+    __device__ void emit(uint32_t i, uint32_t pre) const {
+        const uint4 m = meta[i];
+        if (m.y > 0) { key_out[pre] = m.x; val_out[pre] = i; }
+    }
+};
+
+struct PairCount {        // item s: sorted visible record; output: its first pair
+    const uint4* meta;
+    const uint32_t* sorted_rec;
+    uint32_t* pair_off;
+    __device__ uint32_t value(uint32_t s) const { return meta[sorted_rec[s]].y; }
+    __device__ void emit(uint32_t s, uint32_t pre) const { pair_off[sorted_rec[s]] = pre; }
+};
+
+template <typename F>
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, const uint32_t* __restrict__ n_dev, uint32_t n_host,
+                                                            uint32_t* __restrict__ part, int G) {
+    __shared__ uint32_t s_wave[kScanBlock / kWave];
+    const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+    uint32_t lo, hi;
+    block_range(n, G, blockIdx.x, kScanBlock, lo, hi);
+    uint32_t acc = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kScanBlock) acc += f.value(i);
+    uint32_t tot;
+    block_excl_scan(acc, s_wave, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the G partials in place; total to counters
+__global__ __launch_bounds__(kScanBlock) void k_scan_spine(uint32_t* __restrict__ part, int G,
+                                                           uint32_t* __restrict__ counters, int total_idx,
+                                                           uint64_t capacity) {
+    __shared__ uint32_t s_wave[kScanBlock / kWave];
+    uint32_t carry = 0;
+    for (int base = 0; base < G; base += kScanBlock) {
+        const int i = base + threadIdx.x;
+        const uint32_t v = i < G ? part[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, s_wave, tot);
+        if (i < G) part[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        counters[total_idx] = carry;
+        if (capacity && uint64_t(carry) > capacity) counters[GS_CTR_STATUS] |= GS_STATUS_PAIR_OVERFLOW;
+    }
+}
+
+template <typename F>
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(F f, const uint32_t* __restrict__ n_dev, uint32_t n_host,
+                                                           const uint32_t* __restrict__ part, int G) {
+    __shared__ uint32_t s_wave[kScanBlock / kWave];
+    const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+    uint32_t lo, hi;
+    block_range(n, G, blockIdx.x, kScanBlock, lo, hi);
+    uint32_t carry = part[blockIdx.x];
+    for (uint32_t base = lo; base < hi; base += kScanBlock) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < hi ? f.value(i) : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, s_wave, tot);
+        if (i < hi) f.emit(i, carry + ex);
+        carry += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort of (uint32 key, uint32 value), 8-bit digits,
+// reduce-then-scan with a fixed grid of G blocks over device-sized n
+
+__global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                                                      uint32_t n_host, int shift, uint32_t* __restrict__ hist, int G) {
+    __shared__ uint32_t h[kRsBlock / kWave][256];
+    const int wave = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < 256 * (kRsBlock / kWave); i += kRsBlock) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t n = min(*n_dev, n_host);
+    uint32_t lo, hi;
+    block_range(n, G, blockIdx.x, kRsTile, lo, hi);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kRsBlock) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < kRsBlock / kWave; w++) s += h[w][d];
+    hist[d * G + blockIdx.x] = s;
+}
+
+// single block: exclusive scan of hist[256 * G] in (digit, block) order.
+// Staged through LDS so that global reads and writes stay coalesced.
+__global__ __launch_bounds__(1024) void k_rs_spine(uint32_t* __restrict__ hist, int total) {
+    constexpr int ITEMS = 8;
+    constexpr int SPAN = 1024 * ITEMS;
+    __shared__ uint32_t buf[SPAN + SPAN / 32];   // one pad word per 32 to spread banks
+    __shared__ uint32_t s_wave[1024 / kWave];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    auto at = [](int i) { return i + (i >> 5); };
+    uint32_t carry = 0;
+    for (int base = 0; base < total; base += SPAN) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; k++) {
+            const int i = base + k * 1024 + tid;
+            buf[at(k * 1024 + tid)] = i < total ? hist[i] : 0u;
+        }
+        __syncthreads();
+        uint32_t loc[ITEMS], sum = 0;
+#pragma unroll
+        for (int k = 0; k < ITEMS; k++) { loc[k] = buf[at(tid * ITEMS + k)]; sum += loc[k]; }
+        const uint32_t inc = wave_incl_scan(sum);
+        if (lane == kWave - 1) s_wave[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0, block_total = 0;
+        for (int w = 0; w < 1024 / kWave; w++) {
+            const uint32_t v = s_wave[w];
+            if (w < wave) before += v;
+            block_total += v;
+        }
+        uint32_t run = carry + before + inc - sum;
+#pragma unroll
+        for (int k = 0; k < ITEMS; k++) { buf[at(tid * ITEMS + k)] = run; run += loc[k]; }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < ITEMS; k++) {
+            const int i = base + k * 1024 + tid;
+            if (i < total) hist[i] = buf[at(k * 1024 + tid)];
+        }
+        carry += block_total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
+                                                         const uint32_t* __restrict__ hist, int G) {
+    constexpr int NW = kRsBlock / kWave;
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t wpre[NW][256];
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
+    const uint32_t n = min(*n_dev, n_host);
+    uint32_t lo, hi;
+    block_range(n, G, blockIdx.x, kRsTile, lo, hi);
+    run[tid] = hist[tid * G + blockIdx.x];
+    for (uint32_t base = lo; base < hi; base += kRsTile) {
+        for (int d = lane; d < 256; d += kWave) wcnt[wave][d] = 0;
+        __builtin_amdgcn_wave_barrier();
+        uint32_t key[kRsItems], val[kRsItems], rank[kRsItems];
+#pragma unroll
+        for (int k = 0; k < kRsItems; k++) {
+            const uint32_t i = base + wave * (kWave * kRsItems) + k * kWave + lane;
+            key[k] = 0; val[k] = 0; rank[k] = 0;
+            if (i < hi) {
+                key[k] = kin[i];
+                val[k] = vin[i];
+                const uint32_t dg = (key[k] >> shift) & 255u;
+                uint64_t peers = __ballot(1);
+#pragma unroll
+                for (int bit = 0; bit < 8; bit++) {
+                    const uint64_t m = __ballot((dg >> bit) & 1u);
+                    peers &= ((dg >> bit) & 1u) ? m : ~m;
+                }
+                const uint32_t before = wcnt[wave][dg];
+                rank[k] = before + uint32_t(__popcll(peers & lanemask_lt()));
+                const int leader = 63 - __clzll(peers);
+                if (lane == leader) wcnt[wave][dg] = before + uint32_t(__popcll(peers));
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        uint32_t tot = 0;
+        {
+            const int d = tid;
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                wpre[w][d] = tot;
+                tot += wcnt[w][d];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRsItems; k++) {
+            const uint32_t i = base + wave * (kWave * kRsItems) + k * kWave + lane;
+            if (i < hi) {
+                const uint32_t dg = (key[k] >> shift) & 255u;
+                const uint32_t pos = run[dg] + wpre[wave][dg] + rank[k];
+                kout[pos] = key[k];
+                vout[pos] = val[k];
+            }
+        }
+        __syncthreads();
+        run[tid] += tot;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pair emission and tile ranges
+
+__global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ sorted_rec,
+                                              const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ counters,
+                                              gs_frame frame, uint64_t capacity, uint32_t* __restrict__ tkey,
+                                              uint32_t* __restrict__ tval) {
+    const uint32_t V = counters[GS_CTR_VISIBLE];
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= V) return;
+    const uint32_t r = sorted_rec[s];
+    const uint4 m = meta[r];
+    const uint32_t off = pair_off[r];
+    const int j = job_of_record(frame.jobs, frame.n_jobs, r);
+    const int tile0 = frame.jobs[j].tile0, tiles_x = frame.jobs[j].tiles_x;
+    const uint32_t x0 = m.z & 0xffffu, y0 = m.z >> 16, x1 = m.w & 0xffffu;
+    const uint32_t w = x1 - x0 + 1;
+    for (uint32_t k = 0; k < m.y; k++) {
+        const uint64_t e = uint64_t(off) + k;
+        if (e >= capacity) break;
+        const uint32_t ty = y0 + k / w, tx = x0 + k % w;
+        tkey[e] = uint32_t(tile0) + ty * uint32_t(tiles_x) + tx;
+        tval[e] = r;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ counters,
+                                                uint64_t capacity, uint2* __restrict__ ranges) {
+    const uint32_t P = uint32_t(min(uint64_t(counters[GS_CTR_PAIRS]), capacity));
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < P; e += gridDim.x * blockDim.x) {
+        const uint32_t t = tkey[e];
+        if (e == 0 || tkey[e - 1] != t) ranges[t].x = e;
+        if (e + 1 == P || tkey[e + 1] != t) ranges[t].y = e + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+static int grid_for(uint64_t n_max, int per_block) {
+    uint64_t g = (n_max + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > kMaxGrid) g = kMaxGrid;
+    return int(g);
+}
+
+static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
+                             uint32_t n_max, int bits, uint32_t** k_final, hipStream_t s, BinWs& w) {
+    const int G = grid_for(n_max, kRsTile * 4);
+    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, w.hist, G);
+        hipLaunchKernelGGL(k_rs_spine, dim3(1), dim3(1024), 0, s, w.hist, 256 * G);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, w.hist, G);
+        uint32_t* t;
+        t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    *k_final = ki;
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta_u32, const gs_bins& bins,
+                           void* ws, size_t ws_bytes, hipStream_t s) {
+    (void)cfg;
+    (void)ws_bytes;
+    BinWs w = carve(ws, f.n_records, bins.capacity);
+    const uint4* meta = reinterpret_cast<const uint4*>(meta_u32);
+    const uint32_t nrec = uint32_t(f.n_records);
+    // counts restart every call; the status bits are sticky until the caller clears them
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, bins.counters, 0u, int64_t(GS_CTR_STATUS));
+    const int64_t nr2 = int64_t(f.n_tiles) * 2;
+    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(std::min<int64_t>((nr2 + 255) / 256, 2048))), dim3(256), 0, s,
+                       bins.ranges, 0u, nr2);
+    if (nrec == 0) return hipGetLastError();
+
+    // 1. compact visible records as (depth bits, record)
+    const int Gs = grid_for(nrec, kScanBlock * 8);
+    VisibleFlag vf{meta, w.dkey[0], w.dval[0]};
+    hipLaunchKernelGGL(k_scan_reduce<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
+    hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_VISIBLE,
+                       uint64_t(0));
+    hipLaunchKernelGGL(k_scan_apply<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
+
+    // 2. stable sort by depth bits (32 bits, 4 passes: the result is in buffer 0)
+    uint32_t* dk_final;
+    const uint32_t* n_vis = bins.counters + GS_CTR_VISIBLE;
+    hipError_t e = radix_sort(w.dkey[0], w.dval[0], w.dkey[1], w.dval[1], n_vis, nrec, 32, &dk_final, s, w);
+    if (e != hipSuccess) return e;
+    const uint32_t* sorted_rec = (dk_final == w.dkey[0]) ? w.dval[0] : w.dval[1];
+
+    // 3. first pair of each visible record, in depth order; total pairs
+    PairCount pc{meta, sorted_rec, bins.pair_off};
+    hipLaunchKernelGGL(k_scan_reduce<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
+    hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_PAIRS,
+                       bins.capacity);
+    hipLaunchKernelGGL(k_scan_apply<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
+
+    // 4. emit (tile, record) pairs in depth order, then stable sort by tile id
+    int bits = 0;
+    while ((1ll << bits) < int64_t(f.n_tiles)) bits++;
+    const int passes = (bits + 7) / 8;
+    uint32_t* emit_val = (passes & 1) ? w.tval : bins.vals;
+    uint32_t* other_val = (passes & 1) ? bins.vals : w.tval;
+    hipLaunchKernelGGL(k_emit, dim3(unsigned((nrec + 255) / 256)), dim3(256), 0, s, meta, sorted_rec, bins.pair_off,
+                       bins.counters, f, bins.capacity, w.tkey[0], emit_val);
+    const uint32_t pmax = uint32_t(std::min<uint64_t>(bins.capacity, 0xffffffffull));
+    uint32_t* tk_final = w.tkey[0];
+    if (passes > 0) {
+        e = radix_sort(w.tkey[0], emit_val, w.tkey[1], other_val, bins.counters + GS_CTR_PAIRS, pmax, passes * 8,
+                       &tk_final, s, w);
+        if (e != hipSuccess) return e;
+    }
+
+    // 5. per-tile [start, end)
+    hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity,
+                       reinterpret_cast<uint2*>(bins.ranges));
+    return hipGetLastError();
+}
+
+}  // namespace gs

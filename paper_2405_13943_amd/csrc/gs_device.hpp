@@ -1,0 +1,118 @@
+// Device-side helpers shared by the libgs kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gs {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// scalar-type traits: FP32 product path, FP64 instantiation for adjoint checks
+
+template <typename T> struct Num;
+template <> struct Num<float> {
+    __device__ static inline float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+    __device__ static inline float log2(float x) { return __log2f(x); }
+    __device__ static inline float exp(float x) { return __expf(x); }
+    __device__ static inline float log(float x) { return __logf(x); }
+    __device__ static inline float sqrt(float x) { return __builtin_sqrtf(x); }
+    __device__ static inline float rsqrt(float x) { return 1.0f / __builtin_sqrtf(x); }
+    __device__ static inline float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+};
+template <> struct Num<double> {
+    __device__ static inline double exp2(double x) { return ::exp2(x); }
+    __device__ static inline double log2(double x) { return ::log2(x); }
+    __device__ static inline double exp(double x) { return ::exp(x); }
+    __device__ static inline double log(double x) { return ::log(x); }
+    __device__ static inline double sqrt(double x) { return ::sqrt(x); }
+    __device__ static inline double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    __device__ static inline double fma(double a, double b, double c) { return ::fma(a, b, c); }
+};
+
+// ln 2 and log2 e as the scalar type
+template <typename T> __device__ constexpr T kLn2() { return T(0.69314718055994530942); }
+template <typename T> __device__ constexpr T kLog2e() { return T(1.44269504088896340736); }
+
+// ---------------------------------------------------------------------------
+// job lookup: jobs are laid out in ascending rec0 / tile0 / px0 order
+
+__device__ inline int job_of_record(const gs_job* __restrict__ jobs, int n_jobs, int64_t r) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].rec0 <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline int job_of_tile(const gs_job* __restrict__ jobs, int n_jobs, int tile) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// wave64 primitives
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline uint64_t lanemask_lt() { return (uint64_t(1) << lane_id()) - 1; }
+
+// Sum over the 64 lanes of a wave, returned to every lane.  FP32 uses DPP
+// (quad permutes, row rotations, then row broadcasts into lane 63); FP64
+// uses a butterfly of cross-lane shuffles.
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_move(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ inline float wave_sum(float v) {
+    v += dpp_move<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x124, 0xf>(v);  // row_ror:4
+    v += dpp_move<0x128, 0xf>(v);  // row_ror:8
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// inclusive prefix sum over the lanes of a wave
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = lane_id();
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint32_t t = __shfl_up(v, off, kWave);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware block order: the dispatcher hands consecutive workgroups to the
+// 8 XCDs round robin.  Remapping so that each XCD receives one contiguous run
+// of work items keeps neighbouring tiles (which share Gaussians) in the same
+// L2.
+__device__ inline int xcd_block(int b, int nb) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    const int base = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    return base + idx;
+}
+
+}  // namespace gs

@@ -1,0 +1,41 @@
+// Host-side launchers of the libgs kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+namespace gs {
+
+// project.hip
+template <typename T>
+hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, T* rec,
+                          uint32_t* meta, hipStream_t s);
+template <typename T>
+hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
+                              const uint32_t* meta, const uint32_t* pair_off, uint64_t capacity, const T* pg,
+                              gs_params& grad, hipStream_t s);
+
+// binning.hip
+size_t bin_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles);
+hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta, const gs_bins& bins,
+                           void* ws, size_t ws_bytes, hipStream_t s);
+
+// render.hip
+template <typename T>
+hipError_t launch_render_fwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& bins,
+                             T* rgb, T* Tfin, uint32_t* ncontrib, hipStream_t s);
+template <typename T>
+hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
+                             const gs_bins& bins, const T* rgb, gs_loss_mode mode, const T* grad_in, T* loss_out,
+                             T* pg, hipStream_t s);
+
+// optim.hip
+hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_params& v, const gs_params* w,
+                            const float* mask, const gs_adam_cfg& cfg, hipStream_t s);
+hipError_t launch_consensus(const gs_params& x, gs_params& u, gs_params& w, gs_params& z, const int64_t* hptr,
+                            const int64_t* hidx, float relax, float* resid, hipStream_t s);
+
+}  // namespace gs

@@ -1,0 +1,496 @@
+// Projection of 3D Gaussians into each job's view (forward) and the chain
+// rule from per-record screen-space gradients back to the raw parameter
+// planes (backward).  One thread per (job, Gaussian) record forward and one
+// thread per Gaussian backward; both stream the SoA planes coalesced.
+//
+// Paper: Sec. 3.1 (Eq. 1: Gaussian with Sigma = R S S^T R^T; Eq. 2 and
+// alpha = o X^proj(p); attributes x = {u, q, s, f, o}).  X^proj is read as the
+// EWA local-affine projection (Sigma' = J W Sigma W^T J^T + dilation I).
+#include "gs_device.hpp"
+#include "gs_internal.hpp"
+
+namespace gs {
+
+template <typename T>
+struct Cam {
+    T R[9], t[3], fx, fy, cx, cy;
+    int W, H;
+};
+
+template <typename T>
+__device__ inline void load_cam(const gs_camera& c, Cam<T>& o) {
+#pragma unroll
+    for (int k = 0; k < 9; k++) o.R[k] = T(c.R[k]);
+#pragma unroll
+    for (int k = 0; k < 3; k++) o.t[k] = T(c.t[k]);
+    o.fx = T(c.fx); o.fy = T(c.fy); o.cx = T(c.cx); o.cy = T(c.cy);
+    o.W = c.width; o.H = c.height;
+}
+
+// ---------------------------------------------------------------------------
+// Real spherical harmonics up to degree 3 as polynomials in the unit
+// direction (x, y, z): orthonormal, Condon-Shortley phase, index
+// k = l*l + l + m with m = -l..l.  The constants are
+//   c1 = sqrt(3/(4pi)), c2a = sqrt(15/(4pi)), c2b = sqrt(5/(16pi)),
+//   c2c = sqrt(15/(16pi)), c3a = sqrt(35/(32pi)), c3b = sqrt(105/(4pi)),
+//   c3c = sqrt(21/(32pi)), c3d = sqrt(7/(16pi)), c3e = sqrt(105/(16pi)).
+template <typename T>
+struct SH {
+    static constexpr double c0 = 0.28209479177387814, c1 = 0.48860251190291992;
+    static constexpr double c2a = 1.0925484305920792, c2b = 0.31539156525252005, c2c = 0.54627421529603959;
+    static constexpr double c3a = 0.59004358992664352, c3b = 2.8906114426405538, c3c = 0.45704579946446572;
+    static constexpr double c3d = 0.37317633259011540, c3e = 1.4453057213202769;
+
+    template <int D>
+    __device__ static inline void basis(T x, T y, T z, T* Y) {
+        Y[0] = T(c0);
+        if (D >= 1) { Y[1] = -T(c1) * y; Y[2] = T(c1) * z; Y[3] = -T(c1) * x; }
+        if (D >= 2) {
+            const T xx = x * x, yy = y * y, zz = z * z;
+            Y[4] = T(c2a) * x * y;
+            Y[5] = -T(c2a) * y * z;
+            Y[6] = T(c2b) * (T(2) * zz - xx - yy);
+            Y[7] = -T(c2a) * x * z;
+            Y[8] = T(c2c) * (xx - yy);
+            if (D >= 3) {
+                Y[9] = -T(c3a) * y * (T(3) * xx - yy);
+                Y[10] = T(c3b) * x * y * z;
+                Y[11] = -T(c3c) * y * (T(4) * zz - xx - yy);
+                Y[12] = T(c3d) * z * (T(2) * zz - T(3) * xx - T(3) * yy);
+                Y[13] = -T(c3c) * x * (T(4) * zz - xx - yy);
+                Y[14] = T(c3e) * z * (xx - yy);
+                Y[15] = -T(c3a) * x * (xx - T(3) * yy);
+            }
+        }
+    }
+
+    // d = sum_k w[k] grad Y_k(x, y, z)
+    template <int D>
+    __device__ static inline void grad_dot(T x, T y, T z, const T* w, T* d) {
+        T gx = 0, gy = 0, gz = 0;
+        if (D >= 1) { gy -= T(c1) * w[1]; gz += T(c1) * w[2]; gx -= T(c1) * w[3]; }
+        if (D >= 2) {
+            gx += T(c2a) * y * w[4];            gy += T(c2a) * x * w[4];
+            gy -= T(c2a) * z * w[5];            gz -= T(c2a) * y * w[5];
+            gx -= T(2 * c2b) * x * w[6];        gy -= T(2 * c2b) * y * w[6];   gz += T(4 * c2b) * z * w[6];
+            gx -= T(c2a) * z * w[7];            gz -= T(c2a) * x * w[7];
+            gx += T(2 * c2c) * x * w[8];        gy -= T(2 * c2c) * y * w[8];
+            if (D >= 3) {
+                const T xx = x * x, yy = y * y, zz = z * z;
+                gx -= T(6 * c3a) * x * y * w[9];
+                gy -= T(3 * c3a) * (xx - yy) * w[9];
+                gx += T(c3b) * y * z * w[10]; gy += T(c3b) * x * z * w[10]; gz += T(c3b) * x * y * w[10];
+                gx += T(2 * c3c) * x * y * w[11];
+                gy -= T(c3c) * (T(4) * zz - xx - T(3) * yy) * w[11];
+                gz -= T(8 * c3c) * y * z * w[11];
+                gx -= T(6 * c3d) * x * z * w[12];
+                gy -= T(6 * c3d) * y * z * w[12];
+                gz += T(3 * c3d) * (T(2) * zz - xx - yy) * w[12];
+                gx -= T(c3c) * (T(4) * zz - T(3) * xx - yy) * w[13];
+                gy += T(2 * c3c) * x * y * w[13];
+                gz -= T(8 * c3c) * x * z * w[13];
+                gx += T(2 * c3e) * x * z * w[14]; gy -= T(2 * c3e) * y * z * w[14]; gz += T(c3e) * (xx - yy) * w[14];
+                gx -= T(3 * c3a) * (xx - yy) * w[15];
+                gy += T(6 * c3a) * x * y * w[15];
+            }
+        }
+        d[0] = gx; d[1] = gy; d[2] = gz;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Geometry of one Gaussian in one view.
+
+template <typename T>
+struct Geo {
+    T u[3];          // mean
+    T t[3];          // camera-space mean
+    T rz;            // 1 / t_z
+    T rx, ry;        // clamped x/z, y/z
+    bool clx, cly;   // clamp active
+    T qn[4], qinv;   // normalised quaternion, 1/|q|
+    T R[9];          // rotation of the Gaussian
+    T s[3];          // scales
+    T Sig[6];        // xx xy xz yy yz zz
+    T t0[3], t1[3];  // rows of J W
+    T sxx, sxy, syy; // screen covariance (incl. dilation)
+    T a, b, c;       // conic
+    T mx, my;
+    T o;             // opacity
+};
+
+template <typename T>
+__device__ inline T plane(const T* __restrict__ P, int64_t stride, int a, int64_t g) {
+    return P[int64_t(a) * stride + g];
+}
+
+// Returns false when culled by the near plane or the opacity threshold.
+template <typename T>
+__device__ inline bool geometry(const T* __restrict__ P, int64_t stride, int64_t g, const Cam<T>& cam,
+                                const gs_raster_cfg& cfg, Geo<T>& G) {
+    using N = Num<T>;
+#pragma unroll
+    for (int k = 0; k < 3; k++) G.u[k] = plane(P, stride, k, g);
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+        G.t[r] = cam.R[3 * r] * G.u[0] + cam.R[3 * r + 1] * G.u[1] + cam.R[3 * r + 2] * G.u[2] + cam.t[r];
+    if (!(G.t[2] > T(cfg.near_z))) return false;
+    const T logit = plane(P, stride, 10, g);
+    G.o = T(1) / (T(1) + N::exp(-logit));
+    if (G.o < T(cfg.alpha_min)) return false;
+
+    T q[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = plane(P, stride, 3 + k, g);
+    G.qinv = N::rsqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+    for (int k = 0; k < 4; k++) G.qn[k] = q[k] * G.qinv;
+    const T w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    G.R[0] = T(1) - T(2) * (y * y + z * z); G.R[1] = T(2) * (x * y - w * z); G.R[2] = T(2) * (x * z + w * y);
+    G.R[3] = T(2) * (x * y + w * z); G.R[4] = T(1) - T(2) * (x * x + z * z); G.R[5] = T(2) * (y * z - w * x);
+    G.R[6] = T(2) * (x * z - w * y); G.R[7] = T(2) * (y * z + w * x); G.R[8] = T(1) - T(2) * (x * x + y * y);
+#pragma unroll
+    for (int k = 0; k < 3; k++) G.s[k] = N::exp(plane(P, stride, 7 + k, g));
+    // Sigma = R diag(s^2) R^T
+    T M[9];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) M[3 * r + c] = G.R[3 * r + c] * G.s[c];
+    G.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+    G.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+    G.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+    G.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+    G.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+    G.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+
+    // Jacobian of the perspective map at the (clamped) mean
+    G.rz = T(1) / G.t[2];
+    const T limx = T(cfg.jac_clip) * T(0.5) * T(cam.W) / cam.fx;
+    const T limy = T(cfg.jac_clip) * T(0.5) * T(cam.H) / cam.fy;
+    const T ux = G.t[0] * G.rz, uy = G.t[1] * G.rz;
+    G.clx = (ux < -limx) || (ux > limx);
+    G.cly = (uy < -limy) || (uy > limy);
+    G.rx = ux < -limx ? -limx : (ux > limx ? limx : ux);
+    G.ry = uy < -limy ? -limy : (uy > limy ? limy : uy);
+    const T J00 = cam.fx * G.rz, J02 = -cam.fx * G.rx * G.rz;
+    const T J11 = cam.fy * G.rz, J12 = -cam.fy * G.ry * G.rz;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        G.t0[k] = J00 * cam.R[k] + J02 * cam.R[6 + k];
+        G.t1[k] = J11 * cam.R[3 + k] + J12 * cam.R[6 + k];
+    }
+    // screen covariance t_i^T Sigma t_j
+    T St0[3], St1[3];
+    St0[0] = G.Sig[0] * G.t0[0] + G.Sig[1] * G.t0[1] + G.Sig[2] * G.t0[2];
+    St0[1] = G.Sig[1] * G.t0[0] + G.Sig[3] * G.t0[1] + G.Sig[4] * G.t0[2];
+    St0[2] = G.Sig[2] * G.t0[0] + G.Sig[4] * G.t0[1] + G.Sig[5] * G.t0[2];
+    St1[0] = G.Sig[0] * G.t1[0] + G.Sig[1] * G.t1[1] + G.Sig[2] * G.t1[2];
+    St1[1] = G.Sig[1] * G.t1[0] + G.Sig[3] * G.t1[1] + G.Sig[4] * G.t1[2];
+    St1[2] = G.Sig[2] * G.t1[0] + G.Sig[4] * G.t1[1] + G.Sig[5] * G.t1[2];
+    G.sxx = G.t0[0] * St0[0] + G.t0[1] * St0[1] + G.t0[2] * St0[2] + T(cfg.dilation);
+    G.sxy = G.t0[0] * St1[0] + G.t0[1] * St1[1] + G.t0[2] * St1[2];
+    G.syy = G.t1[0] * St1[0] + G.t1[1] * St1[1] + G.t1[2] * St1[2] + T(cfg.dilation);
+    const T rdet = T(1) / (G.sxx * G.syy - G.sxy * G.sxy);
+    G.a = G.syy * rdet;
+    G.b = -G.sxy * rdet;
+    G.c = G.sxx * rdet;
+    G.mx = cam.fx * G.t[0] * G.rz + cam.cx;
+    G.my = cam.fy * G.t[1] * G.rz + cam.cy;
+    return true;
+}
+
+// view direction from the camera centre c = -R^T t to the mean
+template <typename T>
+__device__ inline T view_dir(const Geo<T>& G, const Cam<T>& cam, T* dir) {
+    T v[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        v[k] = G.u[k] + (cam.R[k] * cam.t[0] + cam.R[3 + k] * cam.t[1] + cam.R[6 + k] * cam.t[2]);
+    const T vinv = Num<T>::rsqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+    for (int k = 0; k < 3; k++) dir[k] = v[k] * vinv;
+    return vinv;
+}
+
+// ---------------------------------------------------------------------------
+// forward
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_t stride, gs_frame frame,
+                                                  gs_raster_cfg cfg, T* __restrict__ rec,
+                                                  uint4* __restrict__ meta) {
+    constexpr int NK = (D + 1) * (D + 1);
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= frame.n_records) return;
+    const int j = job_of_record(frame.jobs, frame.n_jobs, r);
+    const gs_job job = frame.jobs[j];
+    const int64_t g = job.g0 + (r - job.rec0);
+    Cam<T> cam;
+    load_cam(frame.cams[job.cam], cam);
+    Geo<T> G;
+    uint4 m = make_uint4(0xffffffffu, 0u, 0u, 0u);
+    if (!geometry(P, stride, g, cam, cfg, G)) { meta[r] = m; return; }
+
+    // conservative pixel rectangle of {alpha >= alpha_min}: the ellipse
+    // d^T A d <= 2 ln(o / alpha_min) has half-extents sqrt(thr * Sigma'_xx), ...
+    using N = Num<T>;
+    const T thr = T(2) * N::log(G.o / T(cfg.alpha_min));
+    const T hx = N::sqrt(thr * G.sxx) * T(1.0001) + T(0.01);
+    const T hy = N::sqrt(thr * G.syy) * T(1.0001) + T(0.01);
+    T x0 = ceil(G.mx - hx - T(0.5)), x1 = floor(G.mx + hx - T(0.5));
+    T y0 = ceil(G.my - hy - T(0.5)), y1 = floor(G.my + hy - T(0.5));
+    x0 = x0 < T(0) ? T(0) : x0;
+    y0 = y0 < T(0) ? T(0) : y0;
+    x1 = x1 > T(cam.W - 1) ? T(cam.W - 1) : x1;
+    y1 = y1 > T(cam.H - 1) ? T(cam.H - 1) : y1;
+    if (!(x0 <= x1 && y0 <= y1)) { meta[r] = m; return; }
+    const int tx0 = int(x0) / cfg.tile_w, tx1 = int(x1) / cfg.tile_w;
+    const int ty0 = int(y0) / cfg.tile_h, ty1 = int(y1) / cfg.tile_h;
+
+    // colour from the SH coefficients at the view direction
+    T dir[3];
+    view_dir(G, cam, dir);
+    T Y[16];
+    SH<T>::template basis<D>(dir[0], dir[1], dir[2], Y);
+    T col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < NK; k++) s += Y[k] * plane(P, stride, 11 + 3 * k + ch, g);
+        s += T(0.5);
+        col[ch] = s > T(0) ? s : T(0);
+    }
+
+    T* o = rec + r * GS_REC_WORDS;
+    o[0] = G.mx;
+    o[1] = G.my;
+    o[2] = T(-0.5) * kLog2e<T>() * G.a;
+    o[3] = -kLog2e<T>() * G.b;
+    o[4] = T(-0.5) * kLog2e<T>() * G.c;
+    o[5] = N::log2(G.o);
+    o[6] = col[0];
+    o[7] = col[1];
+    o[8] = col[2];
+    o[9] = G.t[2];
+    o[10] = T(0);
+    o[11] = T(0);
+    m.x = __float_as_uint(float(G.t[2]));
+    m.y = uint32_t((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    m.z = uint32_t(tx0) | (uint32_t(ty0) << 16);
+    m.w = uint32_t(tx1) | (uint32_t(ty1) << 16);
+    meta[r] = m;
+}
+
+// ---------------------------------------------------------------------------
+// backward: per Gaussian, sum the per-pair gradients of each of its records
+// (one record per job that holds it), then apply the chain rule through the
+// projection to every raw parameter plane.
+
+template <typename T, int D>
+__global__ __launch_bounds__(128) void k_project_bwd(const T* __restrict__ P, int64_t stride, int64_t n,
+                                                      gs_frame frame, gs_raster_cfg cfg,
+                                                      const uint4* __restrict__ meta,
+                                                      const uint32_t* __restrict__ pair_off, uint64_t capacity,
+                                                      const T* __restrict__ pg, T* __restrict__ grad,
+                                                      int64_t gstride) {
+    constexpr int NK = (D + 1) * (D + 1);
+    constexpr int A = 11 + 3 * NK;
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    T acc[A];
+#pragma unroll
+    for (int a = 0; a < A; a++) acc[a] = T(0);
+
+    for (int j = 0; j < frame.n_jobs; j++) {
+        const gs_job job = frame.jobs[j];
+        if (g < job.g0 || g >= job.g1) continue;
+        const int64_t r = job.rec0 + (g - job.g0);
+        const uint4 m = meta[r];
+        if (m.y == 0) continue;
+        // screen-space gradient of this record: sum over its (tile) pairs
+        T d[9];
+#pragma unroll
+        for (int i = 0; i < 9; i++) d[i] = T(0);
+        // pairs past the capacity were never emitted (the overflow status is
+        // set and the step must be redone); stay inside the buffer
+        const uint64_t p0 = pair_off[r];
+        const uint64_t np = p0 >= capacity ? 0 : (p0 + m.y > capacity ? capacity - p0 : m.y);
+        const T* src = pg + int64_t(p0) * 9;
+        for (uint64_t k = 0; k < np; k++)
+#pragma unroll
+            for (int i = 0; i < 9; i++) d[i] += src[k * 9 + i];
+
+        Cam<T> cam;
+        load_cam(frame.cams[job.cam], cam);
+        Geo<T> G;
+        geometry(P, stride, g, cam, cfg, G);
+
+        // opacity: lo = log2(o), o = sigmoid(logit)
+        acc[10] += d[5] * (T(1) - G.o) / kLn2<T>();
+
+        // colour: c = max(0, sum_k Y_k f_k + 0.5)
+        T dir[3];
+        const T vinv = view_dir(G, cam, dir);
+        T Y[16];
+        SH<T>::template basis<D>(dir[0], dir[1], dir[2], Y);
+        T dc[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            T s = 0;
+#pragma unroll
+            for (int k = 0; k < NK; k++) s += Y[k] * plane(P, stride, 11 + 3 * k + ch, g);
+            s += T(0.5);
+            dc[ch] = s > T(0) ? d[6 + ch] : T(0);
+        }
+        T wk[16];
+#pragma unroll
+        for (int k = 0; k < NK; k++) {
+            T s = 0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                acc[11 + 3 * k + ch] += Y[k] * dc[ch];
+                s += plane(P, stride, 11 + 3 * k + ch, g) * dc[ch];
+            }
+            wk[k] = s;
+        }
+        T ddir[3];
+        SH<T>::template grad_dot<D>(dir[0], dir[1], dir[2], wk, ddir);
+        const T dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
+        T du[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) du[k] = (ddir[k] - dir[k] * dd) * vinv;
+
+        // conic (scaled for exp2) -> conic -> screen covariance: dS = -A dA A
+        const T da = d[2] * (T(-0.5) * kLog2e<T>());
+        const T db = d[3] * (-kLog2e<T>());
+        const T dcn = d[4] * (T(-0.5) * kLog2e<T>());
+        const T a = G.a, b = G.b, c = G.c;
+        const T S00 = -(a * a * da + a * b * db + b * b * dcn);
+        const T S01 = -(a * b * da + T(0.5) * (a * c + b * b) * db + b * c * dcn);
+        const T S11 = -(b * b * da + b * c * db + c * c * dcn);
+
+        // screen covariance -> Sigma and the rows t0, t1 of J W
+        T St0[3], St1[3];
+        St0[0] = G.Sig[0] * G.t0[0] + G.Sig[1] * G.t0[1] + G.Sig[2] * G.t0[2];
+        St0[1] = G.Sig[1] * G.t0[0] + G.Sig[3] * G.t0[1] + G.Sig[4] * G.t0[2];
+        St0[2] = G.Sig[2] * G.t0[0] + G.Sig[4] * G.t0[1] + G.Sig[5] * G.t0[2];
+        St1[0] = G.Sig[0] * G.t1[0] + G.Sig[1] * G.t1[1] + G.Sig[2] * G.t1[2];
+        St1[1] = G.Sig[1] * G.t1[0] + G.Sig[3] * G.t1[1] + G.Sig[4] * G.t1[2];
+        St1[2] = G.Sig[2] * G.t1[0] + G.Sig[4] * G.t1[1] + G.Sig[5] * G.t1[2];
+        T dt0[3], dt1[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            dt0[k] = T(2) * (S00 * St0[k] + S01 * St1[k]);
+            dt1[k] = T(2) * (S11 * St1[k] + S01 * St0[k]);
+        }
+        // dSigma (symmetric, full-matrix gradient)
+        T dS[6];
+        dS[0] = S00 * G.t0[0] * G.t0[0] + S11 * G.t1[0] * G.t1[0] + T(2) * S01 * G.t0[0] * G.t1[0];
+        dS[3] = S00 * G.t0[1] * G.t0[1] + S11 * G.t1[1] * G.t1[1] + T(2) * S01 * G.t0[1] * G.t1[1];
+        dS[5] = S00 * G.t0[2] * G.t0[2] + S11 * G.t1[2] * G.t1[2] + T(2) * S01 * G.t0[2] * G.t1[2];
+        dS[1] = S00 * G.t0[0] * G.t0[1] + S11 * G.t1[0] * G.t1[1] + S01 * (G.t0[0] * G.t1[1] + G.t1[0] * G.t0[1]);
+        dS[2] = S00 * G.t0[0] * G.t0[2] + S11 * G.t1[0] * G.t1[2] + S01 * (G.t0[0] * G.t1[2] + G.t1[0] * G.t0[2]);
+        dS[4] = S00 * G.t0[1] * G.t0[2] + S11 * G.t1[1] * G.t1[2] + S01 * (G.t0[1] * G.t1[2] + G.t1[1] * G.t0[2]);
+
+        // t0 = J00 W0 + J02 W2, t1 = J11 W1 + J12 W2
+        const T dJ00 = dt0[0] * cam.R[0] + dt0[1] * cam.R[1] + dt0[2] * cam.R[2];
+        const T dJ02 = dt0[0] * cam.R[6] + dt0[1] * cam.R[7] + dt0[2] * cam.R[8];
+        const T dJ11 = dt1[0] * cam.R[3] + dt1[1] * cam.R[4] + dt1[2] * cam.R[5];
+        const T dJ12 = dt1[0] * cam.R[6] + dt1[1] * cam.R[7] + dt1[2] * cam.R[8];
+        const T rz = G.rz, rz2 = G.rz * G.rz;
+        const T tx = G.t[0], ty = G.t[1];
+        T dtc[3];
+        dtc[0] = d[0] * cam.fx * rz;
+        dtc[1] = d[1] * cam.fy * rz;
+        dtc[2] = -(d[0] * cam.fx * tx + d[1] * cam.fy * ty) * rz2;
+        dtc[2] += -(dJ00 * cam.fx + dJ11 * cam.fy) * rz2;
+        dtc[2] += (dJ02 * cam.fx * G.rx + dJ12 * cam.fy * G.ry) * rz2;
+        const T drx = -dJ02 * cam.fx * rz, dry = -dJ12 * cam.fy * rz;
+        if (!G.clx) { dtc[0] += drx * rz; dtc[2] -= drx * tx * rz2; }
+        if (!G.cly) { dtc[1] += dry * rz; dtc[2] -= dry * ty * rz2; }
+        // t = W u + t_cw
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            acc[k] += du[k] + cam.R[k] * dtc[0] + cam.R[3 + k] * dtc[1] + cam.R[6 + k] * dtc[2];
+
+        // Sigma = M M^T with M = R diag(s): dM = 2 dSigma M
+        const T dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+        T dR[9];
+#pragma unroll
+        for (int cidx = 0; cidx < 3; cidx++) {
+            T ds = 0;
+#pragma unroll
+            for (int ridx = 0; ridx < 3; ridx++) {
+                T dM = T(0);
+#pragma unroll
+                for (int k = 0; k < 3; k++) dM += dSf[3 * ridx + k] * G.R[3 * k + cidx];
+                dM *= T(2) * G.s[cidx];
+                ds += dM * G.R[3 * ridx + cidx];
+                dR[3 * ridx + cidx] = dM * G.s[cidx];
+            }
+            acc[7 + cidx] += ds * G.s[cidx];   // s = exp(log-scale)
+        }
+        // R(qn)
+        const T w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+        T dq[4];
+        dq[0] = T(2) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+        dq[1] = T(2) * (y * dR[1] + z * dR[2] + y * dR[3] - T(2) * x * dR[4] - w * dR[5] + z * dR[6] +
+                        w * dR[7] - T(2) * x * dR[8]);
+        dq[2] = T(2) * (-T(2) * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                        z * dR[7] - T(2) * y * dR[8]);
+        dq[3] = T(2) * (-T(2) * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - T(2) * z * dR[4] + y * dR[5] +
+                        x * dR[6] + y * dR[7]);
+        const T qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[3 + k] += (dq[k] - G.qn[k] * qd) * G.qinv;
+    }
+#pragma unroll
+    for (int a = 0; a < A; a++) grad[int64_t(a) * gstride + g] = acc[a];
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename T>
+hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, T* rec,
+                          uint32_t* meta, hipStream_t s) {
+    const int64_t n = f.n_records;
+    if (n == 0) return hipSuccess;
+    dim3 grid(unsigned((n + 255) / 256)), block(256);
+    const T* P = static_cast<const T*>(p.data);
+    uint4* M = reinterpret_cast<uint4*>(meta);
+    switch (p.sh_degree) {
+        case 0: hipLaunchKernelGGL((k_project<T, 0>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        case 1: hipLaunchKernelGGL((k_project<T, 1>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        case 2: hipLaunchKernelGGL((k_project<T, 2>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        default: hipLaunchKernelGGL((k_project<T, 3>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
+                              const uint32_t* meta, const uint32_t* pair_off, uint64_t capacity, const T* pg,
+                              gs_params& grad, hipStream_t s) {
+    const int64_t n = p.n;
+    if (n == 0) return hipSuccess;
+    dim3 grid(unsigned((n + 127) / 128)), block(128);
+    const T* P = static_cast<const T*>(p.data);
+    T* Gd = static_cast<T*>(grad.data);
+    const uint4* M = reinterpret_cast<const uint4*>(meta);
+    switch (p.sh_degree) {
+        case 0: hipLaunchKernelGGL((k_project_bwd<T, 0>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
+        case 1: hipLaunchKernelGGL((k_project_bwd<T, 1>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
+        case 2: hipLaunchKernelGGL((k_project_bwd<T, 2>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
+        default: hipLaunchKernelGGL((k_project_bwd<T, 3>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_project<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, float*, uint32_t*, hipStream_t);
+template hipError_t launch_project<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, double*, uint32_t*, hipStream_t);
+template hipError_t launch_project_bwd<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const uint32_t*, uint64_t, const float*, gs_params&, hipStream_t);
+template hipError_t launch_project_bwd<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const uint32_t*, uint64_t, const double*, gs_params&, hipStream_t);
+
+}  // namespace gs

@@ -1,0 +1,340 @@
+// Per-tile front-to-back alpha compositing (Eq. 2) and its hand-written
+// backward.
+//
+// One wavefront owns one screen tile (TW x TH pixels, PPL = TW*TH/64 pixels
+// per lane) and walks the tile's record list in (depth, record) order.
+// Records are staged 64 at a time into a wave-private LDS slice (one record
+// per lane, read back as broadcasts), so a workgroup needs no barrier and
+// each wave stops as soon as all of its pixels have terminated.  Workgroups
+// are remapped so that each XCD renders one contiguous run of tiles.
+//
+// Backward runs front to back as well: it recomputes alpha, T and the
+// accumulated colour exactly as the forward did (same operations in the same
+// order, so the same keep/stop decisions), and gets the colour behind a
+// Gaussian as C_final - C_accumulated.  No per-pair transmittance is stored.
+// Per pair it reduces the 9 screen-space partials over the wave with DPP and
+// writes them at the pair's emission index, where the projection backward
+// sums them per record in a fixed order (deterministic, no float atomics).
+#include "gs_device.hpp"
+#include "gs_internal.hpp"
+
+namespace gs {
+
+constexpr int kRenderWaves = 4;
+
+// record words as produced by the projection
+enum { R_MX = 0, R_MY, R_QA, R_QB, R_QC, R_LO, R_CR, R_CG, R_CB };
+
+template <typename T>
+struct Rec {
+    T mx, my, qa, qb, qc, lo, c[3];
+};
+
+// log2 of the Gaussian's alpha at offset (dx, dy) from its mean:
+// log2 o - (a dx^2 + 2 b dx dy + c dy^2) log2(e) / 2 with the scale folded
+// into qa, qb, qc
+template <typename T>
+__device__ inline T log2_alpha(const Rec<T>& g, T dx, T dy) {
+    using N = Num<T>;
+    const T t = N::fma(g.qa, dx, g.qb * dy);
+    return N::fma(t, dx, N::fma(g.qc * dy, dy, g.lo));
+}
+
+template <typename T, int TW>
+__device__ inline void pixel_of(int lane, int k, int& x, int& y) {
+    constexpr int rows = kWave / TW;
+    x = lane % TW;
+    y = k * rows + lane / TW;
+}
+
+template <typename T>
+__device__ inline void load_rec(const T* __restrict__ rec, uint32_t r, T* dst) {
+    const T* src = rec + int64_t(r) * GS_REC_WORDS;
+#pragma unroll
+    for (int i = 0; i < GS_REC_WORDS; i++) dst[i] = src[i];
+}
+
+template <typename T>
+__device__ inline Rec<T> lds_rec(const T* s) {
+    Rec<T> g;
+    g.mx = s[R_MX]; g.my = s[R_MY]; g.qa = s[R_QA]; g.qb = s[R_QB]; g.qc = s[R_QC]; g.lo = s[R_LO];
+    g.c[0] = s[R_CR]; g.c[1] = s[R_CG]; g.c[2] = s[R_CB];
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// forward
+
+template <typename T, int TW, int TH>
+__global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame frame, gs_raster_cfg cfg,
+                                                                     const T* __restrict__ rec,
+                                                                     const uint32_t* __restrict__ vals,
+                                                                     const uint2* __restrict__ ranges,
+                                                                     T* __restrict__ rgb, T* __restrict__ Tout,
+                                                                     uint32_t* __restrict__ ncontrib) {
+    constexpr int PPL = TW * TH / kWave;
+    __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+    if (tile >= frame.n_tiles) return;
+    const int j = job_of_tile(frame.jobs, frame.n_jobs, tile);
+    const gs_job job = frame.jobs[j];
+    const gs_camera& cam = frame.cams[job.cam];
+    const int W = cam.width, H = cam.height;
+    const int lt = tile - job.tile0;
+    const int tx = lt % job.tiles_x, ty = lt / job.tiles_x;
+
+    T px[PPL], py[PPL], Tr[PPL], C[PPL][3];
+    bool done[PPL];
+    uint32_t last[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        int x, y;
+        pixel_of<T, TW>(lane, k, x, y);
+        x += tx * TW;
+        y += ty * TH;
+        px[k] = T(x) + T(0.5);
+        py[k] = T(y) + T(0.5);
+        done[k] = !(x < W && y < H);
+        Tr[k] = T(1);
+        C[k][0] = C[k][1] = C[k][2] = T(0);
+        last[k] = 0;
+    }
+    const uint2 range = ranges[tile];
+    const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
+    for (uint32_t base = range.x; base < range.y; base += kWave) {
+        bool alive = false;
+#pragma unroll
+        for (int k = 0; k < PPL; k++) alive |= !done[k];
+        if (__ballot(alive) == 0) break;
+        const uint32_t cnt = min(uint32_t(kWave), range.y - base);
+        if (uint32_t(lane) < cnt) load_rec(rec, vals[base + lane], s_rec[wave][lane]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t i = 0; i < cnt; i++) {
+            const Rec<T> g = lds_rec(s_rec[wave][i]);
+#pragma unroll
+            for (int k = 0; k < PPL; k++) {
+                if (done[k]) continue;
+                const T al = Num<T>::exp2(log2_alpha(g, px[k] - g.mx, py[k] - g.my));
+                if (al < amin) continue;
+                const T a = al < amax ? al : amax;
+                const T tn = Tr[k] * (T(1) - a);
+                if (tn < tmin) { done[k] = true; continue; }
+                const T wgt = a * Tr[k];
+                C[k][0] = Num<T>::fma(wgt, g.c[0], C[k][0]);
+                C[k][1] = Num<T>::fma(wgt, g.c[1], C[k][1]);
+                C[k][2] = Num<T>::fma(wgt, g.c[2], C[k][2]);
+                Tr[k] = tn;
+                last[k] = base - range.x + i + 1;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int64_t plane = int64_t(W) * H;
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        int x, y;
+        pixel_of<T, TW>(lane, k, x, y);
+        x += tx * TW;
+        y += ty * TH;
+        if (x < W && y < H) {
+            const int64_t p = job.px0 + int64_t(y) * W + x;
+            T* out = rgb + 3 * job.px0 + int64_t(y) * W + x;
+            out[0] = C[k][0] + Tr[k] * T(cfg.bg[0]);
+            out[plane] = C[k][1] + Tr[k] * T(cfg.bg[1]);
+            out[2 * plane] = C[k][2] + Tr[k] * T(cfg.bg[2]);
+            Tout[p] = Tr[k];
+            ncontrib[p] = last[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward
+
+template <typename T, int TW, int TH>
+__global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
+    gs_frame frame, gs_raster_cfg cfg, const T* __restrict__ rec, const uint4* __restrict__ meta,
+    const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
+    const T* __restrict__ rgb, int mode, const T* __restrict__ gin, T* __restrict__ loss_out, T* __restrict__ pg) {
+    constexpr int PPL = TW * TH / kWave;
+    __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
+    __shared__ uint32_t s_pair[kRenderWaves][kWave];
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+    if (tile >= frame.n_tiles) return;
+    const int j = job_of_tile(frame.jobs, frame.n_jobs, tile);
+    const gs_job job = frame.jobs[j];
+    const gs_camera& cam = frame.cams[job.cam];
+    const int W = cam.width, H = cam.height;
+    const int lt = tile - job.tile0;
+    const int tx = lt % job.tiles_x, ty = lt / job.tiles_x;
+    const int64_t plane = int64_t(W) * H;
+    const T inv = T(job.loss_weight) / T(3 * plane);
+
+    T px[PPL], py[PPL], Tr[PPL], Cf[PPL][3], Acc[PPL][3], gc[PPL][3];
+    bool done[PPL];
+    T loss = T(0);
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        int x, y;
+        pixel_of<T, TW>(lane, k, x, y);
+        x += tx * TW;
+        y += ty * TH;
+        px[k] = T(x) + T(0.5);
+        py[k] = T(y) + T(0.5);
+        const bool in = x < W && y < H;
+        done[k] = !in;
+        Tr[k] = T(1);
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) {
+            Acc[k][ch] = T(0);
+            Cf[k][ch] = T(0);
+            gc[k][ch] = T(0);
+        }
+        if (in) {
+            const int64_t o = 3 * job.px0 + int64_t(y) * W + x;
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) {
+                const T c = rgb[o + ch * plane];
+                Cf[k][ch] = c;
+                if (mode == GS_LOSS_L1) {
+                    const T d = c - gin[o + ch * plane];
+                    gc[k][ch] = d > T(0) ? inv : (d < T(0) ? -inv : T(0));
+                    loss += (d < T(0) ? -d : d) * inv;
+                } else {
+                    gc[k][ch] = gin[o + ch * plane];
+                }
+            }
+        }
+    }
+    if (mode == GS_LOSS_L1 && loss_out) {
+        const T l = wave_sum(loss);
+        if (lane == 0) atomicAdd(loss_out + j, l);
+    }
+
+    const uint2 range = ranges[tile];
+    const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
+    for (uint32_t base = range.x; base < range.y; base += kWave) {
+        const uint32_t cnt = min(uint32_t(kWave), range.y - base);
+        if (uint32_t(lane) < cnt) {
+            const uint32_t r = vals[base + lane];
+            load_rec(rec, r, s_rec[wave][lane]);
+            // emission index of pair (this tile, r): the record's pairs run
+            // row by row over its tile rectangle
+            const uint4 m = meta[r];
+            const uint32_t x0 = m.z & 0xffffu, y0 = m.z >> 16, x1 = m.w & 0xffffu;
+            s_pair[wave][lane] = pair_off[r] + (uint32_t(ty) - y0) * (x1 - x0 + 1) + (uint32_t(tx) - x0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        bool alive = false;
+#pragma unroll
+        for (int k = 0; k < PPL; k++) alive |= !done[k];
+        const bool any_alive = __ballot(alive) != 0;
+        for (uint32_t i = 0; i < cnt; i++) {
+            const uint32_t e = s_pair[wave][i];
+            T gs[9];
+#pragma unroll
+            for (int q = 0; q < 9; q++) gs[q] = T(0);
+            bool hit = false;
+            if (any_alive) {
+                const Rec<T> g = lds_rec(s_rec[wave][i]);
+#pragma unroll
+                for (int k = 0; k < PPL; k++) {
+                    if (done[k]) continue;
+                    const T dx = px[k] - g.mx, dy = py[k] - g.my;
+                    const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
+                    if (al < amin) continue;
+                    const T a = al < amax ? al : amax;
+                    const T tn = Tr[k] * (T(1) - a);
+                    if (tn < tmin) { done[k] = true; continue; }
+                    const T wgt = a * Tr[k];
+                    T ga = T(0);
+                    const T r1a = T(1) / (T(1) - a);
+#pragma unroll
+                    for (int ch = 0; ch < 3; ch++) {
+                        Acc[k][ch] = Num<T>::fma(wgt, g.c[ch], Acc[k][ch]);
+                        gs[6 + ch] += gc[k][ch] * wgt;
+                        ga += gc[k][ch] * (g.c[ch] * Tr[k] - (Cf[k][ch] - Acc[k][ch]) * r1a);
+                    }
+                    Tr[k] = tn;
+                    hit = true;
+                    if (al < amax) {
+                        const T ge = ga * al * kLn2<T>();   // d alpha / d log2-alpha = alpha ln 2
+                        gs[R_LO] += ge;
+                        gs[R_QA] += ge * dx * dx;
+                        gs[R_QB] += ge * dx * dy;
+                        gs[R_QC] += ge * dy * dy;
+                        gs[R_MX] -= ge * (T(2) * g.qa * dx + g.qb * dy);
+                        gs[R_MY] -= ge * (g.qb * dx + T(2) * g.qc * dy);
+                    }
+                }
+            }
+            T out = T(0);
+            if (__ballot(hit) != 0) {
+#pragma unroll
+                for (int q = 0; q < 9; q++) {
+                    const T s = wave_sum(gs[q]);
+                    out = (lane == q) ? s : out;
+                }
+            }
+            if (lane < 9) pg[int64_t(e) * 9 + lane] = out;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename T, int TW, int TH>
+static void fwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& b, T* rgb,
+                       T* Tfin, uint32_t* nc, hipStream_t s) {
+    const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
+    hipLaunchKernelGGL((k_render_fwd<T, TW, TH>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec, b.vals,
+                       reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc);
+}
+
+template <typename T, int TW, int TH>
+static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
+                       const gs_bins& b, const T* rgb, int mode, const T* gin, T* loss, T* pg, hipStream_t s) {
+    const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
+    hipLaunchKernelGGL((k_render_bwd<T, TW, TH>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
+                       reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals,
+                       reinterpret_cast<const uint2*>(b.ranges), rgb, mode, gin, loss, pg);
+}
+
+#define GS_TILE_DISPATCH(FN, ...)                                                       \
+    do {                                                                                \
+        if (cfg.tile_w == 8 && cfg.tile_h == 8) FN<T, 8, 8>(__VA_ARGS__);              \
+        else if (cfg.tile_w == 16 && cfg.tile_h == 8) FN<T, 16, 8>(__VA_ARGS__);       \
+        else if (cfg.tile_w == 32 && cfg.tile_h == 8) FN<T, 32, 8>(__VA_ARGS__);       \
+        else FN<T, 16, 16>(__VA_ARGS__);                                               \
+    } while (0)
+
+template <typename T>
+hipError_t launch_render_fwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& bins,
+                             T* rgb, T* Tfin, uint32_t* ncontrib, hipStream_t s) {
+    if (f.n_tiles == 0) return hipSuccess;
+    GS_TILE_DISPATCH(fwd_launch, f, cfg, rec, bins, rgb, Tfin, ncontrib, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
+                             const gs_bins& bins, const T* rgb, gs_loss_mode mode, const T* gin, T* loss, T* pg,
+                             hipStream_t s) {
+    if (f.n_tiles == 0) return hipSuccess;
+    GS_TILE_DISPATCH(bwd_launch, f, cfg, rec, meta, bins, rgb, int(mode), gin, loss, pg, s);
+    return hipGetLastError();
+}
+
+template hipError_t launch_render_fwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const gs_bins&, float*, float*, uint32_t*, hipStream_t);
+template hipError_t launch_render_fwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const gs_bins&, double*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_render_bwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const uint32_t*, const gs_bins&, const float*, gs_loss_mode, const float*, float*, float*, hipStream_t);
+template hipError_t launch_render_bwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const uint32_t*, const gs_bins&, const double*, gs_loss_mode, const double*, double*, double*, hipStream_t);
+
+}  // namespace gs

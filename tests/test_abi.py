@@ -1,0 +1,131 @@
+"""The C-ABI library loads, exports every symbol include/gs.h declares, its
+struct layouts agree with the binding, and host-side logic (planning,
+argument validation) works without a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs.h")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    from paper_2405_13943_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_2405_13943_amd import gs as g
+    return g
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(gs):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(gs.lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", gs._build.LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (gs_[a-z0-9_]+)", out))
+    assert set(names) <= exported, set(names) - exported
+
+
+def test_struct_layouts_match_header(gs, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "gs.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gs_params), sizeof(gs_camera), sizeof(gs_job),
+         sizeof(gs_frame), sizeof(gs_raster_cfg), sizeof(gs_bins), sizeof(gs_adam_cfg));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(gs_job, g0), offsetof(gs_job, loss_weight), offsetof(gs_frame, g_max),
+         offsetof(gs_raster_cfg, bg), offsetof(gs_adam_cfg, step));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    sizes, offs = [list(map(int, l.split())) for l in subprocess.run([str(exe)], capture_output=True,
+                                                                    text=True).stdout.splitlines()]
+    S = ctypes.sizeof
+    assert sizes == [S(gs.GsParams), S(gs.GsCamera), S(gs.GsJob), S(gs.GsFrame), S(gs.GsRasterCfg), S(gs.GsBins),
+                     S(gs.GsAdamCfg)]
+    assert offs == [gs.GsJob.g0.offset, gs.GsJob.loss_weight.offset, gs.GsFrame.g_max.offset,
+                    gs.GsRasterCfg.bg.offset, gs.GsAdamCfg.step.offset]
+
+
+def test_frame_plan_host_only(gs):
+    from paper_2405_13943_amd import scenes
+    s = scenes.config1()
+    cfg = gs.raster_cfg((16, 16))
+    cams = (gs.GsCamera * 4)(*[gs.camera_struct(c) for c in s.cams])
+    jobs = (gs.GsJob * 4)()
+    for i in range(4):
+        jobs[i].cam, jobs[i].g0, jobs[i].g1 = i, 0, 2000
+    nr, npx, nt, gm = gs.c_i64(), gs.c_i64(), gs.c_i32(), gs.c_i64()
+    rc = gs.lib.gs_frame_plan(cams, 4, jobs, 4, ctypes.byref(cfg), ctypes.byref(nr), ctypes.byref(npx),
+                              ctypes.byref(nt), ctypes.byref(gm))
+    assert rc == 0
+    assert (nr.value, npx.value, nt.value, gm.value) == (8000, 4 * 128 * 128, 4 * 64, 2000)
+    assert [jobs[i].tile0 for i in range(4)] == [0, 64, 128, 192]
+    assert [jobs[i].px0 for i in range(4)] == [0, 16384, 32768, 49152]
+    assert [jobs[i].rec0 for i in range(4)] == [0, 2000, 4000, 6000]
+    # ragged image: 100x70 with 16x16 tiles -> 7 x 5 tiles
+    c2 = scenes.look_at([0, 0, 3], [0, 0, 0], 100, 70, 80.0, 80.0)
+    cams2 = (gs.GsCamera * 1)(gs.camera_struct(c2))
+    jobs2 = (gs.GsJob * 1)()
+    jobs2[0].cam, jobs2[0].g0, jobs2[0].g1 = 0, 5, 9
+    assert gs.lib.gs_frame_plan(cams2, 1, jobs2, 1, ctypes.byref(cfg), ctypes.byref(nr), ctypes.byref(npx),
+                                ctypes.byref(nt), ctypes.byref(gm)) == 0
+    assert (jobs2[0].tiles_x, jobs2[0].tiles_y, nr.value, gm.value) == (7, 5, 4, 9)
+
+
+def test_invalid_arguments_rejected_without_launch(gs):
+    cfg = gs.raster_cfg()
+    f = gs.GsFrame()
+    bad = gs.GsParams(None, -1, 0, 0, 0)
+    assert gs.lib.gs_project(ctypes.byref(bad), ctypes.byref(f), ctypes.byref(cfg), None, None, None) == gs.GS_E_INVALID
+    assert "negative" in gs.lib.gs_last_error().decode()
+    deg4 = gs.GsParams(None, 0, 0, 4, 0)
+    assert gs.lib.gs_project(ctypes.byref(deg4), ctypes.byref(f), ctypes.byref(cfg), None, None, None) == gs.GS_E_INVALID
+    cfg_bad = gs.raster_cfg((12, 12))
+    ok = gs.GsParams(None, 0, 0, 0, 0)
+    assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(cfg_bad), None, None, None) == gs.GS_E_INVALID
+    # jobs reaching past the parameter planes
+    f2 = gs.GsFrame(1, 1, 1, 1, 10, 10, 11)
+    p10 = gs.GsParams(1, 10, 10, 0, 0)
+    assert gs.lib.gs_project(ctypes.byref(p10), ctypes.byref(f2), ctypes.byref(cfg), 1, 1, None) == gs.GS_E_INVALID
+    # backward workspace too small
+    bins = gs.GsBins(1, 1, 1, 1, 1000)
+    rc = gs.lib.gs_render_bwd(ctypes.byref(p10), ctypes.byref(gs.GsFrame(1, 1, 1, 1, 10, 10, 10)), ctypes.byref(cfg),
+                              1, 1, ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), 1, 8, None)
+    assert rc == gs.GS_E_CAPACITY
+    # Adam with mismatched planes, bad step
+    a = gs.GsParams(1, 10, 10, 0, 0)
+    b = gs.GsParams(1, 11, 11, 0, 0)
+    acfg = gs.adam_cfg([1e-3] * 5, [0] * 5, 1)
+    assert gs.lib.gs_adam_admm(ctypes.byref(a), ctypes.byref(b), ctypes.byref(a), ctypes.byref(a), None, None,
+                               ctypes.byref(acfg), None) == gs.GS_E_INVALID
+    acfg0 = gs.adam_cfg([1e-3] * 5, [0] * 5, 0)
+    assert gs.lib.gs_adam_admm(ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), None, None,
+                               ctypes.byref(acfg0), None) == gs.GS_E_INVALID
+    # consensus relaxation outside (0, 2)
+    assert gs.lib.gs_consensus(ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), 1, 1,
+                               2.5, None, None) == gs.GS_E_INVALID
+
+
+def test_workspace_sizes_grow_with_inputs(gs):
+    a = gs.lib.gs_bin_sort_workspace_size(1000, 10000, 64)
+    b = gs.lib.gs_bin_sort_workspace_size(2000, 20000, 64)
+    assert 0 < a < b
+    assert gs.lib.gs_render_bwd_workspace_size(1000, 0) == 1000 * 9 * 4
+    assert gs.lib.gs_render_bwd_workspace_size(1000, 1) == 1000 * 9 * 8

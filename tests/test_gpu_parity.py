@@ -1,0 +1,400 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the
+parity scene (2,000 Gaussians, SH degree 0, four 128x128 views) and on small
+edge cases.
+
+Tolerances (FP32 kernels vs FP64 oracle):
+  - images: |C - C_ref| <= 1e-4 |C_ref| + 1e-6 on pixels the oracle does not
+    flag as near a decision threshold;
+  - gradients: per attribute group ||g - g_ref|| / ||g_ref|| <= 1e-3;
+  - projection: 1e-5 relative (a few FP32 rounding steps);
+  - Adam / consensus: 1e-6 relative + small absolute (a handful of FP32 ops);
+  - binning: bit-exact against a stable sort of the same integer keys.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13943_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2405_13943_amd import gs  # noqa: E402
+
+LOG2E = 1.0 / math.log(2.0)
+GROUPS = {"p": [0, 1, 2], "q": [3, 4, 5, 6], "s": [7, 8, 9], "o": [10]}
+
+
+def group_planes(A):
+    d = dict(GROUPS)
+    d["f"] = list(range(11, A))
+    return d
+
+
+def make_frame(scene, cfg, views=None, weight=None):
+    views = list(range(len(scene.cams))) if views is None else views
+    n = scene.params.shape[1]
+    w = weight if weight is not None else 1.0 / len(views)
+    jobs = [gs.JobSpec(v, 0, n, w) for v in views]
+    return gs.Frame(scene.cams, jobs, cfg)
+
+
+def frame_target(frame, scene, views):
+    return torch.cat([torch.from_numpy(scene.targets[v]).reshape(-1) for v in views]).cuda()
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return scenes.config1()
+
+
+@pytest.fixture(scope="module")
+def gpu1(cfg1):
+    print("\n[gpu] config-1 forward (2000 G, 4 x 128x128)", flush=True)
+    cfg = gs.raster_cfg((16, 16))
+    frame = make_frame(cfg1, cfg)
+    params = torch.from_numpy(cfg1.params).cuda()
+    buf = gs.rasterize(params, frame, cfg)
+    torch.cuda.synchronize()
+    return cfg, frame, params, buf
+
+
+@pytest.fixture(scope="module")
+def ref1(cfg1):
+    return [oracle.render(cfg1.params, c) for c in cfg1.cams]
+
+
+def images(frame, buf):
+    return [frame.image(buf.rgb, i).cpu().numpy().astype(np.float64) for i in range(frame.n_jobs)]
+
+
+def assert_image_close(got, ref, flags, rtol=1e-4, atol=1e-6):
+    ok = flags == 0
+    err = np.abs(got - ref["rgb"])
+    bad = (err > rtol * np.abs(ref["rgb"]) + atol) & ok[None]
+    assert not bad.any(), f"{bad.sum()} pixel-channels off, max err {err[:, ok].max():.3e}"
+
+
+# ---------------------------------------------------------------------------
+
+def test_project_matches_oracle(cfg1, gpu1):
+    cfg, frame, params, buf = gpu1
+    rec = buf.rec.view(-1, gs.REC_WORDS).cpu().numpy().astype(np.float64)
+    meta = buf.meta.view(-1, gs.META_WORDS).cpu().numpy().view(np.uint32)
+    for v in range(4):
+        pr = oracle.project(cfg1.params, cfg1.cams[v])
+        r = rec[v * 2000:(v + 1) * 2000]
+        m = meta[v * 2000:(v + 1) * 2000]
+        vis = m[:, 1] > 0
+        assert vis.sum() > 500
+        assert pr["valid"][vis].all()
+        np.testing.assert_allclose(r[vis, 0:2], pr["mean2d"][vis], rtol=0, atol=2e-4)
+        conic = np.stack([r[:, 2] / (-0.5 * LOG2E), r[:, 3] / -LOG2E, r[:, 4] / (-0.5 * LOG2E)], axis=1)
+        scale = np.abs(pr["conic"][vis]).max(axis=1, keepdims=True)
+        np.testing.assert_allclose(conic[vis] / scale, pr["conic"][vis] / scale, atol=2e-5)
+        np.testing.assert_allclose(2.0 ** r[vis, 5], pr["opacity"][vis], rtol=2e-6)
+        np.testing.assert_allclose(r[vis, 6:9], pr["rgb"][vis], atol=2e-6)
+        np.testing.assert_allclose(r[vis, 9], pr["depth"][vis], rtol=1e-6)
+        np.testing.assert_array_equal(m[vis, 0], np.float32(r[vis, 9]).view(np.uint32))
+
+
+def _bins_check(frame, buf):
+    meta = buf.meta.view(-1, gs.META_WORDS).cpu().numpy().view(np.uint32)
+    c = gs.read_counters(buf)
+    rects = np.stack([meta[:, 2] & 0xFFFF, meta[:, 2] >> 16, meta[:, 3] & 0xFFFF, meta[:, 3] >> 16], axis=1)
+    rects = rects.astype(np.int64)
+    rects[meta[:, 1] == 0] = [1, 1, 0, 0]
+    job_of = np.zeros(frame.n_records, np.int64)
+    for j in range(frame.n_jobs):
+        job_of[frame.job(j).rec0: frame.job(j).rec0 + frame.job(j).g1 - frame.job(j).g0] = j
+    tb = [frame.job(j).tile0 for j in range(frame.n_jobs)]
+    tx = [frame.job(j).tiles_x for j in range(frame.n_jobs)]
+    vals, ranges = oracle.bin_reference(rects, meta[:, 0], tb, tx, job_of, frame.n_tiles)
+    assert c["status"] == 0
+    assert c["pairs"] == len(vals)
+    assert c["visible"] == int((meta[:, 1] > 0).sum())
+    got = buf.vals[:len(vals)].cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(got, vals)
+    np.testing.assert_array_equal(buf.ranges.view(-1, 2).cpu().numpy().view(np.uint32), ranges)
+
+
+def test_bins_bit_exact(gpu1):
+    cfg, frame, params, buf = gpu1
+    _bins_check(frame, buf)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 8)])
+def test_bins_bit_exact_other_tiles(cfg1, tile):
+    cfg = gs.raster_cfg(tile)
+    frame = make_frame(cfg1, cfg)
+    buf = gs.rasterize(torch.from_numpy(cfg1.params).cuda(), frame, cfg)
+    _bins_check(frame, buf)
+
+
+def test_render_fwd_matches_oracle(gpu1, ref1):
+    cfg, frame, params, buf = gpu1
+    nflag = 0
+    for v, img in enumerate(images(frame, buf)):
+        ref = ref1[v]
+        nflag += int((ref["flags"] != 0).sum())
+        assert_image_close(img, ref, ref["flags"])
+        T = frame.plane(buf.T, v).cpu().numpy()
+        ok = ref["flags"] == 0
+        np.testing.assert_allclose(T[ok], ref["T"][ok], rtol=1e-4, atol=1e-6)
+    assert nflag < 50
+
+
+def test_tile_shape_and_batch_invariance(cfg1, gpu1):
+    """Forward images are bit-identical across tile shapes and whether views
+    are rendered batched or one at a time."""
+    cfg, frame, params, buf = gpu1
+    base = images(frame, buf)
+    for tile in [(8, 8), (16, 8), (32, 8)]:
+        c2 = gs.raster_cfg(tile)
+        f2 = make_frame(cfg1, c2)
+        b2 = gs.rasterize(params, f2, c2)
+        for a, b in zip(base, images(f2, b2)):
+            np.testing.assert_array_equal(a, b)
+    for v in range(4):
+        f1 = make_frame(cfg1, cfg, [v])
+        b1 = gs.rasterize(params, f1, cfg)
+        np.testing.assert_array_equal(images(f1, b1)[0], base[v])
+
+
+def test_forward_deterministic(gpu1):
+    cfg, frame, params, buf = gpu1
+    a = buf.rgb.clone()
+    gs.rasterize(params, frame, cfg, buf)
+    assert torch.equal(a, buf.rgb)
+
+
+def _oracle_dldc(scene, views, ref, weight):
+    """L1 gradient from the oracle image, zero at flagged pixels and where
+    |C - target| is within rounding of the kink."""
+    out = []
+    for v in views:
+        C = ref[v]["rgb"]
+        d = C - scene.targets[v]
+        g = weight * np.sign(d) / d.size
+        g[:, ref[v]["flags"] != 0] = 0
+        g[np.abs(d) < 1e-5] = 0
+        out.append(g)
+    return out
+
+
+def test_render_bwd_matches_oracle(cfg1, gpu1, ref1):
+    cfg, frame, params, buf = gpu1
+    views = list(range(4))
+    dl = _oracle_dldc(cfg1, views, ref1, 0.25)
+    g_ref = sum(oracle.backward(cfg1.params, cfg1.cams[v], dl[v]) for v in views)
+    gin = torch.cat([torch.from_numpy(d.astype(np.float32)).reshape(-1) for d in dl]).cuda()
+    grad = torch.empty_like(params)
+    gs.render_bwd(params, frame, cfg, buf, grad, gs.LOSS_EXTERNAL, gin)
+    g = grad.cpu().numpy().astype(np.float64)
+    for name, planes in group_planes(params.shape[0]).items():
+        num = np.linalg.norm(g[planes] - g_ref[planes])
+        den = np.linalg.norm(g_ref[planes])
+        assert den > 0, name
+        assert num / den <= 1e-3, (name, num / den)
+    # determinism of the backward (no float atomics on the gradient path)
+    grad2 = torch.empty_like(params)
+    gs.render_bwd(params, frame, cfg, buf, grad2, gs.LOSS_EXTERNAL, gin)
+    assert torch.equal(grad, grad2)
+
+
+def test_l1_loss_mode(cfg1, gpu1):
+    """GS_LOSS_L1 equals the external mode fed sign(C - target) * w / (3HW),
+    and the loss is w * mean |C - target|."""
+    cfg, frame, params, buf = gpu1
+    target = frame_target(frame, cfg1, range(4))
+    loss = torch.zeros(4, dtype=torch.float32, device="cuda")
+    g1 = torch.empty_like(params)
+    gs.render_bwd(params, frame, cfg, buf, g1, gs.LOSS_L1, target, loss)
+    d = buf.rgb - target
+    n = 3 * 128 * 128
+    dl = 0.25 * torch.sign(d) / n
+    g2 = torch.empty_like(params)
+    gs.render_bwd(params, frame, cfg, buf, g2, gs.LOSS_EXTERNAL, dl)
+    torch.testing.assert_close(g1, g2, rtol=1e-6, atol=1e-12)
+    want = [0.25 * d[i * n:(i + 1) * n].abs().mean().item() for i in range(4)]
+    np.testing.assert_allclose(loss.cpu().numpy(), want, rtol=1e-5)
+
+
+def _adam_bounds(x, g, m, v, w, lr, rho, step, mask, b1, b2, eps):
+    """Per-element FP32 rounding bounds of one Adam + ADMM update, from the
+    magnitudes of the terms each result sums (u = 2^-24, a few ops each):
+    m' = b1 m + (1-b1) g' can cancel, so its bound scales with
+    b1|m| + (1-b1)|g'|, not with |m'|; the step inherits m''s error."""
+    from oracle.admm import penalty_groups
+    u = 2.0 ** -24
+    grp = penalty_groups(x.shape[0])
+    x, g, m, v = (np.asarray(a, np.float64) for a in (x, g, m, v))
+    r = np.asarray(rho)[grp][:, None] * (1.0 if mask is None else mask[None, :]) if w is not None else 0.0
+    gp_terms = np.abs(g) + (np.abs(r) * (np.abs(x) + np.abs(w)) if w is not None else 0.0)
+    gp = g + (r * (x - w) if w is not None else 0.0)
+    sm = b1 * np.abs(m) + (1 - b1) * gp_terms
+    m1 = b1 * m + (1 - b1) * gp
+    v1 = b2 * v + (1 - b2) * gp * gp
+    bc1, bc2 = 1 - b1 ** step, 1 - b2 ** step
+    den = np.sqrt(v1 / bc2) + eps
+    lrp = np.asarray(lr)[grp][:, None]
+    ratio = np.abs(m1 / bc1) / den
+    bm = 16 * u * sm
+    bv = 16 * u * (b2 * v + (1 - b2) * gp_terms ** 2)
+    bx = 16 * u * np.abs(x) + lrp * (16 * u * ratio + bm / bc1 / den + ratio * bv / (2 * v1 + 1e-300))
+    return bx, bm, bv
+
+
+def test_adam_admm_matches_oracle():
+    rng = np.random.default_rng(31)
+    A, N = 59, 10_003                      # ragged tail (not a multiple of 4)
+    x, g, m, w = (rng.standard_normal((A, N)).astype(np.float32) for _ in range(4))
+    v = np.abs(rng.standard_normal((A, N))).astype(np.float32)
+    mask = (rng.random(N) < 0.5).astype(np.float32)
+    lr, rho = [1e-3, 2e-3, 3e-3, 4e-3, 5e-3], [1e-3, 1e4, 1e4, 1e3, 1e4]
+    # the kernel receives its hyper-parameters as FP32; the oracle gets the same values
+    f32 = lambda v: [float(np.float32(a)) for a in v]  # noqa: E731
+    hp = dict(beta1=f32([0.9])[0], beta2=f32([0.999])[0], eps=f32([1e-8])[0])
+    for use_w, use_mask in [(False, False), (True, False), (True, True)]:
+        t = {k: torch.from_numpy(a.copy()).cuda() for k, a in dict(x=x, g=g, m=m, v=v, w=w).items()}
+        tm = torch.from_numpy(mask).cuda() if use_mask else None
+        gs.adam_admm(t["x"], t["g"], t["m"], t["v"], t["w"] if use_w else None, tm, gs.adam_cfg(lr, rho, 7))
+        ww, mm = (w if use_w else None), (mask if use_mask else None)
+        rx, rm, rv = oracle.adam_admm(x, g, m, v, ww, f32(lr), f32(rho), 7, mask=mm, **hp)
+        bx, bm, bv = _adam_bounds(x, g, m, v, ww, f32(lr), f32(rho), 7, mm, hp["beta1"], hp["beta2"], hp["eps"])
+        for name, got, ref, bnd in [("x", t["x"], rx, bx), ("m", t["m"], rm, bm), ("v", t["v"], rv, bv)]:
+            err = np.abs(got.cpu().numpy() - ref)
+            assert (err <= bnd).all(), (name, use_w, use_mask, int((err > bnd).sum()), float((err / bnd).max()))
+    # unaligned stride: scalar path
+    xs = torch.from_numpy(np.ascontiguousarray(x[:, :N - 1])).cuda()
+    big = torch.zeros((A, N), device="cuda")
+    big[:, :N - 1] = xs
+    sub = big[:, :N - 1]
+    gg = torch.from_numpy(np.ascontiguousarray(g[:, :N - 1])).cuda()
+    mm = torch.zeros_like(gg)
+    vv = torch.zeros_like(gg)
+    gs.adam_admm(sub, gg, mm, vv, None, None, gs.adam_cfg(lr, rho, 1))
+    z = 0 * g[:, :N - 1]
+    rx, _, _ = oracle.adam_admm(x[:, :N - 1], g[:, :N - 1], z, z, None, f32(lr), f32(rho), 1, **hp)
+    bx, _, _ = _adam_bounds(x[:, :N - 1], g[:, :N - 1], z, z, None, f32(lr), f32(rho), 1, None, hp["beta1"],
+                            hp["beta2"], hp["eps"])
+    assert (np.abs(sub.cpu().numpy() - rx) <= bx).all()
+
+
+def test_consensus_matches_oracle():
+    rng = np.random.default_rng(32)
+    K, G, A = 4, 3000, 14
+    held = [sorted(rng.choice(K, rng.integers(1, 3), replace=False)) for _ in range(G)]
+    locs, local_of = [], {}
+    for k in range(K):
+        for gid in range(G):
+            if k in held[gid]:
+                local_of[(gid, k)] = len(locs)
+                locs.append(gid)
+    ptr = np.zeros(G + 1, np.int64)
+    idx = []
+    for gid in range(G):
+        idx += [local_of[(gid, k)] for k in held[gid]]
+        ptr[gid + 1] = len(idx)
+    idx = np.asarray(idx, np.int64)
+    L = len(locs)
+    x = rng.standard_normal((A, L)).astype(np.float32)
+    u = (0.1 * rng.standard_normal((A, L))).astype(np.float32)
+    zp = rng.standard_normal((A, G)).astype(np.float32)
+    for relax in (1.0, 1.6):
+        tx, tu = torch.from_numpy(x).cuda(), torch.from_numpy(u.copy()).cuda()
+        tw, tz = torch.zeros_like(tu), torch.from_numpy(zp.copy()).cuda()
+        res = torch.zeros(10, device="cuda")
+        gs.consensus(tx, tu, tw, tz, torch.from_numpy(ptr).cuda(), torch.from_numpy(idx).cuda(), relax, res)
+        rz, ru, rw = oracle.consensus(x, u, ptr, idx, G, relax=relax, z_prev=zp)
+        np.testing.assert_allclose(tz.cpu().numpy(), rz, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(tu.cpu().numpy(), ru, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(tw.cpu().numpy(), rw, rtol=1e-6, atol=1e-6)
+        rp = sum(((x[:, idx[ptr[g]:ptr[g + 1]]] - rz[:, g:g + 1]) ** 2).sum() for g in range(G))
+        assert abs(res[:5].sum().item() / rp - 1) < 1e-4
+
+
+def test_capacity_overflow_reported_then_grown(cfg1):
+    cfg = gs.raster_cfg((16, 16))
+    frame = make_frame(cfg1, cfg)
+    params = torch.from_numpy(cfg1.params).cuda()
+    buf = gs.Buffers(frame, 100)
+    gs.project(params, frame, cfg, buf)
+    gs.bin_sort(frame, cfg, buf)
+    c = gs.read_counters(buf)
+    assert c["status"] & gs.GS_STATUS_PAIR_OVERFLOW and c["pairs"] > 100
+    gs.rasterize(params, frame, cfg, buf)
+    assert buf.capacity >= c["pairs"]
+    _bins_check(frame, buf)
+
+
+def test_ragged_image_and_empty_frame():
+    """A 100x70 image (partial tiles on both edges) and a frame whose
+    Gaussians are all behind the camera."""
+    s = scenes.config1()
+    cam = scenes.look_at([0.0, 0.4, 2.5], [0, 0, 0], 100, 70, 90.0, 90.0)
+    cfg = gs.raster_cfg((16, 16))
+    p = s.params[:, :500].copy()
+    frame = gs.Frame([cam], [gs.JobSpec(0, 0, 500, 1.0)], cfg)
+    buf = gs.rasterize(torch.from_numpy(p).cuda(), frame, cfg)
+    ref = oracle.render(p, cam)
+    assert_image_close(frame.image(buf.rgb, 0).cpu().numpy().astype(np.float64), ref, ref["flags"])
+    behind = p.copy()
+    behind[2] += 10.0                       # all Gaussians behind the camera at z = 2.5
+    b2 = gs.rasterize(torch.from_numpy(behind).cuda(), frame, cfg)
+    assert gs.read_counters(b2)["pairs"] == 0
+    assert torch.count_nonzero(b2.rgb).item() == 0
+    assert torch.all(b2.T == 1).item()
+    grad = torch.empty((p.shape[0], 500), device="cuda")
+    gs.render_bwd(torch.from_numpy(behind).cuda(), frame, cfg, b2, grad, gs.LOSS_L1,
+                  torch.rand(3 * 100 * 70, device="cuda"))
+    assert torch.count_nonzero(grad).item() == 0
+
+
+def test_f64_path_against_finite_differences():
+    """FP64 instantiation of the same kernels: central differences h = 1e-6 of
+    L = sum W * C on the 200-Gaussian, 64x64, SH-3 adjoint scene (seeded
+    subset of coordinates; coordinates whose keep/stop decisions flip inside
+    [-h, h] are discarded)."""
+    s = scenes.config4a()
+    cam = s.cams[0]
+    cfg = gs.raster_cfg((16, 16))
+    frame = gs.Frame([cam], [gs.JobSpec(0, 0, 200, 1.0)], cfg)
+    p64 = torch.from_numpy(s.params.astype(np.float64)).cuda()
+    rng = np.random.default_rng(41)
+    Wt = torch.from_numpy(rng.standard_normal(3 * 64 * 64)).cuda()
+    buf = gs.rasterize(p64, frame, cfg)
+    base_n = buf.ncontrib.clone()
+    grad = torch.empty_like(p64)
+    gs.render_bwd(p64, frame, cfg, buf, grad, gs.LOSS_EXTERNAL, Wt)
+    g = grad.cpu().numpy()
+    # against the oracle's reverse mode (both FP64)
+    g_ref = oracle.backward(s.params.astype(np.float64), cam, Wt.cpu().numpy().reshape(3, 64, 64))
+    np.testing.assert_allclose(g, g_ref, rtol=1e-7, atol=1e-9 * np.abs(g_ref).max())
+    h = 1e-6
+    # FP64 rounding of the sum L, amplified by 1/h, bounds the FD noise
+    fd_noise = 10 * 2.2e-16 * float((Wt * buf.rgb).abs().sum()) / h
+    coords = [(int(a), int(i)) for a, i in zip(rng.integers(0, 59, 600), rng.integers(0, 200, 600))]
+    bad, used = [], 0
+    for a, i in coords:
+        vals = []
+        flip = False
+        for sgn in (1, -1):
+            q = p64.clone()
+            q[a, i] += sgn * h
+            b = gs.rasterize(q, frame, cfg, buf)
+            flip |= not torch.equal(b.ncontrib, base_n)
+            vals.append(float((Wt * b.rgb).sum()))
+        if flip:
+            continue
+        used += 1
+        fd = (vals[0] - vals[1]) / (2 * h)
+        if abs(fd - g[a, i]) > 1e-5 * abs(g[a, i]) + fd_noise:
+            bad.append((a, i, fd, g[a, i]))
+    assert used > 500
+    assert not bad, bad[:10]
