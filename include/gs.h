@@ -112,6 +112,8 @@ typedef struct {
     int64_t n_records;       /* sum of (g1 - g0) */
     int64_t n_pixels;        /* sum of W * H */
     int64_t g_max;           /* max g1 over jobs; must not exceed the parameter count */
+    int32_t jobs_disjoint;   /* 1 when no two jobs share a Gaussian */
+    int32_t reserved;
 } gs_frame;
 
 /* Rasterizer constants.  The paper writes alpha = o X^proj(p) (Eq. 2) without
@@ -167,16 +169,18 @@ void gs_raster_cfg_default(gs_raster_cfg *cfg);
 
 /* Host-side planning of a frame: fills tiles_x/tiles_y/tile0/rec0/px0 of each
  * job from the host copy of the cameras, and the totals of gs_frame (n_tiles,
- * n_records, n_pixels, g_max).  No device work.  The device job table handed
+ * n_records, n_pixels, g_max, jobs_disjoint).  No device work.  The device job table handed
  * to the other calls must be a copy of the planned jobs. */
 gs_status gs_frame_plan(const gs_camera *cams_host, int32_t n_cams, gs_job *jobs_host, int32_t n_jobs,
                         const gs_raster_cfg *cfg, int64_t *n_records, int64_t *n_pixels, int32_t *n_tiles,
-                        int64_t *g_max);
+                        int64_t *g_max, int32_t *jobs_disjoint);
 
 /* Projection (Sec. 3.1: Eq. 1, Sigma = R S S^T R^T, alpha = o X^proj(p), SH
  * colour).  For every (job, Gaussian) slot r = rec0 + g - g0 writes
  *   rec [r][12]: mean2d x, y; the conic scaled for exp2 (-a/2, -b, -c/2
- *                times log2 e); log2 opacity; colour r, g, b; depth; 2 spare
+ *                times log2 e); log2 opacity; colour r, g, b; depth; the
+ *                conservative half-extents (x, y) in pixels of the region
+ *                where alpha >= alpha_min
  *   meta[r][4]:  FP32 bits of the depth, number of covered tiles (0 = culled),
  *                tile rectangle lo (x | y << 16) and hi (inclusive).
  * The rectangle is conservative: every pixel where alpha >= alpha_min lies

@@ -140,7 +140,8 @@ void gs_raster_cfg_default(gs_raster_cfg* cfg) {
 }
 
 gs_status gs_frame_plan(const gs_camera* cams, int32_t n_cams, gs_job* jobs, int32_t n_jobs, const gs_raster_cfg* cfg,
-                        int64_t* n_records, int64_t* n_pixels, int32_t* n_tiles, int64_t* g_max) {
+                        int64_t* n_records, int64_t* n_pixels, int32_t* n_tiles, int64_t* g_max,
+                        int32_t* jobs_disjoint) {
     if (!cfg || !tile_ok(cfg)) return fail(GS_E_INVALID, "bad raster config / tile shape");
     if (n_jobs < 0 || n_cams < 0 || (n_jobs > 0 && (!jobs || !cams))) return fail(GS_E_INVALID, "bad job list");
     int64_t rec = 0, px = 0, tiles = 0, gmax = 0;
@@ -162,11 +163,22 @@ gs_status gs_frame_plan(const gs_camera* cams, int32_t n_cams, gs_job* jobs, int
         if (J.g1 > gmax) gmax = J.g1;
         px += int64_t(c.width) * c.height;
         if (tiles >= (int64_t(1) << 31)) return fail(GS_E_UNSUPPORTED, "too many tiles");
+        if (int64_t(J.tiles_x) * J.tiles_y >= (int64_t(1) << 24))
+            return fail(GS_E_UNSUPPORTED, "job %d: more than 2^24 tiles in one view", j);
     }
+    int32_t disjoint = 1;
+    for (int32_t a = 0; a < n_jobs && disjoint; a++)
+        for (int32_t b = a + 1; b < n_jobs; b++)
+            if (jobs[a].g0 < jobs[b].g1 && jobs[b].g0 < jobs[a].g1 && jobs[a].g1 > jobs[a].g0 &&
+                jobs[b].g1 > jobs[b].g0) {
+                disjoint = 0;
+                break;
+            }
     if (n_records) *n_records = rec;
     if (n_pixels) *n_pixels = px;
     if (n_tiles) *n_tiles = int32_t(tiles);
     if (g_max) *g_max = gmax;
+    if (jobs_disjoint) *jobs_disjoint = disjoint;
     g_err[0] = 0;
     return GS_OK;
 }

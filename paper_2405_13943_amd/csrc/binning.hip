@@ -37,6 +37,8 @@ struct BinWs {
     uint32_t* tval;       // alternate record-id buffer, [capacity]
     uint32_t* part;       // scan partials, [kMaxGrid + 1]
     uint32_t* hist;       // radix histograms, [256 * kMaxGrid]
+    uint32_t* coltot;     // per-digit totals of one radix pass, [256]
+    uint32_t* poff;       // first pair of each visible record in depth order, [n_records]
     size_t bytes;
 };
 
@@ -52,6 +54,8 @@ static BinWs carve(void* base, int64_t n_records, uint64_t capacity) {
     w.tval = take(nc);
     w.part = take(size_t(kMaxGrid + 1) * 4);
     w.hist = take(size_t(256) * kMaxGrid * 4);
+    w.coltot = take(256 * 4);
+    w.poff = take(nr);
     w.bytes = off;
     return w;
 }
@@ -101,19 +105,23 @@ struct VisibleFlag {      // item i: record i is visible; output: compact (depth
     const uint4* meta;
     uint32_t* key_out;
     uint32_t* val_out;
-    __device__ uint32_t value(uint32_t i) const { return meta[i].y > 0 ? 1u : 0u; }
+    __device__ uint32_t value(uint32_t i) const { return meta_tiles(meta[i].y) > 0 ? 1u : 0u; }
     __device__ void emit(uint32_t i, uint32_t pre) const {
         const uint4 m = meta[i];
-        if (m.y > 0) { key_out[pre] = m.x; val_out[pre] = i; }
+        if (meta_tiles(m.y) > 0) { key_out[pre] = m.x; val_out[pre] = i; }
     }
 };
 
 struct PairCount {        // item s: sorted visible record; output: its first pair
     const uint4* meta;
     const uint32_t* sorted_rec;
-    uint32_t* pair_off;
-    __device__ uint32_t value(uint32_t s) const { return meta[sorted_rec[s]].y; }
-    __device__ void emit(uint32_t s, uint32_t pre) const { pair_off[sorted_rec[s]] = pre; }
+    uint32_t* pair_off;       // by record
+    uint32_t* poff;           // by depth rank
+    __device__ uint32_t value(uint32_t s) const { return meta_tiles(meta[sorted_rec[s]].y); }
+    __device__ void emit(uint32_t s, uint32_t pre) const {
+        pair_off[sorted_rec[s]] = pre;
+        poff[s] = pre;
+    }
 };
 
 template <typename F>
@@ -190,53 +198,37 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint32_t* __restrict
     hist[d * G + blockIdx.x] = s;
 }
 
-// single block: exclusive scan of hist[256 * G] in (digit, block) order.
-// Staged through LDS so that global reads and writes stay coalesced.
-__global__ __launch_bounds__(1024) void k_rs_spine(uint32_t* __restrict__ hist, int total) {
-    constexpr int ITEMS = 8;
-    constexpr int SPAN = 1024 * ITEMS;
-    __shared__ uint32_t buf[SPAN + SPAN / 32];   // one pad word per 32 to spread banks
-    __shared__ uint32_t s_wave[1024 / kWave];
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
-    auto at = [](int i) { return i + (i >> 5); };
-    uint32_t carry = 0;
-    for (int base = 0; base < total; base += SPAN) {
+// one block per digit: exclusive scan of that digit's counts over the G
+// blocks (in place) and the digit's total; the digits' base offsets are
+// then an exclusive scan of 256 totals, done by every scatter block
+__global__ __launch_bounds__(kRsBlock) void k_rs_colscan(uint32_t* __restrict__ hist, int G,
+                                                         uint32_t* __restrict__ coltot) {
+    __shared__ uint32_t s_wave[kRsBlock / kWave];
+    uint32_t* col = hist + size_t(blockIdx.x) * G;
+    constexpr int PER = kMaxGrid / kRsBlock;
+    uint32_t v[PER], sum = 0;
 #pragma unroll
-        for (int k = 0; k < ITEMS; k++) {
-            const int i = base + k * 1024 + tid;
-            buf[at(k * 1024 + tid)] = i < total ? hist[i] : 0u;
-        }
-        __syncthreads();
-        uint32_t loc[ITEMS], sum = 0;
-#pragma unroll
-        for (int k = 0; k < ITEMS; k++) { loc[k] = buf[at(tid * ITEMS + k)]; sum += loc[k]; }
-        const uint32_t inc = wave_incl_scan(sum);
-        if (lane == kWave - 1) s_wave[wave] = inc;
-        __syncthreads();
-        uint32_t before = 0, block_total = 0;
-        for (int w = 0; w < 1024 / kWave; w++) {
-            const uint32_t v = s_wave[w];
-            if (w < wave) before += v;
-            block_total += v;
-        }
-        uint32_t run = carry + before + inc - sum;
-#pragma unroll
-        for (int k = 0; k < ITEMS; k++) { buf[at(tid * ITEMS + k)] = run; run += loc[k]; }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < ITEMS; k++) {
-            const int i = base + k * 1024 + tid;
-            if (i < total) hist[i] = buf[at(k * 1024 + tid)];
-        }
-        carry += block_total;
-        __syncthreads();
+    for (int k = 0; k < PER; k++) {
+        const int i = threadIdx.x * PER + k;
+        v[k] = i < G ? col[i] : 0u;
+        sum += v[k];
     }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(sum, s_wave, tot);
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+        const int i = threadIdx.x * PER + k;
+        if (i < G) col[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) coltot[blockIdx.x] = tot;
 }
 
 __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
-                                                         const uint32_t* __restrict__ hist, int G) {
+                                                         const uint32_t* __restrict__ hist, int G,
+                                                         const uint32_t* __restrict__ coltot) {
     constexpr int NW = kRsBlock / kWave;
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcnt[NW][256];
@@ -245,7 +237,12 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
     const uint32_t n = min(*n_dev, n_host);
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kRsTile, lo, hi);
-    run[tid] = hist[tid * G + blockIdx.x];
+    {
+        __shared__ uint32_t s_wave[NW];
+        uint32_t tot;
+        const uint32_t base = block_excl_scan(coltot[tid], s_wave, tot);
+        run[tid] = base + hist[tid * G + blockIdx.x];
+    }
     for (uint32_t base = lo; base < hi; base += kRsTile) {
         for (int d = lane; d < 256; d += kWave) wcnt[wave][d] = 0;
         __builtin_amdgcn_wave_barrier();
@@ -301,26 +298,56 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
 // ---------------------------------------------------------------------------
 // pair emission and tile ranges
 
+// Pair-parallel emission: block-sized chunks of the P pairs; each chunk finds
+// the depth-ordered records it spans by binary search over their first-pair
+// offsets (staged in LDS), so a Gaussian covering thousands of tiles is
+// spread over many threads instead of serialising one.
+constexpr int kEmitChunk = 2048;
+
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ sorted_rec,
-                                              const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ counters,
+                                              const uint32_t* __restrict__ poff, const uint32_t* __restrict__ counters,
                                               gs_frame frame, uint64_t capacity, uint32_t* __restrict__ tkey,
                                               uint32_t* __restrict__ tval) {
+    __shared__ uint32_t s_off[kEmitChunk];
+    __shared__ uint32_t s_rec[kEmitChunk];
+    __shared__ uint32_t s_lo, s_hi;
     const uint32_t V = counters[GS_CTR_VISIBLE];
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= V) return;
-    const uint32_t r = sorted_rec[s];
-    const uint4 m = meta[r];
-    const uint32_t off = pair_off[r];
-    const int j = job_of_record(frame.jobs, frame.n_jobs, r);
-    const int tile0 = frame.jobs[j].tile0, tiles_x = frame.jobs[j].tiles_x;
-    const uint32_t x0 = m.z & 0xffffu, y0 = m.z >> 16, x1 = m.w & 0xffffu;
-    const uint32_t w = x1 - x0 + 1;
-    for (uint32_t k = 0; k < m.y; k++) {
-        const uint64_t e = uint64_t(off) + k;
-        if (e >= capacity) break;
-        const uint32_t ty = y0 + k / w, tx = x0 + k % w;
-        tkey[e] = uint32_t(tile0) + ty * uint32_t(tiles_x) + tx;
-        tval[e] = r;
+    const uint32_t P = uint32_t(min(uint64_t(counters[GS_CTR_PAIRS]), capacity));
+    for (uint32_t e0 = blockIdx.x * kEmitChunk; e0 < P; e0 += gridDim.x * kEmitChunk) {
+        const uint32_t e1 = min(P, e0 + kEmitChunk);
+        if (threadIdx.x < 2) {
+            // last visible rank whose first pair is <= target (ranks with zero
+            // pairs do not exist: every visible record covers a tile)
+            const uint32_t target = threadIdx.x == 0 ? e0 : e1 - 1;
+            uint32_t lo = 0, hi = V - 1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) >> 1;
+                if (poff[mid] <= target) lo = mid; else hi = mid - 1;
+            }
+            if (threadIdx.x == 0) s_lo = lo; else s_hi = lo;
+        }
+        __syncthreads();
+        const uint32_t lo = s_lo, n = s_hi - s_lo + 1;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            s_off[i] = poff[lo + i];
+            s_rec[i] = sorted_rec[lo + i];
+        }
+        __syncthreads();
+        for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            uint32_t a = 0, b = n - 1;
+            while (a < b) {
+                const uint32_t mid = (a + b + 1) >> 1;
+                if (s_off[mid] <= e) a = mid; else b = mid - 1;
+            }
+            const uint32_t r = s_rec[a], k = e - s_off[a];
+            const uint4 m = meta[r];
+            const int j = job_of_record(frame.jobs, frame.n_jobs, r);
+            const uint32_t x0 = m.z & 0xffffu, y0 = m.z >> 16, x1 = m.w & 0xffffu;
+            const uint32_t w = x1 - x0 + 1;
+            tkey[e] = uint32_t(frame.jobs[j].tile0) + (y0 + k / w) * uint32_t(frame.jobs[j].tiles_x) + x0 + k % w;
+            tval[e] = r;
+        }
+        __syncthreads();
     }
 }
 
@@ -349,8 +376,9 @@ static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, w.hist, G);
-        hipLaunchKernelGGL(k_rs_spine, dim3(1), dim3(1024), 0, s, w.hist, 256 * G);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, w.hist, G);
+        hipLaunchKernelGGL(k_rs_colscan, dim3(256), dim3(kRsBlock), 0, s, w.hist, G, w.coltot);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, w.hist, G,
+                           w.coltot);
         uint32_t* t;
         t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -389,7 +417,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     const uint32_t* sorted_rec = (dk_final == w.dkey[0]) ? w.dval[0] : w.dval[1];
 
     // 3. first pair of each visible record, in depth order; total pairs
-    PairCount pc{meta, sorted_rec, bins.pair_off};
+    PairCount pc{meta, sorted_rec, bins.pair_off, w.poff};
     hipLaunchKernelGGL(k_scan_reduce<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
     hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_PAIRS,
                        bins.capacity);
@@ -401,8 +429,8 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     const int passes = (bits + 7) / 8;
     uint32_t* emit_val = (passes & 1) ? w.tval : bins.vals;
     uint32_t* other_val = (passes & 1) ? bins.vals : w.tval;
-    hipLaunchKernelGGL(k_emit, dim3(unsigned((nrec + 255) / 256)), dim3(256), 0, s, meta, sorted_rec, bins.pair_off,
-                       bins.counters, f, bins.capacity, w.tkey[0], emit_val);
+    hipLaunchKernelGGL(k_emit, dim3(unsigned(grid_for(bins.capacity, kEmitChunk))), dim3(256), 0, s, meta, sorted_rec,
+                       w.poff, bins.counters, f, bins.capacity, w.tkey[0], emit_val);
     const uint32_t pmax = uint32_t(std::min<uint64_t>(bins.capacity, 0xffffffffull));
     uint32_t* tk_final = w.tkey[0];
     if (passes > 0) {

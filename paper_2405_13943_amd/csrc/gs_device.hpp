@@ -38,6 +38,14 @@ template <typename T> __device__ constexpr T kLn2() { return T(0.693147180559945
 template <typename T> __device__ constexpr T kLog2e() { return T(1.44269504088896340736); }
 
 // ---------------------------------------------------------------------------
+// per-record metadata word 1: covered tiles in the low 24 bits, the colour
+// clamp of each channel (SH sum + 0.5 <= 0) in bits 24..26
+
+constexpr uint32_t kTilesMask = 0xffffffu;
+__host__ __device__ inline uint32_t meta_tiles(uint32_t y) { return y & kTilesMask; }
+__host__ __device__ inline uint32_t meta_clamp(uint32_t y) { return y >> 24; }
+
+// ---------------------------------------------------------------------------
 // job lookup: jobs are laid out in ascending rec0 / tile0 / px0 order
 
 __device__ inline int job_of_record(const gs_job* __restrict__ jobs, int n_jobs, int64_t r) {

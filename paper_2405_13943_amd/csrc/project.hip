@@ -254,6 +254,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     T Y[16];
     SH<T>::template basis<D>(dir[0], dir[1], dir[2], Y);
     T col[3];
+    uint32_t clamp = 0;
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) {
         T s = 0;
@@ -261,6 +262,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
         for (int k = 0; k < NK; k++) s += Y[k] * plane(P, stride, 11 + 3 * k + ch, g);
         s += T(0.5);
         col[ch] = s > T(0) ? s : T(0);
+        clamp |= s > T(0) ? 0u : (1u << ch);
     }
 
     T* o = rec + r * GS_REC_WORDS;
@@ -274,180 +276,271 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     o[7] = col[1];
     o[8] = col[2];
     o[9] = G.t[2];
-    o[10] = T(0);
-    o[11] = T(0);
+    o[10] = hx;   // conservative half-extents of {alpha >= alpha_min} in pixels
+    o[11] = hy;
     m.x = __float_as_uint(float(G.t[2]));
-    m.y = uint32_t((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    m.y = uint32_t((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) | (clamp << 24);
     m.z = uint32_t(tx0) | (uint32_t(ty0) << 16);
     m.w = uint32_t(tx1) | (uint32_t(ty1) << 16);
     meta[r] = m;
 }
 
 // ---------------------------------------------------------------------------
-// backward: per Gaussian, sum the per-pair gradients of each of its records
-// (one record per job that holds it), then apply the chain rule through the
-// projection to every raw parameter plane.
+// backward: sum each record's per-pair partials, then apply the chain rule
+// through the projection to every raw parameter plane.
 
-template <typename T, int D>
-__global__ __launch_bounds__(128) void k_project_bwd(const T* __restrict__ P, int64_t stride, int64_t n,
-                                                      gs_frame frame, gs_raster_cfg cfg,
-                                                      const uint4* __restrict__ meta,
-                                                      const uint32_t* __restrict__ pair_off, uint64_t capacity,
-                                                      const T* __restrict__ pg, T* __restrict__ grad,
-                                                      int64_t gstride) {
-    constexpr int NK = (D + 1) * (D + 1);
-    constexpr int A = 11 + 3 * NK;
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    T acc[A];
+// Per lane: the 9 partials of its record, the sum of its np pairs starting at
+// p0.  A lane sums a small record itself; the wave sums a large one together
+// (strided partial sums, then a fixed reduction tree), so a Gaussian spanning
+// thousands of tiles does not serialise one lane.  Every lane of the wave
+// must call this (cross-lane reductions).
+template <typename T>
+__device__ inline void record_pair_sum(const T* __restrict__ pg, uint64_t p0, uint64_t np, T* d) {
+    constexpr uint64_t kCoop = 24;
+    const int lane = lane_id();
 #pragma unroll
-    for (int a = 0; a < A; a++) acc[a] = T(0);
-
-    for (int j = 0; j < frame.n_jobs; j++) {
-        const gs_job job = frame.jobs[j];
-        if (g < job.g0 || g >= job.g1) continue;
-        const int64_t r = job.rec0 + (g - job.g0);
-        const uint4 m = meta[r];
-        if (m.y == 0) continue;
-        // screen-space gradient of this record: sum over its (tile) pairs
-        T d[9];
-#pragma unroll
-        for (int i = 0; i < 9; i++) d[i] = T(0);
-        // pairs past the capacity were never emitted (the overflow status is
-        // set and the step must be redone); stay inside the buffer
-        const uint64_t p0 = pair_off[r];
-        const uint64_t np = p0 >= capacity ? 0 : (p0 + m.y > capacity ? capacity - p0 : m.y);
+    for (int i = 0; i < 9; i++) d[i] = T(0);
+    const bool big = np > kCoop;
+    if (!big) {
         const T* src = pg + int64_t(p0) * 9;
         for (uint64_t k = 0; k < np; k++)
 #pragma unroll
             for (int i = 0; i < 9; i++) d[i] += src[k * 9 + i];
+    }
+    uint64_t bigmask = __ballot(big);
+    while (bigmask) {
+        const int src_lane = __ffsll((long long)bigmask) - 1;
+        bigmask &= bigmask - 1;
+        const uint64_t bp0 = __shfl(p0, src_lane, kWave), bnp = __shfl(np, src_lane, kWave);
+        T part[9];
+#pragma unroll
+        for (int i = 0; i < 9; i++) part[i] = T(0);
+        const T* src = pg + int64_t(bp0) * 9;
+        for (uint64_t k = lane; k < bnp; k += kWave)
+#pragma unroll
+            for (int i = 0; i < 9; i++) part[i] += src[k * 9 + i];
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            const T t = wave_sum(part[i]);
+            if (lane == src_lane) d[i] = t;
+        }
+    }
+}
 
-        Cam<T> cam;
-        load_cam(frame.cams[job.cam], cam);
-        Geo<T> G;
-        geometry(P, stride, g, cam, cfg, G);
+// pairs of a record that were emitted (pairs past the capacity never were:
+// the overflow status is set and the step must be redone)
+__device__ inline void record_pairs(uint32_t ntiles, uint32_t off, uint64_t capacity, uint64_t& p0, uint64_t& np) {
+    p0 = off;
+    np = ntiles == 0 || p0 >= capacity ? 0 : (p0 + ntiles > capacity ? capacity - p0 : ntiles);
+}
 
-        // opacity: lo = log2(o), o = sigmoid(logit)
-        acc[10] += d[5] * (T(1) - G.o) / kLn2<T>();
+// Chain rule of one visible record of Gaussian g seen by `camera`; emit(a, v)
+// receives the gradient v of parameter plane a.
+template <typename T, int D, typename Emit>
+__device__ inline void record_chain(const T* __restrict__ P, int64_t stride, int64_t g, const gs_camera& camera,
+                                    const gs_raster_cfg& cfg, uint32_t meta_y, const T* d, Emit emit) {
+    constexpr int NK = (D + 1) * (D + 1);
+    const uint4 m = make_uint4(0u, meta_y, 0u, 0u);
+    Cam<T> cam;
+    load_cam(camera, cam);
+    Geo<T> G;
+    geometry(P, stride, g, cam, cfg, G);
 
-        // colour: c = max(0, sum_k Y_k f_k + 0.5)
-        T dir[3];
-        const T vinv = view_dir(G, cam, dir);
-        T Y[16];
-        SH<T>::template basis<D>(dir[0], dir[1], dir[2], Y);
-        T dc[3];
+    // The compositing backward hands over, per record, the moments of
+    // ge = dL/dalpha * alpha over the covered pixels (offsets dx, dy from
+    // the mean): d[0] = sum ge, d[1] = sum ge dx, d[2] = sum ge dy,
+    // d[3..5] = sum ge (dx^2, dx dy, dy^2); and dL/dcolour in d[6..8].
+    // With alpha = o exp(-(a dx^2 + 2 b dx dy + c dy^2) / 2):
+    //   dL/dlogit = sum ge (1 - o);  dL/dmean2d = (a m1 + b m2, b m1 + c m2);
+    //   dL/da = -m3 / 2, dL/db = -m4, dL/dc = -m5 / 2.
+    emit(10, d[0] * (T(1) - G.o));
+    const T dmx = G.a * d[1] + G.b * d[2];
+    const T dmy = G.b * d[1] + G.c * d[2];
+
+    // colour: c = max(0, sum_k Y_k f_k + 0.5)
+    T dir[3];
+    const T vinv = view_dir(G, cam, dir);
+    T Y[16];
+    SH<T>::template basis<D>(dir[0], dir[1], dir[2], Y);
+    // the projection recorded which channels the clamp at zero cut off
+    const uint32_t clamp = meta_clamp(m.y);
+    T dc[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) dc[ch] = (clamp >> ch) & 1u ? T(0) : d[6 + ch];
+    T wk[16];
+#pragma unroll
+    for (int k = 0; k < NK; k++) {
+        T s = 0;
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
-            T s = 0;
-#pragma unroll
-            for (int k = 0; k < NK; k++) s += Y[k] * plane(P, stride, 11 + 3 * k + ch, g);
-            s += T(0.5);
-            dc[ch] = s > T(0) ? d[6 + ch] : T(0);
+            emit(11 + 3 * k + ch, Y[k] * dc[ch]);
+            s += plane(P, stride, 11 + 3 * k + ch, g) * dc[ch];
         }
-        T wk[16];
-#pragma unroll
-        for (int k = 0; k < NK; k++) {
-            T s = 0;
-#pragma unroll
-            for (int ch = 0; ch < 3; ch++) {
-                acc[11 + 3 * k + ch] += Y[k] * dc[ch];
-                s += plane(P, stride, 11 + 3 * k + ch, g) * dc[ch];
-            }
-            wk[k] = s;
-        }
-        T ddir[3];
-        SH<T>::template grad_dot<D>(dir[0], dir[1], dir[2], wk, ddir);
-        const T dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
-        T du[3];
-#pragma unroll
-        for (int k = 0; k < 3; k++) du[k] = (ddir[k] - dir[k] * dd) * vinv;
-
-        // conic (scaled for exp2) -> conic -> screen covariance: dS = -A dA A
-        const T da = d[2] * (T(-0.5) * kLog2e<T>());
-        const T db = d[3] * (-kLog2e<T>());
-        const T dcn = d[4] * (T(-0.5) * kLog2e<T>());
-        const T a = G.a, b = G.b, c = G.c;
-        const T S00 = -(a * a * da + a * b * db + b * b * dcn);
-        const T S01 = -(a * b * da + T(0.5) * (a * c + b * b) * db + b * c * dcn);
-        const T S11 = -(b * b * da + b * c * db + c * c * dcn);
-
-        // screen covariance -> Sigma and the rows t0, t1 of J W
-        T St0[3], St1[3];
-        St0[0] = G.Sig[0] * G.t0[0] + G.Sig[1] * G.t0[1] + G.Sig[2] * G.t0[2];
-        St0[1] = G.Sig[1] * G.t0[0] + G.Sig[3] * G.t0[1] + G.Sig[4] * G.t0[2];
-        St0[2] = G.Sig[2] * G.t0[0] + G.Sig[4] * G.t0[1] + G.Sig[5] * G.t0[2];
-        St1[0] = G.Sig[0] * G.t1[0] + G.Sig[1] * G.t1[1] + G.Sig[2] * G.t1[2];
-        St1[1] = G.Sig[1] * G.t1[0] + G.Sig[3] * G.t1[1] + G.Sig[4] * G.t1[2];
-        St1[2] = G.Sig[2] * G.t1[0] + G.Sig[4] * G.t1[1] + G.Sig[5] * G.t1[2];
-        T dt0[3], dt1[3];
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            dt0[k] = T(2) * (S00 * St0[k] + S01 * St1[k]);
-            dt1[k] = T(2) * (S11 * St1[k] + S01 * St0[k]);
-        }
-        // dSigma (symmetric, full-matrix gradient)
-        T dS[6];
-        dS[0] = S00 * G.t0[0] * G.t0[0] + S11 * G.t1[0] * G.t1[0] + T(2) * S01 * G.t0[0] * G.t1[0];
-        dS[3] = S00 * G.t0[1] * G.t0[1] + S11 * G.t1[1] * G.t1[1] + T(2) * S01 * G.t0[1] * G.t1[1];
-        dS[5] = S00 * G.t0[2] * G.t0[2] + S11 * G.t1[2] * G.t1[2] + T(2) * S01 * G.t0[2] * G.t1[2];
-        dS[1] = S00 * G.t0[0] * G.t0[1] + S11 * G.t1[0] * G.t1[1] + S01 * (G.t0[0] * G.t1[1] + G.t1[0] * G.t0[1]);
-        dS[2] = S00 * G.t0[0] * G.t0[2] + S11 * G.t1[0] * G.t1[2] + S01 * (G.t0[0] * G.t1[2] + G.t1[0] * G.t0[2]);
-        dS[4] = S00 * G.t0[1] * G.t0[2] + S11 * G.t1[1] * G.t1[2] + S01 * (G.t0[1] * G.t1[2] + G.t1[1] * G.t0[2]);
-
-        // t0 = J00 W0 + J02 W2, t1 = J11 W1 + J12 W2
-        const T dJ00 = dt0[0] * cam.R[0] + dt0[1] * cam.R[1] + dt0[2] * cam.R[2];
-        const T dJ02 = dt0[0] * cam.R[6] + dt0[1] * cam.R[7] + dt0[2] * cam.R[8];
-        const T dJ11 = dt1[0] * cam.R[3] + dt1[1] * cam.R[4] + dt1[2] * cam.R[5];
-        const T dJ12 = dt1[0] * cam.R[6] + dt1[1] * cam.R[7] + dt1[2] * cam.R[8];
-        const T rz = G.rz, rz2 = G.rz * G.rz;
-        const T tx = G.t[0], ty = G.t[1];
-        T dtc[3];
-        dtc[0] = d[0] * cam.fx * rz;
-        dtc[1] = d[1] * cam.fy * rz;
-        dtc[2] = -(d[0] * cam.fx * tx + d[1] * cam.fy * ty) * rz2;
-        dtc[2] += -(dJ00 * cam.fx + dJ11 * cam.fy) * rz2;
-        dtc[2] += (dJ02 * cam.fx * G.rx + dJ12 * cam.fy * G.ry) * rz2;
-        const T drx = -dJ02 * cam.fx * rz, dry = -dJ12 * cam.fy * rz;
-        if (!G.clx) { dtc[0] += drx * rz; dtc[2] -= drx * tx * rz2; }
-        if (!G.cly) { dtc[1] += dry * rz; dtc[2] -= dry * ty * rz2; }
-        // t = W u + t_cw
-#pragma unroll
-        for (int k = 0; k < 3; k++)
-            acc[k] += du[k] + cam.R[k] * dtc[0] + cam.R[3 + k] * dtc[1] + cam.R[6 + k] * dtc[2];
-
-        // Sigma = M M^T with M = R diag(s): dM = 2 dSigma M
-        const T dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
-        T dR[9];
-#pragma unroll
-        for (int cidx = 0; cidx < 3; cidx++) {
-            T ds = 0;
-#pragma unroll
-            for (int ridx = 0; ridx < 3; ridx++) {
-                T dM = T(0);
-#pragma unroll
-                for (int k = 0; k < 3; k++) dM += dSf[3 * ridx + k] * G.R[3 * k + cidx];
-                dM *= T(2) * G.s[cidx];
-                ds += dM * G.R[3 * ridx + cidx];
-                dR[3 * ridx + cidx] = dM * G.s[cidx];
-            }
-            acc[7 + cidx] += ds * G.s[cidx];   // s = exp(log-scale)
-        }
-        // R(qn)
-        const T w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
-        T dq[4];
-        dq[0] = T(2) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-        dq[1] = T(2) * (y * dR[1] + z * dR[2] + y * dR[3] - T(2) * x * dR[4] - w * dR[5] + z * dR[6] +
-                        w * dR[7] - T(2) * x * dR[8]);
-        dq[2] = T(2) * (-T(2) * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
-                        z * dR[7] - T(2) * y * dR[8]);
-        dq[3] = T(2) * (-T(2) * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - T(2) * z * dR[4] + y * dR[5] +
-                        x * dR[6] + y * dR[7]);
-        const T qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
-#pragma unroll
-        for (int k = 0; k < 4; k++) acc[3 + k] += (dq[k] - G.qn[k] * qd) * G.qinv;
+        wk[k] = s;
     }
+    T ddir[3];
+    SH<T>::template grad_dot<D>(dir[0], dir[1], dir[2], wk, ddir);
+    const T dd = ddir[0] * dir[0] + ddir[1] * dir[1] + ddir[2] * dir[2];
+    T du[3];
 #pragma unroll
-    for (int a = 0; a < A; a++) grad[int64_t(a) * gstride + g] = acc[a];
+    for (int k = 0; k < 3; k++) du[k] = (ddir[k] - dir[k] * dd) * vinv;
+
+    // conic -> screen covariance: dS = -A dA A
+    const T da = T(-0.5) * d[3];
+    const T db = -d[4];
+    const T dcn = T(-0.5) * d[5];
+    const T a = G.a, b = G.b, c = G.c;
+    const T S00 = -(a * a * da + a * b * db + b * b * dcn);
+    const T S01 = -(a * b * da + T(0.5) * (a * c + b * b) * db + b * c * dcn);
+    const T S11 = -(b * b * da + b * c * db + c * c * dcn);
+
+    // screen covariance -> Sigma and the rows t0, t1 of J W
+    T St0[3], St1[3];
+    St0[0] = G.Sig[0] * G.t0[0] + G.Sig[1] * G.t0[1] + G.Sig[2] * G.t0[2];
+    St0[1] = G.Sig[1] * G.t0[0] + G.Sig[3] * G.t0[1] + G.Sig[4] * G.t0[2];
+    St0[2] = G.Sig[2] * G.t0[0] + G.Sig[4] * G.t0[1] + G.Sig[5] * G.t0[2];
+    St1[0] = G.Sig[0] * G.t1[0] + G.Sig[1] * G.t1[1] + G.Sig[2] * G.t1[2];
+    St1[1] = G.Sig[1] * G.t1[0] + G.Sig[3] * G.t1[1] + G.Sig[4] * G.t1[2];
+    St1[2] = G.Sig[2] * G.t1[0] + G.Sig[4] * G.t1[1] + G.Sig[5] * G.t1[2];
+    T dt0[3], dt1[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        dt0[k] = T(2) * (S00 * St0[k] + S01 * St1[k]);
+        dt1[k] = T(2) * (S11 * St1[k] + S01 * St0[k]);
+    }
+    // dSigma (symmetric, full-matrix gradient)
+    T dS[6];
+    dS[0] = S00 * G.t0[0] * G.t0[0] + S11 * G.t1[0] * G.t1[0] + T(2) * S01 * G.t0[0] * G.t1[0];
+    dS[3] = S00 * G.t0[1] * G.t0[1] + S11 * G.t1[1] * G.t1[1] + T(2) * S01 * G.t0[1] * G.t1[1];
+    dS[5] = S00 * G.t0[2] * G.t0[2] + S11 * G.t1[2] * G.t1[2] + T(2) * S01 * G.t0[2] * G.t1[2];
+    dS[1] = S00 * G.t0[0] * G.t0[1] + S11 * G.t1[0] * G.t1[1] + S01 * (G.t0[0] * G.t1[1] + G.t1[0] * G.t0[1]);
+    dS[2] = S00 * G.t0[0] * G.t0[2] + S11 * G.t1[0] * G.t1[2] + S01 * (G.t0[0] * G.t1[2] + G.t1[0] * G.t0[2]);
+    dS[4] = S00 * G.t0[1] * G.t0[2] + S11 * G.t1[1] * G.t1[2] + S01 * (G.t0[1] * G.t1[2] + G.t1[1] * G.t0[2]);
+
+    // t0 = J00 W0 + J02 W2, t1 = J11 W1 + J12 W2
+    const T dJ00 = dt0[0] * cam.R[0] + dt0[1] * cam.R[1] + dt0[2] * cam.R[2];
+    const T dJ02 = dt0[0] * cam.R[6] + dt0[1] * cam.R[7] + dt0[2] * cam.R[8];
+    const T dJ11 = dt1[0] * cam.R[3] + dt1[1] * cam.R[4] + dt1[2] * cam.R[5];
+    const T dJ12 = dt1[0] * cam.R[6] + dt1[1] * cam.R[7] + dt1[2] * cam.R[8];
+    const T rz = G.rz, rz2 = G.rz * G.rz;
+    const T tx = G.t[0], ty = G.t[1];
+    T dtc[3];
+    dtc[0] = dmx * cam.fx * rz;
+    dtc[1] = dmy * cam.fy * rz;
+    dtc[2] = -(dmx * cam.fx * tx + dmy * cam.fy * ty) * rz2;
+    dtc[2] += -(dJ00 * cam.fx + dJ11 * cam.fy) * rz2;
+    dtc[2] += (dJ02 * cam.fx * G.rx + dJ12 * cam.fy * G.ry) * rz2;
+    const T drx = -dJ02 * cam.fx * rz, dry = -dJ12 * cam.fy * rz;
+    if (!G.clx) { dtc[0] += drx * rz; dtc[2] -= drx * tx * rz2; }
+    if (!G.cly) { dtc[1] += dry * rz; dtc[2] -= dry * ty * rz2; }
+    // t = W u + t_cw
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        emit(k, du[k] + cam.R[k] * dtc[0] + cam.R[3 + k] * dtc[1] + cam.R[6 + k] * dtc[2]);
+
+    // Sigma = M M^T with M = R diag(s): dM = 2 dSigma M
+    const T dSf[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+    T dR[9];
+#pragma unroll
+    for (int cidx = 0; cidx < 3; cidx++) {
+        T ds = 0;
+#pragma unroll
+        for (int ridx = 0; ridx < 3; ridx++) {
+            T dM = T(0);
+#pragma unroll
+            for (int k = 0; k < 3; k++) dM += dSf[3 * ridx + k] * G.R[3 * k + cidx];
+            dM *= T(2) * G.s[cidx];
+            ds += dM * G.R[3 * ridx + cidx];
+            dR[3 * ridx + cidx] = dM * G.s[cidx];
+        }
+        emit(7 + cidx, ds * G.s[cidx]);   // s = exp(log-scale)
+    }
+    // R(qn)
+    const T w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    T dq[4];
+    dq[0] = T(2) * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    dq[1] = T(2) * (y * dR[1] + z * dR[2] + y * dR[3] - T(2) * x * dR[4] - w * dR[5] + z * dR[6] +
+                    w * dR[7] - T(2) * x * dR[8]);
+    dq[2] = T(2) * (-T(2) * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                    z * dR[7] - T(2) * y * dR[8]);
+    dq[3] = T(2) * (-T(2) * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - T(2) * z * dR[4] + y * dR[5] +
+                    x * dR[6] + y * dR[7]);
+    const T qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+#pragma unroll
+    for (int k = 0; k < 4; k++) emit(3 + k, (dq[k] - G.qn[k] * qd) * G.qinv);
+}
+
+// Jobs over disjoint Gaussian ranges: one thread per record, each gradient
+// plane stored once, as soon as it is known.  Culled records get zeros.
+template <typename T, int D>
+__global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P, int64_t stride, gs_frame frame,
+                                                          gs_raster_cfg cfg, const uint4* __restrict__ meta,
+                                                          const uint32_t* __restrict__ pair_off, uint64_t capacity,
+                                                          const T* __restrict__ pg, T* __restrict__ grad,
+                                                          int64_t gstride) {
+    constexpr int A = 11 + 3 * (D + 1) * (D + 1);
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = r < frame.n_records;   // no early return before the wave-wide sums
+    const int j = job_of_record(frame.jobs, frame.n_jobs, active ? r : 0);
+    const gs_job job = frame.jobs[j];
+    const int64_t g = job.g0 + (r - job.rec0);
+    const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t ntiles = meta_tiles(m.y);
+    uint64_t p0, np;
+    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, p0, np);
+    T d[9];
+    record_pair_sum(pg, p0, np, d);
+    if (!active) return;
+    T* gout = grad + g;
+    if (ntiles == 0) {
+#pragma unroll
+        for (int a = 0; a < A; a++) gout[int64_t(a) * gstride] = T(0);
+        return;
+    }
+    record_chain<T, D>(P, stride, g, frame.cams[job.cam], cfg, m.y, d,
+                       [&](int a, T v) { gout[int64_t(a) * gstride] = v; });
+}
+
+// Gaussians held by several jobs (several views of one block in one step):
+// one thread per Gaussian adds its records' contributions in job order.
+template <typename T, int D>
+__global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P, int64_t stride, int64_t n,
+                                                          gs_frame frame, gs_raster_cfg cfg,
+                                                          const uint4* __restrict__ meta,
+                                                          const uint32_t* __restrict__ pair_off, uint64_t capacity,
+                                                          const T* __restrict__ pg, T* __restrict__ grad,
+                                                          int64_t gstride) {
+    constexpr int A = 11 + 3 * (D + 1) * (D + 1);
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = g < n;
+    T* gout = grad + (active ? g : 0);
+    if (active)
+        for (int a = 0; a < A; a++) gout[int64_t(a) * gstride] = T(0);
+    for (int j = 0; j < frame.n_jobs; j++) {
+        const gs_job job = frame.jobs[j];
+        const bool in_job = active && g >= job.g0 && g < job.g1;
+        const int64_t r = in_job ? job.rec0 + (g - job.g0) : 0;
+        const uint4 m = in_job ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t ntiles = meta_tiles(m.y);
+        uint64_t p0, np;
+        record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, p0, np);
+        T d[9];
+        record_pair_sum(pg, p0, np, d);
+        if (ntiles == 0) continue;
+        record_chain<T, D>(P, stride, g, frame.cams[job.cam], cfg, m.y, d,
+                           [&](int a, T v) { gout[int64_t(a) * gstride] += v; });
+    }
+}
+
+// zeros for Gaussians outside every job (disjoint jobs that do not cover [0, n))
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_uncovered(int64_t n, gs_frame frame, int A, T* __restrict__ grad,
+                                                        int64_t gstride) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    for (int j = 0; j < frame.n_jobs; j++)
+        if (g >= frame.jobs[j].g0 && g < frame.jobs[j].g1) return;
+    for (int a = 0; a < A; a++) grad[int64_t(a) * gstride + g] = T(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -469,21 +562,37 @@ hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster
     return hipGetLastError();
 }
 
+template <typename T, int D>
+static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
+                                 const uint32_t* pair_off, uint64_t capacity, const T* pg, gs_params& grad,
+                                 hipStream_t s) {
+    const T* P = static_cast<const T*>(p.data);
+    T* Gd = static_cast<T*>(grad.data);
+    if (f.jobs_disjoint) {
+        const bool covers = f.n_records == p.n && f.g_max == p.n;
+        if (!covers)
+            hipLaunchKernelGGL((k_zero_uncovered<T>), dim3(unsigned((p.n + 255) / 256)), dim3(256), 0, s, p.n, f,
+                               11 + 3 * (D + 1) * (D + 1), Gd, grad.stride);
+        if (f.n_records > 0)
+            hipLaunchKernelGGL((k_project_bwd_rec<T, D>), dim3(unsigned((f.n_records + 127) / 128)), dim3(128), 0, s,
+                               P, p.stride, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride);
+    } else {
+        hipLaunchKernelGGL((k_project_bwd_acc<T, D>), dim3(unsigned((p.n + 127) / 128)), dim3(128), 0, s, P,
+                           p.stride, p.n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride);
+    }
+}
+
 template <typename T>
 hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
                               const uint32_t* meta, const uint32_t* pair_off, uint64_t capacity, const T* pg,
                               gs_params& grad, hipStream_t s) {
-    const int64_t n = p.n;
-    if (n == 0) return hipSuccess;
-    dim3 grid(unsigned((n + 127) / 128)), block(128);
-    const T* P = static_cast<const T*>(p.data);
-    T* Gd = static_cast<T*>(grad.data);
+    if (p.n == 0) return hipSuccess;
     const uint4* M = reinterpret_cast<const uint4*>(meta);
     switch (p.sh_degree) {
-        case 0: hipLaunchKernelGGL((k_project_bwd<T, 0>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
-        case 1: hipLaunchKernelGGL((k_project_bwd<T, 1>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
-        case 2: hipLaunchKernelGGL((k_project_bwd<T, 2>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
-        default: hipLaunchKernelGGL((k_project_bwd<T, 3>), grid, block, 0, s, P, p.stride, n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride); break;
+        case 0: project_bwd_dispatch<T, 0>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
+        case 1: project_bwd_dispatch<T, 1>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
+        case 2: project_bwd_dispatch<T, 2>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
+        default: project_bwd_dispatch<T, 3>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
     }
     return hipGetLastError();
 }

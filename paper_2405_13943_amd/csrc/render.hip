@@ -1,20 +1,30 @@
 // Per-tile front-to-back alpha compositing (Eq. 2) and its hand-written
 // backward.
 //
-// One wavefront owns one screen tile (TW x TH pixels, PPL = TW*TH/64 pixels
-// per lane) and walks the tile's record list in (depth, record) order.
-// Records are staged 64 at a time into a wave-private LDS slice (one record
-// per lane, read back as broadcasts), so a workgroup needs no barrier and
-// each wave stops as soon as all of its pixels have terminated.  Workgroups
-// are remapped so that each XCD renders one contiguous run of tiles.
+// One wavefront owns one screen tile made of QX x QY quadrants of 8x8 pixels;
+// lane l holds pixel (l % 8, l / 8) of every quadrant, so PPL = QX * QY pixels
+// per lane.  The wave walks the tile's record list in (depth, record) order,
+// staging 64 records at a time in a wave-private LDS slice (one record per
+// lane, read back as broadcasts): no workgroup barrier, and each wave stops
+// as soon as all its pixels have terminated.  While staging, each lane also
+// computes which quadrants its record's conservative pixel box touches, so
+// the compositing loop skips (uniformly, per quadrant) every Gaussian that
+// cannot reach alpha_min there.  Workgroups are remapped so that each XCD
+// renders one contiguous run of tiles (neighbouring tiles share records in
+// that XCD's L2).
 //
-// Backward runs front to back as well: it recomputes alpha, T and the
-// accumulated colour exactly as the forward did (same operations in the same
-// order, so the same keep/stop decisions), and gets the colour behind a
-// Gaussian as C_final - C_accumulated.  No per-pair transmittance is stored.
-// Per pair it reduces the 9 screen-space partials over the wave with DPP and
-// writes them at the pair's emission index, where the projection backward
-// sums them per record in a fixed order (deterministic, no float atomics).
+// The backward runs front to back as well: it recomputes alpha, T and the
+// accumulated colour exactly as the forward did (same operations, same
+// order, hence the same keep/stop decisions) and gets the colour behind a
+// Gaussian as C_final - C_accumulated, so no per-pair transmittance is ever
+// stored.  Per (tile, record) pair it reduces nine partial sums over the wave
+// with DPP and stores them at the pair's emission index; the projection
+// backward then adds each record's pairs in a fixed order (deterministic, no
+// float atomics).  The nine values are, with ge = dL/dalpha * alpha summed
+// over the pair's pixels and (dx, dy) = pixel - mean:
+//   sum ge, sum ge dx, sum ge dy, sum ge dx^2, sum ge dx dy, sum ge dy^2,
+//   and dL/dcolour (r, g, b).
+// The geometric gradients follow from these moments in closed form.
 #include "gs_device.hpp"
 #include "gs_internal.hpp"
 
@@ -23,7 +33,7 @@ namespace gs {
 constexpr int kRenderWaves = 4;
 
 // record words as produced by the projection
-enum { R_MX = 0, R_MY, R_QA, R_QB, R_QC, R_LO, R_CR, R_CG, R_CB };
+enum { R_MX = 0, R_MY, R_QA, R_QB, R_QC, R_LO, R_CR, R_CG, R_CB, R_DEPTH, R_HX, R_HY };
 
 template <typename T>
 struct Rec {
@@ -40,19 +50,9 @@ __device__ inline T log2_alpha(const Rec<T>& g, T dx, T dy) {
     return N::fma(t, dx, N::fma(g.qc * dy, dy, g.lo));
 }
 
-template <typename T, int TW>
-__device__ inline void pixel_of(int lane, int k, int& x, int& y) {
-    constexpr int rows = kWave / TW;
-    x = lane % TW;
-    y = k * rows + lane / TW;
-}
-
-template <typename T>
-__device__ inline void load_rec(const T* __restrict__ rec, uint32_t r, T* dst) {
-    const T* src = rec + int64_t(r) * GS_REC_WORDS;
-#pragma unroll
-    for (int i = 0; i < GS_REC_WORDS; i++) dst[i] = src[i];
-}
+template <typename T> __device__ inline T recip(T x);
+template <> __device__ inline float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double recip<double>(double x) { return 1.0 / x; }
 
 template <typename T>
 __device__ inline Rec<T> lds_rec(const T* s) {
@@ -62,18 +62,41 @@ __device__ inline Rec<T> lds_rec(const T* s) {
     return g;
 }
 
+// Stage record r for this lane: copy it to LDS and return the mask of the
+// tile's quadrants that its conservative pixel box [mean -+ half-extent]
+// reaches (pixel p samples p + 1/2, as in the projection's rectangle).
+template <typename T, int QX, int QY>
+__device__ inline uint32_t stage_rec(const T* __restrict__ rec, uint32_t r, T* dst, int px0, int py0) {
+    const T* src = rec + int64_t(r) * GS_REC_WORDS;
+#pragma unroll
+    for (int i = 0; i < GS_REC_WORDS; i++) dst[i] = src[i];
+    const T x0 = dst[R_MX] - dst[R_HX], x1 = dst[R_MX] + dst[R_HX];
+    const T y0 = dst[R_MY] - dst[R_HY], y1 = dst[R_MY] + dst[R_HY];
+    uint32_t mask = 0;
+#pragma unroll
+    for (int k = 0; k < QX * QY; k++) {
+        const T qx = T(px0 + 8 * (k % QX)), qy = T(py0 + 8 * (k / QX));
+        const bool hit = x1 >= qx + T(0.5) && x0 <= qx + T(7.5) && y1 >= qy + T(0.5) && y0 <= qy + T(7.5);
+        mask |= hit ? (1u << k) : 0u;
+    }
+    return mask;
+}
+
+__device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // ---------------------------------------------------------------------------
 // forward
 
-template <typename T, int TW, int TH>
+template <typename T, int QX, int QY>
 __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame frame, gs_raster_cfg cfg,
                                                                      const T* __restrict__ rec,
                                                                      const uint32_t* __restrict__ vals,
                                                                      const uint2* __restrict__ ranges,
                                                                      T* __restrict__ rgb, T* __restrict__ Tout,
                                                                      uint32_t* __restrict__ ncontrib) {
-    constexpr int PPL = TW * TH / kWave;
+    constexpr int PPL = QX * QY;
     __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
+    __shared__ uint32_t s_mask[kRenderWaves][kWave];
     const int wave = threadIdx.x / kWave, lane = lane_id();
     const int tile = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
     if (tile >= frame.n_tiles) return;
@@ -82,17 +105,15 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
     const gs_camera& cam = frame.cams[job.cam];
     const int W = cam.width, H = cam.height;
     const int lt = tile - job.tile0;
-    const int tx = lt % job.tiles_x, ty = lt / job.tiles_x;
+    const int tpx = (lt % job.tiles_x) * 8 * QX, tpy = (lt / job.tiles_x) * 8 * QY;
+    const int lx = lane & 7, ly = lane >> 3;
 
     T px[PPL], py[PPL], Tr[PPL], C[PPL][3];
     bool done[PPL];
     uint32_t last[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        int x, y;
-        pixel_of<T, TW>(lane, k, x, y);
-        x += tx * TW;
-        y += ty * TH;
+        const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
         px[k] = T(x) + T(0.5);
         py[k] = T(y) + T(0.5);
         done[k] = !(x < W && y < H);
@@ -108,14 +129,17 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
         for (int k = 0; k < PPL; k++) alive |= !done[k];
         if (__ballot(alive) == 0) break;
         const uint32_t cnt = min(uint32_t(kWave), range.y - base);
-        if (uint32_t(lane) < cnt) load_rec(rec, vals[base + lane], s_rec[wave][lane]);
+        if (uint32_t(lane) < cnt)
+            s_mask[wave][lane] = stage_rec<T, QX, QY>(rec, vals[base + lane], s_rec[wave][lane], tpx, tpy);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (uint32_t i = 0; i < cnt; i++) {
+            const uint32_t qmask = uniform(s_mask[wave][i]);
             const Rec<T> g = lds_rec(s_rec[wave][i]);
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
+                if (!(qmask & (1u << k))) continue;
                 if (done[k]) continue;
                 const T al = Num<T>::exp2(log2_alpha(g, px[k] - g.mx, py[k] - g.my));
                 if (al < amin) continue;
@@ -135,10 +159,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
     const int64_t plane = int64_t(W) * H;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        int x, y;
-        pixel_of<T, TW>(lane, k, x, y);
-        x += tx * TW;
-        y += ty * TH;
+        const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
         if (x < W && y < H) {
             const int64_t p = job.px0 + int64_t(y) * W + x;
             T* out = rgb + 3 * job.px0 + int64_t(y) * W + x;
@@ -154,13 +175,14 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
 // ---------------------------------------------------------------------------
 // backward
 
-template <typename T, int TW, int TH>
+template <typename T, int QX, int QY>
 __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     gs_frame frame, gs_raster_cfg cfg, const T* __restrict__ rec, const uint4* __restrict__ meta,
     const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
     const T* __restrict__ rgb, int mode, const T* __restrict__ gin, T* __restrict__ loss_out, T* __restrict__ pg) {
-    constexpr int PPL = TW * TH / kWave;
+    constexpr int PPL = QX * QY;
     __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
+    __shared__ uint32_t s_mask[kRenderWaves][kWave];
     __shared__ uint32_t s_pair[kRenderWaves][kWave];
     const int wave = threadIdx.x / kWave, lane = lane_id();
     const int tile = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
@@ -171,42 +193,41 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     const int W = cam.width, H = cam.height;
     const int lt = tile - job.tile0;
     const int tx = lt % job.tiles_x, ty = lt / job.tiles_x;
+    const int tpx = tx * 8 * QX, tpy = ty * 8 * QY;
+    const int lx = lane & 7, ly = lane >> 3;
     const int64_t plane = int64_t(W) * H;
     const T inv = T(job.loss_weight) / T(3 * plane);
 
-    T px[PPL], py[PPL], Tr[PPL], Cf[PPL][3], Acc[PPL][3], gc[PPL][3];
+    // per pixel: position, transmittance, dL/dC, sum_c dL/dC_c * C_final_c
+    // and the running sum_c dL/dC_c * C_accumulated_c
+    T px[PPL], py[PPL], Tr[PPL], gc[PPL][3], D[PPL], S[PPL];
     bool done[PPL];
     T loss = T(0);
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
-        int x, y;
-        pixel_of<T, TW>(lane, k, x, y);
-        x += tx * TW;
-        y += ty * TH;
+        const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
         px[k] = T(x) + T(0.5);
         py[k] = T(y) + T(0.5);
         const bool in = x < W && y < H;
         done[k] = !in;
         Tr[k] = T(1);
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) {
-            Acc[k][ch] = T(0);
-            Cf[k][ch] = T(0);
-            gc[k][ch] = T(0);
-        }
+        D[k] = S[k] = T(0);
+        gc[k][0] = gc[k][1] = gc[k][2] = T(0);
         if (in) {
             const int64_t o = 3 * job.px0 + int64_t(y) * W + x;
 #pragma unroll
             for (int ch = 0; ch < 3; ch++) {
                 const T c = rgb[o + ch * plane];
-                Cf[k][ch] = c;
+                T g;
                 if (mode == GS_LOSS_L1) {
                     const T d = c - gin[o + ch * plane];
-                    gc[k][ch] = d > T(0) ? inv : (d < T(0) ? -inv : T(0));
+                    g = d > T(0) ? inv : (d < T(0) ? -inv : T(0));
                     loss += (d < T(0) ? -d : d) * inv;
                 } else {
-                    gc[k][ch] = gin[o + ch * plane];
+                    g = gin[o + ch * plane];
                 }
+                gc[k][ch] = g;
+                D[k] = Num<T>::fma(g, c, D[k]);
             }
         }
     }
@@ -221,7 +242,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
         const uint32_t cnt = min(uint32_t(kWave), range.y - base);
         if (uint32_t(lane) < cnt) {
             const uint32_t r = vals[base + lane];
-            load_rec(rec, r, s_rec[wave][lane]);
+            s_mask[wave][lane] = stage_rec<T, QX, QY>(rec, r, s_rec[wave][lane], tpx, tpy);
             // emission index of pair (this tile, r): the record's pairs run
             // row by row over its tile rectangle
             const uint4 m = meta[r];
@@ -237,14 +258,15 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
         const bool any_alive = __ballot(alive) != 0;
         for (uint32_t i = 0; i < cnt; i++) {
             const uint32_t e = s_pair[wave][i];
-            T gs[9];
-#pragma unroll
-            for (int q = 0; q < 9; q++) gs[q] = T(0);
+            const uint32_t qmask = any_alive ? uniform(s_mask[wave][i]) : 0u;
+            T mo[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+            T dcol[3] = {T(0), T(0), T(0)};
             bool hit = false;
-            if (any_alive) {
+            if (qmask) {
                 const Rec<T> g = lds_rec(s_rec[wave][i]);
 #pragma unroll
                 for (int k = 0; k < PPL; k++) {
+                    if (!(qmask & (1u << k))) continue;
                     if (done[k]) continue;
                     const T dx = px[k] - g.mx, dy = py[k] - g.my;
                     const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
@@ -253,36 +275,40 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
                     const T tn = Tr[k] * (T(1) - a);
                     if (tn < tmin) { done[k] = true; continue; }
                     const T wgt = a * Tr[k];
-                    T ga = T(0);
-                    const T r1a = T(1) / (T(1) - a);
+                    const T gcc = Num<T>::fma(gc[k][2], g.c[2], Num<T>::fma(gc[k][1], g.c[1], gc[k][0] * g.c[0]));
+                    S[k] = Num<T>::fma(wgt, gcc, S[k]);
+                    // dL/dalpha = sum_c gc_c (c_c T - (C_final_c - C_acc_c) / (1 - alpha))
+                    const T ga = Num<T>::fma(Tr[k], gcc, -(D[k] - S[k]) * recip(T(1) - a));
 #pragma unroll
-                    for (int ch = 0; ch < 3; ch++) {
-                        Acc[k][ch] = Num<T>::fma(wgt, g.c[ch], Acc[k][ch]);
-                        gs[6 + ch] += gc[k][ch] * wgt;
-                        ga += gc[k][ch] * (g.c[ch] * Tr[k] - (Cf[k][ch] - Acc[k][ch]) * r1a);
-                    }
+                    for (int ch = 0; ch < 3; ch++) dcol[ch] = Num<T>::fma(gc[k][ch], wgt, dcol[ch]);
                     Tr[k] = tn;
                     hit = true;
                     if (al < amax) {
-                        const T ge = ga * al * kLn2<T>();   // d alpha / d log2-alpha = alpha ln 2
-                        gs[R_LO] += ge;
-                        gs[R_QA] += ge * dx * dx;
-                        gs[R_QB] += ge * dx * dy;
-                        gs[R_QC] += ge * dy * dy;
-                        gs[R_MX] -= ge * (T(2) * g.qa * dx + g.qb * dy);
-                        gs[R_MY] -= ge * (g.qb * dx + T(2) * g.qc * dy);
+                        const T ge = ga * al;
+                        const T t1 = ge * dx, t2 = ge * dy;
+                        mo[0] += ge;
+                        mo[1] += t1;
+                        mo[2] += t2;
+                        mo[3] = Num<T>::fma(t1, dx, mo[3]);
+                        mo[4] = Num<T>::fma(t1, dy, mo[4]);
+                        mo[5] = Num<T>::fma(t2, dy, mo[5]);
                     }
                 }
             }
-            T out = T(0);
+            T* dst = pg + int64_t(e) * 9;
             if (__ballot(hit) != 0) {
+                T s[9];
 #pragma unroll
-                for (int q = 0; q < 9; q++) {
-                    const T s = wave_sum(gs[q]);
-                    out = (lane == q) ? s : out;
+                for (int q = 0; q < 6; q++) s[q] = wave_sum(mo[q]);
+#pragma unroll
+                for (int q = 0; q < 3; q++) s[6 + q] = wave_sum(dcol[q]);
+                if (lane == 0) {
+#pragma unroll
+                    for (int q = 0; q < 9; q++) dst[q] = s[q];
                 }
+            } else if (lane < 9) {
+                dst[lane] = T(0);
             }
-            if (lane < 9) pg[int64_t(e) * 9 + lane] = out;
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -290,29 +316,30 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
 
 // ---------------------------------------------------------------------------
 
-template <typename T, int TW, int TH>
+template <typename T, int QX, int QY>
 static void fwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& b, T* rgb,
                        T* Tfin, uint32_t* nc, hipStream_t s) {
     const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
-    hipLaunchKernelGGL((k_render_fwd<T, TW, TH>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec, b.vals,
+    hipLaunchKernelGGL((k_render_fwd<T, QX, QY>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec, b.vals,
                        reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc);
 }
 
-template <typename T, int TW, int TH>
+template <typename T, int QX, int QY>
 static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
                        const gs_bins& b, const T* rgb, int mode, const T* gin, T* loss, T* pg, hipStream_t s) {
     const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
-    hipLaunchKernelGGL((k_render_bwd<T, TW, TH>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
+    hipLaunchKernelGGL((k_render_bwd<T, QX, QY>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
                        reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals,
                        reinterpret_cast<const uint2*>(b.ranges), rgb, mode, gin, loss, pg);
 }
 
+// tile shapes in 8x8 quadrants: 8x8 = 1x1, 16x8 = 2x1, 16x16 = 2x2, 32x8 = 4x1
 #define GS_TILE_DISPATCH(FN, ...)                                                       \
     do {                                                                                \
-        if (cfg.tile_w == 8 && cfg.tile_h == 8) FN<T, 8, 8>(__VA_ARGS__);              \
-        else if (cfg.tile_w == 16 && cfg.tile_h == 8) FN<T, 16, 8>(__VA_ARGS__);       \
-        else if (cfg.tile_w == 32 && cfg.tile_h == 8) FN<T, 32, 8>(__VA_ARGS__);       \
-        else FN<T, 16, 16>(__VA_ARGS__);                                               \
+        if (cfg.tile_w == 8 && cfg.tile_h == 8) FN<T, 1, 1>(__VA_ARGS__);              \
+        else if (cfg.tile_w == 16 && cfg.tile_h == 8) FN<T, 2, 1>(__VA_ARGS__);        \
+        else if (cfg.tile_w == 32 && cfg.tile_h == 8) FN<T, 4, 1>(__VA_ARGS__);        \
+        else FN<T, 2, 2>(__VA_ARGS__);                                                 \
     } while (0)
 
 template <typename T>

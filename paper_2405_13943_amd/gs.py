@@ -44,7 +44,7 @@ class GsJob(ctypes.Structure):
 
 class GsFrame(ctypes.Structure):
     _fields_ = [("cams", c_vp), ("jobs", c_vp), ("n_jobs", c_i32), ("n_tiles", c_i32), ("n_records", c_i64),
-                ("n_pixels", c_i64), ("g_max", c_i64)]
+                ("n_pixels", c_i64), ("g_max", c_i64), ("jobs_disjoint", c_i32), ("reserved", c_i32)]
 
 
 class GsRasterCfg(ctypes.Structure):
@@ -76,7 +76,7 @@ def _load():
         "gs_last_error": ([], ctypes.c_char_p),
         "gs_raster_cfg_default": ([P(GsRasterCfg)], None),
         "gs_frame_plan": ([P(GsCamera), c_i32, P(GsJob), c_i32, P(GsRasterCfg), P(c_i64), P(c_i64), P(c_i32),
-                           P(c_i64)], c_i32),
+                           P(c_i64), P(c_i32)], c_i32),
         "gs_project": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_vp], c_i32),
         "gs_project_f64": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_vp], c_i32),
         "gs_bin_sort_workspace_size": ([c_i64, c_u64, c_i32], ctypes.c_size_t),
@@ -178,18 +178,19 @@ class Frame:
         for i, j in enumerate(jobs):
             self.jobs_host[i].cam, self.jobs_host[i].g0, self.jobs_host[i].g1 = j.cam, j.g0, j.g1
             self.jobs_host[i].loss_weight = j.loss_weight
-        nr, npx, nt, gm = c_i64(), c_i64(), c_i32(), c_i64()
+        nr, npx, nt, gm, dj = c_i64(), c_i64(), c_i32(), c_i64(), c_i32()
         _check(lib.gs_frame_plan(self.cams_host, len(cams), self.jobs_host, len(jobs), ctypes.byref(cfg),
-                                 ctypes.byref(nr), ctypes.byref(npx), ctypes.byref(nt), ctypes.byref(gm)),
-               "gs_frame_plan")
-        self.n_jobs, self.n_records, self.n_pixels, self.n_tiles, self.g_max = len(jobs), nr.value, npx.value, nt.value, gm.value
+                                 ctypes.byref(nr), ctypes.byref(npx), ctypes.byref(nt), ctypes.byref(gm),
+                                 ctypes.byref(dj)), "gs_frame_plan")
+        self.n_jobs, self.n_records, self.n_pixels, self.n_tiles = len(jobs), nr.value, npx.value, nt.value
+        self.g_max, self.jobs_disjoint = gm.value, dj.value
         self.cams = [cams[j.cam] for j in jobs]
         cam_bytes = np.frombuffer(bytes(self.cams_host), np.uint8)
         job_bytes = np.frombuffer(bytes(self.jobs_host), np.uint8)
         self.cams_dev = torch.from_numpy(cam_bytes.copy()).to(device)
         self.jobs_dev = torch.from_numpy(job_bytes.copy()).to(device)
         self.struct = GsFrame(self.cams_dev.data_ptr(), self.jobs_dev.data_ptr(), len(jobs), self.n_tiles,
-                              self.n_records, self.n_pixels, self.g_max)
+                              self.n_records, self.n_pixels, self.g_max, self.jobs_disjoint, 0)
         self.tile = (cfg.tile_w, cfg.tile_h)
 
     def job(self, i) -> GsJob:

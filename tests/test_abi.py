@@ -47,7 +47,7 @@ def test_struct_layouts_match_header(gs, tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gs_params), sizeof(gs_camera), sizeof(gs_job),
          sizeof(gs_frame), sizeof(gs_raster_cfg), sizeof(gs_bins), sizeof(gs_adam_cfg));
-  printf("%zu %zu %zu %zu %zu\\n", offsetof(gs_job, g0), offsetof(gs_job, loss_weight), offsetof(gs_frame, g_max),
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(gs_job, g0), offsetof(gs_job, loss_weight), offsetof(gs_frame, jobs_disjoint),
          offsetof(gs_raster_cfg, bg), offsetof(gs_adam_cfg, step));
   return 0;
 }
@@ -59,7 +59,7 @@ int main(void) {
     S = ctypes.sizeof
     assert sizes == [S(gs.GsParams), S(gs.GsCamera), S(gs.GsJob), S(gs.GsFrame), S(gs.GsRasterCfg), S(gs.GsBins),
                      S(gs.GsAdamCfg)]
-    assert offs == [gs.GsJob.g0.offset, gs.GsJob.loss_weight.offset, gs.GsFrame.g_max.offset,
+    assert offs == [gs.GsJob.g0.offset, gs.GsJob.loss_weight.offset, gs.GsFrame.jobs_disjoint.offset,
                     gs.GsRasterCfg.bg.offset, gs.GsAdamCfg.step.offset]
 
 
@@ -71,11 +71,11 @@ def test_frame_plan_host_only(gs):
     jobs = (gs.GsJob * 4)()
     for i in range(4):
         jobs[i].cam, jobs[i].g0, jobs[i].g1 = i, 0, 2000
-    nr, npx, nt, gm = gs.c_i64(), gs.c_i64(), gs.c_i32(), gs.c_i64()
+    nr, npx, nt, gm, dj = gs.c_i64(), gs.c_i64(), gs.c_i32(), gs.c_i64(), gs.c_i32()
     rc = gs.lib.gs_frame_plan(cams, 4, jobs, 4, ctypes.byref(cfg), ctypes.byref(nr), ctypes.byref(npx),
-                              ctypes.byref(nt), ctypes.byref(gm))
+                              ctypes.byref(nt), ctypes.byref(gm), ctypes.byref(dj))
     assert rc == 0
-    assert (nr.value, npx.value, nt.value, gm.value) == (8000, 4 * 128 * 128, 4 * 64, 2000)
+    assert (nr.value, npx.value, nt.value, gm.value, dj.value) == (8000, 4 * 128 * 128, 4 * 64, 2000, 0)
     assert [jobs[i].tile0 for i in range(4)] == [0, 64, 128, 192]
     assert [jobs[i].px0 for i in range(4)] == [0, 16384, 32768, 49152]
     assert [jobs[i].rec0 for i in range(4)] == [0, 2000, 4000, 6000]
@@ -85,8 +85,19 @@ def test_frame_plan_host_only(gs):
     jobs2 = (gs.GsJob * 1)()
     jobs2[0].cam, jobs2[0].g0, jobs2[0].g1 = 0, 5, 9
     assert gs.lib.gs_frame_plan(cams2, 1, jobs2, 1, ctypes.byref(cfg), ctypes.byref(nr), ctypes.byref(npx),
-                                ctypes.byref(nt), ctypes.byref(gm)) == 0
-    assert (jobs2[0].tiles_x, jobs2[0].tiles_y, nr.value, gm.value) == (7, 5, 4, 9)
+                                ctypes.byref(nt), ctypes.byref(gm), ctypes.byref(dj)) == 0
+    assert (jobs2[0].tiles_x, jobs2[0].tiles_y, nr.value, gm.value, dj.value) == (7, 5, 4, 9, 1)
+    # disjoint blocks: [0, 3), [3, 7); overlapping: [0, 3), [2, 5)
+    jobs3 = (gs.GsJob * 2)()
+    for k, (a, b) in enumerate([(0, 3), (3, 7)]):
+        jobs3[k].cam, jobs3[k].g0, jobs3[k].g1 = 0, a, b
+    gs.lib.gs_frame_plan(cams2, 1, jobs3, 2, ctypes.byref(cfg), ctypes.byref(nr), ctypes.byref(npx),
+                         ctypes.byref(nt), ctypes.byref(gm), ctypes.byref(dj))
+    assert dj.value == 1 and jobs3[1].rec0 == 3 and jobs3[1].tile0 == 35
+    jobs3[1].g0 = 2
+    gs.lib.gs_frame_plan(cams2, 1, jobs3, 2, ctypes.byref(cfg), ctypes.byref(nr), ctypes.byref(npx),
+                         ctypes.byref(nt), ctypes.byref(gm), ctypes.byref(dj))
+    assert dj.value == 0
 
 
 def test_invalid_arguments_rejected_without_launch(gs):
@@ -101,12 +112,12 @@ def test_invalid_arguments_rejected_without_launch(gs):
     ok = gs.GsParams(None, 0, 0, 0, 0)
     assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(cfg_bad), None, None, None) == gs.GS_E_INVALID
     # jobs reaching past the parameter planes
-    f2 = gs.GsFrame(1, 1, 1, 1, 10, 10, 11)
+    f2 = gs.GsFrame(1, 1, 1, 1, 10, 10, 11, 1, 0)
     p10 = gs.GsParams(1, 10, 10, 0, 0)
     assert gs.lib.gs_project(ctypes.byref(p10), ctypes.byref(f2), ctypes.byref(cfg), 1, 1, None) == gs.GS_E_INVALID
     # backward workspace too small
     bins = gs.GsBins(1, 1, 1, 1, 1000)
-    rc = gs.lib.gs_render_bwd(ctypes.byref(p10), ctypes.byref(gs.GsFrame(1, 1, 1, 1, 10, 10, 10)), ctypes.byref(cfg),
+    rc = gs.lib.gs_render_bwd(ctypes.byref(p10), ctypes.byref(gs.GsFrame(1, 1, 1, 1, 10, 10, 10, 1, 0)), ctypes.byref(cfg),
                               1, 1, ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), 1, 8, None)
     assert rc == gs.GS_E_CAPACITY
     # Adam with mismatched planes, bad step

@@ -398,3 +398,33 @@ def test_f64_path_against_finite_differences():
             bad.append((a, i, fd, g[a, i]))
     assert used > 500
     assert not bad, bad[:10]
+
+
+def test_disjoint_and_shared_job_paths_agree(cfg1, gpu1):
+    """Four views of one block (jobs share Gaussians: per-Gaussian accumulation
+    over jobs) against the same four views on four disjoint copies of the
+    block (one thread per record): the copies' gradients sum to the shared
+    gradient, and each copy's image equals the shared-job image bit for bit."""
+    cfg, frame, params, buf = gpu1
+    n = params.shape[1]
+    rep = params.repeat(1, 4).contiguous()
+    jobs = [gs.JobSpec(v, v * n, (v + 1) * n, 0.25) for v in range(4)]
+    f4 = gs.Frame(cfg1.cams, jobs, cfg)
+    assert f4.jobs_disjoint == 1 and frame.jobs_disjoint == 0
+    b4 = gs.rasterize(rep, f4, cfg)
+    for a, b in zip(images(frame, buf), images(f4, b4)):
+        np.testing.assert_array_equal(a, b)
+    target = frame_target(frame, cfg1, range(4))
+    g_shared = torch.empty_like(params)
+    gs.render_bwd(params, frame, cfg, buf, g_shared, gs.LOSS_L1, target)
+    g_copies = torch.empty_like(rep)
+    gs.render_bwd(rep, f4, cfg, b4, g_copies, gs.LOSS_L1, target)
+    summed = sum(g_copies[:, v * n:(v + 1) * n].double() for v in range(4))
+    torch.testing.assert_close(summed, g_shared.double(), rtol=1e-5, atol=1e-9)
+    # Gaussians outside every job get zero gradients
+    f2 = gs.Frame(cfg1.cams, [gs.JobSpec(0, 0, n // 2, 1.0)], cfg)
+    b2 = gs.rasterize(params, f2, cfg)
+    g2 = torch.full_like(params, 7.0)
+    gs.render_bwd(params, f2, cfg, b2, g2, gs.LOSS_L1, target[: 3 * 128 * 128])
+    assert torch.count_nonzero(g2[:, n // 2:]).item() == 0
+    assert torch.count_nonzero(g2[:, : n // 2]).item() > 0
