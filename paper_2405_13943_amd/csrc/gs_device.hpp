@@ -91,6 +91,20 @@ __device__ inline float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sum over each row of 16 lanes, returned to every lane of the row.
+__device__ inline float row_sum(float v) {
+    v += dpp_move<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_move<0x124, 0xf>(v);  // row_ror:4
+    v += dpp_move<0x128, 0xf>(v);  // row_ror:8
+    return v;
+}
+
+__device__ inline double row_sum(double v) {
+    for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
 __device__ inline double wave_sum(double v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;

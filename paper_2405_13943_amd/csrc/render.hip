@@ -4,24 +4,29 @@
 // One wavefront owns one screen tile made of QX x QY quadrants of 8x8 pixels;
 // lane l holds pixel (l % 8, l / 8) of every quadrant, so PPL = QX * QY pixels
 // per lane.  The wave walks the tile's record list in (depth, record) order,
-// staging 64 records at a time in a wave-private LDS slice (one record per
-// lane, read back as broadcasts): no workgroup barrier, and each wave stops
+// staging a batch of records at a time in a wave-private LDS slice (one record
+// per lane, read back as broadcasts): no workgroup barrier, and each wave stops
 // as soon as all its pixels have terminated.  While staging, each lane also
 // computes which quadrants its record's conservative pixel box touches, so
 // the compositing loop skips (uniformly, per quadrant) every Gaussian that
-// cannot reach alpha_min there.  Workgroups are remapped so that each XCD
-// renders one contiguous run of tiles (neighbouring tiles share records in
-// that XCD's L2).
+// cannot reach alpha_min there.  Past that test the per-pixel work is
+// predicated (selects, not branches): a pixel that does not keep a Gaussian
+// adds an exact zero and keeps its transmittance, so divergence costs no
+// exec-mask bookkeeping.  Workgroups are remapped so that each XCD renders
+// one contiguous run of tiles (neighbouring tiles share records in that XCD's
+// L2).
 //
 // The backward runs front to back as well: it recomputes alpha, T and the
 // accumulated colour exactly as the forward did (same operations, same
 // order, hence the same keep/stop decisions) and gets the colour behind a
 // Gaussian as C_final - C_accumulated, so no per-pair transmittance is ever
-// stored.  Per (tile, record) pair it reduces nine partial sums over the wave
-// with DPP and stores them at the pair's emission index; the projection
-// backward then adds each record's pairs in a fixed order (deterministic, no
-// float atomics).  The nine values are, with ge = dL/dalpha * alpha summed
-// over the pair's pixels and (dx, dy) = pixel - mean:
+// stored.  Per (tile, record) pair it sums nine partials over each row of 16
+// lanes with DPP and parks the four row sums in LDS; once per batch of
+// records one lane per record adds the rows and stores the pair's nine values
+// at its emission index, where the projection backward adds each record's
+// pairs in a fixed order (deterministic, no float atomics).  The nine values
+// are, with ge = dL/dalpha * alpha summed over the pair's pixels and
+// (dx, dy) = pixel - mean:
 //   sum ge, sum ge dx, sum ge dy, sum ge dx^2, sum ge dx dy, sum ge dy^2,
 //   and dL/dcolour (r, g, b).
 // The geometric gradients follow from these moments in closed form.
@@ -31,6 +36,7 @@
 namespace gs {
 
 constexpr int kRenderWaves = 4;
+constexpr int kBwdBatch = 32;   // records staged per backward batch
 
 // record words as produced by the projection
 enum { R_MX = 0, R_MY, R_QA, R_QB, R_QC, R_LO, R_CR, R_CG, R_CB, R_DEPTH, R_HX, R_HY };
@@ -84,6 +90,20 @@ __device__ inline uint32_t stage_rec(const T* __restrict__ rec, uint32_t r, T* d
 
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// centre coordinate of a lane's pixel in quadrant column/row q: the lane's
+// quadrant-0 centre plus 8 q (exact in floating point), so that every tile
+// shape computes the same pixel - mean offsets bit for bit
+template <typename T>
+__device__ inline T quad_centre(T base, int q) {
+    return q == 0 ? base : base + T(8 * q);
+}
+
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // forward
 
@@ -107,51 +127,50 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
     const int lt = tile - job.tile0;
     const int tpx = (lt % job.tiles_x) * 8 * QX, tpy = (lt / job.tiles_x) * 8 * QY;
     const int lx = lane & 7, ly = lane >> 3;
+    // pixel centre of quadrant k: (bx + 8 (k % QX), by + 8 (k / QX))
+    const T bx = T(tpx + lx) + T(0.5), by = T(tpy + ly) + T(0.5);
 
-    T px[PPL], py[PPL], Tr[PPL], C[PPL][3];
-    bool done[PPL];
+    T Tr[PPL], C[PPL][3];
+    uint32_t done = 0;
     uint32_t last[PPL];
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
-        px[k] = T(x) + T(0.5);
-        py[k] = T(y) + T(0.5);
-        done[k] = !(x < W && y < H);
+        done |= (x < W && y < H) ? 0u : (1u << k);
         Tr[k] = T(1);
         C[k][0] = C[k][1] = C[k][2] = T(0);
         last[k] = 0;
     }
     const uint2 range = ranges[tile];
     const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
+    constexpr uint32_t all = (1u << PPL) - 1;
     for (uint32_t base = range.x; base < range.y; base += kWave) {
-        bool alive = false;
-#pragma unroll
-        for (int k = 0; k < PPL; k++) alive |= !done[k];
-        if (__ballot(alive) == 0) break;
+        if (__ballot(done != all) == 0) break;
         const uint32_t cnt = min(uint32_t(kWave), range.y - base);
         if (uint32_t(lane) < cnt)
             s_mask[wave][lane] = stage_rec<T, QX, QY>(rec, vals[base + lane], s_rec[wave][lane], tpx, tpy);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_lds_sync();
         for (uint32_t i = 0; i < cnt; i++) {
             const uint32_t qmask = uniform(s_mask[wave][i]);
             const Rec<T> g = lds_rec(s_rec[wave][i]);
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
-                if (!(qmask & (1u << k))) continue;
-                if (done[k]) continue;
-                const T al = Num<T>::exp2(log2_alpha(g, px[k] - g.mx, py[k] - g.my));
-                if (al < amin) continue;
+                if (!(qmask & (1u << k))) continue;   // uniform: box misses quadrant k
+                const T dx = quad_centre(bx, k % QX) - g.mx, dy = quad_centre(by, k / QX) - g.my;
+                const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
+                const bool live = !(done & (1u << k)) && al >= amin;
+                if (__ballot(live) == 0) continue;     // uniform: no pixel of the wave reached
                 const T a = al < amax ? al : amax;
                 const T tn = Tr[k] * (T(1) - a);
-                if (tn < tmin) { done[k] = true; continue; }
-                const T wgt = a * Tr[k];
+                const bool stop = live && tn < tmin;
+                const bool keep = live && !stop;
+                done |= stop ? (1u << k) : 0u;
+                const T wgt = keep ? a * Tr[k] : T(0);
                 C[k][0] = Num<T>::fma(wgt, g.c[0], C[k][0]);
                 C[k][1] = Num<T>::fma(wgt, g.c[1], C[k][1]);
                 C[k][2] = Num<T>::fma(wgt, g.c[2], C[k][2]);
-                Tr[k] = tn;
-                last[k] = base - range.x + i + 1;
+                Tr[k] = keep ? tn : Tr[k];
+                last[k] = keep ? base - range.x + i + 1 : last[k];
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -181,9 +200,9 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
     const T* __restrict__ rgb, int mode, const T* __restrict__ gin, T* __restrict__ loss_out, T* __restrict__ pg) {
     constexpr int PPL = QX * QY;
-    __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
-    __shared__ uint32_t s_mask[kRenderWaves][kWave];
-    __shared__ uint32_t s_pair[kRenderWaves][kWave];
+    __shared__ T s_rec[kRenderWaves][kBwdBatch][GS_REC_WORDS];
+    __shared__ uint32_t s_mask[kRenderWaves][kBwdBatch];
+    __shared__ T s_rows[kRenderWaves][kBwdBatch][4][9];
     const int wave = threadIdx.x / kWave, lane = lane_id();
     const int tile = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
     if (tile >= frame.n_tiles) return;
@@ -195,21 +214,20 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     const int tx = lt % job.tiles_x, ty = lt / job.tiles_x;
     const int tpx = tx * 8 * QX, tpy = ty * 8 * QY;
     const int lx = lane & 7, ly = lane >> 3;
+    const T bx = T(tpx + lx) + T(0.5), by = T(tpy + ly) + T(0.5);
     const int64_t plane = int64_t(W) * H;
     const T inv = T(job.loss_weight) / T(3 * plane);
 
-    // per pixel: position, transmittance, dL/dC, sum_c dL/dC_c * C_final_c
-    // and the running sum_c dL/dC_c * C_accumulated_c
-    T px[PPL], py[PPL], Tr[PPL], gc[PPL][3], D[PPL], S[PPL];
-    bool done[PPL];
+    // per pixel: transmittance, dL/dC, D = sum_c dL/dC_c * C_final_c and the
+    // running S = sum_c dL/dC_c * C_accumulated_c
+    T Tr[PPL], gc[PPL][3], D[PPL], S[PPL];
+    uint32_t done = 0;
     T loss = T(0);
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
-        px[k] = T(x) + T(0.5);
-        py[k] = T(y) + T(0.5);
         const bool in = x < W && y < H;
-        done[k] = !in;
+        done |= in ? 0u : (1u << k);
         Tr[k] = T(1);
         D[k] = S[k] = T(0);
         gc[k][0] = gc[k][1] = gc[k][2] = T(0);
@@ -238,77 +256,91 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
 
     const uint2 range = ranges[tile];
     const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
-    for (uint32_t base = range.x; base < range.y; base += kWave) {
-        const uint32_t cnt = min(uint32_t(kWave), range.y - base);
+    constexpr uint32_t all = (1u << PPL) - 1;
+    const int row = lane >> 4;
+    for (uint32_t base = range.x; base < range.y; base += kBwdBatch) {
+        const uint32_t cnt = min(uint32_t(kBwdBatch), range.y - base);
+        const bool any_alive = __ballot(done != all) != 0;
+        uint32_t e_own = 0;   // pair this lane stores at the end of the batch
         if (uint32_t(lane) < cnt) {
             const uint32_t r = vals[base + lane];
-            s_mask[wave][lane] = stage_rec<T, QX, QY>(rec, r, s_rec[wave][lane], tpx, tpy);
+            if (any_alive) s_mask[wave][lane] = stage_rec<T, QX, QY>(rec, r, s_rec[wave][lane], tpx, tpy);
             // emission index of pair (this tile, r): the record's pairs run
             // row by row over its tile rectangle
             const uint4 m = meta[r];
             const uint32_t x0 = m.z & 0xffffu, y0 = m.z >> 16, x1 = m.w & 0xffffu;
-            s_pair[wave][lane] = pair_off[r] + (uint32_t(ty) - y0) * (x1 - x0 + 1) + (uint32_t(tx) - x0);
+            e_own = pair_off[r] + (uint32_t(ty) - y0) * (x1 - x0 + 1) + (uint32_t(tx) - x0);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        bool alive = false;
+        if (!any_alive) {
+            // every pixel of the tile has terminated: the rest of its pairs
+            // carry zero gradient
+            if (uint32_t(lane) < cnt)
 #pragma unroll
-        for (int k = 0; k < PPL; k++) alive |= !done[k];
-        const bool any_alive = __ballot(alive) != 0;
+                for (int q = 0; q < 9; q++) pg[int64_t(e_own) * 9 + q] = T(0);
+            continue;
+        }
+        wave_lds_sync();
         for (uint32_t i = 0; i < cnt; i++) {
-            const uint32_t e = s_pair[wave][i];
-            const uint32_t qmask = any_alive ? uniform(s_mask[wave][i]) : 0u;
+            const uint32_t qmask = uniform(s_mask[wave][i]);
+            const Rec<T> g = lds_rec(s_rec[wave][i]);
             T mo[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
             T dcol[3] = {T(0), T(0), T(0)};
             bool hit = false;
-            if (qmask) {
-                const Rec<T> g = lds_rec(s_rec[wave][i]);
 #pragma unroll
-                for (int k = 0; k < PPL; k++) {
-                    if (!(qmask & (1u << k))) continue;
-                    if (done[k]) continue;
-                    const T dx = px[k] - g.mx, dy = py[k] - g.my;
-                    const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
-                    if (al < amin) continue;
-                    const T a = al < amax ? al : amax;
-                    const T tn = Tr[k] * (T(1) - a);
-                    if (tn < tmin) { done[k] = true; continue; }
-                    const T wgt = a * Tr[k];
-                    const T gcc = Num<T>::fma(gc[k][2], g.c[2], Num<T>::fma(gc[k][1], g.c[1], gc[k][0] * g.c[0]));
-                    S[k] = Num<T>::fma(wgt, gcc, S[k]);
-                    // dL/dalpha = sum_c gc_c (c_c T - (C_final_c - C_acc_c) / (1 - alpha))
-                    const T ga = Num<T>::fma(Tr[k], gcc, -(D[k] - S[k]) * recip(T(1) - a));
+            for (int k = 0; k < PPL; k++) {
+                if (!(qmask & (1u << k))) continue;   // uniform: box misses quadrant k
+                const T dx = quad_centre(bx, k % QX) - g.mx, dy = quad_centre(by, k / QX) - g.my;
+                const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
+                const bool live = !(done & (1u << k)) && al >= amin;
+                if (__ballot(live) == 0) continue;     // uniform: no pixel of the wave reached
+                // the forward's operations, predicated the same way
+                const T a = al < amax ? al : amax;
+                const T tn = Tr[k] * (T(1) - a);
+                const bool stop = live && tn < tmin;
+                const bool keep = live && !stop;
+                done |= stop ? (1u << k) : 0u;
+                const T wgt = keep ? a * Tr[k] : T(0);
+                const T gcc = Num<T>::fma(gc[k][2], g.c[2], Num<T>::fma(gc[k][1], g.c[1], gc[k][0] * g.c[0]));
+                S[k] = Num<T>::fma(wgt, gcc, S[k]);
+                // dL/dalpha = sum_c gc_c (c_c T - (C_final_c - C_acc_c) / (1 - alpha))
+                const T ga = Num<T>::fma(Tr[k], gcc, -(D[k] - S[k]) * recip(T(1) - a));
 #pragma unroll
-                    for (int ch = 0; ch < 3; ch++) dcol[ch] = Num<T>::fma(gc[k][ch], wgt, dcol[ch]);
-                    Tr[k] = tn;
-                    hit = true;
-                    if (al < amax) {
-                        const T ge = ga * al;
-                        const T t1 = ge * dx, t2 = ge * dy;
-                        mo[0] += ge;
-                        mo[1] += t1;
-                        mo[2] += t2;
-                        mo[3] = Num<T>::fma(t1, dx, mo[3]);
-                        mo[4] = Num<T>::fma(t1, dy, mo[4]);
-                        mo[5] = Num<T>::fma(t2, dy, mo[5]);
-                    }
-                }
+                for (int ch = 0; ch < 3; ch++) dcol[ch] = Num<T>::fma(gc[k][ch], wgt, dcol[ch]);
+                Tr[k] = keep ? tn : Tr[k];
+                hit = hit || keep;
+                // alpha clamped at alpha_max: no gradient to the Gaussian's shape
+                const T ge = keep && al < amax ? ga * al : T(0);
+                const T t1 = ge * dx, t2 = ge * dy;
+                mo[0] += ge;
+                mo[1] += t1;
+                mo[2] += t2;
+                mo[3] = Num<T>::fma(t1, dx, mo[3]);
+                mo[4] = Num<T>::fma(t1, dy, mo[4]);
+                mo[5] = Num<T>::fma(t2, dy, mo[5]);
             }
-            T* dst = pg + int64_t(e) * 9;
+            // per-row partial sums (16 lanes), parked in LDS; the rows are
+            // added and the pair stored once per batch, one lane per record
+            T* rs = s_rows[wave][i][row];
             if (__ballot(hit) != 0) {
-                T s[9];
+                T v[9];
 #pragma unroll
-                for (int q = 0; q < 6; q++) s[q] = wave_sum(mo[q]);
+                for (int q = 0; q < 6; q++) v[q] = row_sum(mo[q]);
 #pragma unroll
-                for (int q = 0; q < 3; q++) s[6 + q] = wave_sum(dcol[q]);
-                if (lane == 0) {
+                for (int q = 0; q < 3; q++) v[6 + q] = row_sum(dcol[q]);
+                if ((lane & 15) == 15)
 #pragma unroll
-                    for (int q = 0; q < 9; q++) dst[q] = s[q];
-                }
-            } else if (lane < 9) {
-                dst[lane] = T(0);
+                    for (int q = 0; q < 9; q++) rs[q] = v[q];
+            } else if ((lane & 15) == 15) {
+#pragma unroll
+                for (int q = 0; q < 9; q++) rs[q] = T(0);
             }
+        }
+        wave_lds_sync();
+        if (uint32_t(lane) < cnt) {
+            const T(*rows)[9] = s_rows[wave][lane];
+            T* dst = pg + int64_t(e_own) * 9;
+#pragma unroll
+            for (int q = 0; q < 9; q++) dst[q] = (rows[0][q] + rows[1][q]) + (rows[2][q] + rows[3][q]);
         }
         __builtin_amdgcn_wave_barrier();
     }
