@@ -112,12 +112,14 @@ def run_gpu(args):
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} steps done")
 
-    # plain timing: events only at the ends of the timed region
+    # timed region: HIP events bracket the whole loop, and events on the same
+    # (current) stream bracket every stage of every step
+    timer = StageTimer(torch, names)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for t in range(args.warmup, args.warmup + args.steps):
-        step(t)
+        step(t, timer)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -125,13 +127,6 @@ def run_gpu(args):
     if status & gs.GS_STATUS_PAIR_OVERFLOW:
         raise SystemExit("pair capacity overflowed during the timed steps; rerun with more headroom")
     log(f"[bench] timed {args.steps} steps: {ms:.2f} ms")
-
-    # per-stage durations over the same number of steps (separate pass, events between calls)
-    timer = StageTimer(torch, names)
-    t_base = args.warmup + args.steps
-    for t in range(t_base, t_base + args.steps):
-        step(t, timer)
-    torch.cuda.synchronize()
     stage = {k: v / args.steps for k, v in timer.totals_ms().items()}
     log("[bench] per-stage ms: " + ", ".join(f"{k} {v:.4f}" for k, v in stage.items()))
 
@@ -181,6 +176,19 @@ def cpu_baseline(scene, budget_s=12.0):
                       f"({t_adam:.1f}s)"}
 
 
+def copy_probe(nbytes=1 << 30, reps=5):
+    """Plain device-to-device copy of known size (reads and writes nbytes
+    each), used to scale the HBM byte counters of rocprofv3."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,7 +200,11 @@ def main():
     ap.add_argument("--height", type=int, default=1066)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path holds all K blocks in one GPU's HBM and this build has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
