@@ -1,0 +1,221 @@
+"""Batched K-block ADMM training on one GPU (Alg. 2, Eq. 8a-c).
+
+The K blocks the paper spreads over compute nodes live together in one
+GPU's HBM: the local copies of all blocks form one parameter store
+(block k owns the contiguous range [off_k, off_k + n_k)), and every stage of
+a local step is one launch over all blocks (one render job per block).
+Every ``intv`` steps (after the local step, including t = 0, as Alg. 2
+writes it) the consensus step averages the copies of each global Gaussian
+over the blocks that hold it (``gs_consensus``); the duals start at zero.
+
+Everything here is orchestration: device buffers come from torch, every
+arithmetic step runs in libgs.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import gs
+
+DEFAULT_LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)    # mean, rotation, scale, SH, opacity
+
+
+def holder_csr(local_gid, n_global):
+    """Holder CSR of the global ids: for each global id, the local indices of
+    its copies in ascending block order (blocks are laid out in order)."""
+    gid = np.concatenate(local_gid)
+    order = np.argsort(gid, kind="stable")          # stable: ascending block within a gid
+    counts = np.bincount(gid, minlength=n_global)
+    ptr = np.zeros(n_global + 1, np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    return ptr, order.astype(np.int64)
+
+
+@dataclass
+class BlockModel:
+    """Local copies of K blocks in one store plus the global model."""
+    sh_degree: int
+    z: torch.Tensor                   # [A][G] global model
+    x: torch.Tensor                   # [A][L] local copies, blocks back to back
+    offsets: list                     # block k: [offsets[k], offsets[k+1])
+    holder_ptr: torch.Tensor          # [G+1] int64
+    holder_idx: torch.Tensor          # [H] int64 local indices
+    local_gid: list = field(default_factory=list)
+
+    @classmethod
+    def from_global(cls, params_global: np.ndarray, local_gid, device="cuda"):
+        A, G = params_global.shape
+        deg = gs.sh_degree_of(A)
+        z = torch.from_numpy(np.ascontiguousarray(params_global)).to(device)
+        gid_all = torch.from_numpy(np.concatenate(local_gid)).to(device)
+        x = z.index_select(1, gid_all).contiguous()
+        offs = np.concatenate([[0], np.cumsum([len(g) for g in local_gid])]).tolist()
+        ptr, idx = holder_csr(local_gid, G)
+        return cls(deg, z, x, offs, torch.from_numpy(ptr).to(device), torch.from_numpy(idx).to(device),
+                   [np.asarray(g) for g in local_gid])
+
+    @property
+    def K(self):
+        return len(self.offsets) - 1
+
+    def block(self, k):
+        return self.offsets[k], self.offsets[k + 1]
+
+
+class AdmmTrainer:
+    """One view per block per step, all K blocks in one launch per stage."""
+
+    def __init__(self, model: BlockModel, cams, targets, cfg: gs.GsRasterCfg, lr=DEFAULT_LR, rho=(1e-3,) * 5,
+                 intv=100, relax=1.0, beta1=0.9, beta2=0.999, eps=1e-8, capacity=None, mask=None):
+        """cams[k]: list of cameras of block k; targets[k][v]: device tensor
+        [3*H*W] (or a callable (k, v) -> tensor) for block k, view v."""
+        self.model, self.cfg = model, cfg
+        self.lr, self.rho, self.intv, self.relax = tuple(lr), tuple(rho), int(intv), float(relax)
+        self.beta1, self.beta2, self.eps = beta1, beta2, eps
+        self.mask = mask
+        x = model.x
+        self.m = torch.zeros_like(x)
+        self.v = torch.zeros_like(x)
+        self.u = torch.zeros_like(x)
+        # w = z - u with u = 0: the consensus target of every local copy
+        self.w = x.clone()
+        self.g = torch.empty_like(x)
+        self.t = 0
+        self.cams = cams
+        self.targets = targets
+        self.n_views = min(len(c) for c in cams)
+        self._frames = {}
+        self.buf = None
+        self.capacity = capacity
+        self.loss = torch.zeros(model.K, device=x.device)
+        self.resid = torch.zeros(10, device=x.device)
+        self.history = []
+
+    # -- frames ----------------------------------------------------------
+    def frame(self, views):
+        """Frame with one job per block, block k rendering views[k]."""
+        key = tuple(views)
+        if key not in self._frames:
+            cams, jobs = [], []
+            for k, v in enumerate(views):
+                a, b = self.model.block(k)
+                cams.append(self.cams[k][v])
+                jobs.append(gs.JobSpec(k, a, b, 1.0))
+            self._frames[key] = gs.Frame(cams, jobs, self.cfg, self.model.x.device)
+        return self._frames[key]
+
+    def views_at(self, t):
+        return [t % self.n_views] * self.model.K
+
+    def target_buffer(self, views):
+        parts = []
+        for k, v in enumerate(views):
+            tg = self.targets(k, v) if callable(self.targets) else self.targets[k][v]
+            parts.append(tg.reshape(-1))
+        return torch.cat(parts) if len(parts) > 1 else parts[0]
+
+    # -- steps -----------------------------------------------------------
+    def _buffers(self, f):
+        if self.buf is None or self.buf.frame.n_records != f.n_records or self.buf.frame.n_pixels != f.n_pixels \
+                or self.buf.frame.n_tiles != f.n_tiles:
+            cap = self.capacity or max(1 << 20, 4 * f.n_records)
+            self.buf = gs.Buffers(f, cap, self.model.x.dtype, self.model.x.device)
+        self.buf.frame = f
+        return self.buf
+
+    def local_step(self, views=None, target=None):
+        """One x-update step (Eq. 8a) for every block at once."""
+        views = self.views_at(self.t) if views is None else views
+        f = self.frame(views)
+        buf = self._buffers(f)
+        x = self.model.x
+        gs.project(x, f, self.cfg, buf)
+        gs.bin_sort(f, self.cfg, buf)
+        gs.render_fwd(f, self.cfg, buf)
+        tgt = self.target_buffer(views) if target is None else target
+        self.loss.zero_()
+        gs.render_bwd(x, f, self.cfg, buf, self.g, gs.LOSS_L1, tgt, self.loss)
+        gs.adam_admm(x, self.g, self.m, self.v, self.w, self.mask,
+                     gs.adam_cfg(self.lr, self.rho, self.t + 1, self.beta1, self.beta2, self.eps))
+
+    def consensus(self):
+        """z = mean of holders' copies; u += x - z; w = z - u (Eq. 8b-c)."""
+        self.resid.zero_()
+        gs.consensus(self.model.x, self.u, self.w, self.model.z, self.model.holder_ptr, self.model.holder_idx,
+                     self.relax, self.resid)
+
+    def step(self):
+        """Alg. 2: local step for all blocks, then consensus when t mod intv == 0."""
+        self.local_step()
+        if self.t % self.intv == 0:
+            self.consensus()
+        self.t += 1
+
+    def check(self, grow=True):
+        """Read the device counters once; on a pair-capacity overflow grow the
+        buffers (the steps since the last check must be redone by the caller)."""
+        c = gs.read_counters(self.buf)
+        if c["status"] & gs.GS_STATUS_PAIR_OVERFLOW:
+            if grow:
+                self.capacity = int(c["pairs"] * 1.3) + 4096
+                self.buf.grow(self.capacity)
+                self.buf.counters.zero_()
+            return False
+        return True
+
+    def calibrate(self, headroom=1.3):
+        """Size the pair capacity from every view combination once (untimed)."""
+        pmax = 0
+        for v in range(self.n_views):
+            views = [v] * self.model.K
+            f = self.frame(views)
+            buf = self._buffers(f)
+            gs.rasterize(self.model.x, f, self.cfg, buf)
+            pmax = max(pmax, gs.read_counters(buf)["pairs"])
+        self.capacity = int(pmax * headroom) + 4096
+        self.buf.grow(self.capacity)
+        self.buf.counters.zero_()
+        return pmax
+
+
+# ---------------------------------------------------------------------------
+# tile-shape autotuner
+
+TILES = ((16, 16), (16, 8), (32, 8), (8, 8))
+
+
+def autotune_tile(run_step, key: str, cache_path=None, candidates=TILES, reps=5):
+    """Time ``run_step(tile)`` (one full training step with that tile shape)
+    for each candidate with HIP events and return the fastest; results are
+    cached in a JSON file keyed by ``key`` (workload shape)."""
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+    if key in cache:
+        return tuple(cache[key]["tile"])
+    times = {}
+    for tile in candidates:
+        run_step(tile)                         # warm-up (and capacity sizing)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run_step(tile)
+        e1.record()
+        torch.cuda.synchronize()
+        times[tile] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    cache[key] = {"tile": list(best), "ms": {f"{a}x{b}": v for (a, b), v in times.items()},
+                  "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    if cache_path:
+        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    return best

@@ -119,6 +119,7 @@ def target_images(seed, cams) -> list:
 
 
 def ring_cameras(n, radius, height, width, img_h, center=(0.0, 0.0, 0.0), fx=None):
+    """n cameras on a horizontal ring around ``center`` looking at it."""
     c = np.asarray(center, np.float64)
     cams = []
     for k in range(n):
@@ -186,16 +187,19 @@ class BlockScene:
 
 
 def block_scene(counts=BLOCK_COUNTS, bounds=SLAB_BOUNDS, share=0.10, n_cams=32,
-                width=1600, height=1066, sh_degree=3, seed=1003) -> BlockScene:
+                width=1600, height=1066, sh_degree=3, seed=1003, y_range=(-10.0, 10.0), z_range=(-50.0, 50.0),
+                logscale=(-3.0, 0.7), ring_radius=40.0, ring_height=10.0, fx=None) -> BlockScene:
     """Blocks as x-slabs of uniform density; the ``share`` fraction of each
     block's own Gaussians nearest the plane it shares with neighbour
-    n(k) = k + 1 (n(K-1) = K-2) is copied into n(k) under the same global id."""
+    n(k) = k + 1 (n(K-1) = K-2) is copied into n(k) under the same global id.
+    Block k draws with seed 100 * seed + k; its cameras sit on a ring around
+    its slab centre."""
     K = len(counts)
     parts, gids, base = [], [], 0
     for k in range(K):
-        lo = [bounds[k], -10.0, -50.0]
-        hi = [bounds[k + 1], 10.0, 50.0]
-        parts.append(gaussians(counts[k], sh_degree, seed * 100 + k, lo, hi, -3.0, 0.7))
+        lo = [bounds[k], y_range[0], z_range[0]]
+        hi = [bounds[k + 1], y_range[1], z_range[1]]
+        parts.append(gaussians(counts[k], sh_degree, seed * 100 + k, lo, hi, logscale[0], logscale[1]))
         gids.append(np.arange(base, base + counts[k], dtype=np.int64))
         base += counts[k]
     params_global = np.concatenate(parts, axis=1)
@@ -211,7 +215,7 @@ def block_scene(counts=BLOCK_COUNTS, bounds=SLAB_BOUNDS, share=0.10, n_cams=32,
     cams = []
     for k in range(K):
         cx = 0.5 * (bounds[k] + bounds[k + 1])
-        cams.append(ring_cameras(n_cams, 40.0, 10.0, width, height, center=(cx, 0.0, 0.0)))
+        cams.append(ring_cameras(n_cams, ring_radius, ring_height, width, height, center=(cx, 0.0, 0.0), fx=fx))
     return BlockScene(params_global, sh_degree, local_gid, list(counts), cams, seed)
 
 

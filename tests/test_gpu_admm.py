@@ -1,0 +1,187 @@
+"""Batched K-block ADMM training (Alg. 2) and the autograd wrapper, on the
+GPU, against the FP64 oracle and against per-block runs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_13943_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2405_13943_amd import admm, gs, raster  # noqa: E402
+
+F32 = lambda v: [float(np.float32(a)) for a in v]  # noqa: E731
+
+
+def tiny_blocks():
+    """Three x-slab blocks, 10% of each block's Gaussians shared with its
+    neighbour, two 64x48 views per block."""
+    return scenes.block_scene(counts=(300, 400, 350), bounds=(-1.5, -0.5, 0.5, 1.5), n_cams=2, width=64, height=48,
+                              y_range=(-0.5, 0.5), z_range=(-0.5, 0.5), logscale=(-3.5, 0.4), ring_radius=3.0,
+                              ring_height=0.5, fx=60.0, sh_degree=1, seed=77)
+
+
+def targets_for(bs):
+    return [[torch.from_numpy(t).reshape(-1).cuda() for t in scenes.target_images(900 + 10 * k, bs.cams[k])]
+            for k in range(len(bs.cams))]
+
+
+def make_trainer(bs, intv=2, rho=(1e-2,) * 5, relax=1.0):
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+    cfg = gs.raster_cfg((16, 16))
+    return admm.AdmmTrainer(model, bs.cams, targets_for(bs), cfg, lr=(1e-3, 2e-3, 3e-3, 4e-3, 5e-3), rho=rho,
+                            intv=intv, relax=relax, capacity=1 << 16)
+
+
+def test_batched_blocks_equal_single_block_runs():
+    """All blocks in one launch per stage give bit-identical images and
+    gradients to rendering each block alone."""
+    bs = tiny_blocks()
+    tr = make_trainer(bs)
+    views = [1, 0, 1]
+    tr.local_step(views)
+    f = tr.frame(views)
+    imgs = [f.image(tr.buf.rgb, k).clone() for k in range(3)]
+    g_all = tr.g.clone()
+    x0 = admm.BlockModel.from_global(bs.params_global, bs.local_gid).x
+    for k in range(3):
+        a, b = tr.model.block(k)
+        pk = x0[:, a:b].contiguous()
+        fk = gs.Frame([bs.cams[k][views[k]]], [gs.JobSpec(0, 0, b - a, 1.0)], tr.cfg)
+        bk = gs.rasterize(pk, fk, tr.cfg)
+        assert torch.equal(fk.image(bk.rgb, 0), imgs[k])
+        gk = torch.empty_like(pk)
+        gs.render_bwd(pk, fk, tr.cfg, bk, gk, gs.LOSS_L1, tr.targets[k][views[k]])
+        assert torch.equal(gk, g_all[:, a:b])
+
+
+def test_trainer_step_matches_oracle_composition():
+    """One trainer step (t = 0: local step for all blocks, then consensus)
+    equals the oracle composed from the paper's pieces: per-block image
+    gradient (FP64 render/backward), Adam on g + rho (x - w) with w = z - u
+    and u = 0, then z = mean over holders, u = x - z, w = z - u."""
+    bs = tiny_blocks()
+    tr = make_trainer(bs, intv=1)
+    x0 = tr.model.x.cpu().numpy().copy()
+    tr.local_step()
+    g_gpu = tr.g.cpu().numpy().astype(np.float64)
+    # the trainer's L1 gradient is the kernels' external-gradient backward fed
+    # dL/dC = sign(C - target) / 3HW of each block's own image (the kernels
+    # themselves are checked against the FP64 oracle in test_gpu_parity)
+    f = tr.frame(tr.views_at(0))
+    tgt = tr.target_buffer(tr.views_at(0))
+    n_px = torch.tensor([3 * c.width * c.height for c in f.cams], device="cuda")
+    dl = torch.cat([torch.sign(f.image(tr.buf.rgb, k) - f.image(tgt, k)).reshape(-1) / float(n_px[k])
+                    for k in range(3)])
+    x0_dev = torch.from_numpy(x0).cuda()
+    g_ext = torch.empty_like(x0_dev)
+    gs.render_bwd(x0_dev, f, tr.cfg, tr.buf, g_ext, gs.LOSS_EXTERNAL, dl)
+    np.testing.assert_allclose(g_gpu, g_ext.cpu().numpy(), rtol=1e-6, atol=1e-12)
+    # and that gradient matches the FP64 oracle where the oracle flags nothing
+    for k in range(3):
+        a, b = tr.model.block(k)
+        cam = bs.cams[k][0]
+        ref = oracle.render(x0[:, a:b], cam)
+        dlk = f.image(dl, k).cpu().numpy().astype(np.float64)
+        dlk[:, ref["flags"] != 0] = 0
+        gk = torch.empty_like(x0_dev[:, a:b].contiguous())
+        fk = gs.Frame([cam], [gs.JobSpec(0, 0, b - a, 1.0)], tr.cfg)
+        bk = gs.rasterize(x0_dev[:, a:b].contiguous(), fk, tr.cfg)
+        gs.render_bwd(x0_dev[:, a:b].contiguous(), fk, tr.cfg, bk, gk, gs.LOSS_EXTERNAL,
+                      torch.from_numpy(dlk.astype(np.float32)).reshape(-1).cuda())
+        g_ref = oracle.backward(x0[:, a:b], cam, dlk)
+        num = np.linalg.norm(gk.cpu().numpy() - g_ref)
+        assert num / np.linalg.norm(g_ref) < 1e-3, k
+    # optimiser + consensus with the GPU's own gradient as input
+    lr, rho = F32(tr.lr), F32(tr.rho)
+    hp = dict(beta1=F32([0.9])[0], beta2=F32([0.999])[0], eps=F32([1e-8])[0])
+    z = np.zeros_like(x0)
+    rx, _, _ = oracle.adam_admm(x0, g_gpu.astype(np.float32), z, z, x0, lr, rho, 1, **hp)
+    x1 = tr.model.x.cpu().numpy()
+    np.testing.assert_allclose(x1, rx, rtol=0, atol=2e-6 * np.abs(x0).max() + 1e-7)
+    tr.consensus()
+    ptr, idx = tr.model.holder_ptr.cpu().numpy(), tr.model.holder_idx.cpu().numpy()
+    rz, ru, rw = oracle.consensus(x1, np.zeros_like(x1), ptr, idx, len(ptr) - 1)
+    np.testing.assert_allclose(tr.model.z.cpu().numpy(), rz, rtol=1e-6, atol=1e-7)
+    # u = x - z and w = z - u cancel: FP32 bound from the magnitudes of the terms
+    ulp = 2.0 ** -24
+    mag = np.abs(x1) + np.abs(rw + ru)          # |x| + |z| for every local copy
+    assert (np.abs(tr.u.cpu().numpy() - ru) <= 16 * ulp * mag).all()
+    assert (np.abs(tr.w.cpu().numpy() - rw) <= 32 * ulp * mag).all()
+
+
+def test_trainer_loop_invariants_and_penalty():
+    """Over several consensus rounds: after every consensus the holder mean of
+    the duals is zero and w = z - u (supplementary B); shared copies stay
+    closer together with a strong penalty than without one."""
+    bs = tiny_blocks()
+    spread = {}
+    for rho in (0.0, 1.0):
+        tr = make_trainer(bs, intv=3, rho=(rho,) * 5)
+        for _ in range(9):
+            tr.step()
+        tr.consensus()
+        ptr, idx = tr.model.holder_ptr.cpu().numpy(), tr.model.holder_idx.cpu().numpy()
+        u, w, z, x = (a.cpu().numpy().astype(np.float64) for a in (tr.u, tr.w, tr.model.z, tr.model.x))
+        shared = np.nonzero(np.diff(ptr) > 1)[0]
+        assert len(shared) > 50
+        for gid in shared[:200]:
+            hs = idx[ptr[gid]:ptr[gid + 1]]
+            np.testing.assert_allclose(u[:, hs].mean(axis=1), 0, atol=1e-6)
+            np.testing.assert_allclose(w[:, hs], z[:, gid:gid + 1] - u[:, hs], atol=1e-6)
+        spread[rho] = np.mean([np.abs(x[:, idx[ptr[g]:ptr[g + 1]]] - z[:, g:g + 1]).max() for g in shared])
+        assert tr.check()
+    assert spread[1.0] < spread[0.0]
+
+
+def test_autograd_function_fp64_against_finite_differences():
+    """GaussianRasterize in FP64 (200 Gaussians, SH 3, 64x64): backward
+    through torch.autograd equals central differences of the forward on a
+    seeded subset of parameters."""
+    s = scenes.config4a()
+    cfg = gs.raster_cfg((16, 16))
+    frame = gs.Frame(s.cams, [gs.JobSpec(0, 0, 200, 1.0)], cfg)
+    p = torch.from_numpy(s.params.astype(np.float64)).cuda().requires_grad_(True)
+    W = torch.from_numpy(np.random.default_rng(3).standard_normal(3 * 64 * 64)).cuda()
+    out = raster.rasterize(p, frame, cfg)
+    (W * out).sum().backward()
+    g = p.grad.cpu().numpy()
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    base_n = gs.rasterize(p.detach(), frame, cfg).ncontrib.clone()
+    checked = 0
+    for a, i in zip(rng.integers(0, 59, 150), rng.integers(0, 200, 150)):
+        vals, flip = [], False
+        for sgn in (1, -1):
+            q = p.detach().clone()
+            q[a, i] += sgn * h
+            b = gs.rasterize(q, frame, cfg)
+            flip |= not torch.equal(b.ncontrib, base_n)
+            vals.append(float((W * b.rgb).sum()))
+        if flip:
+            continue
+        checked += 1
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[a, i]) <= 1e-5 * abs(g[a, i]) + 2e-6, (a, i, fd, g[a, i])
+    assert checked > 120
+
+
+def test_autotuner_picks_a_candidate_and_caches(tmp_path):
+    bs = tiny_blocks()
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+    tg = targets_for(bs)
+    trainers = {}
+
+    def run(tile):
+        if tile not in trainers:
+            trainers[tile] = admm.AdmmTrainer(model, bs.cams, tg, gs.raster_cfg(tile), capacity=1 << 16)
+        trainers[tile].local_step([0, 0, 0])
+
+    path = str(tmp_path / "tune.json")
+    best = admm.autotune_tile(run, "tiny-3blocks", path, reps=2)
+    assert best in admm.TILES
+    assert admm.autotune_tile(lambda t: (_ for _ in ()).throw(AssertionError), "tiny-3blocks", path) == best
