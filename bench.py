@@ -9,7 +9,13 @@ Workload (one block): 500k Gaussians, SH degree 3, 64 ring cameras at
 
 with all inputs resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serve]
+
+The default line also carries a serving leg (``serve``): the 6M-Gaussian
+global model under Poisson requests at 200 req/s over mixed resolutions,
+p50/p99 latency and frames/s.  ``--workload blocks4`` instead prints the
+batched K = 4 block line (batched against sequential per-block steps) and
+``--workload serve`` the serving leg alone.
 """
 from __future__ import annotations
 
@@ -139,6 +145,181 @@ def run_gpu(args):
                 adam_gbs=achieved, pairs_max=pmax, N=N, A=A, scene=scene)
 
 
+def run_serve(args):
+    """Serving the global model: 6M Gaussians SH3 resident, Poisson requests at
+    ``--rate`` req/s over mixed resolutions, continuous batching; latency is
+    arrival -> image landed in pinned host memory."""
+    import torch
+    from paper_2405_13943_amd import gs, scenes, serve
+    t0 = time.time()
+    scene = scenes.config5(args.serve_n)
+    params = torch.from_numpy(scene.params).to("cuda")
+    del scene
+    cfg = gs.raster_cfg((args.tile, args.tile))
+    srv = serve.RenderServer(params, cfg, hbm_budget=args.serve_hbm * 1e9, n_slots=args.serve_slots,
+                             max_batch=args.serve_max_batch, resolutions=scenes.SERVE_RESOLUTIONS)
+    log(f"[serve] setup {time.time() - t0:.1f}s: N={params.shape[1]}, max_batch {srv.max_batch}, "
+        f"{len(srv.slots)} slots x {srv.slots[0].arena.nbytes() / 1e9:.2f} GB, pairs/px {srv.pairs_per_px:.2f}")
+    # warm-up burst (first launches, pinned pool), not measured
+    wcams = scenes.serve_requests(24, 55)
+    srv.run_open_loop(wcams, np.zeros(len(wcams)))
+    torch.cuda.synchronize()
+    # open loop at the offered rate; the first second is not counted
+    warm = 1.0
+    arr = scenes.poisson_arrivals(args.rate, args.serve_seconds + warm, 5005)
+    cams = scenes.serve_requests(len(arr), 5006)
+    stats, _ = srv.run_open_loop(cams, arr, warmup=warm)
+    log(f"[serve] open loop {args.rate:.0f} req/s: {stats}")
+    # saturation: a burst of requests all arriving at t = 0
+    nb = int(args.rate * 2)
+    bcams = scenes.serve_requests(nb, 5007)
+    sat, _ = srv.run_open_loop(bcams, np.zeros(nb))
+    log(f"[serve] burst of {nb}: {sat}")
+    out = {"workload": f"global model {params.shape[1] // 1_000_000}M Gaussians SH3, Poisson {args.rate:.0f} req/s "
+                       f"over {args.serve_seconds:.0f}s, resolutions uniform over "
+                       + ", ".join(f"{w}x{h}" for w, h in scenes.SERVE_RESOLUTIONS),
+           "requests": stats["requests"], "p50_ms": round(stats["p50_ms"], 3), "p99_ms": round(stats["p99_ms"], 3),
+           "frames_per_s": round(stats["frames_per_s"], 1), "mpx_per_s": round(stats["mpx_per_s"], 1),
+           "retries": stats["retries"], "max_batch": srv.max_batch, "slots": len(srv.slots),
+           "saturated_frames_per_s": round(sat["frames_per_s"], 1), "saturated_mpx_per_s": round(sat["mpx_per_s"], 1),
+           "saturated_p50_ms": round(sat["p50_ms"], 2)}
+    del srv, params
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_blocks4(args):
+    """K = 4 uneven blocks (0.8M/1.5M/2.2M/3.0M own Gaussians, 10% shared with
+    a neighbour), 32 ring views per block at 1600x1066: the batched trainer
+    (one launch per stage over all blocks, consensus every 100 steps) against
+    the same four blocks stepped one after another as plain single-block
+    steps.  Tile shape from the autotuner."""
+    import torch
+    from paper_2405_13943_amd import admm, gs, scenes
+    t0 = time.time()
+    bs = scenes.block_scene(n_cams=args.block_cams)
+    K = len(bs.local_gid)
+    dev = torch.device("cuda", 0)
+    tg_cache = {}
+
+    def target(k, v):
+        if (k, v) not in tg_cache:
+            c = bs.cams[k][v]
+            tg_cache[(k, v)] = torch.from_numpy(
+                scenes.rng(bs.seed * 1000 + 100 * k + v).random((3, c.height, c.width)).astype(np.float32)
+            ).reshape(-1).to(dev)
+        return tg_cache[(k, v)]
+
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+    log(f"[blocks4] setup {time.time() - t0:.1f}s: local {[len(g) for g in bs.local_gid]}, store "
+        f"{tuple(model.x.shape)}, global {model.z.shape[1]}")
+    x0 = model.x.clone()
+    trainers = {}
+
+    def trainer(tile):
+        if tile not in trainers:
+            tr = admm.AdmmTrainer(model, bs.cams, target, gs.raster_cfg(tile), lr=LR, rho=RHO, intv=100)
+            tr.calibrate()
+            trainers[tile] = tr
+        return trainers[tile]
+
+    def run(tile):
+        tr = trainer(tile)
+        tr.local_step()
+        tr.t += 1
+
+    tile = admm.autotune_tile(run, f"blocks4-{model.x.shape[1]}-1600x1066", args.tune_cache, reps=3) \
+        if not args.no_tile_auto else (args.tile, args.tile)
+    log(f"[blocks4] tile {tile[0]}x{tile[1]}")
+    for t, tr in list(trainers.items()):
+        if t != tile:
+            del trainers[t]
+    torch.cuda.empty_cache()
+    # fresh state for the timed run
+    model.x.copy_(x0)
+    tr = admm.AdmmTrainer(model, bs.cams, target, gs.raster_cfg(tile), lr=LR, rho=RHO, intv=100,
+                          capacity=trainers[tile].capacity if tile in trainers else None)
+    trainers.clear()
+    if tr.capacity is None:
+        tr.calibrate()
+    else:
+        tr._buffers(tr.frame([0] * K))
+    cfg = tr.cfg
+    # sequential baseline: each block as its own plain single-block model
+    seq = []
+    for k in range(K):
+        mk = admm.BlockModel.from_global(bs.params_global, [bs.local_gid[k]])
+        tk = admm.AdmmTrainer(mk, [bs.cams[k]], (lambda kk: (lambda _k, v: target(kk, v)))(k), cfg, lr=LR, rho=RHO,
+                              intv=1 << 30)
+        tk.calibrate()
+        seq.append(tk)
+    # the batched frame renders every block exactly as its own plain render
+    views = [0] * K
+    f = tr.frame(views)
+    gs.rasterize(model.x, f, cfg, tr.buf)
+    same = True
+    for k in range(K):
+        fk = seq[k].frame([0])
+        gs.rasterize(seq[k].model.x, fk, cfg, seq[k].buf)
+        same &= bool(torch.equal(f.image(tr.buf.rgb, k), fk.image(seq[k].buf.rgb, 0)))
+    for b in [tr] + seq:
+        b.buf.counters.zero_()
+    log(f"[blocks4] batched images equal to per-block renders: {same}")
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    for _ in range(args.warmup):
+        tr.step()
+        for tk in seq:
+            tk.local_step()
+            tk.t += 1
+    cons_ms = []
+
+    def batched_step():
+        tr.local_step()
+        if tr.t % tr.intv == 0:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            tr.consensus()
+            b.record()
+            cons_ms.append((a, b))
+        tr.t += 1
+
+    def seq_step():
+        for tk in seq:
+            tk.local_step()
+            tk.t += 1
+
+    steps = args.block_steps
+    ms_b = timed(batched_step, steps)
+    ms_s = timed(seq_step, steps)
+    ok = all(b.check(grow=False) for b in [tr] + seq)
+    if not ok:
+        raise SystemExit("pair capacity overflowed during the timed steps; rerun with more headroom")
+    c_ms = [a.elapsed_time(b) for a, b in cons_ms]
+    res = tr.resid.cpu().numpy().tolist()
+    out = {"metric": "K-block ADMM train steps/s (4 blocks, 1 view each, fwd+bwd+Adam/ADMM + consensus/100)",
+           "value": 1000.0 * steps / ms_b, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+           "ms_per_step": ms_b / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic (seeded slab blocks, ring cameras, U(0,1) targets)",
+           "config": {"workload": "batched K=4 blocks 0.8M/1.5M/2.2M/3.0M own Gaussians SH3 + 10% shared copies "
+                                  f"({model.x.shape[1]} local slots), {args.block_cams} ring views per block at "
+                                  "1600x1066, consensus every 100 steps",
+                      "tile": f"{tile[0]}x{tile[1]}"},
+           "sequential_ms_per_step": ms_s / steps, "batched_speedup": ms_s / ms_b,
+           "consensus_ms": c_ms, "consensus_calls": len(c_ms), "images_equal_per_block": same,
+           "last_residuals": res}
+    return out
+
+
 def cpu_baseline(scene, budget_s=12.0):
     """The FP64 oracle on the host: fwd + bwd of one 1600x1066 view on a
     seeded pixel sample (extrapolated by pixel count), plus the Adam + ADMM
@@ -200,6 +381,19 @@ def main():
     ap.add_argument("--height", type=int, default=1066)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("train", "blocks4", "serve"), default="train",
+                    help="train: single block at scale (+ serve leg); blocks4: batched K=4 blocks; serve: serving only")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the train workload")
+    ap.add_argument("--serve-n", type=int, default=6_000_000)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-hbm", type=float, default=48.0, help="GB of transient serving buffers")
+    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-max-batch", type=int, default=8)
+    ap.add_argument("--block-cams", type=int, default=32)
+    ap.add_argument("--block-steps", type=int, default=200)
+    ap.add_argument("--no-tile-auto", action="store_true", help="blocks4: use --tile instead of the autotuner")
+    ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
     if args.copy_probe:
@@ -209,7 +403,16 @@ def main():
         print("bench.py measures one GPU: the path holds all K blocks in one GPU's HBM and this build has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "blocks4":
+        print(json.dumps(run_blocks4(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps({"serve": run_serve(args)}), flush=True)
+        return
     r = run_gpu(args)
+    srv = None
+    if not args.no_serve:
+        srv = run_serve(args)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -237,6 +440,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["adam_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": None},
         "cpu_baseline": cpu,
+        "serve": srv,
     }
     print(json.dumps(out), flush=True)
 

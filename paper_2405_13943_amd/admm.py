@@ -26,15 +26,21 @@ from . import gs
 DEFAULT_LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)    # mean, rotation, scale, SH, opacity
 
 
-def holder_csr(local_gid, n_global):
+def holder_csr(local_gid, n_global, local_index=None):
     """Holder CSR of the global ids: for each global id, the local indices of
-    its copies in ascending block order (blocks are laid out in order)."""
+    its copies in ascending block order (blocks are laid out in order).
+    ``local_index[k]`` gives the store column of each of block k's copies
+    (default: blocks back to back without padding)."""
     gid = np.concatenate(local_gid)
+    if local_index is None:
+        cols = np.arange(len(gid), dtype=np.int64)
+    else:
+        cols = np.concatenate(local_index)
     order = np.argsort(gid, kind="stable")          # stable: ascending block within a gid
     counts = np.bincount(gid, minlength=n_global)
     ptr = np.zeros(n_global + 1, np.int64)
     np.cumsum(counts, out=ptr[1:])
-    return ptr, order.astype(np.int64)
+    return ptr, cols[order].astype(np.int64)
 
 
 @dataclass
@@ -43,29 +49,45 @@ class BlockModel:
     sh_degree: int
     z: torch.Tensor                   # [A][G] global model
     x: torch.Tensor                   # [A][L] local copies, blocks back to back
-    offsets: list                     # block k: [offsets[k], offsets[k+1])
+    offsets: list                     # block k's slot: [offsets[k], offsets[k+1]), 64-column aligned
     holder_ptr: torch.Tensor          # [G+1] int64
     holder_idx: torch.Tensor          # [H] int64 local indices
     local_gid: list = field(default_factory=list)
+    ends: list = None                 # block k's copies: [offsets[k], ends[k])
 
     @classmethod
-    def from_global(cls, params_global: np.ndarray, local_gid, device="cuda"):
+    def from_global(cls, params_global: np.ndarray, local_gid, device="cuda", align=64):
+        """Local copies of each block start on a multiple of ``align``
+        columns (16-byte aligned slices for per-block streaming); the padding
+        columns belong to no block and no holder set."""
         A, G = params_global.shape
         deg = gs.sh_degree_of(A)
         z = torch.from_numpy(np.ascontiguousarray(params_global)).to(device)
-        gid_all = torch.from_numpy(np.concatenate(local_gid)).to(device)
-        x = z.index_select(1, gid_all).contiguous()
-        offs = np.concatenate([[0], np.cumsum([len(g) for g in local_gid])]).tolist()
-        ptr, idx = holder_csr(local_gid, G)
-        return cls(deg, z, x, offs, torch.from_numpy(ptr).to(device), torch.from_numpy(idx).to(device),
-                   [np.asarray(g) for g in local_gid])
+        offs, col_gid, base = [], [], 0
+        for g in local_gid:
+            offs.append(base)
+            n = len(g)
+            pad = (-n) % align
+            col_gid.append(np.asarray(g, np.int64))
+            if pad:
+                col_gid.append(np.full(pad, int(g[0]) if n else 0, np.int64))
+            base += n + pad
+        offs.append(base)
+        x = z.index_select(1, torch.from_numpy(np.concatenate(col_gid)).to(device)).contiguous()
+        local_index = [np.arange(offs[k], offs[k] + len(local_gid[k]), dtype=np.int64) for k in range(len(local_gid))]
+        ptr, idx = holder_csr(local_gid, G, local_index)
+        ends = [offs[k] + len(local_gid[k]) for k in range(len(local_gid))]
+        return cls(deg, z, x, offs[:-1] + [offs[-1]], torch.from_numpy(ptr).to(device),
+                   torch.from_numpy(idx).to(device), [np.asarray(g) for g in local_gid], ends)
 
     @property
     def K(self):
         return len(self.offsets) - 1
 
     def block(self, k):
-        return self.offsets[k], self.offsets[k + 1]
+        """Store columns of block k's copies."""
+        end = self.ends[k] if self.ends is not None else self.offsets[k + 1]
+        return self.offsets[k], end
 
 
 class AdmmTrainer:

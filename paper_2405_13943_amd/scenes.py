@@ -163,6 +163,18 @@ def config2_targets(scene: Scene, views) -> list:
             for v in views]
 
 
+def config5(n=6_000_000) -> Scene:
+    """Serving case: the global model, 6M Gaussians, SH degree 3, in the same
+    100 x 20 x 100 m box as the scale case (drawn in chunks of 1M, chunk c
+    with seed 1005 * 1000 + c, so the FP64 temporaries stay small)."""
+    seed = 1005
+    step = 1_000_000
+    parts = [gaussians(min(step, n - a), 3, seed * 1000 + a // step, [-50, -10, -50], [50, 10, 50], -3.0, 0.7)
+             for a in range(0, n, step)]
+    p = np.concatenate(parts, axis=1) if len(parts) > 1 else parts[0]
+    return Scene(f"serve-{n // 1_000_000}M-sh3", p, 3, [], [], seed)
+
+
 def config4a() -> Scene:
     """Adjoint case: 200 Gaussians, SH degree 3, one 64x64 view (fx = 75)."""
     seed = 1004
