@@ -32,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+BWD_FLOPS = 46
 LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)       # mean, rotation, scale, SH, opacity
 RHO = (1e-3,) * 5
 
@@ -96,7 +98,10 @@ def run_gpu(args):
     loss = torch.zeros(1, device="cuda")
     buf.counters.zero_()
 
-    names = ["project", "bin_sort", "render_fwd", "render_bwd", "adam_admm", "end"]
+    if args.unfused:
+        names = ["project", "bin_sort", "render_fwd", "render_bwd", "adam_admm", "end"]
+    else:
+        names = ["project", "bin_sort", "render_fwd", "render_bwd_adam", "end"]
 
     def step(t, timer=None):
         f = frames[t % len(frames)]
@@ -107,10 +112,16 @@ def run_gpu(args):
         gs.bin_sort(f, cfg, buf)
         mark("render_fwd")
         gs.render_fwd(f, cfg, buf)
-        mark("render_bwd")
-        gs.render_bwd(st["x"], f, cfg, buf, st["g"], gs.LOSS_L1, targets[t % len(frames)], loss)
-        mark("adam_admm")
-        gs.adam_admm(st["x"], st["g"], st["m"], st["v"], st["w"], None, gs.adam_cfg(LR, RHO, t + 1))
+        acfg = gs.adam_cfg(LR, RHO, t + 1)
+        if args.unfused:
+            mark("render_bwd")
+            gs.render_bwd(st["x"], f, cfg, buf, st["g"], gs.LOSS_L1, targets[t % len(frames)], loss)
+            mark("adam_admm")
+            gs.adam_admm(st["x"], st["g"], st["m"], st["v"], st["w"], None, acfg)
+        else:
+            mark("render_bwd_adam")
+            gs.render_bwd_adam(st["x"], f, cfg, buf, st["m"], st["v"], st["w"], None, acfg, gs.LOSS_L1,
+                               targets[t % len(frames)], loss)
         mark("end")
 
     for t in range(args.warmup):
@@ -121,6 +132,10 @@ def run_gpu(args):
     # timed region: HIP events bracket the whole loop, and events on the same
     # (current) stream bracket every stage of every step
     timer = StageTimer(torch, names)
+    # the library times the launches of these kernels with its own HIP events
+    # on the launch stream (fused calls hold several kernels)
+    kernels = ["k_render_bwd", "k_render_fwd", "k_adam_admm" if args.unfused else "k_project_bwd_adam"]
+    gs.profile_set(kernels)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -129,6 +144,22 @@ def run_gpu(args):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    kern = {}
+    for k in kernels:
+        tot, n = gs.profile_get(k)
+        kern[k] = tot / max(n, 1)
+    gs.profile_set(None)
+    # work of the timed views, counted after the timed region on the final
+    # parameters: (pixel, Gaussian) contributions and tile pairs per view
+    kept = pairs = 0
+    nv = min(args.steps, len(frames))
+    for t in range(args.warmup, args.warmup + nv):
+        f = frames[t % len(frames)]
+        gs.project(st["x"], f, cfg, buf)
+        gs.bin_sort(f, cfg, buf)
+        kept += gs.render_fwd_stats(f, cfg, buf)
+        pairs += gs.read_counters(buf)["pairs"]
+    kept, pairs = kept / nv, pairs / nv
     status = gs.read_counters(buf)["status"]
     if status & gs.GS_STATUS_PAIR_OVERFLOW:
         raise SystemExit("pair capacity overflowed during the timed steps; rerun with more headroom")
@@ -136,13 +167,25 @@ def run_gpu(args):
     stage = {k: v / args.steps for k, v in timer.totals_ms().items()}
     log("[bench] per-stage ms: " + ", ".join(f"{k} {v:.4f}" for k, v in stage.items()))
 
-    # algorithmic bytes of the dominant streaming kernel (Adam + ADMM): read x, g, m, v, w;
-    # write x, m, v -> 8 planes x 4 B x A per Gaussian
-    adam_bytes = 32 * A * N
-    adam_ms = stage["adam_admm"]
-    achieved = adam_bytes / (adam_ms * 1e-3) / 1e9
-    return dict(ms_per_step=ms / args.steps, steps=args.steps, stage_ms=stage, adam_bytes=adam_bytes,
-                adam_gbs=achieved, pairs_max=pmax, N=N, A=A, scene=scene)
+    log("[bench] per-launch kernel ms: " + ", ".join(f"{k} {v:.4f}" for k, v in kern.items()))
+    # HBM roofline of the streaming optimiser kernel.  Algorithmic bytes per
+    # Gaussian: the two-call path reads x, g, m, v, w and writes x, m, v
+    # (8 planes of 4 B); the fused kernel reads x, m, v, w and writes x, m, v
+    # (7 planes) plus, per Gaussian, its meta word (16 B), pair offset (4 B)
+    # and the nine FP32 partials of each of its tile pairs (36 B per pair).
+    if args.unfused:
+        opt_kernel, opt_bytes = "k_adam_admm", 32 * A * N
+    else:
+        opt_kernel, opt_bytes = "k_project_bwd_adam", 28 * A * N + 20 * N + 36 * pairs
+    opt_ms = kern[opt_kernel]
+    # ALU roofline of the compositing backward: BWD_FLOPS FP32 operations per
+    # (pixel, Gaussian) contribution (alpha recomputed, transmittance, colour
+    # behind, dL/dalpha, colour and moment accumulations; an FMA counts 2)
+    bwd_flops = BWD_FLOPS * kept
+    return dict(ms_per_step=ms / args.steps, steps=args.steps, stage_ms=stage, kernel_ms=kern, opt_kernel=opt_kernel,
+                opt_bytes=opt_bytes, opt_gbs=opt_bytes / (opt_ms * 1e-3) / 1e9, pairs_max=pmax, pairs=pairs,
+                kept=kept, bwd_flops=bwd_flops, bwd_tflops=bwd_flops / (kern["k_render_bwd"] * 1e-3) / 1e12, N=N, A=A,
+                scene=scene)
 
 
 def run_serve(args):
@@ -188,6 +231,27 @@ def run_serve(args):
     return out
 
 
+KERNELS = ("k_project", "k_fill_u32", "k_scan_reduce", "k_scan_spine", "k_scan_apply", "k_rs_hist", "k_rs_colscan",
+           "k_rs_scatter", "k_emit", "k_ranges", "k_render_fwd", "k_render_bwd", "k_project_bwd_rec",
+           "k_zero_uncovered", "k_project_bwd_adam", "k_adam_uncovered", "k_adam_admm", "k_consensus")
+
+
+def kernel_breakdown(gs, torch, fn, steps):
+    """Per-kernel device time per step (ms) of ``steps`` calls of fn, from the
+    library's own HIP events (run outside the timed region)."""
+    gs.profile_set("*")
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    out = {}
+    for k in KERNELS:
+        ms, n = gs.profile_get(k)
+        if n:
+            out[k] = round(ms / steps, 4)
+    gs.profile_set(None)
+    return out
+
+
 def run_blocks4(args):
     """K = 4 uneven blocks (0.8M/1.5M/2.2M/3.0M own Gaussians, 10% shared with
     a neighbour), 32 ring views per block at 1600x1066: the batched trainer
@@ -210,6 +274,10 @@ def run_blocks4(args):
             ).reshape(-1).to(dev)
         return tg_cache[(k, v)]
 
+    # every block's targets on the device before anything is timed
+    for k in range(K):
+        for v in range(args.block_cams):
+            target(k, v)
     model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
     log(f"[blocks4] setup {time.time() - t0:.1f}s: local {[len(g) for g in bs.local_gid]}, store "
         f"{tuple(model.x.shape)}, global {model.z.shape[1]}")
@@ -305,6 +373,10 @@ def run_blocks4(args):
     if not ok:
         raise SystemExit("pair capacity overflowed during the timed steps; rerun with more headroom")
     c_ms = [a.elapsed_time(b) for a, b in cons_ms]
+    kb = kernel_breakdown(gs, torch, lambda: (tr.local_step(), setattr(tr, "t", tr.t + 1)), 5)
+    ks = kernel_breakdown(gs, torch, seq_step, 5)
+    log(f"[blocks4] batched kernels ms/step: {kb}")
+    log(f"[blocks4] sequential kernels ms/step: {ks}")
     res = tr.resid.cpu().numpy().tolist()
     out = {"metric": "K-block ADMM train steps/s (4 blocks, 1 view each, fwd+bwd+Adam/ADMM + consensus/100)",
            "value": 1000.0 * steps / ms_b, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
@@ -316,6 +388,7 @@ def run_blocks4(args):
                       "tile": f"{tile[0]}x{tile[1]}"},
            "sequential_ms_per_step": ms_s / steps, "batched_speedup": ms_s / ms_b,
            "consensus_ms": c_ms, "consensus_calls": len(c_ms), "images_equal_per_block": same,
+           "kernel_ms_batched": kb, "kernel_ms_sequential": ks,
            "last_residuals": res}
     return out
 
@@ -381,6 +454,7 @@ def main():
     ap.add_argument("--height", type=int, default=1066)
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unfused", action="store_true", help="backward and optimiser as two calls (gradient in HBM)")
     ap.add_argument("--workload", choices=("train", "blocks4", "serve"), default="train",
                     help="train: single block at scale (+ serve leg); blocks4: batched K=4 blocks; serve: serving only")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the train workload")
@@ -436,9 +510,14 @@ def main():
                                f"{args.cams} ring views, one view per step, L1 + Adam/ADMM rho=1e-3",
                    "tile": f"{args.tile}x{args.tile}", "max_pairs": r["pairs_max"]},
         "stage_ms": {k: round(v, 5) for k, v in r["stage_ms"].items()},
-        "roofline": {"bound": "hbm", "kernel": "k_adam_admm", "achieved": round(r["adam_gbs"], 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["adam_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+        "kernel_ms": {k: round(v, 5) for k, v in r["kernel_ms"].items()},
+        "roofline": {"bound": "alu", "kernel": "k_render_bwd", "achieved": round(r["bwd_tflops"], 3),
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(r["bwd_tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "work": f"{BWD_FLOPS} flops x {r['kept']:.4g} (pixel, Gaussian) contributions per launch"},
+        "roofline_stream": {"bound": "hbm", "kernel": r["opt_kernel"], "achieved": round(r["opt_gbs"], 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["opt_gbs"] / HBM_PEAK_GBS, 4),
+                            "traffic": None, "bytes": int(r["opt_bytes"])},
         "cpu_baseline": cpu,
         "serve": srv,
     }

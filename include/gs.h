@@ -210,6 +210,13 @@ gs_status gs_render_fwd(const gs_frame *frame, const gs_raster_cfg *cfg, const v
 gs_status gs_render_fwd_f64(const gs_frame *frame, const gs_raster_cfg *cfg, const void *rec_dev,
                             const gs_bins *bins, void *rgb_dev, void *T_dev, uint32_t *n_contrib_dev,
                             gs_stream stream);
+/* gs_render_fwd (FP32) that also adds the number of (pixel, Gaussian)
+ * contributions of the frame (kept pairs of Eq. 2, each pixel up to its
+ * termination) to *kept_dev (device uint64; the caller zeroes it).  Same
+ * image; a measurement of the work the compositing passes do. */
+gs_status gs_render_fwd_stats(const gs_frame *frame, const gs_raster_cfg *cfg, const void *rec_dev,
+                              const gs_bins *bins, void *rgb_dev, void *T_dev, uint32_t *n_contrib_dev,
+                              uint64_t *kept_dev, gs_stream stream);
 
 /* Backward of the loss through compositing and projection to the raw
  * parameter planes.  GS_LOSS_L1: L = sum_jobs loss_weight * mean |C - target|
@@ -238,6 +245,33 @@ gs_status gs_render_bwd_f64(const gs_params *params, const gs_frame *frame, cons
  * all x->n Gaussians; all five gs_params must share n and sh_degree. */
 gs_status gs_adam_admm(gs_params *x, const gs_params *g, gs_params *m, gs_params *v, const gs_params *w,
                        const float *mask_dev, const gs_adam_cfg *cfg, gs_stream stream);
+
+/* Backward and x-update of one local step in one call: gs_render_bwd in
+ * FP32 followed by gs_adam_admm, with the gradient of each parameter plane
+ * handed from the projection backward to the optimiser in registers (it is
+ * never written to memory).  Same results, bit for bit, as gs_render_bwd
+ * into a gradient buffer followed by gs_adam_admm on it.  Requires jobs over
+ * disjoint Gaussian ranges (frame->jobs_disjoint; otherwise GS_E_UNSUPPORTED:
+ * use the two calls); Gaussians in no job take the update with a zero
+ * gradient.  x is read by the backward and updated in place; m, v, w, mask
+ * and acfg as in gs_adam_admm; the other arguments and the workspace as in
+ * gs_render_bwd. */
+gs_status gs_render_bwd_adam(gs_params *x, const gs_frame *frame, const gs_raster_cfg *cfg,
+                             const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,
+                             const void *rgb_dev, gs_loss_mode mode, const void *grad_in_dev,
+                             float *loss_out_dev, gs_params *m, gs_params *v, const gs_params *w,
+                             const float *mask_dev, const gs_adam_cfg *acfg, void *ws_dev, size_t ws_bytes,
+                             gs_stream stream);
+
+/* Per-kernel timing with HIP events (measurement tooling; off by default).
+ * gs_profile_set(names): comma-separated kernel names to time, "*" for all,
+ * NULL or "" for none; resets every total.  While a kernel is selected, each
+ * of its launches records a pair of events on its stream (a few microseconds
+ * of device time).  gs_profile_get(name, &total_ms, &launches): waits for the
+ * recorded launches of that kernel and returns their summed durations (0 and
+ * 0 for a kernel never launched). */
+gs_status gs_profile_set(const char *names);
+gs_status gs_profile_get(const char *name, double *total_ms, int64_t *launches);
 
 /* Consensus step (Eq. 8b-c, Alg. 2) over K blocks held in one parameter
  * store.  For each global id gid with local holders

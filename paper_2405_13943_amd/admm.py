@@ -94,9 +94,12 @@ class AdmmTrainer:
     """One view per block per step, all K blocks in one launch per stage."""
 
     def __init__(self, model: BlockModel, cams, targets, cfg: gs.GsRasterCfg, lr=DEFAULT_LR, rho=(1e-3,) * 5,
-                 intv=100, relax=1.0, beta1=0.9, beta2=0.999, eps=1e-8, capacity=None, mask=None):
+                 intv=100, relax=1.0, beta1=0.9, beta2=0.999, eps=1e-8, capacity=None, mask=None, fused=True):
         """cams[k]: list of cameras of block k; targets[k][v]: device tensor
-        [3*H*W] (or a callable (k, v) -> tensor) for block k, view v."""
+        [3*H*W] (or a callable (k, v) -> tensor) for block k, view v.
+        fused: backward and optimiser in one call (gs_render_bwd_adam, the
+        gradient never stored); else gs_render_bwd into a gradient buffer,
+        then gs_adam_admm."""
         self.model, self.cfg = model, cfg
         self.lr, self.rho, self.intv, self.relax = tuple(lr), tuple(rho), int(intv), float(relax)
         self.beta1, self.beta2, self.eps = beta1, beta2, eps
@@ -107,7 +110,8 @@ class AdmmTrainer:
         self.u = torch.zeros_like(x)
         # w = z - u with u = 0: the consensus target of every local copy
         self.w = x.clone()
-        self.g = torch.empty_like(x)
+        self.fused = fused
+        self.g = None
         self.t = 0
         self.cams = cams
         self.targets = targets
@@ -162,9 +166,15 @@ class AdmmTrainer:
         gs.render_fwd(f, self.cfg, buf)
         tgt = self.target_buffer(views) if target is None else target
         self.loss.zero_()
-        gs.render_bwd(x, f, self.cfg, buf, self.g, gs.LOSS_L1, tgt, self.loss)
-        gs.adam_admm(x, self.g, self.m, self.v, self.w, self.mask,
-                     gs.adam_cfg(self.lr, self.rho, self.t + 1, self.beta1, self.beta2, self.eps))
+        acfg = gs.adam_cfg(self.lr, self.rho, self.t + 1, self.beta1, self.beta2, self.eps)
+        if self.fused and f.jobs_disjoint:
+            gs.render_bwd_adam(x, f, self.cfg, buf, self.m, self.v, self.w, self.mask, acfg, gs.LOSS_L1, tgt,
+                               self.loss)
+        else:
+            if self.g is None:
+                self.g = torch.empty_like(x)
+            gs.render_bwd(x, f, self.cfg, buf, self.g, gs.LOSS_L1, tgt, self.loss)
+            gs.adam_admm(x, self.g, self.m, self.v, self.w, self.mask, acfg)
 
     def consensus(self):
         """z = mean of holders' copies; u += x - z; w = z - u (Eq. 8b-c)."""

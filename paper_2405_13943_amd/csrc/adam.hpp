@@ -1,0 +1,47 @@
+// Per-element Adam update with the scaled ADMM penalty (Eq. 8a, per-attribute
+// rho and learning rate of the supplementary Sec. C), shared by the streaming
+// optimiser kernel and the fused projection-backward + optimiser kernel so
+// that both produce the same bits.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "gs.h"
+
+namespace gs {
+
+// attribute group of plane a: 0 p (mean), 1 q (rotation), 2 s (scale), 3 f (SH), 4 o (opacity)
+__host__ __device__ constexpr int plane_group(int a) {
+    return a < 3 ? 0 : (a < 7 ? 1 : (a < 10 ? 2 : (a == 10 ? 4 : 3)));
+}
+
+struct AdamConsts {
+    float lr[5], rho[5];
+    float b1, b2, eps, bc1, bc2;
+};
+
+// bias corrections 1 - beta^t evaluated in double on the host, then rounded
+inline AdamConsts adam_consts(const gs_adam_cfg& cfg) {
+    AdamConsts c;
+    for (int k = 0; k < 5; k++) { c.lr[k] = cfg.lr[k]; c.rho[k] = cfg.rho[k]; }
+    c.b1 = cfg.beta1; c.b2 = cfg.beta2; c.eps = cfg.eps;
+    c.bc1 = float(1.0 - std::pow(double(cfg.beta1), double(cfg.step)));
+    c.bc2 = float(1.0 - std::pow(double(cfg.beta2), double(cfg.step)));
+    return c;
+}
+
+// g' = g + rho (x - w); m, v moments; x -= lr m^ / (sqrt(v^) + eps)
+__device__ inline float adam_one(float& x, float g, float& m, float& v, float w, float rho, float lr,
+                                 const AdamConsts& c) {
+    const float gp = g + rho * (x - w);
+    m = c.b1 * m + (1.0f - c.b1) * gp;
+    v = c.b2 * v + (1.0f - c.b2) * gp * gp;
+    const float mh = m / c.bc1;
+    const float vh = v / c.bc2;
+    x = x - lr * mh / (__builtin_sqrtf(vh) + c.eps);
+    return x;
+}
+
+}  // namespace gs

@@ -1,8 +1,14 @@
 // C ABI of libgs (declared in include/gs.h): argument validation, workspace
 // sizing and kernel launches.  No device memory is allocated here.
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
 
 #include "gs_internal.hpp"
 
@@ -74,14 +80,15 @@ gs_status project_impl(const gs_params* params, const gs_frame* frame, const gs_
 
 template <typename T>
 gs_status render_fwd_impl(const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec, const gs_bins* bins,
-                          void* rgb, void* Tf, uint32_t* nc, gs_stream stream) {
+                          void* rgb, void* Tf, uint32_t* nc, gs_stream stream, uint64_t* kept = nullptr) {
     gs_status st;
     if ((st = check_frame(frame, cfg)) != GS_OK) return st;
     if ((st = check_bins(bins, frame)) != GS_OK) return st;
     if (frame->n_pixels > 0 && (!rgb || !Tf || !nc)) return fail(GS_E_INVALID, "null image buffers");
     if (frame->n_records > 0 && !rec) return fail(GS_E_INVALID, "null record buffer");
     return check_hip(gs::launch_render_fwd<T>(*frame, *cfg, static_cast<const T*>(rec), *bins, static_cast<T*>(rgb),
-                                              static_cast<T*>(Tf), nc, (hipStream_t)stream),
+                                              static_cast<T*>(Tf), nc, reinterpret_cast<unsigned long long*>(kept),
+                                              (hipStream_t)stream),
                      "gs_render_fwd");
 }
 
@@ -213,6 +220,12 @@ gs_status gs_render_fwd(const gs_frame* frame, const gs_raster_cfg* cfg, const v
     return render_fwd_impl<float>(frame, cfg, rec, bins, rgb, T, nc, stream);
 }
 
+gs_status gs_render_fwd_stats(const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec, const gs_bins* bins,
+                              void* rgb, void* Tf, uint32_t* nc, uint64_t* kept, gs_stream stream) {
+    if (!kept) return fail(GS_E_INVALID, "null contribution counter");
+    return render_fwd_impl<float>(frame, cfg, rec, bins, rgb, Tf, nc, stream, kept);
+}
+
 gs_status gs_render_fwd_f64(const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec, const gs_bins* bins,
                             void* rgb, void* T, uint32_t* nc, gs_stream stream) {
     return render_fwd_impl<double>(frame, cfg, rec, bins, rgb, T, nc, stream);
@@ -234,11 +247,14 @@ gs_status gs_render_bwd_f64(const gs_params* params, const gs_frame* frame, cons
                                    stream);
 }
 
-gs_status gs_adam_admm(gs_params* x, const gs_params* g, gs_params* m, gs_params* v, const gs_params* w,
-                       const float* mask, const gs_adam_cfg* cfg, gs_stream stream) {
+namespace {
+
+// x, m, v (and w when given) are planes of one shape; g too when given
+gs_status check_adam(const gs_params* x, const gs_params* g, const gs_params* m, const gs_params* v,
+                     const gs_params* w, const float* mask, const gs_adam_cfg* cfg) {
     gs_status st;
     if ((st = check_params(x, "x")) != GS_OK) return st;
-    if ((st = check_params(g, "g")) != GS_OK) return st;
+    if (g && (st = check_params(g, "g")) != GS_OK) return st;
     if ((st = check_params(m, "m")) != GS_OK) return st;
     if ((st = check_params(v, "v")) != GS_OK) return st;
     if (w && (st = check_params(w, "w")) != GS_OK) return st;
@@ -251,7 +267,46 @@ gs_status gs_adam_admm(gs_params* x, const gs_params* g, gs_params* m, gs_params
     if (!(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) || !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) || !(cfg->eps >= 0.f))
         return fail(GS_E_INVALID, "adam betas/eps out of range");
     if (mask && !w) return fail(GS_E_INVALID, "mask given without a consensus target");
+    return GS_OK;
+}
+
+}  // namespace
+
+gs_status gs_adam_admm(gs_params* x, const gs_params* g, gs_params* m, gs_params* v, const gs_params* w,
+                       const float* mask, const gs_adam_cfg* cfg, gs_stream stream) {
+    gs_status st;
+    if (!g) return fail(GS_E_INVALID, "g: null gs_params");
+    if ((st = check_adam(x, g, m, v, w, mask, cfg)) != GS_OK) return st;
     return check_hip(gs::launch_adam_admm(*x, *g, *m, *v, w, mask, *cfg, (hipStream_t)stream), "gs_adam_admm");
+}
+
+gs_status gs_render_bwd_adam(gs_params* x, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
+                             const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
+                             const void* gin, float* loss, gs_params* m, gs_params* v, const gs_params* w,
+                             const float* mask, const gs_adam_cfg* acfg, void* ws, size_t ws_bytes,
+                             gs_stream stream) {
+    gs_status st;
+    if ((st = check_adam(x, nullptr, m, v, w, mask, acfg)) != GS_OK) return st;
+    if ((st = check_frame(frame, cfg)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if (!frame->jobs_disjoint)
+        return fail(GS_E_UNSUPPORTED, "jobs share Gaussians: call gs_render_bwd, then gs_adam_admm");
+    if (frame->g_max > x->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
+                                         (long long)frame->g_max, (long long)x->n);
+    if (mode != GS_LOSS_L1 && mode != GS_LOSS_EXTERNAL) return fail(GS_E_INVALID, "unknown loss mode");
+    if (frame->n_pixels > 0 && (!rgb || !gin)) return fail(GS_E_INVALID, "null image or gradient input");
+    if (frame->n_records > 0 && (!rec || !meta)) return fail(GS_E_INVALID, "null record buffers");
+    if (!ws || ws_bytes < bwd_ws(bins->capacity, 0))
+        return fail(GS_E_CAPACITY, "backward workspace too small (%zu < %zu)", ws_bytes, bwd_ws(bins->capacity, 0));
+    float* pg = static_cast<float*>(ws);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = gs::launch_render_bwd<float>(*frame, *cfg, static_cast<const float*>(rec), meta, *bins,
+                                                static_cast<const float*>(rgb), mode, static_cast<const float*>(gin),
+                                                loss, pg, s);
+    if (e != hipSuccess) return check_hip(e, "gs_render_bwd_adam (composite)");
+    return check_hip(gs::launch_project_bwd_adam(*x, *frame, *cfg, meta, bins->pair_off, bins->capacity, pg, *m, *v, w,
+                                                 mask, *acfg, s),
+                     "gs_render_bwd_adam (projection + optimiser)");
 }
 
 gs_status gs_consensus(const gs_params* x, gs_params* u, gs_params* w, gs_params* z, const int64_t* hptr,
@@ -271,3 +326,110 @@ gs_status gs_consensus(const gs_params* x, gs_params* u, gs_params* w, gs_params
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+
+namespace {
+
+struct ProfState {
+    std::mutex mu;
+    std::atomic<bool> on{false};
+    bool all = false;
+    std::set<std::string> names;
+    struct Entry {
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+        double ms = 0;
+        int64_t launches = 0;
+    };
+    std::map<std::string, Entry> entries;
+    std::vector<hipEvent_t> pool;
+};
+
+ProfState& prof() {
+    static ProfState* p = new ProfState();   // lives until the process ends
+    return *p;
+}
+
+// waits for a recorded pair and adds its duration; returns the events to the pool
+void resolve(ProfState& P, ProfState::Entry& e) {
+    for (auto& ev : e.pending) {
+        float t = 0.f;
+        if (ev.second && hipEventSynchronize(ev.second) == hipSuccess &&
+            hipEventElapsedTime(&t, ev.first, ev.second) == hipSuccess)
+            e.ms += t;
+        e.launches += 1;
+        P.pool.push_back(ev.first);
+        if (ev.second) P.pool.push_back(ev.second);
+    }
+    e.pending.clear();
+}
+
+}  // namespace
+
+namespace gs {
+
+bool profile_wanted(const char* name) {
+    ProfState& P = prof();
+    if (!P.on.load(std::memory_order_relaxed)) return false;
+    std::lock_guard<std::mutex> lk(P.mu);
+    return P.all || P.names.count(name) != 0;
+}
+
+hipEvent_t profile_event() {
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (!P.pool.empty()) {
+        hipEvent_t e = P.pool.back();
+        P.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void profile_record(const char* name, hipEvent_t begin, hipEvent_t end) {
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.entries[name].pending.emplace_back(begin, end);
+}
+
+}  // namespace gs
+
+gs_status gs_profile_set(const char* names) {
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    for (auto& kv : P.entries) resolve(P, kv.second);
+    P.entries.clear();
+    P.names.clear();
+    P.all = false;
+    std::string s = names ? names : "";
+    size_t a = 0;
+    while (a <= s.size() && !s.empty()) {
+        size_t b = s.find(',', a);
+        if (b == std::string::npos) b = s.size();
+        std::string n = s.substr(a, b - a);
+        if (n == "*") P.all = true;
+        else if (!n.empty()) P.names.insert(n);
+        a = b + 1;
+    }
+    P.on.store(P.all || !P.names.empty(), std::memory_order_relaxed);
+    g_err[0] = 0;
+    return GS_OK;
+}
+
+gs_status gs_profile_get(const char* name, double* total_ms, int64_t* launches) {
+    if (!name || !total_ms || !launches) return fail(GS_E_INVALID, "gs_profile_get: null argument");
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto it = P.entries.find(name);
+    if (it == P.entries.end()) {
+        *total_ms = 0;
+        *launches = 0;
+        return GS_OK;
+    }
+    resolve(P, it->second);
+    *total_ms = it->second.ms;
+    *launches = it->second.launches;
+    return GS_OK;
+}

@@ -375,9 +375,9 @@ static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
     const int G = grid_for(n_max, kRsTile * 4);
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     for (int shift = 0; shift < bits; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, w.hist, G);
-        hipLaunchKernelGGL(k_rs_colscan, dim3(256), dim3(kRsBlock), 0, s, w.hist, G, w.coltot);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, w.hist, G,
+        GS_LAUNCH("k_rs_hist", k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, w.hist, G);
+        GS_LAUNCH("k_rs_colscan", k_rs_colscan, dim3(256), dim3(kRsBlock), 0, s, w.hist, G, w.coltot);
+        GS_LAUNCH("k_rs_scatter", k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, w.hist, G,
                            w.coltot);
         uint32_t* t;
         t = ki; ki = ko; ko = t;
@@ -395,19 +395,19 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     const uint4* meta = reinterpret_cast<const uint4*>(meta_u32);
     const uint32_t nrec = uint32_t(f.n_records);
     // counts restart every call; the status bits are sticky until the caller clears them
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, bins.counters, 0u, int64_t(GS_CTR_STATUS));
+    GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, bins.counters, 0u, int64_t(GS_CTR_STATUS));
     const int64_t nr2 = int64_t(f.n_tiles) * 2;
-    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(std::min<int64_t>((nr2 + 255) / 256, 2048))), dim3(256), 0, s,
+    GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(std::min<int64_t>((nr2 + 255) / 256, 2048))), dim3(256), 0, s,
                        bins.ranges, 0u, nr2);
     if (nrec == 0) return hipGetLastError();
 
     // 1. compact visible records as (depth bits, record)
     const int Gs = grid_for(nrec, kScanBlock * 8);
     VisibleFlag vf{meta, w.dkey[0], w.dval[0]};
-    hipLaunchKernelGGL(k_scan_reduce<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
-    hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_VISIBLE,
+    GS_LAUNCH("k_scan_reduce", k_scan_reduce<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
+    GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_VISIBLE,
                        uint64_t(0));
-    hipLaunchKernelGGL(k_scan_apply<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
+    GS_LAUNCH("k_scan_apply", k_scan_apply<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
 
     // 2. stable sort by depth bits (32 bits, 4 passes: the result is in buffer 0)
     uint32_t* dk_final;
@@ -418,10 +418,10 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
 
     // 3. first pair of each visible record, in depth order; total pairs
     PairCount pc{meta, sorted_rec, bins.pair_off, w.poff};
-    hipLaunchKernelGGL(k_scan_reduce<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
-    hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_PAIRS,
+    GS_LAUNCH("k_scan_reduce", k_scan_reduce<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
+    GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_PAIRS,
                        bins.capacity);
-    hipLaunchKernelGGL(k_scan_apply<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
+    GS_LAUNCH("k_scan_apply", k_scan_apply<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
 
     // 4. emit (tile, record) pairs in depth order, then stable sort by tile id
     int bits = 0;
@@ -429,7 +429,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     const int passes = (bits + 7) / 8;
     uint32_t* emit_val = (passes & 1) ? w.tval : bins.vals;
     uint32_t* other_val = (passes & 1) ? bins.vals : w.tval;
-    hipLaunchKernelGGL(k_emit, dim3(unsigned(grid_for(bins.capacity, kEmitChunk))), dim3(256), 0, s, meta, sorted_rec,
+    GS_LAUNCH("k_emit", k_emit, dim3(unsigned(grid_for(bins.capacity, kEmitChunk))), dim3(256), 0, s, meta, sorted_rec,
                        w.poff, bins.counters, f, bins.capacity, w.tkey[0], emit_val);
     const uint32_t pmax = uint32_t(std::min<uint64_t>(bins.capacity, 0xffffffffull));
     uint32_t* tk_final = w.tkey[0];
@@ -440,7 +440,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     }
 
     // 5. per-tile [start, end)
-    hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity,
+    GS_LAUNCH("k_ranges", k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity,
                        reinterpret_cast<uint2*>(bins.ranges));
     return hipGetLastError();
 }

@@ -22,6 +22,8 @@ template <> struct Num<float> {
     __device__ static inline float sqrt(float x) { return __builtin_sqrtf(x); }
     __device__ static inline float rsqrt(float x) { return 1.0f / __builtin_sqrtf(x); }
     __device__ static inline float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+    __device__ static inline float max(float a, float b) { return __builtin_fmaxf(a, b); }
+    __device__ static inline float min(float a, float b) { return __builtin_fminf(a, b); }
 };
 template <> struct Num<double> {
     __device__ static inline double exp2(double x) { return ::exp2(x); }
@@ -31,6 +33,8 @@ template <> struct Num<double> {
     __device__ static inline double sqrt(double x) { return ::sqrt(x); }
     __device__ static inline double rsqrt(double x) { return 1.0 / ::sqrt(x); }
     __device__ static inline double fma(double a, double b, double c) { return ::fma(a, b, c); }
+    __device__ static inline double max(double a, double b) { return ::fmax(a, b); }
+    __device__ static inline double min(double a, double b) { return ::fmin(a, b); }
 };
 
 // ln 2 and log2 e as the scalar type
@@ -81,6 +85,12 @@ __device__ inline float dpp_move(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
 }
 
+// DPP move over all rows and banks in which a lane without a source reads 0
+template <int CTRL>
+__device__ inline float dpp_move_bc(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
 __device__ inline float wave_sum(float v) {
     v += dpp_move<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
     v += dpp_move<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
@@ -89,6 +99,22 @@ __device__ inline float wave_sum(float v) {
     v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
     v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Sum over each row of 16 lanes, complete in the row's last lane (15):
+// quad sums, then shifts right by 4 and 8 lanes within the row (lanes with
+// no source add zero), so every step is one fused DPP add.
+__device__ inline float row_sum_last(float v) {
+    v += dpp_move_bc<0xb1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move_bc<0x4e>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move_bc<0x114>(v);   // row_shr:4
+    v += dpp_move_bc<0x118>(v);   // row_shr:8
+    return v;
+}
+
+__device__ inline double row_sum_last(double v) {
+    for (int off = 8; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
 }
 
 // Sum over each row of 16 lanes, returned to every lane of the row.

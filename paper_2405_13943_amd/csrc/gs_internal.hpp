@@ -9,6 +9,34 @@
 
 namespace gs {
 
+// Optional per-kernel timing (gs_profile_set): when a kernel's name is
+// selected, HIP events are recorded on its stream around each launch and
+// resolved by gs_profile_get.  One relaxed flag test per launch otherwise.
+bool profile_wanted(const char* name);
+hipEvent_t profile_event();
+void profile_record(const char* name, hipEvent_t begin, hipEvent_t end);
+
+struct KernelTimer {
+    const char* name;
+    hipStream_t stream;
+    hipEvent_t begin = nullptr;
+    KernelTimer(const char* n, hipStream_t s) : name(n), stream(s) {
+        if (profile_wanted(n) && (begin = profile_event()) != nullptr) (void)hipEventRecord(begin, s);
+    }
+    ~KernelTimer() {
+        if (!begin) return;
+        hipEvent_t end = profile_event();
+        if (end) (void)hipEventRecord(end, stream);
+        profile_record(name, begin, end);
+    }
+};
+
+#define GS_LAUNCH(NAME, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)             \
+    do {                                                                     \
+        ::gs::KernelTimer gs_kernel_timer_(NAME, STREAM);                    \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__); \
+    } while (0)
+
 // project.hip
 template <typename T>
 hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, T* rec,
@@ -18,6 +46,12 @@ hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_ra
                               const uint32_t* meta, const uint32_t* pair_off, uint64_t capacity, const T* pg,
                               gs_params& grad, hipStream_t s);
 
+// fused projection backward + Adam/ADMM (FP32, jobs over disjoint ranges)
+hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta,
+                                   const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
+                                   gs_params& v, const gs_params* w, const float* mask, const gs_adam_cfg& acfg,
+                                   hipStream_t s);
+
 // binning.hip
 size_t bin_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles);
 hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta, const gs_bins& bins,
@@ -26,7 +60,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
 // render.hip
 template <typename T>
 hipError_t launch_render_fwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& bins,
-                             T* rgb, T* Tfin, uint32_t* ncontrib, hipStream_t s);
+                             T* rgb, T* Tfin, uint32_t* ncontrib, unsigned long long* kept, hipStream_t s);
 template <typename T>
 hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
                              const gs_bins& bins, const T* rgb, gs_loss_mode mode, const T* grad_in, T* loss_out,

@@ -5,33 +5,13 @@
 //     copies, u += x - z, w = z - u, with optional over-relaxation (Sec. 3.3).
 // Both are pure HBM streams over the SoA planes: 16-byte vector accesses,
 // one pass, no re-reads.
+#include "adam.hpp"
 #include "gs_device.hpp"
 #include "gs_internal.hpp"
 
 #include <cmath>
 
 namespace gs {
-
-// attribute group of plane a: 0 p (mean), 1 q (rotation), 2 s (scale), 3 f (SH), 4 o (opacity)
-__host__ __device__ inline int plane_group(int a) {
-    return a < 3 ? 0 : (a < 7 ? 1 : (a < 10 ? 2 : (a == 10 ? 4 : 3)));
-}
-
-struct AdamConsts {
-    float lr[5], rho[5];
-    float b1, b2, eps, bc1, bc2;
-};
-
-__device__ inline float adam_one(float& x, float g, float& m, float& v, float w, float rho, float lr,
-                                 const AdamConsts& c) {
-    const float gp = g + rho * (x - w);
-    m = c.b1 * m + (1.0f - c.b1) * gp;
-    v = c.b2 * v + (1.0f - c.b2) * gp * gp;
-    const float mh = m / c.bc1;
-    const float vh = v / c.bc2;
-    x = x - lr * mh / (__builtin_sqrtf(vh) + c.eps);
-    return x;
-}
 
 // grid: y = plane, x covers the plane in 4-wide vectors (tail handled by the last vector)
 template <bool PEN, bool MASK, bool VEC>
@@ -81,9 +61,9 @@ static void adam_launch(bool vec, dim3 grid, hipStream_t s, float* x, const floa
                         const float* w, const float* mask, int64_t n, int64_t sx, int64_t sg, int64_t sm, int64_t sv,
                         int64_t sw, const AdamConsts& c) {
     if (vec)
-        hipLaunchKernelGGL((k_adam_admm<PEN, MASK, true>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg, sm, sv, sw, c);
+        GS_LAUNCH("k_adam_admm", (k_adam_admm<PEN, MASK, true>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg, sm, sv, sw, c);
     else
-        hipLaunchKernelGGL((k_adam_admm<PEN, MASK, false>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg, sm, sv, sw, c);
+        GS_LAUNCH("k_adam_admm", (k_adam_admm<PEN, MASK, false>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg, sm, sv, sw, c);
 }
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -93,11 +73,7 @@ hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_p
     const int64_t n = x.n;
     if (n == 0) return hipSuccess;
     const int A = 11 + 3 * (x.sh_degree + 1) * (x.sh_degree + 1);
-    AdamConsts c;
-    for (int k = 0; k < 5; k++) { c.lr[k] = cfg.lr[k]; c.rho[k] = cfg.rho[k]; }
-    c.b1 = cfg.beta1; c.b2 = cfg.beta2; c.eps = cfg.eps;
-    c.bc1 = float(1.0 - std::pow(double(cfg.beta1), double(cfg.step)));
-    c.bc2 = float(1.0 - std::pow(double(cfg.beta2), double(cfg.step)));
+    const AdamConsts c = adam_consts(cfg);
     bool vec = aligned16(x.data) && aligned16(g.data) && aligned16(m.data) && aligned16(v.data) &&
                x.stride % 4 == 0 && g.stride % 4 == 0 && m.stride % 4 == 0 && v.stride % 4 == 0;
     if (w) vec = vec && aligned16(w->data) && w->stride % 4 == 0;
@@ -169,7 +145,7 @@ hipError_t launch_consensus(const gs_params& x, gs_params& u, gs_params& w, gs_p
     const int64_t G = z.n;
     if (G == 0) return hipSuccess;
     const int A = 11 + 3 * (x.sh_degree + 1) * (x.sh_degree + 1);
-    hipLaunchKernelGGL(k_consensus, dim3(unsigned((G + 255) / 256)), dim3(256), 0, s, static_cast<const float*>(x.data),
+    GS_LAUNCH("k_consensus", k_consensus, dim3(unsigned((G + 255) / 256)), dim3(256), 0, s, static_cast<const float*>(x.data),
                        static_cast<float*>(u.data), static_cast<float*>(w.data), static_cast<float*>(z.data), hptr, hidx,
                        G, A, x.stride, u.stride, w.stride, z.stride, relax, resid);
     return hipGetLastError();

@@ -6,6 +6,7 @@
 // Paper: Sec. 3.1 (Eq. 1: Gaussian with Sigma = R S S^T R^T; Eq. 2 and
 // alpha = o X^proj(p); attributes x = {u, q, s, f, o}).  X^proj is read as the
 // EWA local-affine projection (Sigma' = J W Sigma W^T J^T + dilation I).
+#include "adam.hpp"
 #include "gs_device.hpp"
 #include "gs_internal.hpp"
 
@@ -335,10 +336,16 @@ __device__ inline void record_pairs(uint32_t ntiles, uint32_t off, uint64_t capa
 }
 
 // Chain rule of one visible record of Gaussian g seen by `camera`; emit(a, v)
-// receives the gradient v of parameter plane a.
+// receives the gradient v of parameter plane a.  Plane a of Gaussian g is
+// read (if at all) before emit(a, .) is called and never after, so emit may
+// update the parameter in place.
+// With sh_basis_out / sh_dc_out, also hands out the SH basis values Y[k] and
+// the clamped colour gradient dc[ch], whose products are the SH-plane
+// gradients.
 template <typename T, int D, typename Emit>
-__device__ inline void record_chain(const T* __restrict__ P, int64_t stride, int64_t g, const gs_camera& camera,
-                                    const gs_raster_cfg& cfg, uint32_t meta_y, const T* d, Emit emit) {
+__device__ inline void record_chain(const T* P, int64_t stride, int64_t g, const gs_camera& camera,
+                                    const gs_raster_cfg& cfg, uint32_t meta_y, const T* d, Emit emit,
+                                    T* sh_basis_out = nullptr, T* sh_dc_out = nullptr) {
     constexpr int NK = (D + 1) * (D + 1);
     const uint4 m = make_uint4(0u, meta_y, 0u, 0u);
     Cam<T> cam;
@@ -367,14 +374,20 @@ __device__ inline void record_chain(const T* __restrict__ P, int64_t stride, int
     T dc[3];
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) dc[ch] = (clamp >> ch) & 1u ? T(0) : d[6 + ch];
+    if (sh_basis_out) {
+#pragma unroll
+        for (int k = 0; k < NK; k++) sh_basis_out[k] = Y[k];
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) sh_dc_out[ch] = dc[ch];
+    }
     T wk[16];
 #pragma unroll
     for (int k = 0; k < NK; k++) {
         T s = 0;
 #pragma unroll
         for (int ch = 0; ch < 3; ch++) {
-            emit(11 + 3 * k + ch, Y[k] * dc[ch]);
             s += plane(P, stride, 11 + 3 * k + ch, g) * dc[ch];
+            emit(11 + 3 * k + ch, Y[k] * dc[ch]);
         }
         wk[k] = s;
     }
@@ -532,6 +545,155 @@ __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P
     }
 }
 
+// Fused projection backward + Adam/ADMM for jobs over disjoint Gaussian
+// ranges (one record per Gaussian).  A block of kFusedBlock records works in
+// two phases.  (1) Each thread runs the chain rule of its record and leaves in
+// LDS the 11 geometry gradients, the SH basis values Y[k] and the clamped
+// colour gradient dc[ch] (the SH-plane gradient is the product Y[k] dc[ch],
+// formed exactly as the chain rule emits it); a culled record leaves zeros.
+// (2) The block streams the optimiser over all planes of its Gaussians: when
+// they are contiguous and 16-byte aligned, as items of (plane, 4 Gaussians)
+// with 16-byte accesses, else one Gaussian per thread.  The gradient never
+// reaches HBM and the parameters read by the chain are still in cache for the
+// update.  Same arithmetic as k_project_bwd_rec followed by k_adam_admm.
+constexpr int kFusedBlock = 128;
+
+// gradient of plane a of the block's Gaussian i from the phase-1 LDS arrays
+// (geo [11][kFusedBlock], Y [NK][kFusedBlock], dc [3][kFusedBlock])
+__device__ inline float staged_grad(const float* geo, const float* Y, const float* dc, int a, int i) {
+    return a < 11 ? geo[a * kFusedBlock + i]
+                  : Y[((a - 11) / 3) * kFusedBlock + i] * dc[((a - 11) % 3) * kFusedBlock + i];
+}
+
+// phase 2 over contiguous, 16-byte aligned Gaussians g0 .. g0 + kFusedBlock - 1:
+// items (plane, 4 Gaussians), 16-byte accesses
+template <int A, bool PEN, bool MASK>
+__device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* __restrict__ M, int64_t sm,
+                                      float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
+                                      const float* __restrict__ mask, int64_t g0, const float* geo, const float* Y,
+                                      const float* dc, const AdamConsts& c) {
+    constexpr int kCols = kFusedBlock / 4;
+    const int t = threadIdx.x;
+    const int col = t % kCols;
+    const int i = 4 * col;
+    const int64_t gv = g0 + i;
+    float4 kv = make_float4(1.f, 1.f, 1.f, 1.f);
+    if (MASK) kv = *reinterpret_cast<const float4*>(mask + gv);
+    for (int a = t / kCols; a < A; a += kFusedBlock / kCols) {
+        const int grp = plane_group(a);
+        const float lr = c.lr[grp], rho = c.rho[grp];
+        float4 xv = *reinterpret_cast<const float4*>(X + a * sx + gv);
+        float4 mv = *reinterpret_cast<const float4*>(M + a * sm + gv);
+        float4 vv = *reinterpret_cast<const float4*>(V + a * sv + gv);
+        float4 wv = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (PEN) wv = *reinterpret_cast<const float4*>(Wp + a * sw + gv);
+        adam_one(xv.x, staged_grad(geo, Y, dc, a, i + 0), mv.x, vv.x, wv.x, PEN ? rho * kv.x : 0.f, lr, c);
+        adam_one(xv.y, staged_grad(geo, Y, dc, a, i + 1), mv.y, vv.y, wv.y, PEN ? rho * kv.y : 0.f, lr, c);
+        adam_one(xv.z, staged_grad(geo, Y, dc, a, i + 2), mv.z, vv.z, wv.z, PEN ? rho * kv.z : 0.f, lr, c);
+        adam_one(xv.w, staged_grad(geo, Y, dc, a, i + 3), mv.w, vv.w, wv.w, PEN ? rho * kv.w : 0.f, lr, c);
+        *reinterpret_cast<float4*>(X + a * sx + gv) = xv;
+        *reinterpret_cast<float4*>(M + a * sm + gv) = mv;
+        *reinterpret_cast<float4*>(V + a * sv + gv) = vv;
+    }
+}
+
+// phase 2 for one Gaussian g (the block's i-th record), all planes
+template <int A, bool PEN, bool MASK>
+__device__ inline void adam_block_one(float* __restrict__ X, int64_t sx, float* __restrict__ M, int64_t sm,
+                                      float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
+                                      const float* __restrict__ mask, int64_t g, int i, const float* geo,
+                                      const float* Y, const float* dc, const AdamConsts& c) {
+    const float k = MASK ? mask[g] : 1.f;
+    for (int a = 0; a < A; a++) {
+        const int grp = plane_group(a);
+        float xv = X[a * sx + g], mv = M[a * sm + g], vv = V[a * sv + g];
+        const float wv = PEN ? Wp[a * sw + g] : 0.f;
+        adam_one(xv, staged_grad(geo, Y, dc, a, i), mv, vv, wv, PEN ? c.rho[grp] * k : 0.f, c.lr[grp], c);
+        X[a * sx + g] = xv;
+        M[a * sm + g] = mv;
+        V[a * sv + g] = vv;
+    }
+}
+
+template <int D, bool PEN, bool MASK, bool VEC>
+__global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
+    float* X, int64_t sx, gs_frame frame, gs_raster_cfg cfg, const uint4* __restrict__ meta,
+    const uint32_t* __restrict__ pair_off, uint64_t capacity, const float* __restrict__ pg, float* __restrict__ M,
+    int64_t sm, float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
+    const float* __restrict__ mask, AdamConsts c) {
+    constexpr int NK = (D + 1) * (D + 1);
+    constexpr int A = 11 + 3 * NK;
+    __shared__ float s_geo[11][kFusedBlock];
+    __shared__ float s_Y[NK][kFusedBlock];
+    __shared__ float s_dc[3][kFusedBlock];
+    const int t = threadIdx.x;
+    const int64_t r0 = int64_t(blockIdx.x) * kFusedBlock;
+    const int64_t r = r0 + t;
+    const bool active = r < frame.n_records;   // no early return before the wave-wide sums and the barrier
+    const int j = job_of_record(frame.jobs, frame.n_jobs, active ? r : 0);
+    const gs_job job = frame.jobs[j];
+    const int64_t g = job.g0 + (r - job.rec0);
+    const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t ntiles = meta_tiles(m.y);
+    uint64_t p0, np;
+    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, p0, np);
+    float d[9];
+    record_pair_sum(pg, p0, np, d);
+
+    // phase 1: chain rule into LDS
+    float Y[NK], dc[3];
+#pragma unroll
+    for (int a = 0; a < 11; a++) s_geo[a][t] = 0.f;
+#pragma unroll
+    for (int q = 0; q < NK; q++) Y[q] = 0.f;
+    dc[0] = dc[1] = dc[2] = 0.f;
+    if (active && ntiles != 0)
+        record_chain<float, D>(X, sx, g, frame.cams[job.cam], cfg, m.y, d,
+                               [&](int a, float v) {
+                                   if (a < 11) s_geo[a][t] = v;
+                               },
+                               Y, dc);
+#pragma unroll
+    for (int q = 0; q < NK; q++) s_Y[q][t] = Y[q];
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) s_dc[ch][t] = dc[ch];
+    // the block's Gaussians are contiguous when its records all lie in one job
+    const int j0 = job_of_record(frame.jobs, frame.n_jobs, r0);
+    const int64_t g0 = frame.jobs[j0].g0 + (r0 - frame.jobs[j0].rec0);
+    const bool contiguous = __syncthreads_and(active && j == j0) != 0;
+
+    // phase 2: optimiser over the planes
+    if (VEC && contiguous && (g0 & 3) == 0)
+        adam_block_vec<A, PEN, MASK>(X, sx, M, sm, V, sv, Wp, sw, mask, g0, &s_geo[0][0], &s_Y[0][0], &s_dc[0][0], c);
+    else if (active)
+        adam_block_one<A, PEN, MASK>(X, sx, M, sm, V, sv, Wp, sw, mask, g, t, &s_geo[0][0], &s_Y[0][0], &s_dc[0][0],
+                                     c);
+}
+
+// Adam/ADMM with a zero gradient for Gaussians outside every job (disjoint
+// jobs that do not cover [0, n)); the fused kernel updates all the others.
+template <bool PEN, bool MASK>
+__global__ __launch_bounds__(256) void k_adam_uncovered(int64_t n, gs_frame frame, int A, float* __restrict__ X,
+                                                        int64_t sx, float* __restrict__ M, int64_t sm,
+                                                        float* __restrict__ V, int64_t sv,
+                                                        const float* __restrict__ Wp, int64_t sw,
+                                                        const float* __restrict__ mask, AdamConsts c) {
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    for (int j = 0; j < frame.n_jobs; j++)
+        if (g >= frame.jobs[j].g0 && g < frame.jobs[j].g1) return;
+    const float k = MASK ? mask[g] : 1.f;
+    for (int a = 0; a < A; a++) {
+        const int grp = plane_group(a);
+        float xv = X[a * sx + g], mv = M[a * sm + g], vv = V[a * sv + g];
+        const float wv = PEN ? Wp[a * sw + g] : 0.f;
+        adam_one(xv, 0.f, mv, vv, wv, PEN ? c.rho[grp] * k : 0.f, c.lr[grp], c);
+        X[a * sx + g] = xv;
+        M[a * sm + g] = mv;
+        V[a * sv + g] = vv;
+    }
+}
+
 // zeros for Gaussians outside every job (disjoint jobs that do not cover [0, n))
 template <typename T>
 __global__ __launch_bounds__(256) void k_zero_uncovered(int64_t n, gs_frame frame, int A, T* __restrict__ grad,
@@ -554,10 +716,10 @@ hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster
     const T* P = static_cast<const T*>(p.data);
     uint4* M = reinterpret_cast<uint4*>(meta);
     switch (p.sh_degree) {
-        case 0: hipLaunchKernelGGL((k_project<T, 0>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
-        case 1: hipLaunchKernelGGL((k_project<T, 1>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
-        case 2: hipLaunchKernelGGL((k_project<T, 2>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
-        default: hipLaunchKernelGGL((k_project<T, 3>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        case 0: GS_LAUNCH("k_project", (k_project<T, 0>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        case 1: GS_LAUNCH("k_project", (k_project<T, 1>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        case 2: GS_LAUNCH("k_project", (k_project<T, 2>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        default: GS_LAUNCH("k_project", (k_project<T, 3>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
     }
     return hipGetLastError();
 }
@@ -571,13 +733,13 @@ static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs
     if (f.jobs_disjoint) {
         const bool covers = f.n_records == p.n && f.g_max == p.n;
         if (!covers)
-            hipLaunchKernelGGL((k_zero_uncovered<T>), dim3(unsigned((p.n + 255) / 256)), dim3(256), 0, s, p.n, f,
+            GS_LAUNCH("k_zero_uncovered", (k_zero_uncovered<T>), dim3(unsigned((p.n + 255) / 256)), dim3(256), 0, s, p.n, f,
                                11 + 3 * (D + 1) * (D + 1), Gd, grad.stride);
         if (f.n_records > 0)
-            hipLaunchKernelGGL((k_project_bwd_rec<T, D>), dim3(unsigned((f.n_records + 127) / 128)), dim3(128), 0, s,
+            GS_LAUNCH("k_project_bwd_rec", (k_project_bwd_rec<T, D>), dim3(unsigned((f.n_records + 127) / 128)), dim3(128), 0, s,
                                P, p.stride, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride);
     } else {
-        hipLaunchKernelGGL((k_project_bwd_acc<T, D>), dim3(unsigned((p.n + 127) / 128)), dim3(128), 0, s, P,
+        GS_LAUNCH("k_project_bwd_acc", (k_project_bwd_acc<T, D>), dim3(unsigned((p.n + 127) / 128)), dim3(128), 0, s, P,
                            p.stride, p.n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride);
     }
 }
@@ -593,6 +755,60 @@ hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_ra
         case 1: project_bwd_dispatch<T, 1>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
         case 2: project_bwd_dispatch<T, 2>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
         default: project_bwd_dispatch<T, 3>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
+    }
+    return hipGetLastError();
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+template <int D, bool PEN, bool MASK>
+static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
+                                    const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
+                                    gs_params& v, const gs_params* w, const float* mask, const AdamConsts& c,
+                                    hipStream_t s) {
+    float* X = static_cast<float*>(x.data);
+    float* Mo = static_cast<float*>(m.data);
+    float* Vo = static_cast<float*>(v.data);
+    const float* Wd = w ? static_cast<const float*>(w->data) : nullptr;
+    const int64_t sw = w ? w->stride : 0;
+    const bool covers = f.n_records == x.n && f.g_max == x.n;
+    if (!covers)
+        GS_LAUNCH("k_adam_uncovered", (k_adam_uncovered<PEN, MASK>), dim3(unsigned((x.n + 255) / 256)), dim3(256), 0, s, x.n, f,
+                           11 + 3 * (D + 1) * (D + 1), X, x.stride, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+    const bool vec = aligned16(X) && aligned16(Mo) && aligned16(Vo) && (!Wd || aligned16(Wd)) &&
+                     (!mask || aligned16(mask)) && x.stride % 4 == 0 && m.stride % 4 == 0 && v.stride % 4 == 0 &&
+                     sw % 4 == 0;
+    const dim3 grid(unsigned((f.n_records + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
+    if (f.n_records > 0 && vec)
+        GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, true>), grid, block, 0, s, X, x.stride, f,
+                  cfg, M, pair_off, capacity, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+    else if (f.n_records > 0)
+        GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, false>), grid, block, 0, s, X, x.stride,
+                  f, cfg, M, pair_off, capacity, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+}
+
+template <int D>
+static void project_bwd_adam_pen(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
+                                 const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
+                                 gs_params& v, const gs_params* w, const float* mask, const AdamConsts& c,
+                                 hipStream_t s) {
+    if (w && mask) project_bwd_adam_launch<D, true, true>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s);
+    else if (w) project_bwd_adam_launch<D, true, false>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s);
+    else project_bwd_adam_launch<D, false, false>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s);
+}
+
+hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta,
+                                   const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
+                                   gs_params& v, const gs_params* w, const float* mask, const gs_adam_cfg& acfg,
+                                   hipStream_t s) {
+    if (x.n == 0) return hipSuccess;
+    const uint4* M = reinterpret_cast<const uint4*>(meta);
+    const AdamConsts c = adam_consts(acfg);
+    switch (x.sh_degree) {
+        case 0: project_bwd_adam_pen<0>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
+        case 1: project_bwd_adam_pen<1>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
+        case 2: project_bwd_adam_pen<2>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
+        default: project_bwd_adam_pen<3>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
     }
     return hipGetLastError();
 }

@@ -7,9 +7,11 @@
 // staging a batch of records at a time in a wave-private LDS slice (one record
 // per lane, read back as broadcasts): no workgroup barrier, and each wave stops
 // as soon as all its pixels have terminated.  While staging, each lane also
-// computes which quadrants its record's conservative pixel box touches, so
-// the compositing loop skips (uniformly, per quadrant) every Gaussian that
-// cannot reach alpha_min there.  Past that test the per-pixel work is
+// computes which quadrants its record can reach (pixel box and an exact,
+// conservative bound of alpha over the quadrant), only records that reach
+// one are staged (compacted with a ballot prefix), and the compositing loop
+// skips (uniformly, per quadrant) every Gaussian that cannot reach alpha_min
+// there.  Past that test the per-pixel work is
 // predicated (selects, not branches): a pixel that does not keep a Gaussian
 // adds an exact zero and keeps its transmittance, so divergence costs no
 // exec-mask bookkeeping.  Workgroups are remapped so that each XCD renders
@@ -68,22 +70,57 @@ __device__ inline Rec<T> lds_rec(const T* s) {
     return g;
 }
 
-// Stage record r for this lane: copy it to LDS and return the mask of the
-// tile's quadrants that its conservative pixel box [mean -+ half-extent]
-// reaches (pixel p samples p + 1/2, as in the projection's rectangle).
-template <typename T, int QX, int QY>
-__device__ inline uint32_t stage_rec(const T* __restrict__ rec, uint32_t r, T* dst, int px0, int py0) {
+// Load record r into registers (one record per lane while staging).
+template <typename T>
+__device__ inline void load_rec(const T* __restrict__ rec, uint32_t r, T (&w)[GS_REC_WORDS]) {
     const T* src = rec + int64_t(r) * GS_REC_WORDS;
 #pragma unroll
-    for (int i = 0; i < GS_REC_WORDS; i++) dst[i] = src[i];
-    const T x0 = dst[R_MX] - dst[R_HX], x1 = dst[R_MX] + dst[R_HX];
-    const T y0 = dst[R_MY] - dst[R_HY], y1 = dst[R_MY] + dst[R_HY];
+    for (int i = 0; i < GS_REC_WORDS; i++) w[i] = src[i];
+}
+
+template <typename T>
+__device__ inline T clamp_to(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Quadrant mask of a record for the tile whose top-left pixel is (px0, py0):
+// bit k is set unless no pixel centre of quadrant k can reach alpha_min.
+// Two conservative tests must both pass.  (1) The record's pixel box
+// [mean -+ half-extent] meets the quadrant.  (2) The largest log2 alpha over
+// the quadrant's rectangle of pixel centres is at least log2 alpha_min, less a
+// margin that covers the rounding of this bound and of the per-pixel
+// evaluation.  The exponent is a concave quadratic in (dx, dy): over a
+// rectangle that holds the mean its maximum is at the mean, otherwise on an
+// edge, at the edge's stationary point clamped to the edge.  Test (2) drops
+// what the box keeps only because it is axis-aligned (elongated, rotated
+// Gaussians); a skipped pixel would have had alpha < alpha_min, so images and
+// gradients are unchanged.
+template <typename T, int QX, int QY>
+__device__ inline uint32_t quad_mask(const T (&w)[GS_REC_WORDS], int px0, int py0, T lmin) {
+    using N = Num<T>;
+    const T mx = w[R_MX], my = w[R_MY], qa = w[R_QA], qb = w[R_QB], qc = w[R_QC], lo = w[R_LO];
+    const T x0 = mx - w[R_HX], x1 = mx + w[R_HX];
+    const T y0 = my - w[R_HY], y1 = my + w[R_HY];
+    // on an edge dx = e the maximum over dy sits at dy = sx e; on dy = e, at dx = sy e
+    const T sx = -qb * recip(T(2) * qc), sy = -qb * recip(T(2) * qa);
+    const T aqb = qb < T(0) ? -qb : qb;
+    const T alo = lo < T(0) ? -lo : lo;
+    auto expo = [&](T dx, T dy) { return N::fma(N::fma(qa, dx, qb * dy), dx, qc * dy * dy); };
     uint32_t mask = 0;
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < QX * QY; k++) {
         const T qx = T(px0 + 8 * (k % QX)), qy = T(py0 + 8 * (k / QX));
-        const bool hit = x1 >= qx + T(0.5) && x0 <= qx + T(7.5) && y1 >= qy + T(0.5) && y0 <= qy + T(7.5);
-        mask |= hit ? (1u << k) : 0u;
+        const bool box = x1 >= qx + T(0.5) && x0 <= qx + T(7.5) && y1 >= qy + T(0.5) && y0 <= qy + T(7.5);
+        const T ax = qx + T(0.5) - mx, bx = qx + T(7.5) - mx;
+        const T ay = qy + T(0.5) - my, by = qy + T(7.5) - my;
+        const bool inside = ax <= T(0) && bx >= T(0) && ay <= T(0) && by >= T(0);
+        T best = expo(ax, clamp_to(sx * ax, ay, by));
+        best = N::max(best, expo(bx, clamp_to(sx * bx, ay, by)));
+        best = N::max(best, expo(clamp_to(sy * ay, ax, bx), ay));
+        best = N::max(best, expo(clamp_to(sy * by, ax, bx), by));
+        // magnitude of the exponent's terms over the rectangle: scale of the rounding
+        const T X = N::max(-ax, bx), Y = N::max(-ay, by);
+        const T mag = N::fma(-qa * X, X, N::fma(aqb * X, Y, -qc * Y * Y)) + alo;
+        const bool ell = inside || best + lo >= lmin - (T(1e-3) + mag * T(4e-6));
+        mask |= box && ell ? (1u << k) : 0u;
     }
     return mask;
 }
@@ -107,13 +144,16 @@ __device__ inline void wave_lds_sync() {
 // ---------------------------------------------------------------------------
 // forward
 
-template <typename T, int QX, int QY>
+// STATS: also add the number of (pixel, Gaussian) contributions of the
+// launch to *kept (one 64-bit atomic per wave).
+template <typename T, int QX, int QY, bool STATS>
 __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame frame, gs_raster_cfg cfg,
                                                                      const T* __restrict__ rec,
                                                                      const uint32_t* __restrict__ vals,
                                                                      const uint2* __restrict__ ranges,
                                                                      T* __restrict__ rgb, T* __restrict__ Tout,
-                                                                     uint32_t* __restrict__ ncontrib) {
+                                                                     uint32_t* __restrict__ ncontrib,
+                                                                     unsigned long long* __restrict__ kept) {
     constexpr int PPL = QX * QY;
     __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
     __shared__ uint32_t s_mask[kRenderWaves][kWave];
@@ -133,6 +173,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
     T Tr[PPL], C[PPL][3];
     uint32_t done = 0;
     uint32_t last[PPL];
+    uint32_t n_kept = 0;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
@@ -144,14 +185,35 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
     const uint2 range = ranges[tile];
     const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
     constexpr uint32_t all = (1u << PPL) - 1;
+    const T lmin = Num<T>::log2(amin);
     for (uint32_t base = range.x; base < range.y; base += kWave) {
         if (__ballot(done != all) == 0) break;
         const uint32_t cnt = min(uint32_t(kWave), range.y - base);
-        if (uint32_t(lane) < cnt)
-            s_mask[wave][lane] = stage_rec<T, QX, QY>(rec, vals[base + lane], s_rec[wave][lane], tpx, tpy);
+        // stage the batch's records that reach some quadrant, compacted, each
+        // with its quadrant mask and its position in the tile list
+        T w[GS_REC_WORDS];
+        uint32_t m = 0, r = 0;
+        if (uint32_t(lane) < cnt) {
+            r = vals[base + lane];
+            load_rec(rec, r, w);
+            m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin);
+        }
+        const uint64_t staged = __ballot(m != 0);
+        if (m != 0) {
+            const uint32_t slot = __builtin_popcountll(staged & lanemask_lt());
+            const T* src = rec + int64_t(r) * GS_REC_WORDS;
+            T* dst = s_rec[wave][slot];
+#pragma unroll
+            for (int q = 0; q < 6; q++) dst[q] = w[q];
+#pragma unroll
+            for (int q = 6; q < 9; q++) dst[q] = src[q];
+            s_mask[wave][slot] = m | (uint32_t(lane) << 8);
+        }
         wave_lds_sync();
-        for (uint32_t i = 0; i < cnt; i++) {
-            const uint32_t qmask = uniform(s_mask[wave][i]);
+        const uint32_t n = __builtin_popcountll(staged);
+        for (uint32_t i = 0; i < n; i++) {
+            const uint32_t word = uniform(s_mask[wave][i]);
+            const uint32_t qmask = word & 0xffu, pos = word >> 8;
             const Rec<T> g = lds_rec(s_rec[wave][i]);
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
@@ -160,7 +222,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
                 const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
                 const bool live = !(done & (1u << k)) && al >= amin;
                 if (__ballot(live) == 0) continue;     // uniform: no pixel of the wave reached
-                const T a = al < amax ? al : amax;
+                const T a = Num<T>::min(al, amax);
                 const T tn = Tr[k] * (T(1) - a);
                 const bool stop = live && tn < tmin;
                 const bool keep = live && !stop;
@@ -170,10 +232,15 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
                 C[k][1] = Num<T>::fma(wgt, g.c[1], C[k][1]);
                 C[k][2] = Num<T>::fma(wgt, g.c[2], C[k][2]);
                 Tr[k] = keep ? tn : Tr[k];
-                last[k] = keep ? base - range.x + i + 1 : last[k];
+                last[k] = keep ? base - range.x + pos + 1 : last[k];
+                if (STATS) n_kept += keep ? 1u : 0u;
             }
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    if (STATS) {
+        const uint32_t w = wave_sum_u32(n_kept);
+        if (lane == 0) atomicAdd(kept, static_cast<unsigned long long>(w));
     }
     const int64_t plane = int64_t(W) * H;
 #pragma unroll
@@ -256,19 +323,25 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
 
     const uint2 range = ranges[tile];
     const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
+    const T lmin = Num<T>::log2(amin);
     constexpr uint32_t all = (1u << PPL) - 1;
     const int row = lane >> 4;
     for (uint32_t base = range.x; base < range.y; base += kBwdBatch) {
         const uint32_t cnt = min(uint32_t(kBwdBatch), range.y - base);
         const bool any_alive = __ballot(done != all) != 0;
         uint32_t e_own = 0;   // pair this lane stores at the end of the batch
+        T w[GS_REC_WORDS];
+        uint32_t m = 0, r = 0;
         if (uint32_t(lane) < cnt) {
-            const uint32_t r = vals[base + lane];
-            if (any_alive) s_mask[wave][lane] = stage_rec<T, QX, QY>(rec, r, s_rec[wave][lane], tpx, tpy);
+            r = vals[base + lane];
+            if (any_alive) {
+                load_rec(rec, r, w);
+                m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin);
+            }
             // emission index of pair (this tile, r): the record's pairs run
             // row by row over its tile rectangle
-            const uint4 m = meta[r];
-            const uint32_t x0 = m.z & 0xffffu, y0 = m.z >> 16, x1 = m.w & 0xffffu;
+            const uint4 mt = meta[r];
+            const uint32_t x0 = mt.z & 0xffffu, y0 = mt.z >> 16, x1 = mt.w & 0xffffu;
             e_own = pair_off[r] + (uint32_t(ty) - y0) * (x1 - x0 + 1) + (uint32_t(tx) - x0);
         }
         if (!any_alive) {
@@ -279,8 +352,22 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
                 for (int q = 0; q < 9; q++) pg[int64_t(e_own) * 9 + q] = T(0);
             continue;
         }
+        // records that reach some quadrant are staged compacted; the others
+        // store zero partials below
+        const uint64_t staged = __ballot(m != 0);
+        const uint32_t slot = __builtin_popcountll(staged & lanemask_lt());
+        if (m != 0) {
+            const T* src = rec + int64_t(r) * GS_REC_WORDS;
+            T* dst = s_rec[wave][slot];
+#pragma unroll
+            for (int q = 0; q < 6; q++) dst[q] = w[q];
+#pragma unroll
+            for (int q = 6; q < 9; q++) dst[q] = src[q];
+            s_mask[wave][slot] = m;
+        }
         wave_lds_sync();
-        for (uint32_t i = 0; i < cnt; i++) {
+        const uint32_t n = __builtin_popcountll(staged);
+        for (uint32_t i = 0; i < n; i++) {
             const uint32_t qmask = uniform(s_mask[wave][i]);
             const Rec<T> g = lds_rec(s_rec[wave][i]);
             T mo[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
@@ -294,7 +381,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
                 const bool live = !(done & (1u << k)) && al >= amin;
                 if (__ballot(live) == 0) continue;     // uniform: no pixel of the wave reached
                 // the forward's operations, predicated the same way
-                const T a = al < amax ? al : amax;
+                const T a = Num<T>::min(al, amax);
                 const T tn = Tr[k] * (T(1) - a);
                 const bool stop = live && tn < tmin;
                 const bool keep = live && !stop;
@@ -324,9 +411,9 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             if (__ballot(hit) != 0) {
                 T v[9];
 #pragma unroll
-                for (int q = 0; q < 6; q++) v[q] = row_sum(mo[q]);
+                for (int q = 0; q < 6; q++) v[q] = row_sum_last(mo[q]);
 #pragma unroll
-                for (int q = 0; q < 3; q++) v[6 + q] = row_sum(dcol[q]);
+                for (int q = 0; q < 3; q++) v[6 + q] = row_sum_last(dcol[q]);
                 if ((lane & 15) == 15)
 #pragma unroll
                     for (int q = 0; q < 9; q++) rs[q] = v[q];
@@ -337,10 +424,11 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
         }
         wave_lds_sync();
         if (uint32_t(lane) < cnt) {
-            const T(*rows)[9] = s_rows[wave][lane];
+            const T(*rows)[9] = s_rows[wave][slot];
             T* dst = pg + int64_t(e_own) * 9;
 #pragma unroll
-            for (int q = 0; q < 9; q++) dst[q] = (rows[0][q] + rows[1][q]) + (rows[2][q] + rows[3][q]);
+            for (int q = 0; q < 9; q++)
+                dst[q] = m != 0 ? (rows[0][q] + rows[1][q]) + (rows[2][q] + rows[3][q]) : T(0);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -350,17 +438,21 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
 
 template <typename T, int QX, int QY>
 static void fwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& b, T* rgb,
-                       T* Tfin, uint32_t* nc, hipStream_t s) {
+                       T* Tfin, uint32_t* nc, unsigned long long* kept, hipStream_t s) {
     const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
-    hipLaunchKernelGGL((k_render_fwd<T, QX, QY>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec, b.vals,
-                       reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc);
+    if (kept)
+        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, true>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg,
+                  rec, b.vals, reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept);
+    else
+        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, false>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f,
+                  cfg, rec, b.vals, reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept);
 }
 
 template <typename T, int QX, int QY>
 static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
                        const gs_bins& b, const T* rgb, int mode, const T* gin, T* loss, T* pg, hipStream_t s) {
     const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
-    hipLaunchKernelGGL((k_render_bwd<T, QX, QY>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
+    GS_LAUNCH("k_render_bwd", (k_render_bwd<T, QX, QY>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
                        reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals,
                        reinterpret_cast<const uint2*>(b.ranges), rgb, mode, gin, loss, pg);
 }
@@ -376,9 +468,9 @@ static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec
 
 template <typename T>
 hipError_t launch_render_fwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& bins,
-                             T* rgb, T* Tfin, uint32_t* ncontrib, hipStream_t s) {
+                             T* rgb, T* Tfin, uint32_t* ncontrib, unsigned long long* kept, hipStream_t s) {
     if (f.n_tiles == 0) return hipSuccess;
-    GS_TILE_DISPATCH(fwd_launch, f, cfg, rec, bins, rgb, Tfin, ncontrib, s);
+    GS_TILE_DISPATCH(fwd_launch, f, cfg, rec, bins, rgb, Tfin, ncontrib, kept, s);
     return hipGetLastError();
 }
 
@@ -391,8 +483,8 @@ hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const 
     return hipGetLastError();
 }
 
-template hipError_t launch_render_fwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const gs_bins&, float*, float*, uint32_t*, hipStream_t);
-template hipError_t launch_render_fwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const gs_bins&, double*, double*, uint32_t*, hipStream_t);
+template hipError_t launch_render_fwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const gs_bins&, float*, float*, uint32_t*, unsigned long long*, hipStream_t);
+template hipError_t launch_render_fwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const gs_bins&, double*, double*, uint32_t*, unsigned long long*, hipStream_t);
 template hipError_t launch_render_bwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const uint32_t*, const gs_bins&, const float*, gs_loss_mode, const float*, float*, float*, hipStream_t);
 template hipError_t launch_render_bwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const uint32_t*, const gs_bins&, const double*, gs_loss_mode, const double*, double*, double*, hipStream_t);
 

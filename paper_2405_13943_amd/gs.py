@@ -83,6 +83,7 @@ def _load():
         "gs_bin_sort": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, ctypes.c_size_t, c_vp], c_i32),
         "gs_render_fwd": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_render_fwd_f64": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp], c_i32),
+        "gs_render_fwd_stats": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_render_bwd_workspace_size": ([c_u64, c_i32], ctypes.c_size_t),
         "gs_render_bwd": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_i32, c_vp, c_vp,
                            P(GsParams), c_vp, ctypes.c_size_t, c_vp], c_i32),
@@ -90,7 +91,12 @@ def _load():
                                c_vp, P(GsParams), c_vp, ctypes.c_size_t, c_vp], c_i32),
         "gs_adam_admm": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg),
                           c_vp], c_i32),
+        "gs_render_bwd_adam": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_i32, c_vp,
+                                c_vp, P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg), c_vp,
+                                ctypes.c_size_t, c_vp], c_i32),
         "gs_consensus": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, c_f, c_vp, c_vp], c_i32),
+        "gs_profile_set": ([ctypes.c_char_p], c_i32),
+        "gs_profile_get": ([ctypes.c_char_p, P(ctypes.c_double), P(c_i64)], c_i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -267,6 +273,17 @@ def render_fwd(frame: Frame, cfg: GsRasterCfg, buf: Buffers):
               _ptr(buf.T), _ptr(buf.ncontrib), _stream()), "gs_render_fwd")
 
 
+def render_fwd_stats(frame: Frame, cfg: GsRasterCfg, buf: Buffers) -> int:
+    """Forward (FP32) that also counts the frame's (pixel, Gaussian)
+    contributions; returns the count (host read)."""
+    kept = torch.zeros(1, dtype=torch.int64, device=buf.rgb.device)
+    b = buf.bins
+    _check(lib.gs_render_fwd_stats(ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.rec), ctypes.byref(b),
+                                   _ptr(buf.rgb), _ptr(buf.T), _ptr(buf.ncontrib), _ptr(kept), _stream()),
+           "gs_render_fwd_stats")
+    return int(kept.item())
+
+
 def render_bwd(params: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffers, grad_out: torch.Tensor,
                mode=LOSS_L1, grad_in: torch.Tensor = None, loss_out: torch.Tensor = None):
     """Backward into ``grad_out`` ([A][N] like params).  mode LOSS_L1: grad_in
@@ -296,6 +313,21 @@ def adam_admm(x, g, m, v, w=None, mask=None, cfg: GsAdamCfg = None):
            "gs_adam_admm")
 
 
+def render_bwd_adam(x: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffers, m, v, w=None, mask=None,
+                    acfg: GsAdamCfg = None, mode=LOSS_L1, grad_in: torch.Tensor = None, loss_out: torch.Tensor = None):
+    """Backward and Adam/ADMM update of x in one call (FP32, jobs over
+    disjoint Gaussian ranges); equal to render_bwd into a gradient buffer
+    followed by adam_admm."""
+    px, pm, pv = (params_struct(t) for t in (x, m, v))
+    pw = params_struct(w) if w is not None else None
+    b = buf.bins
+    _check(lib.gs_render_bwd_adam(ctypes.byref(px), ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.rec),
+                                  _ptr(buf.meta), ctypes.byref(b), _ptr(buf.rgb), mode, _ptr(grad_in),
+                                  _ptr(loss_out), ctypes.byref(pm), ctypes.byref(pv),
+                                  ctypes.byref(pw) if pw is not None else None, _ptr(mask), ctypes.byref(acfg),
+                                  _ptr(buf.bwd_ws), buf.bwd_ws.numel(), _stream()), "gs_render_bwd_adam")
+
+
 def consensus(x, u, w, z, holder_ptr, holder_idx, relax=1.0, resid=None):
     px, pu, pw, pz = (params_struct(t) for t in (x, u, w, z))
     _check(lib.gs_consensus(ctypes.byref(px), ctypes.byref(pu), ctypes.byref(pw), ctypes.byref(pz),
@@ -323,3 +355,18 @@ def rasterize(params: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffers
         buf.grow(int(c["pairs"] * 1.25) + 1024)
     render_fwd(frame, cfg, buf)
     return buf
+
+
+def profile_set(names):
+    """Time the launches of the named kernels (list or comma string, "*" all,
+    None off) with HIP events inside the library; resets the totals."""
+    if names is not None and not isinstance(names, str):
+        names = ",".join(names)
+    _check(lib.gs_profile_set(names.encode() if names else None), "gs_profile_set")
+
+
+def profile_get(name):
+    """(summed duration in ms, launches) of a profiled kernel; waits for them."""
+    ms, n = ctypes.c_double(), c_i64()
+    _check(lib.gs_profile_get(name.encode(), ctypes.byref(ms), ctypes.byref(n)), "gs_profile_get")
+    return ms.value, n.value

@@ -175,6 +175,19 @@ def config5(n=6_000_000) -> Scene:
     return Scene(f"serve-{n // 1_000_000}M-sh3", p, 3, [], [], seed)
 
 
+def config4b(n=2_000_000, width=1920, height=1080) -> Scene:
+    """Adjoint case at scale: 2M Gaussians, SH degree 3, in the 100 x 20 x 100 m
+    box, one 1920x1080 view from the 40 m ring at 10 m height (drawn in chunks
+    of 1M with seed 1044 * 1000 + chunk)."""
+    seed = 1044
+    step = 1_000_000
+    parts = [gaussians(min(step, n - a), 3, seed * 1000 + a // step, [-50, -10, -50], [50, 10, 50], -3.0, 0.7)
+             for a in range(0, n, step)]
+    p = np.concatenate(parts, axis=1) if len(parts) > 1 else parts[0]
+    cams = [look_at([40.0 * math.cos(0.3), 10.0, 40.0 * math.sin(0.3)], [0, 0, 0], width, height)]
+    return Scene(f"adjoint-{n // 1_000_000}M-sh3-{width}x{height}", p, 3, cams, [], seed)
+
+
 def config4a() -> Scene:
     """Adjoint case: 200 Gaussians, SH degree 3, one 64x64 view (fx = 75)."""
     seed = 1004

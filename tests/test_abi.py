@@ -133,6 +133,33 @@ def test_invalid_arguments_rejected_without_launch(gs):
     assert gs.lib.gs_consensus(ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), 1, 1,
                                2.5, None, None) == gs.GS_E_INVALID
 
+    # fused backward + Adam: shared Gaussians unsupported, bad planes, small workspace
+    fr_shared = gs.GsFrame(1, 1, 2, 2, 20, 20, 10, 0, 0)
+    rc = gs.lib.gs_render_bwd_adam(ctypes.byref(p10), ctypes.byref(fr_shared), ctypes.byref(cfg), 1, 1,
+                                   ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), ctypes.byref(p10), None, None,
+                                   ctypes.byref(acfg), 1, 1 << 20, None)
+    assert rc == gs.GS_E_UNSUPPORTED and "share" in gs.lib.gs_last_error().decode()
+    fr_disj = gs.GsFrame(1, 1, 1, 1, 10, 10, 10, 1, 0)
+    rc = gs.lib.gs_render_bwd_adam(ctypes.byref(p10), ctypes.byref(fr_disj), ctypes.byref(cfg), 1, 1,
+                                   ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(b), ctypes.byref(p10), None, None,
+                                   ctypes.byref(acfg), 1, 1 << 20, None)
+    assert rc == gs.GS_E_INVALID
+    rc = gs.lib.gs_render_bwd_adam(ctypes.byref(p10), ctypes.byref(fr_disj), ctypes.byref(cfg), 1, 1,
+                                   ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), ctypes.byref(p10), None, None,
+                                   ctypes.byref(acfg), 1, 8, None)
+    assert rc == gs.GS_E_CAPACITY
+
+
+def test_profile_registry_host_only(gs):
+    """Selecting kernels to time launches nothing; kernels never launched
+    report zero."""
+    gs.profile_set(["k_render_bwd", "k_project_bwd_adam"])
+    assert gs.profile_get("k_render_bwd") == (0.0, 0)
+    gs.profile_set("*")
+    gs.profile_set(None)
+    assert gs.profile_get("k_emit") == (0.0, 0)
+    assert gs.lib.gs_profile_get(None, None, None) == gs.GS_E_INVALID
+
 
 def test_workspace_sizes_grow_with_inputs(gs):
     a = gs.lib.gs_bin_sort_workspace_size(1000, 10000, 64)

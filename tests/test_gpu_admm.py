@@ -30,18 +30,18 @@ def targets_for(bs):
             for k in range(len(bs.cams))]
 
 
-def make_trainer(bs, intv=2, rho=(1e-2,) * 5, relax=1.0):
+def make_trainer(bs, intv=2, rho=(1e-2,) * 5, relax=1.0, fused=True):
     model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
     cfg = gs.raster_cfg((16, 16))
     return admm.AdmmTrainer(model, bs.cams, targets_for(bs), cfg, lr=(1e-3, 2e-3, 3e-3, 4e-3, 5e-3), rho=rho,
-                            intv=intv, relax=relax, capacity=1 << 16)
+                            intv=intv, relax=relax, capacity=1 << 16, fused=fused)
 
 
 def test_batched_blocks_equal_single_block_runs():
     """All blocks in one launch per stage give bit-identical images and
     gradients to rendering each block alone."""
     bs = tiny_blocks()
-    tr = make_trainer(bs)
+    tr = make_trainer(bs, fused=False)
     views = [1, 0, 1]
     tr.local_step(views)
     f = tr.frame(views)
@@ -68,12 +68,16 @@ def test_trainer_step_matches_oracle_composition():
     tr = make_trainer(bs, intv=1)
     x0 = tr.model.x.cpu().numpy().copy()
     tr.local_step()
-    g_gpu = tr.g.cpu().numpy().astype(np.float64)
-    # the trainer's L1 gradient is the kernels' external-gradient backward fed
-    # dL/dC = sign(C - target) / 3HW of each block's own image (the kernels
-    # themselves are checked against the FP64 oracle in test_gpu_parity)
+    # the trainer's step (backward and optimiser fused) used the L1 gradient of
+    # x0, recomputed here from the same records and bins
     f = tr.frame(tr.views_at(0))
     tgt = tr.target_buffer(tr.views_at(0))
+    g_l1 = torch.empty_like(tr.model.x)
+    gs.render_bwd(torch.from_numpy(x0).cuda(), f, tr.cfg, tr.buf, g_l1, gs.LOSS_L1, tgt)
+    g_gpu = g_l1.cpu().numpy().astype(np.float64)
+    # the L1 gradient is the kernels' external-gradient backward fed
+    # dL/dC = sign(C - target) / 3HW of each block's own image (the kernels
+    # themselves are checked against the FP64 oracle in test_gpu_parity)
     n_px = torch.tensor([3 * c.width * c.height for c in f.cams], device="cuda")
     dl = torch.cat([torch.sign(f.image(tr.buf.rgb, k) - f.image(tgt, k)).reshape(-1) / float(n_px[k])
                     for k in range(3)])
@@ -118,6 +122,20 @@ def test_trainer_step_matches_oracle_composition():
     pad = np.setdiff1d(np.arange(x1.shape[1]), held)
     assert len(pad) > 0
     assert (tr.u.cpu().numpy()[:, pad] == 0).all()
+
+
+def test_fused_and_unfused_trainers_agree():
+    """Several steps with consensus: the fused trainer (gs_render_bwd_adam)
+    and the two-call trainer end with bit-identical state."""
+    bs = tiny_blocks()
+    trs = [make_trainer(bs, intv=2, fused=f) for f in (True, False)]
+    for tr in trs:
+        for _ in range(5):
+            tr.step()
+    a, b = trs
+    for name in ("m", "v", "u", "w"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    assert torch.equal(a.model.x, b.model.x) and torch.equal(a.model.z, b.model.z)
 
 
 def test_trainer_loop_invariants_and_penalty():

@@ -187,6 +187,20 @@ def _oracle_dldc(scene, views, ref, weight):
     return out
 
 
+def test_contribution_count_matches_oracle(cfg1, gpu1, ref1):
+    """gs_render_fwd_stats counts the (pixel, Gaussian) contributions of
+    Eq. 2: the oracle's per-pixel contributor counts summed over the frame,
+    up to one per flagged pixel; the image is the plain forward's."""
+    cfg, frame, params, buf = gpu1
+    rgb = buf.rgb.clone()
+    kept = gs.render_fwd_stats(frame, cfg, buf)
+    assert torch.equal(buf.rgb, rgb)
+    n_ref = sum(int(r["n"].sum()) for r in ref1)
+    flagged = sum(int(np.count_nonzero(r["flags"])) for r in ref1)
+    assert n_ref > 10_000
+    assert abs(kept - n_ref) <= flagged, (kept, n_ref, flagged)
+
+
 def test_render_bwd_matches_oracle(cfg1, gpu1, ref1):
     cfg, frame, params, buf = gpu1
     views = list(range(4))
