@@ -38,6 +38,33 @@ LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)       # mean, rotation, scale, SH, opaci
 RHO = (1e-3,) * 5
 
 
+def kernel_sources_sha256():
+    """Fingerprint of the HIP sources (kernels and their headers)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2405_13943_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(d, "*.hip")) + glob.glob(os.path.join(d, "*.hpp"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE / WRITE_SIZE scaled by a copy of known size), or None
+    when the kernel sources have changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel)
+    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return int(rec["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -90,7 +117,8 @@ def run_gpu(args):
     from paper_2405_13943_amd import gs
     torch.cuda.set_device(0)
     t0 = time.time()
-    scene, cfg, st, frames, targets = setup(args.n, args.cams, args.width, args.height, (args.tile, args.tile))
+    scene, cfg, st, frames, targets = setup(args.n, args.cams, args.width, args.height,
+                                            (args.tile, args.tile, args.fwd_waves, args.bwd_waves))
     A, N = st["x"].shape
     log(f"[bench] setup {time.time() - t0:.1f}s: N={N} A={A} views={len(frames)} {args.width}x{args.height}")
     buf, pmax = calibrate_capacity(gs, st, frames, cfg)
@@ -198,7 +226,7 @@ def run_serve(args):
     scene = scenes.config5(args.serve_n)
     params = torch.from_numpy(scene.params).to("cuda")
     del scene
-    cfg = gs.raster_cfg((args.tile, args.tile))
+    cfg = gs.raster_cfg((args.tile, args.tile, args.fwd_waves, args.bwd_waves))
     srv = serve.RenderServer(params, cfg, hbm_budget=args.serve_hbm * 1e9, n_slots=args.serve_slots,
                              max_batch=args.serve_max_batch, resolutions=scenes.SERVE_RESOLUTIONS)
     log(f"[serve] setup {time.time() - t0:.1f}s: N={params.shape[1]}, max_batch {srv.max_batch}, "
@@ -297,8 +325,8 @@ def run_blocks4(args):
         tr.t += 1
 
     tile = admm.autotune_tile(run, f"blocks4-{model.x.shape[1]}-1600x1066", args.tune_cache, reps=3) \
-        if not args.no_tile_auto else (args.tile, args.tile)
-    log(f"[blocks4] tile {tile[0]}x{tile[1]}")
+        if not args.no_tile_auto else (args.tile, args.tile, args.fwd_waves, args.bwd_waves)
+    log(f"[blocks4] tile {'x'.join(map(str, tile))}")
     for t, tr in list(trainers.items()):
         if t != tile:
             del trainers[t]
@@ -385,7 +413,7 @@ def run_blocks4(args):
            "config": {"workload": "batched K=4 blocks 0.8M/1.5M/2.2M/3.0M own Gaussians SH3 + 10% shared copies "
                                   f"({model.x.shape[1]} local slots), {args.block_cams} ring views per block at "
                                   "1600x1066, consensus every 100 steps",
-                      "tile": f"{tile[0]}x{tile[1]}"},
+                      "tile": "x".join(map(str, tile[:2])), "waves_per_tile_fwd_bwd": list(tile[2:])},
            "sequential_ms_per_step": ms_s / steps, "batched_speedup": ms_s / ms_b,
            "consensus_ms": c_ms, "consensus_calls": len(c_ms), "images_equal_per_block": same,
            "kernel_ms_batched": kb, "kernel_ms_sequential": ks,
@@ -415,10 +443,15 @@ def cpu_baseline(scene, budget_s=12.0):
         oracle.backward(scene.params, cam, dl, pixels=pix)
         return time.time() - t
 
-    t_small = fwd_bwd(64)
-    npx = int(min(npx_total, max(64, 64 * (0.6 * budget_s) / max(t_small, 1e-3))))
+    # per-call time = fixed projection cost + per-pixel cost: two probes
+    # separate them, then the sample is sized to about budget_s
+    t64 = fwd_bwd(64)
+    t256 = fwd_bwd(256)
+    per_px = max((t256 - t64) / 192.0, 1e-6)
+    npx = int(min(npx_total, max(256, (budget_s - t64) / per_px)))
     t_px = fwd_bwd(npx)
-    t_img = t_px * npx_total / npx
+    # the whole view: one fixed part plus every pixel at the sampled rate
+    t_img = t64 + (t_px - t64) * (npx_total - 64) / max(npx - 64, 1)
     x = scene.params
     t = time.time()
     oracle.adam_admm(x, np.zeros_like(x), np.zeros_like(x), np.zeros_like(x), x, LR, RHO, 1)
@@ -453,6 +486,8 @@ def main():
     ap.add_argument("--width", type=int, default=1600)
     ap.add_argument("--height", type=int, default=1066)
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--fwd-waves", type=int, default=2, help="forward compositing wavefronts per tile (1, 2, 4)")
+    ap.add_argument("--bwd-waves", type=int, default=1, help="backward compositing wavefronts per tile (1, 2, 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="backward and optimiser as two calls (gradient in HBM)")
     ap.add_argument("--workload", choices=("train", "blocks4", "serve"), default="train",
@@ -508,7 +543,8 @@ def main():
         "data": "synthetic (seeded Gaussians, ring cameras, U(0,1) targets)",
         "config": {"workload": f"single block, {r['N']} Gaussians SH3, {args.width}x{args.height}, "
                                f"{args.cams} ring views, one view per step, L1 + Adam/ADMM rho=1e-3",
-                   "tile": f"{args.tile}x{args.tile}", "max_pairs": r["pairs_max"]},
+                   "tile": f"{args.tile}x{args.tile}", "waves_per_tile_fwd_bwd": [args.fwd_waves, args.bwd_waves],
+                   "max_pairs": r["pairs_max"]},
         "stage_ms": {k: round(v, 5) for k, v in r["stage_ms"].items()},
         "kernel_ms": {k: round(v, 5) for k, v in r["kernel_ms"].items()},
         "roofline": {"bound": "alu", "kernel": "k_render_bwd", "achieved": round(r["bwd_tflops"], 3),
@@ -517,7 +553,7 @@ def main():
                      "work": f"{BWD_FLOPS} flops x {r['kept']:.4g} (pixel, Gaussian) contributions per launch"},
         "roofline_stream": {"bound": "hbm", "kernel": r["opt_kernel"], "achieved": round(r["opt_gbs"], 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["opt_gbs"] / HBM_PEAK_GBS, 4),
-                            "traffic": None, "bytes": int(r["opt_bytes"])},
+                            "traffic": measured_traffic(r["opt_kernel"]), "bytes": int(r["opt_bytes"])},
         "cpu_baseline": cpu,
         "serve": srv,
     }

@@ -123,7 +123,7 @@ typedef struct {
  * `near_z`, alpha = min(alpha_max, o G), keep when alpha >= alpha_min, stop
  * before the Gaussian that takes T below T_min, background bg. */
 typedef struct {
-    int32_t tile_w, tile_h;  /* 8x8, 16x8 or 16x16 */
+    int32_t tile_w, tile_h;  /* binning tile: 8x8, 16x8, 16x16 or 32x8 */
     float near_z;            /* 0.2 */
     float alpha_min;         /* 1/255 */
     float alpha_max;         /* 0.99 */
@@ -131,7 +131,11 @@ typedef struct {
     float dilation;          /* 0.3 */
     float jac_clip;          /* 1.3 */
     float bg[3];             /* 0, 0, 0 */
-    int32_t reserved;
+    int16_t fwd_waves;       /* wavefronts per tile in the forward and in the backward */
+    int16_t bwd_waves;       /* compositing, each owning an equal part of the tile and walking
+                                the whole list: 1 (0 = 1), 2 (16x8, 16x16, 32x8) or 4 (16x16,
+                                32x8).  Images do not depend on them; gradients only through
+                                the order of their sums. */
 } gs_raster_cfg;
 
 /* Tile bins produced by gs_bin_sort. */
@@ -225,7 +229,8 @@ gs_status gs_render_fwd_stats(const gs_frame *frame, const gs_raster_cfg *cfg, c
  * dL/dC laid out like rgb.  The transmittance is recomputed front to back
  * (never stored per pair).  grad->data receives dense gradient planes
  * (zero for Gaussians in no job or culled); grad must cover params->n.
- * Workspace: gs_render_bwd_workspace_size bytes. */
+ * Workspace: gs_render_bwd_workspace_size bytes (nine partials per tile pair
+ * and compositing wavefront, sized for up to 4 wavefronts per tile). */
 size_t gs_render_bwd_workspace_size(uint64_t capacity, int32_t f64);
 gs_status gs_render_bwd(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
                         const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,

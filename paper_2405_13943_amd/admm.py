@@ -219,7 +219,9 @@ class AdmmTrainer:
 # ---------------------------------------------------------------------------
 # tile-shape autotuner
 
-TILES = ((16, 16), (16, 8), (32, 8), (8, 8))
+# (binning tile w, h, forward and backward compositing wavefronts per tile)
+TILES = ((16, 16, 2, 1), (16, 16, 1, 1), (16, 16, 4, 1), (16, 16, 2, 2), (32, 8, 2, 1), (32, 8, 4, 1),
+         (32, 8, 1, 1), (16, 8, 2, 1), (8, 8, 1, 1))
 
 
 def autotune_tile(run_step, key: str, cache_path=None, candidates=TILES, reps=5):
@@ -244,7 +246,7 @@ def autotune_tile(run_step, key: str, cache_path=None, candidates=TILES, reps=5)
         torch.cuda.synchronize()
         times[tile] = e0.elapsed_time(e1) / reps
     best = min(times, key=times.get)
-    cache[key] = {"tile": list(best), "ms": {f"{a}x{b}": v for (a, b), v in times.items()},
+    cache[key] = {"tile": list(best), "ms": {"x".join(map(str, t)): v for t, v in times.items()},
                   "when": time.strftime("%Y-%m-%d %H:%M:%S")}
     if cache_path:
         os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)

@@ -39,10 +39,15 @@ gs_status check_params(const gs_params* p, const char* name, bool allow_null_dat
     return GS_OK;
 }
 
-bool tile_ok(const gs_raster_cfg* c) {
-    return (c->tile_w == 8 && c->tile_h == 8) || (c->tile_w == 16 && c->tile_h == 8) ||
-           (c->tile_w == 16 && c->tile_h == 16) || (c->tile_w == 32 && c->tile_h == 8);
+bool waves_ok(const gs_raster_cfg* c, int waves) {
+    const int S = waves == 0 ? 1 : waves;
+    if (c->tile_w == 8 && c->tile_h == 8) return S == 1;
+    if (c->tile_w == 16 && c->tile_h == 8) return S == 1 || S == 2;
+    if ((c->tile_w == 16 && c->tile_h == 16) || (c->tile_w == 32 && c->tile_h == 8)) return S == 1 || S == 2 || S == 4;
+    return false;
 }
+
+bool tile_ok(const gs_raster_cfg* c) { return waves_ok(c, c->fwd_waves) && waves_ok(c, c->bwd_waves); }
 
 gs_status check_frame(const gs_frame* f, const gs_raster_cfg* cfg) {
     if (!f || !cfg) return fail(GS_E_INVALID, "null frame or raster config");
@@ -50,7 +55,9 @@ gs_status check_frame(const gs_frame* f, const gs_raster_cfg* cfg) {
         return fail(GS_E_INVALID, "negative frame totals");
     if (f->n_jobs > 0 && (!f->cams || !f->jobs)) return fail(GS_E_INVALID, "null cams/jobs");
     if (f->n_records >= (int64_t(1) << 32)) return fail(GS_E_UNSUPPORTED, "more than 2^32 - 1 records");
-    if (!tile_ok(cfg)) return fail(GS_E_INVALID, "tile %dx%d not one of 8x8, 16x8, 16x16, 32x8", cfg->tile_w, cfg->tile_h);
+    if (!tile_ok(cfg))
+        return fail(GS_E_INVALID, "tile %dx%d with %d/%d wavefronts per tile (fwd/bwd): not one of 8x8/1, 16x8/1-2, "
+                    "16x16/1-2-4, 32x8/1-2-4", cfg->tile_w, cfg->tile_h, cfg->fwd_waves, cfg->bwd_waves);
     if (!(cfg->alpha_min > 0.f) || !(cfg->alpha_max > cfg->alpha_min) || !(cfg->alpha_max < 1.f) ||
         !(cfg->T_min > 0.f) || !(cfg->near_z > 0.f) || !(cfg->dilation >= 0.f) || !(cfg->jac_clip > 0.f))
         return fail(GS_E_INVALID, "raster constants out of range");
@@ -92,9 +99,10 @@ gs_status render_fwd_impl(const gs_frame* frame, const gs_raster_cfg* cfg, const
                      "gs_render_fwd");
 }
 
+// nine partials per tile pair and compositing wavefront, up to 4 wavefronts per tile
 size_t bwd_ws(uint64_t capacity, int f64) {
     const size_t e = f64 ? sizeof(double) : sizeof(float);
-    return size_t(capacity > 0 ? capacity : 1) * 9 * e;
+    return size_t(capacity > 0 ? capacity : 1) * 9 * 4 * e;
 }
 
 template <typename T>
@@ -144,6 +152,8 @@ void gs_raster_cfg_default(gs_raster_cfg* cfg) {
     cfg->T_min = 1e-4f;
     cfg->dilation = 0.3f;
     cfg->jac_clip = 1.3f;
+    cfg->fwd_waves = 1;
+    cfg->bwd_waves = 1;
 }
 
 gs_status gs_frame_plan(const gs_camera* cams, int32_t n_cams, gs_job* jobs, int32_t n_jobs, const gs_raster_cfg* cfg,

@@ -45,6 +45,10 @@ template <typename T> __device__ constexpr T kLog2e() { return T(1.4426950408889
 // per-record metadata word 1: covered tiles in the low 24 bits, the colour
 // clamp of each channel (SH sum + 0.5 <= 0) in bits 24..26
 
+// compositing wavefronts per tile of the forward and the backward (0 reads as 1)
+__host__ __device__ inline int fwd_waves(const gs_raster_cfg& c) { return c.fwd_waves <= 1 ? 1 : c.fwd_waves; }
+__host__ __device__ inline int bwd_waves(const gs_raster_cfg& c) { return c.bwd_waves <= 1 ? 1 : c.bwd_waves; }
+
 constexpr uint32_t kTilesMask = 0xffffffu;
 __host__ __device__ inline uint32_t meta_tiles(uint32_t y) { return y & kTilesMask; }
 __host__ __device__ inline uint32_t meta_clamp(uint32_t y) { return y >> 24; }

@@ -328,11 +328,15 @@ __device__ inline void record_pair_sum(const T* __restrict__ pg, uint64_t p0, ui
     }
 }
 
-// pairs of a record that were emitted (pairs past the capacity never were:
-// the overflow status is set and the step must be redone)
-__device__ inline void record_pairs(uint32_t ntiles, uint32_t off, uint64_t capacity, uint64_t& p0, uint64_t& np) {
+// partial slots of a record: its emitted pairs (pairs past the capacity never
+// were: the overflow status is set and the step must be redone), each with S
+// consecutive slots, one per compositing wavefront of the tile
+__device__ inline void record_pairs(uint32_t ntiles, uint32_t off, uint64_t capacity, int S, uint64_t& p0,
+                                    uint64_t& np) {
     p0 = off;
     np = ntiles == 0 || p0 >= capacity ? 0 : (p0 + ntiles > capacity ? capacity - p0 : ntiles);
+    p0 *= uint64_t(S);
+    np *= uint64_t(S);
 }
 
 // Chain rule of one visible record of Gaussian g seen by `camera`; emit(a, v)
@@ -489,7 +493,7 @@ template <typename T, int D>
 __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P, int64_t stride, gs_frame frame,
                                                           gs_raster_cfg cfg, const uint4* __restrict__ meta,
                                                           const uint32_t* __restrict__ pair_off, uint64_t capacity,
-                                                          const T* __restrict__ pg, T* __restrict__ grad,
+                                                          int S, const T* __restrict__ pg, T* __restrict__ grad,
                                                           int64_t gstride) {
     constexpr int A = 11 + 3 * (D + 1) * (D + 1);
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -500,7 +504,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P
     const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t ntiles = meta_tiles(m.y);
     uint64_t p0, np;
-    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, p0, np);
+    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, S, p0, np);
     T d[9];
     record_pair_sum(pg, p0, np, d);
     if (!active) return;
@@ -521,7 +525,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P
                                                           gs_frame frame, gs_raster_cfg cfg,
                                                           const uint4* __restrict__ meta,
                                                           const uint32_t* __restrict__ pair_off, uint64_t capacity,
-                                                          const T* __restrict__ pg, T* __restrict__ grad,
+                                                          int S, const T* __restrict__ pg, T* __restrict__ grad,
                                                           int64_t gstride) {
     constexpr int A = 11 + 3 * (D + 1) * (D + 1);
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P
         const uint4 m = in_job ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
         const uint32_t ntiles = meta_tiles(m.y);
         uint64_t p0, np;
-        record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, p0, np);
+        record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, S, p0, np);
         T d[9];
         record_pair_sum(pg, p0, np, d);
         if (ntiles == 0) continue;
@@ -618,7 +622,7 @@ __device__ inline void adam_block_one(float* __restrict__ X, int64_t sx, float* 
 template <int D, bool PEN, bool MASK, bool VEC>
 __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     float* X, int64_t sx, gs_frame frame, gs_raster_cfg cfg, const uint4* __restrict__ meta,
-    const uint32_t* __restrict__ pair_off, uint64_t capacity, const float* __restrict__ pg, float* __restrict__ M,
+    const uint32_t* __restrict__ pair_off, uint64_t capacity, int S, const float* __restrict__ pg, float* __restrict__ M,
     int64_t sm, float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
     const float* __restrict__ mask, AdamConsts c) {
     constexpr int NK = (D + 1) * (D + 1);
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t ntiles = meta_tiles(m.y);
     uint64_t p0, np;
-    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, p0, np);
+    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, S, p0, np);
     float d[9];
     record_pair_sum(pg, p0, np, d);
 
@@ -737,10 +741,10 @@ static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs
                                11 + 3 * (D + 1) * (D + 1), Gd, grad.stride);
         if (f.n_records > 0)
             GS_LAUNCH("k_project_bwd_rec", (k_project_bwd_rec<T, D>), dim3(unsigned((f.n_records + 127) / 128)), dim3(128), 0, s,
-                               P, p.stride, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride);
+                               P, p.stride, f, cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Gd, grad.stride);
     } else {
         GS_LAUNCH("k_project_bwd_acc", (k_project_bwd_acc<T, D>), dim3(unsigned((p.n + 127) / 128)), dim3(128), 0, s, P,
-                           p.stride, p.n, f, cfg, M, pair_off, capacity, pg, Gd, grad.stride);
+                           p.stride, p.n, f, cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Gd, grad.stride);
     }
 }
 
@@ -781,10 +785,10 @@ static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_ra
     const dim3 grid(unsigned((f.n_records + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
     if (f.n_records > 0 && vec)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, true>), grid, block, 0, s, X, x.stride, f,
-                  cfg, M, pair_off, capacity, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+                  cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
     else if (f.n_records > 0)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, false>), grid, block, 0, s, X, x.stride,
-                  f, cfg, M, pair_off, capacity, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+                  f, cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
 }
 
 template <int D>

@@ -146,7 +146,7 @@ __device__ inline void wave_lds_sync() {
 
 // STATS: also add the number of (pixel, Gaussian) contributions of the
 // launch to *kept (one 64-bit atomic per wave).
-template <typename T, int QX, int QY, bool STATS>
+template <typename T, int QX, int QY, int NS, bool STATS>
 __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame frame, gs_raster_cfg cfg,
                                                                      const T* __restrict__ rec,
                                                                      const uint32_t* __restrict__ vals,
@@ -158,14 +158,18 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
     __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
     __shared__ uint32_t s_mask[kRenderWaves][kWave];
     const int wave = threadIdx.x / kWave, lane = lane_id();
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+    // NS wavefronts per tile: wave `sub` owns the tile's sub-tile of QX x QY quadrants
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+    const int tile = gw / NS, sub = gw % NS;
     if (tile >= frame.n_tiles) return;
     const int j = job_of_tile(frame.jobs, frame.n_jobs, tile);
     const gs_job job = frame.jobs[j];
     const gs_camera& cam = frame.cams[job.cam];
     const int W = cam.width, H = cam.height;
     const int lt = tile - job.tile0;
-    const int tpx = (lt % job.tiles_x) * 8 * QX, tpy = (lt / job.tiles_x) * 8 * QY;
+    const int sxn = cfg.tile_w / (8 * QX);   // sub-tiles per tile row
+    const int tpx = (lt % job.tiles_x) * cfg.tile_w + (sub % sxn) * 8 * QX;
+    const int tpy = (lt / job.tiles_x) * cfg.tile_h + (sub / sxn) * 8 * QY;
     const int lx = lane & 7, ly = lane >> 3;
     // pixel centre of quadrant k: (bx + 8 (k % QX), by + 8 (k / QX))
     const T bx = T(tpx + lx) + T(0.5), by = T(tpy + ly) + T(0.5);
@@ -261,7 +265,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
 // ---------------------------------------------------------------------------
 // backward
 
-template <typename T, int QX, int QY>
+template <typename T, int QX, int QY, int NS>
 __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     gs_frame frame, gs_raster_cfg cfg, const T* __restrict__ rec, const uint4* __restrict__ meta,
     const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
@@ -271,7 +275,10 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     __shared__ uint32_t s_mask[kRenderWaves][kBwdBatch];
     __shared__ T s_rows[kRenderWaves][kBwdBatch][4][9];
     const int wave = threadIdx.x / kWave, lane = lane_id();
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+    // NS wavefronts per tile: wave `sub` owns the tile's sub-tile of QX x QY
+    // quadrants and stores its own nine partials per pair (slot e NS + sub)
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+    const int tile = gw / NS, sub = gw % NS;
     if (tile >= frame.n_tiles) return;
     const int j = job_of_tile(frame.jobs, frame.n_jobs, tile);
     const gs_job job = frame.jobs[j];
@@ -279,7 +286,8 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     const int W = cam.width, H = cam.height;
     const int lt = tile - job.tile0;
     const int tx = lt % job.tiles_x, ty = lt / job.tiles_x;
-    const int tpx = tx * 8 * QX, tpy = ty * 8 * QY;
+    const int sxn = cfg.tile_w / (8 * QX);
+    const int tpx = tx * cfg.tile_w + (sub % sxn) * 8 * QX, tpy = ty * cfg.tile_h + (sub / sxn) * 8 * QY;
     const int lx = lane & 7, ly = lane >> 3;
     const T bx = T(tpx + lx) + T(0.5), by = T(tpy + ly) + T(0.5);
     const int64_t plane = int64_t(W) * H;
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             // carry zero gradient
             if (uint32_t(lane) < cnt)
 #pragma unroll
-                for (int q = 0; q < 9; q++) pg[int64_t(e_own) * 9 + q] = T(0);
+                for (int q = 0; q < 9; q++) pg[(int64_t(e_own) * NS + sub) * 9 + q] = T(0);
             continue;
         }
         // records that reach some quadrant are staged compacted; the others
@@ -425,7 +433,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
         wave_lds_sync();
         if (uint32_t(lane) < cnt) {
             const T(*rows)[9] = s_rows[wave][slot];
-            T* dst = pg + int64_t(e_own) * 9;
+            T* dst = pg + (int64_t(e_own) * NS + sub) * 9;
 #pragma unroll
             for (int q = 0; q < 9; q++)
                 dst[q] = m != 0 ? (rows[0][q] + rows[1][q]) + (rows[2][q] + rows[3][q]) : T(0);
@@ -436,41 +444,53 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
 
 // ---------------------------------------------------------------------------
 
-template <typename T, int QX, int QY>
+template <typename T, int QX, int QY, int NS>
 static void fwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& b, T* rgb,
                        T* Tfin, uint32_t* nc, unsigned long long* kept, hipStream_t s) {
-    const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
+    const int nb = int((int64_t(f.n_tiles) * NS + kRenderWaves - 1) / kRenderWaves);
     if (kept)
-        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, true>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg,
-                  rec, b.vals, reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept);
+        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, true>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f,
+                  cfg, rec, b.vals, reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept);
     else
-        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, false>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f,
+        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, false>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f,
                   cfg, rec, b.vals, reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept);
 }
 
-template <typename T, int QX, int QY>
+template <typename T, int QX, int QY, int NS>
 static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
                        const gs_bins& b, const T* rgb, int mode, const T* gin, T* loss, T* pg, hipStream_t s) {
-    const int nb = (f.n_tiles + kRenderWaves - 1) / kRenderWaves;
-    GS_LAUNCH("k_render_bwd", (k_render_bwd<T, QX, QY>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
+    const int nb = int((int64_t(f.n_tiles) * NS + kRenderWaves - 1) / kRenderWaves);
+    GS_LAUNCH("k_render_bwd", (k_render_bwd<T, QX, QY, NS>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
                        reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals,
                        reinterpret_cast<const uint2*>(b.ranges), rgb, mode, gin, loss, pg);
 }
 
-// tile shapes in 8x8 quadrants: 8x8 = 1x1, 16x8 = 2x1, 16x16 = 2x2, 32x8 = 4x1
-#define GS_TILE_DISPATCH(FN, ...)                                                       \
-    do {                                                                                \
-        if (cfg.tile_w == 8 && cfg.tile_h == 8) FN<T, 1, 1>(__VA_ARGS__);              \
-        else if (cfg.tile_w == 16 && cfg.tile_h == 8) FN<T, 2, 1>(__VA_ARGS__);        \
-        else if (cfg.tile_w == 32 && cfg.tile_h == 8) FN<T, 4, 1>(__VA_ARGS__);        \
-        else FN<T, 2, 2>(__VA_ARGS__);                                                 \
+// (binning tile, wavefronts per tile) -> quadrants per wavefront QX x QY:
+// 8x8/1 = 1x1; 16x8/1 = 2x1, /2 = 1x1; 16x16/1 = 2x2, /2 = 2x1 (halves stacked),
+// /4 = 1x1; 32x8/1 = 4x1, /2 = 2x1 (halves side by side), /4 = 1x1
+#define GS_TILE_DISPATCH(WAVES, FN, ...)                                                  \
+    do {                                                                                  \
+        const int S_ = WAVES;                                                             \
+        if (cfg.tile_w == 8 && cfg.tile_h == 8) FN<T, 1, 1, 1>(__VA_ARGS__);              \
+        else if (cfg.tile_w == 16 && cfg.tile_h == 8) {                                   \
+            if (S_ == 2) FN<T, 1, 1, 2>(__VA_ARGS__);                                     \
+            else FN<T, 2, 1, 1>(__VA_ARGS__);                                             \
+        } else if (cfg.tile_w == 32 && cfg.tile_h == 8) {                                 \
+            if (S_ == 4) FN<T, 1, 1, 4>(__VA_ARGS__);                                     \
+            else if (S_ == 2) FN<T, 2, 1, 2>(__VA_ARGS__);                                \
+            else FN<T, 4, 1, 1>(__VA_ARGS__);                                             \
+        } else {                                                                          \
+            if (S_ == 4) FN<T, 1, 1, 4>(__VA_ARGS__);                                     \
+            else if (S_ == 2) FN<T, 2, 1, 2>(__VA_ARGS__);                                \
+            else FN<T, 2, 2, 1>(__VA_ARGS__);                                             \
+        }                                                                                 \
     } while (0)
 
 template <typename T>
 hipError_t launch_render_fwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& bins,
                              T* rgb, T* Tfin, uint32_t* ncontrib, unsigned long long* kept, hipStream_t s) {
     if (f.n_tiles == 0) return hipSuccess;
-    GS_TILE_DISPATCH(fwd_launch, f, cfg, rec, bins, rgb, Tfin, ncontrib, kept, s);
+    GS_TILE_DISPATCH(fwd_waves(cfg), fwd_launch, f, cfg, rec, bins, rgb, Tfin, ncontrib, kept, s);
     return hipGetLastError();
 }
 
@@ -479,7 +499,7 @@ hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const 
                              const gs_bins& bins, const T* rgb, gs_loss_mode mode, const T* gin, T* loss, T* pg,
                              hipStream_t s) {
     if (f.n_tiles == 0) return hipSuccess;
-    GS_TILE_DISPATCH(bwd_launch, f, cfg, rec, meta, bins, rgb, int(mode), gin, loss, pg, s);
+    GS_TILE_DISPATCH(bwd_waves(cfg), bwd_launch, f, cfg, rec, meta, bins, rgb, int(mode), gin, loss, pg, s);
     return hipGetLastError();
 }
 

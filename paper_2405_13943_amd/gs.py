@@ -49,7 +49,8 @@ class GsFrame(ctypes.Structure):
 
 class GsRasterCfg(ctypes.Structure):
     _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("near_z", c_f), ("alpha_min", c_f), ("alpha_max", c_f),
-                ("T_min", c_f), ("dilation", c_f), ("jac_clip", c_f), ("bg", c_f * 3), ("reserved", c_i32)]
+                ("T_min", c_f), ("dilation", c_f), ("jac_clip", c_f), ("bg", c_f * 3), ("fwd_waves", ctypes.c_int16),
+                ("bwd_waves", ctypes.c_int16)]
 
 
 class GsBins(ctypes.Structure):
@@ -143,10 +144,17 @@ def params_struct(t: torch.Tensor, sh_degree=None) -> GsParams:
 
 
 def raster_cfg(tile=(16, 16), near_z=0.2, alpha_min=1.0 / 255.0, alpha_max=0.99, T_min=1e-4, dilation=0.3,
-               jac_clip=1.3, bg=(0.0, 0.0, 0.0)) -> GsRasterCfg:
+               jac_clip=1.3, bg=(0.0, 0.0, 0.0), fwd_waves=1, bwd_waves=1) -> GsRasterCfg:
+    """tile: (w, h) binning tile, optionally followed by the forward's and the
+    backward's wavefronts per tile: (w, h, fwd_waves[, bwd_waves])."""
     c = GsRasterCfg()
     lib.gs_raster_cfg_default(ctypes.byref(c))
-    c.tile_w, c.tile_h = tile
+    tile = tuple(tile)
+    if len(tile) >= 3:
+        fwd_waves = tile[2]
+        bwd_waves = tile[3] if len(tile) >= 4 else tile[2]
+    c.tile_w, c.tile_h = tile[:2]
+    c.fwd_waves, c.bwd_waves = int(fwd_waves), int(bwd_waves)
     c.near_z, c.alpha_min, c.alpha_max, c.T_min = near_z, alpha_min, alpha_max, T_min
     c.dilation, c.jac_clip = dilation, jac_clip
     for k in range(3):

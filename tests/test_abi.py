@@ -47,8 +47,8 @@ def test_struct_layouts_match_header(gs, tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gs_params), sizeof(gs_camera), sizeof(gs_job),
          sizeof(gs_frame), sizeof(gs_raster_cfg), sizeof(gs_bins), sizeof(gs_adam_cfg));
-  printf("%zu %zu %zu %zu %zu\\n", offsetof(gs_job, g0), offsetof(gs_job, loss_weight), offsetof(gs_frame, jobs_disjoint),
-         offsetof(gs_raster_cfg, bg), offsetof(gs_adam_cfg, step));
+  printf("%zu %zu %zu %zu %zu %zu\\n", offsetof(gs_job, g0), offsetof(gs_job, loss_weight), offsetof(gs_frame, jobs_disjoint),
+         offsetof(gs_raster_cfg, bg), offsetof(gs_adam_cfg, step), offsetof(gs_raster_cfg, bwd_waves));
   return 0;
 }
 """)
@@ -60,7 +60,7 @@ int main(void) {
     assert sizes == [S(gs.GsParams), S(gs.GsCamera), S(gs.GsJob), S(gs.GsFrame), S(gs.GsRasterCfg), S(gs.GsBins),
                      S(gs.GsAdamCfg)]
     assert offs == [gs.GsJob.g0.offset, gs.GsJob.loss_weight.offset, gs.GsFrame.jobs_disjoint.offset,
-                    gs.GsRasterCfg.bg.offset, gs.GsAdamCfg.step.offset]
+                    gs.GsRasterCfg.bg.offset, gs.GsAdamCfg.step.offset, gs.GsRasterCfg.bwd_waves.offset]
 
 
 def test_frame_plan_host_only(gs):
@@ -111,6 +111,12 @@ def test_invalid_arguments_rejected_without_launch(gs):
     cfg_bad = gs.raster_cfg((12, 12))
     ok = gs.GsParams(None, 0, 0, 0, 0)
     assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(cfg_bad), None, None, None) == gs.GS_E_INVALID
+    for tile in [(8, 8, 2), (16, 8, 4), (16, 16, 3), (32, 8, 8), (16, 16, 2, 3), (8, 8, 1, 2)]:
+        c = gs.raster_cfg(tile)
+        assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None) == gs.GS_E_INVALID
+    for tile in [(16, 16, 4), (32, 8, 2), (16, 8, 2), (16, 16, 2, 1), (32, 8, 4, 2)]:
+        c = gs.raster_cfg(tile)
+        assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None) == gs.GS_OK
     # jobs reaching past the parameter planes
     f2 = gs.GsFrame(1, 1, 1, 1, 10, 10, 11, 1, 0)
     p10 = gs.GsParams(1, 10, 10, 0, 0)
@@ -165,5 +171,5 @@ def test_workspace_sizes_grow_with_inputs(gs):
     a = gs.lib.gs_bin_sort_workspace_size(1000, 10000, 64)
     b = gs.lib.gs_bin_sort_workspace_size(2000, 20000, 64)
     assert 0 < a < b
-    assert gs.lib.gs_render_bwd_workspace_size(1000, 0) == 1000 * 9 * 4
-    assert gs.lib.gs_render_bwd_workspace_size(1000, 1) == 1000 * 9 * 8
+    assert gs.lib.gs_render_bwd_workspace_size(1000, 0) == 1000 * 9 * 4 * 4   # 4 wavefronts per tile at most
+    assert gs.lib.gs_render_bwd_workspace_size(1000, 1) == 1000 * 9 * 8 * 4

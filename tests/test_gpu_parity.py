@@ -150,11 +150,11 @@ def test_render_fwd_matches_oracle(gpu1, ref1):
 
 
 def test_tile_shape_and_batch_invariance(cfg1, gpu1):
-    """Forward images are bit-identical across tile shapes and whether views
-    are rendered batched or one at a time."""
+    """Forward images are bit-identical across tile shapes, wavefronts per
+    tile, and whether views are rendered batched or one at a time."""
     cfg, frame, params, buf = gpu1
     base = images(frame, buf)
-    for tile in [(8, 8), (16, 8), (32, 8)]:
+    for tile in [(8, 8), (16, 8), (32, 8), (16, 8, 2), (16, 16, 2), (16, 16, 4), (32, 8, 2), (32, 8, 4)]:
         c2 = gs.raster_cfg(tile)
         f2 = make_frame(cfg1, c2)
         b2 = gs.rasterize(params, f2, c2)
@@ -216,6 +216,30 @@ def test_render_bwd_matches_oracle(cfg1, gpu1, ref1):
         assert den > 0, name
         assert num / den <= 1e-3, (name, num / den)
     # determinism of the backward (no float atomics on the gradient path)
+    grad2 = torch.empty_like(params)
+    gs.render_bwd(params, frame, cfg, buf, grad2, gs.LOSS_EXTERNAL, gin)
+    assert torch.equal(grad, grad2)
+
+
+@pytest.mark.parametrize("tile", [(16, 16, 2), (16, 16, 4), (32, 8, 4), (16, 8, 2)])
+def test_render_bwd_sub_tile_waves_match_oracle(cfg1, ref1, tile):
+    """Several wavefronts per tile, each storing its own partials per pair:
+    gradients against the FP64 oracle as for one wavefront per tile, and
+    deterministic."""
+    cfg = gs.raster_cfg(tile)
+    frame = make_frame(cfg1, cfg)
+    params = torch.from_numpy(cfg1.params).cuda()
+    buf = gs.rasterize(params, frame, cfg)
+    views = list(range(4))
+    dl = _oracle_dldc(cfg1, views, ref1, 0.25)
+    g_ref = sum(oracle.backward(cfg1.params, cfg1.cams[v], dl[v]) for v in views)
+    gin = torch.cat([torch.from_numpy(d.astype(np.float32)).reshape(-1) for d in dl]).cuda()
+    grad = torch.empty_like(params)
+    gs.render_bwd(params, frame, cfg, buf, grad, gs.LOSS_EXTERNAL, gin)
+    g = grad.cpu().numpy().astype(np.float64)
+    for name, planes in group_planes(params.shape[0]).items():
+        num = np.linalg.norm(g[planes] - g_ref[planes])
+        assert num / np.linalg.norm(g_ref[planes]) <= 1e-3, (name, tile)
     grad2 = torch.empty_like(params)
     gs.render_bwd(params, frame, cfg, buf, grad2, gs.LOSS_EXTERNAL, gin)
     assert torch.equal(grad, grad2)
