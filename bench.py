@@ -486,8 +486,10 @@ def main():
     ap.add_argument("--width", type=int, default=1600)
     ap.add_argument("--height", type=int, default=1066)
     ap.add_argument("--tile", type=int, default=16)
-    ap.add_argument("--fwd-waves", type=int, default=2, help="forward compositing wavefronts per tile (1, 2, 4)")
-    ap.add_argument("--bwd-waves", type=int, default=1, help="backward compositing wavefronts per tile (1, 2, 4)")
+    ap.add_argument("--fwd-waves", type=int, default=-1,
+                    help="forward compositing wavefronts per tile: 1, 2, 4, or -1 per tile from its list length")
+    ap.add_argument("--bwd-waves", type=int, default=-1,
+                    help="backward compositing wavefronts per tile: 1, 2, 4, or -1 per tile from its list length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="backward and optimiser as two calls (gradient in HBM)")
     ap.add_argument("--workload", choices=("train", "blocks4", "serve"), default="train",

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 1
+#define GS_ABI_VERSION 2
 
 typedef enum {
     GS_OK = 0,
@@ -134,9 +134,13 @@ typedef struct {
     int16_t fwd_waves;       /* wavefronts per tile in the forward and in the backward */
     int16_t bwd_waves;       /* compositing, each owning an equal part of the tile and walking
                                 the whole list: 1 (0 = 1), 2 (16x8, 16x16, 32x8) or 4 (16x16,
-                                32x8).  Images do not depend on them; gradients only through
-                                the order of their sums. */
+                                32x8); bwd_waves = GS_WAVES_ADAPTIVE picks 1, 2 or 4 per tile
+                                from its list length against the frame mean (4 above 2.5x,
+                                2 above 1.25x).  Images do not depend on them; gradients only
+                                through the order of their sums. */
 } gs_raster_cfg;
+
+#define GS_WAVES_ADAPTIVE (-1)
 
 /* Tile bins produced by gs_bin_sort. */
 typedef struct {
@@ -145,6 +149,10 @@ typedef struct {
     uint32_t *pair_off;      /* device [n_records]: first pair of each visible record */
     uint32_t *counters;      /* device [GS_N_COUNTERS] */
     uint64_t capacity;       /* pairs vals can hold */
+    uint32_t *tile_order;    /* device [n_tiles + 4] or NULL: the compositing plan written by
+                                gs_bin_sort, needed when fwd_waves or bwd_waves is
+                                GS_WAVES_ADAPTIVE: [0..2] = tiles taking 4, 2 and 1 wavefronts,
+                                then the tile ids, those groups in that order */
 } gs_bins;
 
 /* Adam with the ADMM penalty (Eq. 8a, supplementary Sec. C).  Groups in the
@@ -185,7 +193,8 @@ gs_status gs_frame_plan(const gs_camera *cams_host, int32_t n_cams, gs_job *jobs
  *                times log2 e); log2 opacity; colour r, g, b; depth; the
  *                conservative half-extents (x, y) in pixels of the region
  *                where alpha >= alpha_min
- *   meta[r][4]:  FP32 bits of the depth, number of covered tiles (0 = culled),
+ *   meta[r][4]:  FP32 bits of the depth, number of covered tiles (0 = culled) in
+ *                bits 0..23 with the colour-clamp flags of r, g, b in bits 24..26,
  *                tile rectangle lo (x | y << 16) and hi (inclusive).
  * The rectangle is conservative: every pixel where alpha >= alpha_min lies
  * inside it. */

@@ -219,9 +219,10 @@ class AdmmTrainer:
 # ---------------------------------------------------------------------------
 # tile-shape autotuner
 
-# (binning tile w, h, forward and backward compositing wavefronts per tile)
-TILES = ((16, 16, 2, 1), (16, 16, 1, 1), (16, 16, 4, 1), (16, 16, 2, 2), (32, 8, 2, 1), (32, 8, 4, 1),
-         (32, 8, 1, 1), (16, 8, 2, 1), (8, 8, 1, 1))
+# (binning tile w, h, forward and backward compositing wavefronts per tile;
+# -1: per tile from its list length)
+TILES = ((16, 16, -1, -1), (32, 8, -1, -1), (16, 16, 2, 1), (16, 16, 2, -1), (16, 16, -1, 1), (32, 8, 2, 1),
+         (16, 8, -1, -1), (8, 8, 1, 1))
 
 
 def autotune_tile(run_step, key: str, cache_path=None, candidates=TILES, reps=5):

@@ -47,7 +47,10 @@ bool waves_ok(const gs_raster_cfg* c, int waves) {
     return false;
 }
 
-bool tile_ok(const gs_raster_cfg* c) { return waves_ok(c, c->fwd_waves) && waves_ok(c, c->bwd_waves); }
+bool tile_ok(const gs_raster_cfg* c) {
+    auto ok = [&](int w) { return w == GS_WAVES_ADAPTIVE ? waves_ok(c, 1) : waves_ok(c, w); };
+    return ok(c->fwd_waves) && ok(c->bwd_waves);
+}
 
 gs_status check_frame(const gs_frame* f, const gs_raster_cfg* cfg) {
     if (!f || !cfg) return fail(GS_E_INVALID, "null frame or raster config");
@@ -64,8 +67,10 @@ gs_status check_frame(const gs_frame* f, const gs_raster_cfg* cfg) {
     return GS_OK;
 }
 
-gs_status check_bins(const gs_bins* b, const gs_frame* f) {
+gs_status check_bins(const gs_bins* b, const gs_frame* f, const gs_raster_cfg* cfg = nullptr) {
     if (!b) return fail(GS_E_INVALID, "null gs_bins");
+    if (cfg && !b->tile_order && (cfg->fwd_waves == GS_WAVES_ADAPTIVE || cfg->bwd_waves == GS_WAVES_ADAPTIVE))
+        return fail(GS_E_INVALID, "adaptive wavefronts need gs_bins.tile_order");
     if (!b->counters || !b->ranges || (!b->pair_off && f->n_records > 0) || (!b->vals && b->capacity > 0))
         return fail(GS_E_INVALID, "null gs_bins buffer");
     if (b->capacity >= (uint64_t(1) << 32)) return fail(GS_E_UNSUPPORTED, "pair capacity must be below 2^32");
@@ -90,7 +95,7 @@ gs_status render_fwd_impl(const gs_frame* frame, const gs_raster_cfg* cfg, const
                           void* rgb, void* Tf, uint32_t* nc, gs_stream stream, uint64_t* kept = nullptr) {
     gs_status st;
     if ((st = check_frame(frame, cfg)) != GS_OK) return st;
-    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame, cfg)) != GS_OK) return st;
     if (frame->n_pixels > 0 && (!rgb || !Tf || !nc)) return fail(GS_E_INVALID, "null image buffers");
     if (frame->n_records > 0 && !rec) return fail(GS_E_INVALID, "null record buffer");
     return check_hip(gs::launch_render_fwd<T>(*frame, *cfg, static_cast<const T*>(rec), *bins, static_cast<T*>(rgb),
@@ -113,7 +118,7 @@ gs_status render_bwd_impl(const gs_params* params, const gs_frame* frame, const 
     if ((st = check_params(params, "params")) != GS_OK) return st;
     if ((st = check_params(grad, "grad")) != GS_OK) return st;
     if ((st = check_frame(frame, cfg)) != GS_OK) return st;
-    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame, cfg)) != GS_OK) return st;
     if (grad->n != params->n || grad->sh_degree != params->sh_degree)
         return fail(GS_E_INVALID, "grad planes do not match params");
     if (frame->g_max > params->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
@@ -129,7 +134,7 @@ gs_status render_bwd_impl(const gs_params* params, const gs_frame* frame, const 
     hipError_t e = gs::launch_render_bwd<T>(*frame, *cfg, static_cast<const T*>(rec), meta, *bins,
                                             static_cast<const T*>(rgb), mode, static_cast<const T*>(gin), loss, pg, s);
     if (e != hipSuccess) return check_hip(e, "gs_render_bwd (composite)");
-    return check_hip(gs::launch_project_bwd<T>(*params, *frame, *cfg, meta, bins->pair_off, bins->capacity, pg, *grad, s),
+    return check_hip(gs::launch_project_bwd<T>(*params, *frame, *cfg, meta, *bins, pg, *grad, s),
                      "gs_render_bwd (projection)");
 }
 
@@ -218,7 +223,7 @@ gs_status gs_bin_sort(const gs_frame* frame, const gs_raster_cfg* cfg, const uin
                       void* ws, size_t ws_bytes, gs_stream stream) {
     gs_status st;
     if ((st = check_frame(frame, cfg)) != GS_OK) return st;
-    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame, cfg)) != GS_OK) return st;
     if (frame->n_records > 0 && !meta) return fail(GS_E_INVALID, "null meta");
     const size_t need = gs::bin_workspace_size(frame->n_records, bins->capacity, frame->n_tiles);
     if (!ws || ws_bytes < need) return fail(GS_E_CAPACITY, "binning workspace too small (%zu < %zu)", ws_bytes, need);
@@ -298,7 +303,7 @@ gs_status gs_render_bwd_adam(gs_params* x, const gs_frame* frame, const gs_raste
     gs_status st;
     if ((st = check_adam(x, nullptr, m, v, w, mask, acfg)) != GS_OK) return st;
     if ((st = check_frame(frame, cfg)) != GS_OK) return st;
-    if ((st = check_bins(bins, frame)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame, cfg)) != GS_OK) return st;
     if (!frame->jobs_disjoint)
         return fail(GS_E_UNSUPPORTED, "jobs share Gaussians: call gs_render_bwd, then gs_adam_admm");
     if (frame->g_max > x->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
@@ -314,8 +319,7 @@ gs_status gs_render_bwd_adam(gs_params* x, const gs_frame* frame, const gs_raste
                                                 static_cast<const float*>(rgb), mode, static_cast<const float*>(gin),
                                                 loss, pg, s);
     if (e != hipSuccess) return check_hip(e, "gs_render_bwd_adam (composite)");
-    return check_hip(gs::launch_project_bwd_adam(*x, *frame, *cfg, meta, bins->pair_off, bins->capacity, pg, *m, *v, w,
-                                                 mask, *acfg, s),
+    return check_hip(gs::launch_project_bwd_adam(*x, *frame, *cfg, meta, *bins, pg, *m, *v, w, mask, *acfg, s),
                      "gs_render_bwd_adam (projection + optimiser)");
 }
 

@@ -361,6 +361,36 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tke
     }
 }
 
+// Compositing plan for adaptive wavefronts: every tile's wavefront count
+// (adaptive_waves of its list length) and the tiles grouped by it, 4-wave
+// tiles first (one workgroup each, and the longest lists start first), then
+// 2-wave, then 1-wave tiles.  One workgroup; the order inside a group is
+// whatever the LDS atomics give, which changes no result (each tile is
+// composited on its own).
+__global__ __launch_bounds__(1024) void k_tile_plan(const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ counters, int n_tiles, int quads,
+                                                    uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[3], cur[3];
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t pairs = counters[GS_CTR_PAIRS];
+    auto group = [&](int t) {
+        const uint2 rg = ranges[t];
+        const int w = adaptive_waves(rg.y - rg.x, pairs, n_tiles, quads);
+        return w == 4 ? 0 : (w == 2 ? 1 : 2);
+    };
+    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) atomicAdd(&cnt[group(t)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cur[0] = 0u;
+        cur[1] = cnt[0];
+        cur[2] = cnt[0] + cnt[1];
+    }
+    if (threadIdx.x < 3) order[threadIdx.x] = cnt[threadIdx.x];
+    __syncthreads();
+    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) order[4 + atomicAdd(&cur[group(t)], 1u)] = uint32_t(t);
+}
+
 // ---------------------------------------------------------------------------
 
 static int grid_for(uint64_t n_max, int per_block) {
@@ -399,7 +429,16 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     const int64_t nr2 = int64_t(f.n_tiles) * 2;
     GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(std::min<int64_t>((nr2 + 255) / 256, 2048))), dim3(256), 0, s,
                        bins.ranges, 0u, nr2);
-    if (nrec == 0) return hipGetLastError();
+    auto plan = [&]() {
+        if (bins.tile_order && (fwd_waves(cfg) == 0 || bwd_waves(cfg) == 0))
+            GS_LAUNCH("k_tile_plan", k_tile_plan, dim3(1), dim3(1024), 0, s,
+                      reinterpret_cast<const uint2*>(bins.ranges), bins.counters, f.n_tiles,
+                      (cfg.tile_w / 8) * (cfg.tile_h / 8), bins.tile_order);
+    };
+    if (nrec == 0) {
+        plan();
+        return hipGetLastError();
+    }
 
     // 1. compact visible records as (depth bits, record)
     const int Gs = grid_for(nrec, kScanBlock * 8);
@@ -442,6 +481,8 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     // 5. per-tile [start, end)
     GS_LAUNCH("k_ranges", k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity,
                        reinterpret_cast<uint2*>(bins.ranges));
+    // 6. compositing plan, when a pass splits tiles adaptively
+    plan();
     return hipGetLastError();
 }
 

@@ -45,13 +45,74 @@ template <typename T> __device__ constexpr T kLog2e() { return T(1.4426950408889
 // per-record metadata word 1: covered tiles in the low 24 bits, the colour
 // clamp of each channel (SH sum + 0.5 <= 0) in bits 24..26
 
-// compositing wavefronts per tile of the forward and the backward (0 reads as 1)
-__host__ __device__ inline int fwd_waves(const gs_raster_cfg& c) { return c.fwd_waves <= 1 ? 1 : c.fwd_waves; }
-__host__ __device__ inline int bwd_waves(const gs_raster_cfg& c) { return c.bwd_waves <= 1 ? 1 : c.bwd_waves; }
+// compositing wavefronts per tile of the forward and the backward (0 reads
+// as 1; GS_WAVES_ADAPTIVE in the backward: per tile, see adaptive_waves)
+__host__ __device__ inline int fwd_waves(const gs_raster_cfg& c) {
+    return c.fwd_waves == GS_WAVES_ADAPTIVE ? 0 : (c.fwd_waves <= 1 ? 1 : c.fwd_waves);
+}
+__host__ __device__ inline bool bwd_adaptive(const gs_raster_cfg& c) { return c.bwd_waves == GS_WAVES_ADAPTIVE; }
+__host__ __device__ inline int bwd_waves(const gs_raster_cfg& c) {
+    return bwd_adaptive(c) ? 0 : (c.bwd_waves <= 1 ? 1 : c.bwd_waves);
+}
+// backward partial slots per tile pair the projection backward reads: one
+// per wavefront; adaptive: one (split tiles fold theirs into the first)
+__host__ __device__ inline int bwd_slots(const gs_raster_cfg& c) { return bwd_adaptive(c) ? 1 : bwd_waves(c); }
+
+// Wavefronts of one tile in the adaptive backward, from its list length
+// against the frame's mean list length: 4 above 2.5 x the mean, 2 above
+// 1.25 x, else 1; never more than the tile's quadrants.  Exact integer
+// arithmetic, so the compositing backward and the projection backward agree.
+__device__ inline int adaptive_waves(uint32_t count, uint32_t pairs, int n_tiles, int quads) {
+    const uint64_t a = 4ull * count * uint64_t(n_tiles);
+    const int s = a > 10ull * pairs ? 4 : (a > 5ull * pairs ? 2 : 1);
+    return s < quads ? s : quads;
+}
+
+// Wavefront gw of an adaptive compositing launch -> (tile, sub, waves) from
+// the plan of k_tile_plan; false when the wavefront has no work (past the
+// plan, or a plan that does not describe n_tiles tiles).
+__device__ inline bool plan_wave(const uint32_t* __restrict__ order, int n_tiles, uint32_t gw, int& tile, int& sub,
+                                 int& waves) {
+    const uint32_t nt = uint32_t(n_tiles), n4 = order[0], n2 = order[1], n1 = order[2];
+    if (n4 > nt || n2 > nt || n1 > nt || n4 + n2 + n1 != nt) return false;
+    const uint32_t* list = order + 4;
+    uint32_t g = gw, t;
+    if (g < 4u * n4) {
+        t = list[g / 4u];
+        sub = int(g % 4u);
+        waves = 4;
+    } else if ((g -= 4u * n4) < 2u * n2) {
+        t = list[n4 + g / 2u];
+        sub = int(g % 2u);
+        waves = 2;
+    } else if ((g -= 2u * n2) < n1) {
+        t = list[n4 + n2 + g];
+        sub = 0;
+        waves = 1;
+    } else {
+        return false;
+    }
+    tile = int(t);
+    return t < nt;
+}
+
+// Partials of wavefront `sub` for pair e in the adaptive layout: slot 0 of
+// every pair dense at e, the slots of the further wavefronts of split tiles
+// after all of them (3 per pair), so a one-wavefront tile's pairs stay
+// contiguous.  Capacity counts pairs; 9 values per slot.
+__host__ __device__ inline int64_t adaptive_slot(uint64_t capacity, uint64_t e, int sub) {
+    return sub == 0 ? int64_t(e) * 9 : (int64_t(capacity) + int64_t(e) * 3 + (sub - 1)) * 9;
+}
+
+// quadrants (bit k = quadrant k of the tile) owned by wavefront `sub` of `waves`
+__device__ inline uint32_t owned_quadrants(int quads, int waves, int sub) {
+    const int per = quads / waves;
+    return ((1u << per) - 1u) << (sub * per);
+}
 
 constexpr uint32_t kTilesMask = 0xffffffu;
 __host__ __device__ inline uint32_t meta_tiles(uint32_t y) { return y & kTilesMask; }
-__host__ __device__ inline uint32_t meta_clamp(uint32_t y) { return y >> 24; }
+__host__ __device__ inline uint32_t meta_clamp(uint32_t y) { return (y >> 24) & 7u; }
 
 // ---------------------------------------------------------------------------
 // job lookup: jobs are laid out in ascending rec0 / tile0 / px0 order

@@ -43,14 +43,12 @@ hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster
                           uint32_t* meta, hipStream_t s);
 template <typename T>
 hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
-                              const uint32_t* meta, const uint32_t* pair_off, uint64_t capacity, const T* pg,
-                              gs_params& grad, hipStream_t s);
+                              const uint32_t* meta, const gs_bins& bins, const T* pg, gs_params& grad, hipStream_t s);
 
 // fused projection backward + Adam/ADMM (FP32, jobs over disjoint ranges)
 hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta,
-                                   const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
-                                   gs_params& v, const gs_params* w, const float* mask, const gs_adam_cfg& acfg,
-                                   hipStream_t s);
+                                   const gs_bins& bins, const float* pg, gs_params& m, gs_params& v,
+                                   const gs_params* w, const float* mask, const gs_adam_cfg& acfg, hipStream_t s);
 
 // binning.hip
 size_t bin_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles);

@@ -328,15 +328,30 @@ __device__ inline void record_pair_sum(const T* __restrict__ pg, uint64_t p0, ui
     }
 }
 
-// partial slots of a record: its emitted pairs (pairs past the capacity never
-// were: the overflow status is set and the step must be redone), each with S
-// consecutive slots, one per compositing wavefront of the tile
-__device__ inline void record_pairs(uint32_t ntiles, uint32_t off, uint64_t capacity, int S, uint64_t& p0,
+// emitted pairs of a record (pairs past the capacity never were: the
+// overflow status is set and the step must be redone)
+__device__ inline void record_pairs(uint32_t ntiles, uint32_t off, uint64_t capacity, uint64_t& p0,
                                     uint64_t& np) {
     p0 = off;
     np = ntiles == 0 || p0 >= capacity ? 0 : (p0 + ntiles > capacity ? capacity - p0 : ntiles);
-    p0 *= uint64_t(S);
-    np *= uint64_t(S);
+}
+
+// Where the compositing backward left a pair's partials: `slots` consecutive
+// slots per pair, one per wavefront of its tile (one when the wavefronts were
+// adaptive: split tiles fold theirs into the first).
+struct PartialLayout {
+    int slots;
+};
+
+// Per lane: the 9 partials of its record summed over its pairs' slots (pair,
+// then slot, ascending; large records cooperatively).  Every lane of the wave
+// must call this.
+template <typename T>
+__device__ inline void record_partials(const T* __restrict__ pg, const PartialLayout& L, const uint4& m,
+                                       uint32_t off, uint64_t capacity, T* d) {
+    uint64_t p0, np;
+    record_pairs(meta_tiles(m.y), off, capacity, p0, np);
+    record_pair_sum(pg, p0 * uint64_t(L.slots), np * uint64_t(L.slots), d);
 }
 
 // Chain rule of one visible record of Gaussian g seen by `camera`; emit(a, v)
@@ -493,7 +508,7 @@ template <typename T, int D>
 __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P, int64_t stride, gs_frame frame,
                                                           gs_raster_cfg cfg, const uint4* __restrict__ meta,
                                                           const uint32_t* __restrict__ pair_off, uint64_t capacity,
-                                                          int S, const T* __restrict__ pg, T* __restrict__ grad,
+                                                          PartialLayout L, const T* __restrict__ pg, T* __restrict__ grad,
                                                           int64_t gstride) {
     constexpr int A = 11 + 3 * (D + 1) * (D + 1);
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -503,10 +518,8 @@ __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P
     const int64_t g = job.g0 + (r - job.rec0);
     const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t ntiles = meta_tiles(m.y);
-    uint64_t p0, np;
-    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, S, p0, np);
     T d[9];
-    record_pair_sum(pg, p0, np, d);
+    record_partials(pg, L, m, ntiles ? pair_off[r] : 0u, capacity, d);
     if (!active) return;
     T* gout = grad + g;
     if (ntiles == 0) {
@@ -525,7 +538,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P
                                                           gs_frame frame, gs_raster_cfg cfg,
                                                           const uint4* __restrict__ meta,
                                                           const uint32_t* __restrict__ pair_off, uint64_t capacity,
-                                                          int S, const T* __restrict__ pg, T* __restrict__ grad,
+                                                          PartialLayout L, const T* __restrict__ pg, T* __restrict__ grad,
                                                           int64_t gstride) {
     constexpr int A = 11 + 3 * (D + 1) * (D + 1);
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -539,10 +552,8 @@ __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P
         const int64_t r = in_job ? job.rec0 + (g - job.g0) : 0;
         const uint4 m = in_job ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
         const uint32_t ntiles = meta_tiles(m.y);
-        uint64_t p0, np;
-        record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, S, p0, np);
         T d[9];
-        record_pair_sum(pg, p0, np, d);
+        record_partials(pg, L, m, ntiles ? pair_off[r] : 0u, capacity, d);
         if (ntiles == 0) continue;
         record_chain<T, D>(P, stride, g, frame.cams[job.cam], cfg, m.y, d,
                            [&](int a, T v) { gout[int64_t(a) * gstride] += v; });
@@ -622,7 +633,8 @@ __device__ inline void adam_block_one(float* __restrict__ X, int64_t sx, float* 
 template <int D, bool PEN, bool MASK, bool VEC>
 __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     float* X, int64_t sx, gs_frame frame, gs_raster_cfg cfg, const uint4* __restrict__ meta,
-    const uint32_t* __restrict__ pair_off, uint64_t capacity, int S, const float* __restrict__ pg, float* __restrict__ M,
+    const uint32_t* __restrict__ pair_off, uint64_t capacity, PartialLayout L, const float* __restrict__ pg,
+    float* __restrict__ M,
     int64_t sm, float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
     const float* __restrict__ mask, AdamConsts c) {
     constexpr int NK = (D + 1) * (D + 1);
@@ -639,10 +651,8 @@ __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     const int64_t g = job.g0 + (r - job.rec0);
     const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t ntiles = meta_tiles(m.y);
-    uint64_t p0, np;
-    record_pairs(ntiles, ntiles ? pair_off[r] : 0u, capacity, S, p0, np);
     float d[9];
-    record_pair_sum(pg, p0, np, d);
+    record_partials(pg, L, m, ntiles ? pair_off[r] : 0u, capacity, d);
 
     // phase 1: chain rule into LDS
     float Y[NK], dc[3];
@@ -728,10 +738,17 @@ hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster
     return hipGetLastError();
 }
 
+template <typename T>
+static PartialLayout partial_layout(const gs_raster_cfg& cfg, const gs_bins&, const T*) {
+    PartialLayout L;
+    L.slots = bwd_slots(cfg);
+    return L;
+}
+
 template <typename T, int D>
 static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
-                                 const uint32_t* pair_off, uint64_t capacity, const T* pg, gs_params& grad,
-                                 hipStream_t s) {
+                                 const uint32_t* pair_off, uint64_t capacity, const PartialLayout& L, const T* pg,
+                                 gs_params& grad, hipStream_t s) {
     const T* P = static_cast<const T*>(p.data);
     T* Gd = static_cast<T*>(grad.data);
     if (f.jobs_disjoint) {
@@ -741,24 +758,26 @@ static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs
                                11 + 3 * (D + 1) * (D + 1), Gd, grad.stride);
         if (f.n_records > 0)
             GS_LAUNCH("k_project_bwd_rec", (k_project_bwd_rec<T, D>), dim3(unsigned((f.n_records + 127) / 128)), dim3(128), 0, s,
-                               P, p.stride, f, cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Gd, grad.stride);
+                               P, p.stride, f, cfg, M, pair_off, capacity, L, pg, Gd, grad.stride);
     } else {
         GS_LAUNCH("k_project_bwd_acc", (k_project_bwd_acc<T, D>), dim3(unsigned((p.n + 127) / 128)), dim3(128), 0, s, P,
-                           p.stride, p.n, f, cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Gd, grad.stride);
+                           p.stride, p.n, f, cfg, M, pair_off, capacity, L, pg, Gd, grad.stride);
     }
 }
 
 template <typename T>
 hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
-                              const uint32_t* meta, const uint32_t* pair_off, uint64_t capacity, const T* pg,
-                              gs_params& grad, hipStream_t s) {
+                              const uint32_t* meta, const gs_bins& bins, const T* pg, gs_params& grad, hipStream_t s) {
     if (p.n == 0) return hipSuccess;
     const uint4* M = reinterpret_cast<const uint4*>(meta);
+    const PartialLayout L = partial_layout(cfg, bins, pg);
+    const uint32_t* po = bins.pair_off;
+    const uint64_t cap = bins.capacity;
     switch (p.sh_degree) {
-        case 0: project_bwd_dispatch<T, 0>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
-        case 1: project_bwd_dispatch<T, 1>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
-        case 2: project_bwd_dispatch<T, 2>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
-        default: project_bwd_dispatch<T, 3>(p, f, cfg, M, pair_off, capacity, pg, grad, s); break;
+        case 0: project_bwd_dispatch<T, 0>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
+        case 1: project_bwd_dispatch<T, 1>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
+        case 2: project_bwd_dispatch<T, 2>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
+        default: project_bwd_dispatch<T, 3>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
     }
     return hipGetLastError();
 }
@@ -767,9 +786,9 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 template <int D, bool PEN, bool MASK>
 static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
-                                    const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
-                                    gs_params& v, const gs_params* w, const float* mask, const AdamConsts& c,
-                                    hipStream_t s) {
+                                    const uint32_t* pair_off, uint64_t capacity, const PartialLayout& L,
+                                    const float* pg, gs_params& m, gs_params& v, const gs_params* w,
+                                    const float* mask, const AdamConsts& c, hipStream_t s) {
     float* X = static_cast<float*>(x.data);
     float* Mo = static_cast<float*>(m.data);
     float* Vo = static_cast<float*>(v.data);
@@ -785,41 +804,43 @@ static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_ra
     const dim3 grid(unsigned((f.n_records + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
     if (f.n_records > 0 && vec)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, true>), grid, block, 0, s, X, x.stride, f,
-                  cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+                  cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
     else if (f.n_records > 0)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, false>), grid, block, 0, s, X, x.stride,
-                  f, cfg, M, pair_off, capacity, bwd_waves(cfg), pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+                  f, cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
 }
 
 template <int D>
 static void project_bwd_adam_pen(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
-                                 const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
-                                 gs_params& v, const gs_params* w, const float* mask, const AdamConsts& c,
-                                 hipStream_t s) {
-    if (w && mask) project_bwd_adam_launch<D, true, true>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s);
-    else if (w) project_bwd_adam_launch<D, true, false>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s);
-    else project_bwd_adam_launch<D, false, false>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s);
+                                 const uint32_t* po, uint64_t cap, const PartialLayout& L, const float* pg,
+                                 gs_params& m, gs_params& v, const gs_params* w, const float* mask,
+                                 const AdamConsts& c, hipStream_t s) {
+    if (w && mask) project_bwd_adam_launch<D, true, true>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s);
+    else if (w) project_bwd_adam_launch<D, true, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s);
+    else project_bwd_adam_launch<D, false, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s);
 }
 
 hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta,
-                                   const uint32_t* pair_off, uint64_t capacity, const float* pg, gs_params& m,
-                                   gs_params& v, const gs_params* w, const float* mask, const gs_adam_cfg& acfg,
-                                   hipStream_t s) {
+                                   const gs_bins& bins, const float* pg, gs_params& m, gs_params& v,
+                                   const gs_params* w, const float* mask, const gs_adam_cfg& acfg, hipStream_t s) {
     if (x.n == 0) return hipSuccess;
     const uint4* M = reinterpret_cast<const uint4*>(meta);
     const AdamConsts c = adam_consts(acfg);
+    const PartialLayout L = partial_layout(cfg, bins, pg);
+    const uint32_t* po = bins.pair_off;
+    const uint64_t cap = bins.capacity;
     switch (x.sh_degree) {
-        case 0: project_bwd_adam_pen<0>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
-        case 1: project_bwd_adam_pen<1>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
-        case 2: project_bwd_adam_pen<2>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
-        default: project_bwd_adam_pen<3>(x, f, cfg, M, pair_off, capacity, pg, m, v, w, mask, c, s); break;
+        case 0: project_bwd_adam_pen<0>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
+        case 1: project_bwd_adam_pen<1>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
+        case 2: project_bwd_adam_pen<2>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
+        default: project_bwd_adam_pen<3>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
     }
     return hipGetLastError();
 }
 
 template hipError_t launch_project<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, float*, uint32_t*, hipStream_t);
 template hipError_t launch_project<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, double*, uint32_t*, hipStream_t);
-template hipError_t launch_project_bwd<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const uint32_t*, uint64_t, const float*, gs_params&, hipStream_t);
-template hipError_t launch_project_bwd<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const uint32_t*, uint64_t, const double*, gs_params&, hipStream_t);
+template hipError_t launch_project_bwd<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const gs_bins&, const float*, gs_params&, hipStream_t);
+template hipError_t launch_project_bwd<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const gs_bins&, const double*, gs_params&, hipStream_t);
 
 }  // namespace gs

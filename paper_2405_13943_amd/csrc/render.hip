@@ -153,23 +153,37 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
                                                                      const uint2* __restrict__ ranges,
                                                                      T* __restrict__ rgb, T* __restrict__ Tout,
                                                                      uint32_t* __restrict__ ncontrib,
-                                                                     unsigned long long* __restrict__ kept) {
+                                                                     unsigned long long* __restrict__ kept,
+                                                                     const uint32_t* __restrict__ order) {
     constexpr int PPL = QX * QY;
+    // NS wavefronts per tile, wave `sub` owning the tile's sub-tile of QX x QY
+    // quadrants; NS = 0: the plan's wavefronts, heavy tiles first, each owning
+    // a run of the tile's quadrants (QX x QY is then the tile)
+    constexpr bool ADAPT = NS == 0;
+    constexpr int NSD = ADAPT ? 1 : NS;
     __shared__ T s_rec[kRenderWaves][kWave][GS_REC_WORDS];
     __shared__ uint32_t s_mask[kRenderWaves][kWave];
     const int wave = threadIdx.x / kWave, lane = lane_id();
-    // NS wavefronts per tile: wave `sub` owns the tile's sub-tile of QX x QY quadrants
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
-    const int tile = gw / NS, sub = gw % NS;
-    if (tile >= frame.n_tiles) return;
+    int tile, sub;
+    uint32_t owned = (1u << PPL) - 1u;
+    if (ADAPT) {
+        int waves;
+        if (!plan_wave(order, frame.n_tiles, blockIdx.x * kRenderWaves + wave, tile, sub, waves)) return;
+        owned = owned_quadrants(PPL, waves, sub);
+    } else {
+        const int gw = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+        tile = gw / NSD;
+        sub = gw % NSD;
+        if (tile >= frame.n_tiles) return;
+    }
     const int j = job_of_tile(frame.jobs, frame.n_jobs, tile);
     const gs_job job = frame.jobs[j];
     const gs_camera& cam = frame.cams[job.cam];
     const int W = cam.width, H = cam.height;
     const int lt = tile - job.tile0;
     const int sxn = cfg.tile_w / (8 * QX);   // sub-tiles per tile row
-    const int tpx = (lt % job.tiles_x) * cfg.tile_w + (sub % sxn) * 8 * QX;
-    const int tpy = (lt / job.tiles_x) * cfg.tile_h + (sub / sxn) * 8 * QY;
+    const int tpx = (lt % job.tiles_x) * cfg.tile_w + (ADAPT ? 0 : (sub % sxn) * 8 * QX);
+    const int tpy = (lt / job.tiles_x) * cfg.tile_h + (ADAPT ? 0 : (sub / sxn) * 8 * QY);
     const int lx = lane & 7, ly = lane >> 3;
     // pixel centre of quadrant k: (bx + 8 (k % QX), by + 8 (k / QX))
     const T bx = T(tpx + lx) + T(0.5), by = T(tpy + ly) + T(0.5);
@@ -181,7 +195,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
-        done |= (x < W && y < H) ? 0u : (1u << k);
+        done |= (x < W && y < H && (owned & (1u << k))) ? 0u : (1u << k);
         Tr[k] = T(1);
         C[k][0] = C[k][1] = C[k][2] = T(0);
         last[k] = 0;
@@ -200,7 +214,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
         if (uint32_t(lane) < cnt) {
             r = vals[base + lane];
             load_rec(rec, r, w);
-            m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin);
+            m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin) & owned;
         }
         const uint64_t staged = __ballot(m != 0);
         if (m != 0) {
@@ -250,7 +264,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
-        if (x < W && y < H) {
+        if (x < W && y < H && (owned & (1u << k))) {
             const int64_t p = job.px0 + int64_t(y) * W + x;
             T* out = rgb + 3 * job.px0 + int64_t(y) * W + x;
             out[0] = C[k][0] + Tr[k] * T(cfg.bg[0]);
@@ -269,17 +283,37 @@ template <typename T, int QX, int QY, int NS>
 __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     gs_frame frame, gs_raster_cfg cfg, const T* __restrict__ rec, const uint4* __restrict__ meta,
     const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
-    const T* __restrict__ rgb, int mode, const T* __restrict__ gin, T* __restrict__ loss_out, T* __restrict__ pg) {
+    const uint32_t* __restrict__ order, uint64_t capacity, const T* __restrict__ rgb, int mode,
+    const T* __restrict__ gin, T* __restrict__ loss_out, T* __restrict__ pg) {
     constexpr int PPL = QX * QY;
+    // NS wavefronts per tile, wave `sub` owning the tile's sub-tile of QX x QY
+    // quadrants and storing its own nine partials per pair (slot e NS + sub);
+    // NS = 0: the plan's wavefronts, heavy tiles first, each owning a run of
+    // the tile's quadrants (QX x QY is then the tile), partials in the
+    // adaptive layout
+    constexpr bool ADAPT = NS == 0;
+    constexpr int NSD = ADAPT ? 1 : NS;
     __shared__ T s_rec[kRenderWaves][kBwdBatch][GS_REC_WORDS];
     __shared__ uint32_t s_mask[kRenderWaves][kBwdBatch];
     __shared__ T s_rows[kRenderWaves][kBwdBatch][4][9];
     const int wave = threadIdx.x / kWave, lane = lane_id();
-    // NS wavefronts per tile: wave `sub` owns the tile's sub-tile of QX x QY
-    // quadrants and stores its own nine partials per pair (slot e NS + sub)
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
-    const int tile = gw / NS, sub = gw % NS;
-    if (tile >= frame.n_tiles) return;
+    int tile = 0, sub = 0, nwaves = NSD;
+    uint32_t owned = (1u << PPL) - 1u;
+    bool valid = true;   // adaptive: no early return, the workgroup may meet at a barrier below
+    if (ADAPT) {
+        valid = plan_wave(order, frame.n_tiles, blockIdx.x * kRenderWaves + wave, tile, sub, nwaves);
+        owned = valid ? owned_quadrants(PPL, nwaves, sub) : 0u;
+    } else {
+        const int gw = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
+        tile = gw / NSD;
+        sub = gw % NSD;
+        if (tile >= frame.n_tiles) return;
+    }
+    auto pslot = [&](uint32_t e) {
+        return ADAPT ? adaptive_slot(capacity, e, sub) : (int64_t(e) * NSD + sub) * 9;
+    };
+    do {
+    if (!valid) break;
     const int j = job_of_tile(frame.jobs, frame.n_jobs, tile);
     const gs_job job = frame.jobs[j];
     const gs_camera& cam = frame.cams[job.cam];
@@ -287,7 +321,8 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     const int lt = tile - job.tile0;
     const int tx = lt % job.tiles_x, ty = lt / job.tiles_x;
     const int sxn = cfg.tile_w / (8 * QX);
-    const int tpx = tx * cfg.tile_w + (sub % sxn) * 8 * QX, tpy = ty * cfg.tile_h + (sub / sxn) * 8 * QY;
+    const int tpx = tx * cfg.tile_w + (ADAPT ? 0 : (sub % sxn) * 8 * QX);
+    const int tpy = ty * cfg.tile_h + (ADAPT ? 0 : (sub / sxn) * 8 * QY);
     const int lx = lane & 7, ly = lane >> 3;
     const T bx = T(tpx + lx) + T(0.5), by = T(tpy + ly) + T(0.5);
     const int64_t plane = int64_t(W) * H;
@@ -301,7 +336,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
-        const bool in = x < W && y < H;
+        const bool in = x < W && y < H && (owned & (1u << k));
         done |= in ? 0u : (1u << k);
         Tr[k] = T(1);
         D[k] = S[k] = T(0);
@@ -344,7 +379,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             r = vals[base + lane];
             if (any_alive) {
                 load_rec(rec, r, w);
-                m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin);
+                m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin) & owned;
             }
             // emission index of pair (this tile, r): the record's pairs run
             // row by row over its tile rectangle
@@ -357,7 +392,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             // carry zero gradient
             if (uint32_t(lane) < cnt)
 #pragma unroll
-                for (int q = 0; q < 9; q++) pg[(int64_t(e_own) * NS + sub) * 9 + q] = T(0);
+                for (int q = 0; q < 9; q++) pg[pslot(e_own) + q] = T(0);
             continue;
         }
         // records that reach some quadrant are staged compacted; the others
@@ -433,54 +468,109 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
         wave_lds_sync();
         if (uint32_t(lane) < cnt) {
             const T(*rows)[9] = s_rows[wave][slot];
-            T* dst = pg + (int64_t(e_own) * NS + sub) * 9;
+            T* dst = pg + pslot(e_own);
 #pragma unroll
             for (int q = 0; q < 9; q++)
                 dst[q] = m != 0 ? (rows[0][q] + rows[1][q]) + (rows[2][q] + rows[3][q]) : T(0);
         }
         __builtin_amdgcn_wave_barrier();
     }
+    } while (0);
+
+    // Adaptive: a split tile's wavefronts share this workgroup.  Once all of
+    // them have stored their partials, fold each pair's further slots into
+    // slot 0 (slot 0 + 1 + 2 + 3, in that order), so the projection backward
+    // reads one dense slot per pair.  Whether a workgroup holds a split tile
+    // is the same for all its wavefronts (the plan puts split tiles first),
+    // and none of them has left the kernel.
+    if (ADAPT) {
+        const uint64_t split_waves = 4ull * order[0] + 2ull * order[1];
+        if (4ull * blockIdx.x < split_waves) {
+            __syncthreads();
+            if (valid && nwaves > 1) {
+                const int jf = job_of_tile(frame.jobs, frame.n_jobs, tile);
+                const gs_job jb = frame.jobs[jf];
+                const int ltf = tile - jb.tile0;
+                const uint32_t ftx = uint32_t(ltf % jb.tiles_x), fty = uint32_t(ltf / jb.tiles_x);
+                const uint2 rg = ranges[tile];
+                for (uint32_t i = rg.x + uint32_t(sub * kWave + lane); i < rg.y; i += uint32_t(nwaves * kWave)) {
+                    const uint32_t r = vals[i];
+                    const uint4 mt = meta[r];
+                    const uint32_t x0 = mt.z & 0xffffu, y0 = mt.z >> 16, x1 = mt.w & 0xffffu;
+                    const uint32_t e = pair_off[r] + (fty - y0) * (x1 - x0 + 1) + (ftx - x0);
+                    T* d0 = pg + adaptive_slot(capacity, e, 0);
+                    T acc[9];
+#pragma unroll
+                    for (int q = 0; q < 9; q++) acc[q] = d0[q];
+                    for (int sl = 1; sl < nwaves; sl++) {
+                        const T* src = pg + adaptive_slot(capacity, e, sl);
+#pragma unroll
+                        for (int q = 0; q < 9; q++) acc[q] += src[q];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 9; q++) d0[q] = acc[q];
+                }
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 
+// grid of a compositing launch: NS (or 4, adaptive) wavefronts per tile, in
+// workgroups of kRenderWaves wavefronts (1, adaptive)
+template <int NS>
+static void compositing_grid(const gs_frame& f, dim3& grid, dim3& block) {
+    const int wpt = NS == 0 ? 4 : NS;   // adaptive: at most 4 per tile, the plan's count
+    grid = dim3(unsigned((int64_t(f.n_tiles) * wpt + kRenderWaves - 1) / kRenderWaves));
+    block = dim3(unsigned(kWave * kRenderWaves));
+}
+
 template <typename T, int QX, int QY, int NS>
 static void fwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const gs_bins& b, T* rgb,
                        T* Tfin, uint32_t* nc, unsigned long long* kept, hipStream_t s) {
-    const int nb = int((int64_t(f.n_tiles) * NS + kRenderWaves - 1) / kRenderWaves);
+    dim3 grid, block;
+    compositing_grid<NS>(f, grid, block);
     if (kept)
-        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, true>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f,
-                  cfg, rec, b.vals, reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept);
+        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, true>), grid, block, 0, s, f, cfg, rec, b.vals,
+                  reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept, b.tile_order);
     else
-        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, false>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f,
-                  cfg, rec, b.vals, reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept);
+        GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, false>), grid, block, 0, s, f, cfg, rec, b.vals,
+                  reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept, b.tile_order);
 }
 
 template <typename T, int QX, int QY, int NS>
 static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
                        const gs_bins& b, const T* rgb, int mode, const T* gin, T* loss, T* pg, hipStream_t s) {
-    const int nb = int((int64_t(f.n_tiles) * NS + kRenderWaves - 1) / kRenderWaves);
-    GS_LAUNCH("k_render_bwd", (k_render_bwd<T, QX, QY, NS>), dim3(nb), dim3(kWave * kRenderWaves), 0, s, f, cfg, rec,
-                       reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals,
-                       reinterpret_cast<const uint2*>(b.ranges), rgb, mode, gin, loss, pg);
+    dim3 grid, block;
+    compositing_grid<NS>(f, grid, block);
+    GS_LAUNCH("k_render_bwd", (k_render_bwd<T, QX, QY, NS>), grid, block, 0, s, f, cfg, rec,
+              reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals, reinterpret_cast<const uint2*>(b.ranges),
+              b.tile_order, b.capacity, rgb, mode, gin, loss, pg);
 }
 
 // (binning tile, wavefronts per tile) -> quadrants per wavefront QX x QY:
 // 8x8/1 = 1x1; 16x8/1 = 2x1, /2 = 1x1; 16x16/1 = 2x2, /2 = 2x1 (halves stacked),
-// /4 = 1x1; 32x8/1 = 4x1, /2 = 2x1 (halves side by side), /4 = 1x1
+// /4 = 1x1; 32x8/1 = 4x1, /2 = 2x1 (halves side by side), /4 = 1x1.  Adaptive
+// (WAVES = 0): the whole tile's quadrants, split per tile at run time.
 #define GS_TILE_DISPATCH(WAVES, FN, ...)                                                  \
     do {                                                                                  \
         const int S_ = WAVES;                                                             \
-        if (cfg.tile_w == 8 && cfg.tile_h == 8) FN<T, 1, 1, 1>(__VA_ARGS__);              \
-        else if (cfg.tile_w == 16 && cfg.tile_h == 8) {                                   \
-            if (S_ == 2) FN<T, 1, 1, 2>(__VA_ARGS__);                                     \
+        if (cfg.tile_w == 8 && cfg.tile_h == 8) {                                         \
+            if (S_ == 0) FN<T, 1, 1, 0>(__VA_ARGS__);                                     \
+            else FN<T, 1, 1, 1>(__VA_ARGS__);                                             \
+        } else if (cfg.tile_w == 16 && cfg.tile_h == 8) {                                 \
+            if (S_ == 0) FN<T, 2, 1, 0>(__VA_ARGS__);                                     \
+            else if (S_ == 2) FN<T, 1, 1, 2>(__VA_ARGS__);                                \
             else FN<T, 2, 1, 1>(__VA_ARGS__);                                             \
         } else if (cfg.tile_w == 32 && cfg.tile_h == 8) {                                 \
-            if (S_ == 4) FN<T, 1, 1, 4>(__VA_ARGS__);                                     \
+            if (S_ == 0) FN<T, 4, 1, 0>(__VA_ARGS__);                                     \
+            else if (S_ == 4) FN<T, 1, 1, 4>(__VA_ARGS__);                                \
             else if (S_ == 2) FN<T, 2, 1, 2>(__VA_ARGS__);                                \
             else FN<T, 4, 1, 1>(__VA_ARGS__);                                             \
         } else {                                                                          \
-            if (S_ == 4) FN<T, 1, 1, 4>(__VA_ARGS__);                                     \
+            if (S_ == 0) FN<T, 2, 2, 0>(__VA_ARGS__);                                     \
+            else if (S_ == 4) FN<T, 1, 1, 4>(__VA_ARGS__);                                \
             else if (S_ == 2) FN<T, 2, 1, 2>(__VA_ARGS__);                                \
             else FN<T, 2, 2, 1>(__VA_ARGS__);                                             \
         }                                                                                 \

@@ -23,6 +23,7 @@ c_f, c_i32, c_i64, c_u64, c_vp = ctypes.c_float, ctypes.c_int32, ctypes.c_int64,
 
 GS_OK, GS_E_INVALID, GS_E_CAPACITY, GS_E_DEVICE, GS_E_UNSUPPORTED = range(5)
 GS_STATUS_PAIR_OVERFLOW = 1
+GS_WAVES_ADAPTIVE = -1
 CTR_VISIBLE, CTR_PAIRS, CTR_STATUS, N_COUNTERS = 0, 1, 2, 4
 LOSS_L1, LOSS_EXTERNAL = 0, 1
 REC_WORDS, META_WORDS = 12, 4
@@ -54,7 +55,8 @@ class GsRasterCfg(ctypes.Structure):
 
 
 class GsBins(ctypes.Structure):
-    _fields_ = [("vals", c_vp), ("ranges", c_vp), ("pair_off", c_vp), ("counters", c_vp), ("capacity", c_u64)]
+    _fields_ = [("vals", c_vp), ("ranges", c_vp), ("pair_off", c_vp), ("counters", c_vp), ("capacity", c_u64),
+                ("tile_order", c_vp)]
 
 
 class GsAdamCfg(ctypes.Structure):
@@ -238,6 +240,7 @@ class Buffers:
         self.rgb = torch.empty(max(frame.n_pixels, 1) * 3, dtype=dtype, device=device)
         self.T = torch.empty(max(frame.n_pixels, 1), dtype=dtype, device=device)
         self.ncontrib = torch.empty(max(frame.n_pixels, 1), dtype=torch.int32, device=device)
+        self.tile_order = torch.empty(max(frame.n_tiles, 1) + 4, dtype=torch.int32, device=device)
         self.frame = frame
         self._alloc_pairs(capacity, device)
 
@@ -255,7 +258,7 @@ class Buffers:
     @property
     def bins(self) -> GsBins:
         return GsBins(self.vals.data_ptr(), self.ranges.data_ptr(), self.pair_off.data_ptr(),
-                      self.counters.data_ptr(), self.capacity)
+                      self.counters.data_ptr(), self.capacity, self.tile_order.data_ptr())
 
 
 # ---------------------------------------------------------------------------

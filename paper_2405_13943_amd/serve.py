@@ -58,6 +58,7 @@ class Arena:
         self.meta = torch.empty(R * gs.META_WORDS, dtype=torch.int32, device=device)
         self.pair_off = torch.empty(R, dtype=torch.int32, device=device)
         self.ranges = torch.empty(max_tiles * 2, dtype=torch.int32, device=device)
+        self.tile_order = torch.empty(max_tiles + 4, dtype=torch.int32, device=device)
         self.counters = torch.zeros(gs.N_COUNTERS, dtype=torch.int32, device=device)
         self.rgb = torch.empty(max_pixels * 3, dtype=torch.float32, device=device)
         self.T = torch.empty(max_pixels, dtype=torch.float32, device=device)
@@ -71,12 +72,13 @@ class Arena:
 
     def nbytes(self):
         return sum(t.numel() * t.element_size() for t in (self.rec, self.meta, self.pair_off, self.ranges,
-                                                           self.rgb, self.T, self.ncontrib, self.vals, self.bin_ws))
+                                                           self.tile_order, self.rgb, self.T, self.ncontrib,
+                                                           self.vals, self.bin_ws))
 
     @property
     def bins(self) -> gs.GsBins:
         return gs.GsBins(self.vals.data_ptr(), self.ranges.data_ptr(), self.pair_off.data_ptr(),
-                         self.counters.data_ptr(), self.capacity)
+                         self.counters.data_ptr(), self.capacity, self.tile_order.data_ptr())
 
 
 class Slot:

@@ -111,10 +111,10 @@ def test_invalid_arguments_rejected_without_launch(gs):
     cfg_bad = gs.raster_cfg((12, 12))
     ok = gs.GsParams(None, 0, 0, 0, 0)
     assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(cfg_bad), None, None, None) == gs.GS_E_INVALID
-    for tile in [(8, 8, 2), (16, 8, 4), (16, 16, 3), (32, 8, 8), (16, 16, 2, 3), (8, 8, 1, 2)]:
+    for tile in [(8, 8, 2), (16, 8, 4), (16, 16, 3), (32, 8, 8), (16, 16, 2, 3), (8, 8, 1, 2), (16, 16, 2, -2)]:
         c = gs.raster_cfg(tile)
         assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None) == gs.GS_E_INVALID
-    for tile in [(16, 16, 4), (32, 8, 2), (16, 8, 2), (16, 16, 2, 1), (32, 8, 4, 2)]:
+    for tile in [(16, 16, 4), (32, 8, 2), (16, 8, 2), (16, 16, 2, 1), (32, 8, 4, 2), (16, 16, 2, -1), (8, 8, -1, -1)]:
         c = gs.raster_cfg(tile)
         assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None) == gs.GS_OK
     # jobs reaching past the parameter planes
@@ -122,7 +122,7 @@ def test_invalid_arguments_rejected_without_launch(gs):
     p10 = gs.GsParams(1, 10, 10, 0, 0)
     assert gs.lib.gs_project(ctypes.byref(p10), ctypes.byref(f2), ctypes.byref(cfg), 1, 1, None) == gs.GS_E_INVALID
     # backward workspace too small
-    bins = gs.GsBins(1, 1, 1, 1, 1000)
+    bins = gs.GsBins(1, 1, 1, 1, 1000, 1)
     rc = gs.lib.gs_render_bwd(ctypes.byref(p10), ctypes.byref(gs.GsFrame(1, 1, 1, 1, 10, 10, 10, 1, 0)), ctypes.byref(cfg),
                               1, 1, ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), 1, 8, None)
     assert rc == gs.GS_E_CAPACITY

@@ -154,7 +154,8 @@ def test_tile_shape_and_batch_invariance(cfg1, gpu1):
     tile, and whether views are rendered batched or one at a time."""
     cfg, frame, params, buf = gpu1
     base = images(frame, buf)
-    for tile in [(8, 8), (16, 8), (32, 8), (16, 8, 2), (16, 16, 2), (16, 16, 4), (32, 8, 2), (32, 8, 4)]:
+    for tile in [(8, 8), (16, 8), (32, 8), (16, 8, 2), (16, 16, 2), (16, 16, 4), (32, 8, 2), (32, 8, 4),
+                 (16, 16, -1), (32, 8, -1), (16, 8, -1), (8, 8, -1)]:
         c2 = gs.raster_cfg(tile)
         f2 = make_frame(cfg1, c2)
         b2 = gs.rasterize(params, f2, c2)
@@ -221,11 +222,12 @@ def test_render_bwd_matches_oracle(cfg1, gpu1, ref1):
     assert torch.equal(grad, grad2)
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 2), (16, 16, 4), (32, 8, 4), (16, 8, 2)])
+@pytest.mark.parametrize("tile", [(16, 16, 2), (16, 16, 4), (32, 8, 4), (16, 8, 2), (16, 16, 2, -1), (32, 8, 1, -1),
+                                  (16, 8, 2, -1), (8, 8, 1, -1)])
 def test_render_bwd_sub_tile_waves_match_oracle(cfg1, ref1, tile):
-    """Several wavefronts per tile, each storing its own partials per pair:
-    gradients against the FP64 oracle as for one wavefront per tile, and
-    deterministic."""
+    """Several wavefronts per tile (fixed, or per tile from its list length),
+    each storing its own partials per pair: gradients against the FP64
+    oracle as for one wavefront per tile, and deterministic."""
     cfg = gs.raster_cfg(tile)
     frame = make_frame(cfg1, cfg)
     params = torch.from_numpy(cfg1.params).cuda()
