@@ -134,9 +134,9 @@ typedef struct {
     int16_t fwd_waves;       /* wavefronts per tile in the forward and in the backward */
     int16_t bwd_waves;       /* compositing, each owning an equal part of the tile and walking
                                 the whole list: 1 (0 = 1), 2 (16x8, 16x16, 32x8) or 4 (16x16,
-                                32x8); bwd_waves = GS_WAVES_ADAPTIVE picks 1, 2 or 4 per tile
-                                from its list length against the frame mean (4 above 2.5x,
-                                2 above 1.25x).  Images do not depend on them; gradients only
+                                32x8); GS_WAVES_ADAPTIVE picks 1, 2 or 4 per tile from its
+                                list length against the frame mean (4 above 4x, 2 above
+                                1.25x; needs gs_bins.tile_order).  Images do not depend on them; gradients only
                                 through the order of their sums. */
 } gs_raster_cfg;
 

@@ -374,12 +374,23 @@ __global__ __launch_bounds__(1024) void k_tile_plan(const uint2* __restrict__ ra
     if (threadIdx.x < 3) cnt[threadIdx.x] = 0u;
     __syncthreads();
     const uint32_t pairs = counters[GS_CTR_PAIRS];
+    const int lane = lane_id();
     auto group = [&](int t) {
+        if (t >= n_tiles) return -1;
         const uint2 rg = ranges[t];
         const int w = adaptive_waves(rg.y - rg.x, pairs, n_tiles, quads);
         return w == 4 ? 0 : (w == 2 ? 1 : 2);
     };
-    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) atomicAdd(&cnt[group(t)], 1u);
+    // counts: one LDS atomic per group and wavefront
+    const int n_round = (n_tiles + int(blockDim.x) - 1) / int(blockDim.x) * int(blockDim.x);
+    for (int t = threadIdx.x; t < n_round; t += blockDim.x) {
+        const int gr = group(t);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint64_t b = __ballot(gr == k);
+            if (lane == 0 && b) atomicAdd(&cnt[k], uint32_t(__builtin_popcountll(b)));
+        }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         cur[0] = 0u;
@@ -388,7 +399,18 @@ __global__ __launch_bounds__(1024) void k_tile_plan(const uint2* __restrict__ ra
     }
     if (threadIdx.x < 3) order[threadIdx.x] = cnt[threadIdx.x];
     __syncthreads();
-    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) order[4 + atomicAdd(&cur[group(t)], 1u)] = uint32_t(t);
+    // scatter: a wavefront reserves a run per group, lanes rank inside it
+    for (int t = threadIdx.x; t < n_round; t += blockDim.x) {
+        const int gr = group(t);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint64_t b = __ballot(gr == k);
+            uint32_t base = 0u;
+            if (lane == 0 && b) base = atomicAdd(&cur[k], uint32_t(__builtin_popcountll(b)));
+            base = __shfl(base, 0, kWave);
+            if (gr == k) order[4 + base + __builtin_popcountll(b & lanemask_lt())] = uint32_t(t);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

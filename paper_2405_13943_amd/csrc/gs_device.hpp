@@ -58,13 +58,13 @@ __host__ __device__ inline int bwd_waves(const gs_raster_cfg& c) {
 // per wavefront; adaptive: one (split tiles fold theirs into the first)
 __host__ __device__ inline int bwd_slots(const gs_raster_cfg& c) { return bwd_adaptive(c) ? 1 : bwd_waves(c); }
 
-// Wavefronts of one tile in the adaptive backward, from its list length
-// against the frame's mean list length: 4 above 2.5 x the mean, 2 above
+// Wavefronts of one tile in an adaptive compositing pass, from its list
+// length against the frame's mean list length: 4 above 4 x the mean, 2 above
 // 1.25 x, else 1; never more than the tile's quadrants.  Exact integer
-// arithmetic, so the compositing backward and the projection backward agree.
+// arithmetic, so every kernel that needs it agrees.
 __device__ inline int adaptive_waves(uint32_t count, uint32_t pairs, int n_tiles, int quads) {
     const uint64_t a = 4ull * count * uint64_t(n_tiles);
-    const int s = a > 10ull * pairs ? 4 : (a > 5ull * pairs ? 2 : 1);
+    const int s = a > 16ull * pairs ? 4 : (a > 5ull * pairs ? 2 : 1);
     return s < quads ? s : quads;
 }
 

@@ -602,10 +602,19 @@ __device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* 
         float4 vv = *reinterpret_cast<const float4*>(V + a * sv + gv);
         float4 wv = make_float4(0.f, 0.f, 0.f, 0.f);
         if (PEN) wv = *reinterpret_cast<const float4*>(Wp + a * sw + gv);
-        adam_one(xv.x, staged_grad(geo, Y, dc, a, i + 0), mv.x, vv.x, wv.x, PEN ? rho * kv.x : 0.f, lr, c);
-        adam_one(xv.y, staged_grad(geo, Y, dc, a, i + 1), mv.y, vv.y, wv.y, PEN ? rho * kv.y : 0.f, lr, c);
-        adam_one(xv.z, staged_grad(geo, Y, dc, a, i + 2), mv.z, vv.z, wv.z, PEN ? rho * kv.z : 0.f, lr, c);
-        adam_one(xv.w, staged_grad(geo, Y, dc, a, i + 3), mv.w, vv.w, wv.w, PEN ? rho * kv.w : 0.f, lr, c);
+        // the four Gaussians' gradients of plane a: one 16-byte LDS read per array
+        float4 gq;
+        if (a < 11) {
+            gq = *reinterpret_cast<const float4*>(geo + a * kFusedBlock + i);
+        } else {
+            const float4 yq = *reinterpret_cast<const float4*>(Y + ((a - 11) / 3) * kFusedBlock + i);
+            const float4 dq = *reinterpret_cast<const float4*>(dc + ((a - 11) % 3) * kFusedBlock + i);
+            gq = make_float4(yq.x * dq.x, yq.y * dq.y, yq.z * dq.z, yq.w * dq.w);
+        }
+        adam_one(xv.x, gq.x, mv.x, vv.x, wv.x, PEN ? rho * kv.x : 0.f, lr, c);
+        adam_one(xv.y, gq.y, mv.y, vv.y, wv.y, PEN ? rho * kv.y : 0.f, lr, c);
+        adam_one(xv.z, gq.z, mv.z, vv.z, wv.z, PEN ? rho * kv.z : 0.f, lr, c);
+        adam_one(xv.w, gq.w, mv.w, vv.w, wv.w, PEN ? rho * kv.w : 0.f, lr, c);
         *reinterpret_cast<float4*>(X + a * sx + gv) = xv;
         *reinterpret_cast<float4*>(M + a * sm + gv) = mv;
         *reinterpret_cast<float4*>(V + a * sv + gv) = vv;
@@ -639,9 +648,9 @@ __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     const float* __restrict__ mask, AdamConsts c) {
     constexpr int NK = (D + 1) * (D + 1);
     constexpr int A = 11 + 3 * NK;
-    __shared__ float s_geo[11][kFusedBlock];
-    __shared__ float s_Y[NK][kFusedBlock];
-    __shared__ float s_dc[3][kFusedBlock];
+    __shared__ __align__(16) float s_geo[11][kFusedBlock];
+    __shared__ __align__(16) float s_Y[NK][kFusedBlock];
+    __shared__ __align__(16) float s_dc[3][kFusedBlock];
     const int t = threadIdx.x;
     const int64_t r0 = int64_t(blockIdx.x) * kFusedBlock;
     const int64_t r = r0 + t;
