@@ -13,6 +13,6 @@ differences); see the individual docstrings.
 """
 from .raster import (Camera, RasterConfig, project, render, backward, sh_basis,  # noqa: F401
                      quat_rotation, l1_loss_and_grad, FLAG_NAMES, load_library)
-from .admm import (adam_admm, consensus, consensus_full, penalty_groups,  # noqa: F401
-                   scaled_lagrangian, unscaled_lagrangian)
+from .admm import (adam_admm, adaptive_rho, consensus, consensus_full, penalty_groups,  # noqa: F401
+                   rescale_duals, residual_sums, scaled_lagrangian, unscaled_lagrangian)
 from .binning import bin_reference  # noqa: F401

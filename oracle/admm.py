@@ -113,3 +113,73 @@ def scaled_lagrangian(f, x, z, u, rho):
     """Scaled form of Eq. 7: sum_i f_i + rho/2 ||x_i - z + u_i||^2 - rho/2 ||u_i||^2."""
     return sum(fi + 0.5 * rho * (xi - z + ui) @ (xi - z + ui) - 0.5 * rho * ui @ ui
                for fi, xi, ui in zip(f, x, u))
+
+
+def residual_sums(x_local, z_new, z_prev, holder_ptr, holder_idx, n_global):
+    """Squared residual sums per attribute group (Sec. 3.3), over the local
+    copies of every Gaussian held by at least one block:
+
+        primal  sum_k ||x_k - z||^2            (r = x_i - z, one term per copy)
+        dual    sum_k ||z - z_prev||^2         (s = rho (z - z_prev), one term
+                                                per copy, without the rho^2)
+
+    Reading: the dual residual is counted once per holding block, as the
+    primal one is (the consensus form of the residuals in the cited Boyd et
+    al. survey).  Returns (primal[5], dual[5]) in GROUPS order, FP64."""
+    x = np.asarray(x_local, np.float64)
+    zn = np.asarray(z_new, np.float64)
+    zp = np.asarray(z_prev, np.float64)
+    grp = penalty_groups(x.shape[0])
+    rp = np.zeros(5)
+    rd = np.zeros(5)
+    for gid in range(n_global):
+        hs = holder_idx[holder_ptr[gid]:holder_ptr[gid + 1]]
+        if len(hs) == 0:
+            continue
+        dp = ((x[:, hs] - zn[:, gid:gid + 1]) ** 2).sum(axis=1)
+        dd = len(hs) * (zn[:, gid] - zp[:, gid]) ** 2
+        np.add.at(rp, grp, dp)
+        np.add.at(rd, grp, dd)
+    return rp, rd
+
+
+def adaptive_rho(rho, primal_sq, dual_sq, mu=10.0, tau_inc=2.0, tau_dec=2.0):
+    """Penalty update of Sec. 3.3 per attribute group:
+
+        rho * tau_inc   when ||r|| > mu ||s||
+        rho / tau_dec   when ||s|| > mu ||r||
+        rho             otherwise
+
+    with ||r|| = sqrt(primal_sq) and ||s|| = rho * sqrt(dual_sq).  The paper's
+    third branch reads "=" where "otherwise" is meant.  Returns the new rho
+    (FP64 array of 5)."""
+    rho = np.asarray(rho, np.float64)
+    r = np.sqrt(np.asarray(primal_sq, np.float64))
+    s = rho * np.sqrt(np.asarray(dual_sq, np.float64))
+    out = rho.copy()
+    inc = r > mu * s
+    dec = ~inc & (s > mu * r)
+    out[inc] = rho[inc] * tau_inc
+    out[dec] = rho[dec] / tau_dec
+    return out
+
+
+def rescale_duals(u_local, z_global, holder_ptr, holder_idx, n_global, scale):
+    """Scaled duals after a penalty change: u = y / rho, so keeping y fixed
+    while rho becomes rho' multiplies u by rho / rho' (per group, ``scale``);
+    the consensus targets follow, w = z - u.  The paper does not spell this
+    step out; it is the rule of the scaled form (supplementary A).  Columns
+    held by no Gaussian are left as they are (u) or zero (w).  Returns
+    (u, w) in FP64."""
+    u = np.array(u_local, np.float64, copy=True)
+    z = np.asarray(z_global, np.float64)
+    grp = penalty_groups(u.shape[0])
+    sc = np.asarray(scale, np.float64)[grp][:, None]
+    w = np.zeros_like(u)
+    for gid in range(n_global):
+        hs = holder_idx[holder_ptr[gid]:holder_ptr[gid + 1]]
+        if len(hs) == 0:
+            continue
+        u[:, hs] = u[:, hs] * sc
+        w[:, hs] = z[:, gid:gid + 1] - u[:, hs]
+    return u, w

@@ -197,3 +197,126 @@ def test_bin_reference_brute_force():
         want.sort(key=lambda i: (int(depth[i]), i))
         got = list(vals[ranges[t, 0]:ranges[t, 1]])
         assert got == want, t
+
+
+def test_residual_sums_worked_example():
+    """One Gaussian held by two blocks, every plane of copy a at 1 and of
+    copy b at 3, previous z at 0: z = 2, each plane adds (1-2)^2 + (3-2)^2 = 2
+    to the primal sum and 2 copies x (2-0)^2 = 8 to the dual sum (Sec. 3.3).
+    Planes per group (p, q, s, f, o) at SH degree 1: means 3, rotation 4,
+    scales 3, SH colour 3 x 4 = 12, opacity 1."""
+    A = 14 + 9
+    x = np.concatenate([np.ones((A, 1)), 3 * np.ones((A, 1))], axis=1)
+    ptr, idx = np.array([0, 2]), np.array([0, 1])
+    z, _, _ = oracle.consensus(x, np.zeros_like(x), ptr, idx, 1)
+    np.testing.assert_array_equal(z, 2.0)
+    rp, rd = oracle.residual_sums(x, z, np.zeros((A, 1)), ptr, idx, 1)
+    np.testing.assert_array_equal(rp, [6, 8, 6, 24, 2])
+    np.testing.assert_array_equal(rd, [24, 32, 24, 96, 8])
+
+
+def test_primal_residual_is_the_dual_increment():
+    """Without relaxation the u-update adds x - z to every copy, so the
+    primal sum equals sum ||u_new - u_old||^2 (Eq. 8c); at the holder mean it
+    also equals sum ||x||^2 - |H| ||z||^2 (variance split)."""
+    idx, ptr, locs, _ = _holders(seed=20)
+    r = np.random.default_rng(21)
+    A, L, G = 14, len(locs), len(ptr) - 1
+    x = r.standard_normal((A, L))
+    u0 = r.standard_normal((A, L))
+    zp = r.standard_normal((A, G))
+    z, u1, _ = oracle.consensus(x, u0, ptr, idx, G)
+    rp, rd = oracle.residual_sums(x, z, zp, ptr, idx, G)
+    grp = penalty_groups(A)
+    want = np.array([((u1 - u0)[grp == k] ** 2).sum() for k in range(5)])
+    np.testing.assert_allclose(rp, want, rtol=1e-12)
+    cnt = np.diff(ptr)
+    split = np.array([(x[grp == k] ** 2).sum() - (cnt * (z[grp == k] ** 2)).sum() for k in range(5)])
+    np.testing.assert_allclose(rp, split, rtol=1e-10)
+    # dual: every local copy sees the move of its own z
+    dz = (z - zp)[:, locs]
+    np.testing.assert_allclose(rd, [(dz[grp == k] ** 2).sum() for k in range(5)], rtol=1e-12)
+
+
+def test_adaptive_rho_branches():
+    """rho grows by tau_inc when ||r|| > mu ||s||, shrinks by tau_dec when
+    ||s|| > mu ||r|| (||s|| carries the factor rho), stays otherwise (Sec. 3.3)."""
+    rho = np.array([1.0, 1.0, 2.0, 0.5, 1.0])
+    # ||r|| = 11, ||s|| = 1           -> inc
+    # ||r|| = 1,  ||s|| = 11          -> dec
+    # ||r|| = 4,  ||s|| = 2 * 2 = 4   -> keep
+    # ||r|| = 0,  ||s|| = 0           -> keep
+    # ||r|| = 9,  ||s|| = 1 (mu = 10) -> keep
+    new = oracle.adaptive_rho(rho, [121, 1, 16, 0, 81], [1, 121, 4, 0, 1], mu=10, tau_inc=2, tau_dec=4)
+    np.testing.assert_array_equal(new, [2.0, 0.25, 2.0, 0.5, 1.0])
+    # equal residual sums: the factor rho in s decides (||r|| = 1, ||s|| = rho)
+    np.testing.assert_array_equal(oracle.adaptive_rho([0.01] * 5, [1] * 5, [1] * 5), [0.02] * 5)
+    np.testing.assert_array_equal(oracle.adaptive_rho([100.0] * 5, [1] * 5, [1] * 5), [50.0] * 5)
+
+
+def test_dual_rescale_keeps_the_unscaled_x_update():
+    """After rho -> rho', the scaled x-update with u' = u rho / rho' is the
+    unscaled one of Eq. 5 with y = rho u held fixed: on f = 1/2 ||x - a||^2,
+    argmin f + y (x - z) + rho'/2 ||x - z||^2 = (a - y + rho' z) / (1 + rho')."""
+    idx, ptr, locs, _ = _holders(seed=22)
+    r = np.random.default_rng(23)
+    A, L, G = 14, len(locs), len(ptr) - 1
+    a = r.standard_normal((A, L))
+    u = r.standard_normal((A, L))
+    z = r.standard_normal((A, G))
+    grp = penalty_groups(A)
+    rho = np.array([0.5, 1.0, 2.0, 4.0, 8.0])
+    rho_new = np.array([1.0, 0.5, 2.0, 1.0, 16.0])
+    u2, w2 = oracle.rescale_duals(u, z, ptr, idx, G, rho / rho_new)
+    rn = rho_new[grp][:, None]
+    scaled = (a + rn * w2) / (1 + rn)                       # w = z - u
+    y = rho[grp][:, None] * u
+    unscaled = (a - y + rn * z[:, locs]) / (1 + rn)
+    np.testing.assert_allclose(scaled, unscaled, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(w2, z[:, locs] - u2, atol=1e-15)
+
+
+def _toy_run(rho0, adaptive, iters=400, seed=24, tol=1e-8):
+    idx, ptr, locs, _ = _holders(K=4, G=60, seed=seed)
+    A, L, G = 14, len(locs), len(ptr) - 1
+    grp = penalty_groups(A)
+    a = np.random.default_rng(seed + 1).standard_normal((A, L)) * 3
+    ref = np.stack([a[:, idx[ptr[g]:ptr[g + 1]]].mean(axis=1) for g in range(G)], axis=1)
+    rho = np.full(5, rho0)
+    z = np.zeros((A, G))
+    u = np.zeros((A, L))
+    for t in range(1, iters + 1):
+        rn = rho[grp][:, None]
+        x = (a + rn * (z[:, locs] - u)) / (1 + rn)
+        z_prev = z
+        z, u, _ = oracle.consensus(x, u, ptr, idx, G)
+        if np.abs(z - ref).max() < tol:
+            return t, z, ref
+        if adaptive and t <= 100:
+            rp, rd = oracle.residual_sums(x, z, z_prev, ptr, idx, G)
+            new = oracle.adaptive_rho(rho, rp, rd)
+            u, _ = oracle.rescale_duals(u, z, ptr, idx, G, rho / new)
+            rho = new
+    return iters, z, ref
+
+
+@pytest.mark.parametrize("rho0", [1e3, 1e5])
+def test_adaptive_penalty_recovers_from_a_poor_initial_rho(rho0):
+    """Consensus ADMM on the quadratic toy problem converges to the holder
+    mean with the residual-balancing penalty (frozen after 100 iterations
+    here) and does so in far fewer iterations than with the poor fixed rho
+    it started from (Sec. 3.3, the scheme of Boyd et al.).  On this problem
+    z moves by the factor rho / (1 + rho) per iteration, so a large rho is the
+    poor start."""
+    t_ad, z, ref = _toy_run(rho0, True)
+    np.testing.assert_allclose(z, ref, atol=1e-8)
+    t_fx, _, _ = _toy_run(rho0, False)
+    assert t_ad < 150 and t_fx == 400, (t_ad, t_fx)
+
+
+def test_adaptive_penalty_keeps_a_good_rho_converging():
+    """From a small rho the toy problem is solved in a few iterations with or
+    without adaptation; adaptation must not spoil that."""
+    t_ad, z, ref = _toy_run(1e-3, True)
+    np.testing.assert_allclose(z, ref, atol=1e-8)
+    assert t_ad < 20
