@@ -280,6 +280,34 @@ def kernel_breakdown(gs, torch, fn, steps):
     return out
 
 
+def consensus_roofline(model, tr, c_ms, kernels):
+    """HBM roofline of the consensus kernel: algorithmic bytes (each held
+    local copy's x and u read and w written, u written for Gaussians with
+    several holders, z read and written per held global id, the holder CSR
+    read once) over its mean launch duration (HIP events around each launch).
+    ``call_ms`` is the whole trainer call: with the adaptive penalty it adds
+    the host read of the residual sums and the dual rescale."""
+    ptr = model.holder_ptr.cpu().numpy()
+    cnt = np.diff(ptr)
+    A = model.x.shape[0]
+    copies = int(cnt.sum())
+    multi = int(cnt[cnt > 1].sum())
+    g_held = int((cnt > 0).sum())
+    # the trainer always asks for the residual sums, so the previous z is read
+    planes = 4 * A * (3 * copies + multi + 2 * g_held)
+    nbytes = planes + 8 * (len(ptr) + copies)
+    k_ms, k_n = kernels["k_consensus"]
+    if not c_ms or not k_n:
+        return None
+    ms = k_ms / k_n
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    r_ms, r_n = kernels["k_dual_rescale"]
+    return {"bound": "hbm", "kernel": "k_consensus", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(gbs / 8000.0, 4), "bytes": nbytes, "ms": round(ms, 4),
+            "call_ms": round(float(np.mean(c_ms)), 4), "dual_rescale_ms": round(r_ms / r_n, 4) if r_n else None,
+            "copies": copies, "multi_holder_copies": multi, "held_global": g_held}
+
+
 def run_blocks4(args):
     """K = 4 uneven blocks (0.8M/1.5M/2.2M/3.0M own Gaussians, 10% shared with
     a neighbour), 32 ring views per block at 1600x1066: the batched trainer
@@ -333,8 +361,10 @@ def run_blocks4(args):
     torch.cuda.empty_cache()
     # fresh state for the timed run
     model.x.copy_(x0)
+    adaptive = admm.AdaptivePenalty() if args.adaptive else None
     tr = admm.AdmmTrainer(model, bs.cams, target, gs.raster_cfg(tile), lr=LR, rho=RHO, intv=100,
-                          capacity=trainers[tile].capacity if tile in trainers else None)
+                          capacity=trainers[tile].capacity if tile in trainers else None, relax=args.relax,
+                          adaptive=adaptive)
     trainers.clear()
     if tr.capacity is None:
         tr.calibrate()
@@ -395,7 +425,10 @@ def run_blocks4(args):
             tk.t += 1
 
     steps = args.block_steps
+    gs.profile_set(["k_consensus", "k_dual_rescale"])
     ms_b = timed(batched_step, steps)
+    cons_kernels = {k: gs.profile_get(k) for k in ("k_consensus", "k_dual_rescale")}
+    gs.profile_set(None)
     ms_s = timed(seq_step, steps)
     ok = all(b.check(grow=False) for b in [tr] + seq)
     if not ok:
@@ -406,6 +439,8 @@ def run_blocks4(args):
     log(f"[blocks4] batched kernels ms/step: {kb}")
     log(f"[blocks4] sequential kernels ms/step: {ks}")
     res = tr.resid.cpu().numpy().tolist()
+    cons = consensus_roofline(model, tr, c_ms, cons_kernels)
+    log(f"[blocks4] consensus: {cons}")
     out = {"metric": "K-block ADMM train steps/s (4 blocks, 1 view each, fwd+bwd+Adam/ADMM + consensus/100)",
            "value": 1000.0 * steps / ms_b, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
            "ms_per_step": ms_b / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -415,7 +450,8 @@ def run_blocks4(args):
                                   "1600x1066, consensus every 100 steps",
                       "tile": "x".join(map(str, tile[:2])), "waves_per_tile_fwd_bwd": list(tile[2:])},
            "sequential_ms_per_step": ms_s / steps, "batched_speedup": ms_s / ms_b,
-           "consensus_ms": c_ms, "consensus_calls": len(c_ms), "images_equal_per_block": same,
+           "consensus_ms": c_ms, "consensus_calls": len(c_ms), "consensus_roofline": cons,
+           "relax": args.relax, "adaptive_penalty": bool(args.adaptive), "images_equal_per_block": same,
            "kernel_ms_batched": kb, "kernel_ms_sequential": ks,
            "last_residuals": res}
     return out
@@ -504,6 +540,8 @@ def main():
     ap.add_argument("--block-cams", type=int, default=32)
     ap.add_argument("--block-steps", type=int, default=200)
     ap.add_argument("--no-tile-auto", action="store_true", help="blocks4: use --tile instead of the autotuner")
+    ap.add_argument("--relax", type=float, default=1.0, help="blocks4: over-relaxation alpha of the consensus")
+    ap.add_argument("--adaptive", action="store_true", help="blocks4: residual-balancing penalty (until 2000)")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     args = ap.parse_args()

@@ -293,11 +293,40 @@ gs_status gs_profile_get(const char *name, double *total_ms, int64_t *launches);
  *   xh_k = relax * x_k + (1 - relax) * z_gid   (over-relaxation; relax = 1: none)
  *   z_gid = mean_k xh_k;  u_k += xh_k - z_gid;  w_k = z_gid - u_k.
  * z_global is read (previous z) and overwritten.  resid_out (device float[10],
- * may be NULL) accumulates per group the squared primal residual
- * sum (x_k - z)^2 (0..4) and sum (z - z_prev)^2 (5..9); the caller zeroes it. */
+ * may be NULL) accumulates, per attribute group (p, q, s, f, o), the squared
+ * residual sums of Sec. 3.3 over every local copy of every held Gaussian:
+ * [0..4] primal sum_k (x_k - z)^2 with the unrelaxed x_k; [5..9] dual
+ * sum_k (z - z_prev)^2, i.e. |H| (z - z_prev)^2 per global id (the penalty
+ * factor of s = rho (z - z_prev) is left to gs_penalty_update).  The caller
+ * zeroes it; the order of the float additions varies from call to call.
+ * A copy whose Gaussian has a single holder gets z = x exactly, so its u is
+ * not rewritten. */
 gs_status gs_consensus(const gs_params *x_local, gs_params *u_local, gs_params *w_local, gs_params *z_global,
                        const int64_t *holder_ptr_dev, const int64_t *holder_idx_dev, float relax,
                        float *resid_out_dev, gs_stream stream);
+
+/* Residual-balancing penalty update of Sec. 3.3 (host only, no device work).
+ * resid_host: the 10 sums gs_consensus accumulated (copied to the host).
+ * Per group k, with ||r|| = sqrt(resid[k]) and ||s|| = rho[k] sqrt(resid[5+k]):
+ *   rho[k] *= tau_inc when ||r|| > mu ||s||;  rho[k] /= tau_dec when
+ *   ||s|| > mu ||r||;  unchanged otherwise (decisions taken in double).
+ * rho (host float[5]) is updated in place; scale_out (host float[5], may be
+ * NULL) receives old rho / new rho, the factor gs_dual_rescale applies to the
+ * scaled duals.  Requires mu > 1, tau_inc >= 1, tau_dec >= 1 and finite,
+ * non-negative sums; on error nothing is written. */
+gs_status gs_penalty_update(const float *resid_host, float *rho_host, float mu, float tau_inc, float tau_dec,
+                            float *scale_out_host);
+
+/* Scaled duals after a penalty change (Sec. 3.3 with the scaled form of
+ * Eq. 7: u = y / rho, so keeping y while rho becomes rho' multiplies u by
+ * rho / rho').  For every local copy k of every held global id and every
+ * plane of group g: u_k *= scale_host[g]; w_k = z_gid - u_k.  Entries whose u
+ * does not change (u = 0, or scale 1) are left untouched, so w must already
+ * equal z - u there, as gs_consensus leaves it.  Groups with scale 1 are not
+ * read.  u_local/w_local as in gs_consensus; z_global is read only. */
+gs_status gs_dual_rescale(gs_params *u_local, gs_params *w_local, const gs_params *z_global,
+                          const int64_t *holder_ptr_dev, const int64_t *holder_idx_dev, const float *scale_host,
+                          gs_stream stream);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,10 @@ a local step is one launch over all blocks (one render job per block).
 Every ``intv`` steps (after the local step, including t = 0, as Alg. 2
 writes it) the consensus step averages the copies of each global Gaussian
 over the blocks that hold it (``gs_consensus``); the duals start at zero.
+With an ``AdaptivePenalty`` the per-group rho follows the primal and dual
+residuals of each consensus (Sec. 3.3, ``gs_penalty_update``), the scaled
+duals are rescaled with it (``gs_dual_rescale``), and the adjustment stops
+after a fixed iteration.
 
 Everything here is orchestration: device buffers come from torch, every
 arithmetic step runs in libgs.
@@ -26,6 +30,18 @@ from . import gs
 DEFAULT_LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)    # mean, rotation, scale, SH, opacity
 
 
+@dataclass(frozen=True)
+class AdaptivePenalty:
+    """Residual balancing of Sec. 3.3: mu > 1 and the factors tau_inc,
+    tau_dec (the paper leaves their values open; these are the usual ones of
+    the scheme it adopts), applied at every consensus before iteration
+    ``until`` (2000 in the paper's experiments)."""
+    mu: float = 10.0
+    tau_inc: float = 2.0
+    tau_dec: float = 2.0
+    until: int = 2000
+
+
 def holder_csr(local_gid, n_global, local_index=None):
     """Holder CSR of the global ids: for each global id, the local indices of
     its copies in ascending block order (blocks are laid out in order).
@@ -43,6 +59,36 @@ def holder_csr(local_gid, n_global, local_index=None):
     return ptr, cols[order].astype(np.int64)
 
 
+def holder_order(local_gid, n_global):
+    """Numbering of the global ids grouped by holder set: ids held by the
+    same blocks become consecutive, groups ordered by (first holder, number
+    of holders, holder set), original order kept inside a group, ids held by
+    no block last.  Returns (perm, inv): new id j is original id perm[j];
+    original id i becomes inv[i].
+
+    With every block's copies stored in this order, the copies of one
+    holder group are consecutive columns in each of its blocks, so the
+    consensus streams dense lines: no wavefront mixes single-held and shared
+    ids, and the duals of single-held ids (which never change) are never
+    written between shared ones."""
+    K = len(local_gid)
+    if K > 63:
+        raise ValueError("holder_order supports up to 63 blocks")
+    mask = np.zeros(n_global, np.uint64)
+    for k, g in enumerate(local_gid):
+        mask[np.asarray(g, np.int64)] |= np.uint64(1 << k)
+    count = np.zeros(n_global, np.int64)
+    first = np.full(n_global, K, np.int64)
+    for k in range(K - 1, -1, -1):
+        bit = (mask >> np.uint64(k)) & np.uint64(1)
+        count += bit.astype(np.int64)
+        first[bit.astype(bool)] = k
+    perm = np.lexsort((np.arange(n_global), mask, count, first)).astype(np.int64)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(n_global, dtype=np.int64)
+    return perm, inv
+
+
 @dataclass
 class BlockModel:
     """Local copies of K blocks in one store plus the global model."""
@@ -52,16 +98,25 @@ class BlockModel:
     offsets: list                     # block k's slot: [offsets[k], offsets[k+1]), 64-column aligned
     holder_ptr: torch.Tensor          # [G+1] int64
     holder_idx: torch.Tensor          # [H] int64 local indices
-    local_gid: list = field(default_factory=list)
+    local_gid: list = field(default_factory=list)   # per block: global ids (store numbering) of its columns
     ends: list = None                 # block k's copies: [offsets[k], ends[k])
+    perm: np.ndarray = None           # store id j is the caller's global id perm[j] (None: identity)
 
     @classmethod
-    def from_global(cls, params_global: np.ndarray, local_gid, device="cuda", align=64):
+    def from_global(cls, params_global: np.ndarray, local_gid, device="cuda", align=64, group_holders=True):
         """Local copies of each block start on a multiple of ``align``
         columns (16-byte aligned slices for per-block streaming); the padding
-        columns belong to no block and no holder set."""
+        columns belong to no block and no holder set.  With
+        ``group_holders`` the global ids are renumbered by holder set
+        (``holder_order``) and each block's copies stored in that order;
+        ``global_params`` returns z in the caller's order."""
         A, G = params_global.shape
         deg = gs.sh_degree_of(A)
+        perm = None
+        if group_holders:
+            perm, inv = holder_order(local_gid, G)
+            params_global = params_global[:, perm]
+            local_gid = [np.sort(inv[np.asarray(g, np.int64)]) for g in local_gid]
         z = torch.from_numpy(np.ascontiguousarray(params_global)).to(device)
         offs, col_gid, base = [], [], 0
         for g in local_gid:
@@ -78,11 +133,19 @@ class BlockModel:
         ptr, idx = holder_csr(local_gid, G, local_index)
         ends = [offs[k] + len(local_gid[k]) for k in range(len(local_gid))]
         return cls(deg, z, x, offs[:-1] + [offs[-1]], torch.from_numpy(ptr).to(device),
-                   torch.from_numpy(idx).to(device), [np.asarray(g) for g in local_gid], ends)
+                   torch.from_numpy(idx).to(device), [np.asarray(g) for g in local_gid], ends, perm)
 
     @property
     def K(self):
         return len(self.offsets) - 1
+
+    def global_params(self) -> torch.Tensor:
+        """The global model z with columns in the caller's global-id order."""
+        if self.perm is None:
+            return self.z
+        out = torch.empty_like(self.z)
+        out[:, torch.from_numpy(self.perm).to(self.z.device)] = self.z
+        return out
 
     def block(self, k):
         """Store columns of block k's copies."""
@@ -94,12 +157,16 @@ class AdmmTrainer:
     """One view per block per step, all K blocks in one launch per stage."""
 
     def __init__(self, model: BlockModel, cams, targets, cfg: gs.GsRasterCfg, lr=DEFAULT_LR, rho=(1e-3,) * 5,
-                 intv=100, relax=1.0, beta1=0.9, beta2=0.999, eps=1e-8, capacity=None, mask=None, fused=True):
+                 intv=100, relax=1.0, beta1=0.9, beta2=0.999, eps=1e-8, capacity=None, mask=None, fused=True,
+                 adaptive: AdaptivePenalty | None = None):
         """cams[k]: list of cameras of block k; targets[k][v]: device tensor
         [3*H*W] (or a callable (k, v) -> tensor) for block k, view v.
         fused: backward and optimiser in one call (gs_render_bwd_adam, the
         gradient never stored); else gs_render_bwd into a gradient buffer,
-        then gs_adam_admm."""
+        then gs_adam_admm.  relax: over-relaxation alpha of the consensus
+        (1: none; the paper uses 1.5-1.8).  adaptive: residual-balancing
+        penalty (one host read of the residual sums per consensus while it
+        is active)."""
         self.model, self.cfg = model, cfg
         self.lr, self.rho, self.intv, self.relax = tuple(lr), tuple(rho), int(intv), float(relax)
         self.beta1, self.beta2, self.eps = beta1, beta2, eps
@@ -120,8 +187,9 @@ class AdmmTrainer:
         self.buf = None
         self.capacity = capacity
         self.loss = torch.zeros(model.K, device=x.device)
+        self.adaptive = adaptive
         self.resid = torch.zeros(10, device=x.device)
-        self.history = []
+        self.history = []        # (t, residual sums, rho after the update) per adaptive consensus
 
     # -- frames ----------------------------------------------------------
     def frame(self, views):
@@ -177,10 +245,20 @@ class AdmmTrainer:
             gs.adam_admm(x, self.g, self.m, self.v, self.w, self.mask, acfg)
 
     def consensus(self):
-        """z = mean of holders' copies; u += x - z; w = z - u (Eq. 8b-c)."""
+        """z = mean of holders' copies; u += x - z; w = z - u (Eq. 8b-c);
+        then, while the adaptive penalty is active, the rho update and the
+        matching rescale of the scaled duals (Sec. 3.3)."""
         self.resid.zero_()
-        gs.consensus(self.model.x, self.u, self.w, self.model.z, self.model.holder_ptr, self.model.holder_idx,
-                     self.relax, self.resid)
+        mdl = self.model
+        gs.consensus(mdl.x, self.u, self.w, mdl.z, mdl.holder_ptr, mdl.holder_idx, self.relax, self.resid)
+        ap = self.adaptive
+        if ap is not None and self.t < ap.until:
+            res = self.resid.cpu().tolist()
+            rho, scale = gs.penalty_update(res, self.rho, ap.mu, ap.tau_inc, ap.tau_dec)
+            if any(f != 1.0 for f in scale):
+                gs.dual_rescale(self.u, self.w, mdl.z, mdl.holder_ptr, mdl.holder_idx, scale)
+            self.rho = rho
+            self.history.append((self.t, res, rho))
 
     def step(self):
         """Alg. 2: local step for all blocks, then consensus when t mod intv == 0."""

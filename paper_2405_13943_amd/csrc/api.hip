@@ -1,6 +1,7 @@
 // C ABI of libgs (declared in include/gs.h): argument validation, workspace
 // sizing and kernel launches.  No device memory is allocated here.
 #include <atomic>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -335,8 +336,54 @@ gs_status gs_consensus(const gs_params* x, gs_params* u, gs_params* w, gs_params
         return fail(GS_E_INVALID, "planes disagree in sh_degree");
     if (z->n > 0 && (!hptr || !hidx)) return fail(GS_E_INVALID, "null holder CSR");
     if (!(relax > 0.f && relax < 2.f)) return fail(GS_E_INVALID, "relaxation %g outside (0, 2)", double(relax));
+    if (x->n >= (int64_t(1) << 30) || z->n >= (int64_t(1) << 30))
+        return fail(GS_E_INVALID, "consensus supports fewer than 2^30 local and global columns");
     return check_hip(gs::launch_consensus(*x, *u, *w, *z, hptr, hidx, relax, resid, (hipStream_t)stream),
                      "gs_consensus");
+}
+
+gs_status gs_penalty_update(const float* resid, float* rho, float mu, float tau_inc, float tau_dec, float* scale) {
+    if (!resid || !rho) return fail(GS_E_INVALID, "null resid or rho");
+    if (!(mu > 1.f) || !(tau_inc >= 1.f) || !(tau_dec >= 1.f) || !std::isfinite(mu) || !std::isfinite(tau_inc) ||
+        !std::isfinite(tau_dec))
+        return fail(GS_E_INVALID, "penalty update needs mu > 1 and tau >= 1 (got %g, %g, %g)", double(mu),
+                    double(tau_inc), double(tau_dec));
+    float out[5];
+    for (int k = 0; k < 5; k++) {
+        const double rp = resid[k], rd = resid[5 + k], r0 = rho[k];
+        if (!(rp >= 0) || !(rd >= 0) || !std::isfinite(rp) || !std::isfinite(rd))
+            return fail(GS_E_INVALID, "residual sums of group %d not finite and >= 0", k);
+        if (!(r0 > 0) || !std::isfinite(r0)) return fail(GS_E_INVALID, "rho[%d] = %g not positive", k, r0);
+        const double r = std::sqrt(rp), sn = r0 * std::sqrt(rd);
+        double nr = r0;
+        if (r > double(mu) * sn) nr = r0 * double(tau_inc);
+        else if (sn > double(mu) * r) nr = r0 / double(tau_dec);
+        out[k] = float(nr);
+    }
+    for (int k = 0; k < 5; k++) {
+        if (scale) scale[k] = rho[k] / out[k];
+        rho[k] = out[k];
+    }
+    return GS_OK;
+}
+
+gs_status gs_dual_rescale(gs_params* u, gs_params* w, const gs_params* z, const int64_t* hptr, const int64_t* hidx,
+                          const float* scale, gs_stream stream) {
+    gs_status st;
+    if ((st = check_params(u, "u_local")) != GS_OK) return st;
+    if ((st = check_params(w, "w_local")) != GS_OK) return st;
+    if ((st = check_params(z, "z_global")) != GS_OK) return st;
+    if (w->n != u->n) return fail(GS_E_INVALID, "local planes disagree in n");
+    if (w->sh_degree != u->sh_degree || z->sh_degree != u->sh_degree)
+        return fail(GS_E_INVALID, "planes disagree in sh_degree");
+    if (!scale) return fail(GS_E_INVALID, "null scale");
+    for (int k = 0; k < 5; k++)
+        if (!(scale[k] > 0.f) || !std::isfinite(scale[k]))
+            return fail(GS_E_INVALID, "scale[%d] = %g not positive and finite", k, double(scale[k]));
+    if (z->n > 0 && (!hptr || !hidx)) return fail(GS_E_INVALID, "null holder CSR");
+    if (u->n >= (int64_t(1) << 30) || z->n >= (int64_t(1) << 30))
+        return fail(GS_E_INVALID, "dual rescale supports fewer than 2^30 local and global columns");
+    return check_hip(gs::launch_dual_rescale(*u, *w, *z, hptr, hidx, scale, (hipStream_t)stream), "gs_dual_rescale");
 }
 
 }  // extern "C"

@@ -69,5 +69,7 @@ hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_p
                             const float* mask, const gs_adam_cfg& cfg, hipStream_t s);
 hipError_t launch_consensus(const gs_params& x, gs_params& u, gs_params& w, gs_params& z, const int64_t* hptr,
                             const int64_t* hidx, float relax, float* resid, hipStream_t s);
+hipError_t launch_dual_rescale(gs_params& u, gs_params& w, const gs_params& z, const int64_t* hptr,
+                               const int64_t* hidx, const float* scale, hipStream_t s);
 
 }  // namespace gs

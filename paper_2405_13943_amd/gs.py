@@ -98,6 +98,8 @@ def _load():
                                 c_vp, P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg), c_vp,
                                 ctypes.c_size_t, c_vp], c_i32),
         "gs_consensus": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, c_f, c_vp, c_vp], c_i32),
+        "gs_penalty_update": ([P(c_f), P(c_f), c_f, c_f, c_f, P(c_f)], c_i32),
+        "gs_dual_rescale": ([P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, P(c_f), c_vp], c_i32),
         "gs_profile_set": ([ctypes.c_char_p], c_i32),
         "gs_profile_get": ([ctypes.c_char_p, P(ctypes.c_double), P(c_i64)], c_i32),
     }
@@ -344,6 +346,27 @@ def consensus(x, u, w, z, holder_ptr, holder_idx, relax=1.0, resid=None):
     _check(lib.gs_consensus(ctypes.byref(px), ctypes.byref(pu), ctypes.byref(pw), ctypes.byref(pz),
                             _ptr(holder_ptr), _ptr(holder_idx), float(relax), _ptr(resid), _stream()),
            "gs_consensus")
+
+
+def penalty_update(resid, rho, mu=10.0, tau_inc=2.0, tau_dec=2.0):
+    """Residual-balancing penalty update (gs_penalty_update, host only).
+    resid: the 10 residual sums of a consensus call (tensor or sequence);
+    returns (new rho, old/new scale) as tuples of 5 floats."""
+    if isinstance(resid, torch.Tensor):
+        resid = resid.detach().float().cpu().tolist()
+    r = (c_f * 10)(*[float(v) for v in resid])
+    rh = (c_f * 5)(*[float(v) for v in rho])
+    sc = (c_f * 5)()
+    _check(lib.gs_penalty_update(r, rh, float(mu), float(tau_inc), float(tau_dec), sc), "gs_penalty_update")
+    return tuple(rh), tuple(sc)
+
+
+def dual_rescale(u, w, z, holder_ptr, holder_idx, scale):
+    """u_k *= scale[group], w_k = z - u_k over every held copy (gs_dual_rescale)."""
+    pu, pw, pz = (params_struct(t) for t in (u, w, z))
+    sc = (c_f * 5)(*[float(v) for v in scale])
+    _check(lib.gs_dual_rescale(ctypes.byref(pu), ctypes.byref(pw), ctypes.byref(pz), _ptr(holder_ptr),
+                               _ptr(holder_idx), sc, _stream()), "gs_dual_rescale")
 
 
 def read_counters(buf: Buffers):

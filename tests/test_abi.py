@@ -173,3 +173,32 @@ def test_workspace_sizes_grow_with_inputs(gs):
     assert 0 < a < b
     assert gs.lib.gs_render_bwd_workspace_size(1000, 0) == 1000 * 9 * 4 * 4   # 4 wavefronts per tile at most
     assert gs.lib.gs_render_bwd_workspace_size(1000, 1) == 1000 * 9 * 8 * 4
+
+
+def test_penalty_update_host_only_matches_oracle(gs):
+    """gs_penalty_update (host code, no device work) takes the oracle's
+    decisions on random residual sums, including exact ties at the mu
+    boundary, and rejects invalid hyper-parameters."""
+    import oracle
+    rng = np.random.default_rng(3)
+    for trial in range(200):
+        rho = np.float32(10.0 ** rng.uniform(-4, 4, 5))
+        rp = np.float32(10.0 ** rng.uniform(-6, 6, 5))
+        rd = np.float32(10.0 ** rng.uniform(-6, 6, 5))
+        if trial % 7 == 0:
+            rp[:] = 0
+        mu, ti, td = (10.0, 2.0, 2.0) if trial % 2 else (5.0, 3.0, 1.5)
+        new, scale = gs.penalty_update(np.concatenate([rp, rd]), rho, mu, ti, td)
+        want = oracle.adaptive_rho(rho.astype(np.float64), rp.astype(np.float64), rd.astype(np.float64), mu, ti, td)
+        assert np.array_equal(np.float32(new), np.float32(want)), trial
+        np.testing.assert_array_equal(np.float32(scale), rho / np.float32(want))
+    # ||r|| = mu ||s|| exactly: no change
+    new, scale = gs.penalty_update([100.0] * 5 + [1.0] * 5, [1.0] * 5, mu=10.0)
+    assert new == (1.0,) * 5 and scale == (1.0,) * 5
+    for bad in (dict(mu=1.0), dict(tau_inc=0.5), dict(tau_dec=float("nan"))):
+        with pytest.raises(gs.GsError, match="penalty"):
+            gs.penalty_update([1.0] * 10, [1.0] * 5, **bad)
+    with pytest.raises(gs.GsError, match="residual"):
+        gs.penalty_update([-1.0] + [1.0] * 9, [1.0] * 5)
+    with pytest.raises(gs.GsError, match="rho"):
+        gs.penalty_update([1.0] * 10, [0.0] + [1.0] * 4)

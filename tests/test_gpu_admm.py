@@ -162,6 +162,51 @@ def test_trainer_loop_invariants_and_penalty():
     assert spread[1.0] < spread[0.0]
 
 
+def test_adaptive_penalty_rounds_match_oracle():
+    """Consensus rounds with the residual-balancing penalty and
+    over-relaxation: each round's residual sums, rho decision and rescaled
+    duals against the oracle fed the GPU's own x and previous z, u; no
+    adjustment once the freeze iteration is passed (Sec. 3.3)."""
+    bs = tiny_blocks()
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+    cfg = gs.raster_cfg((16, 16))
+    ap = admm.AdaptivePenalty(mu=10.0, tau_inc=2.0, tau_dec=2.0, until=6)
+    tr = admm.AdmmTrainer(model, bs.cams, targets_for(bs), cfg, lr=(1e-3, 2e-3, 3e-3, 4e-3, 5e-3),
+                          rho=(1e-4, 1e-2, 1.0, 1e2, 1e-3), intv=2, relax=1.6, capacity=1 << 16, adaptive=ap)
+    ptr, idx = model.holder_ptr.cpu().numpy(), model.holder_idx.cpu().numpy()
+    G = len(ptr) - 1
+    held = np.sort(idx)
+    changed = 0
+    for t in range(10):
+        tr.local_step()
+        if t % tr.intv:
+            tr.t += 1
+            continue
+        x, u0, zp = (a.cpu().numpy().astype(np.float64) for a in (tr.model.x, tr.u, tr.model.z))
+        rho0 = np.asarray(tr.rho, np.float64)
+        n_hist = len(tr.history)
+        tr.consensus()
+        rz, ru, _ = oracle.consensus(x, u0, ptr, idx, G, relax=1.6, z_prev=zp)
+        if t >= ap.until:
+            assert len(tr.history) == n_hist and tuple(tr.rho) == tuple(np.float32(rho0))
+            tr.t += 1
+            continue
+        _, res, rho1 = tr.history[-1]
+        rp, rd = oracle.residual_sums(x, rz, zp, ptr, idx, G)
+        np.testing.assert_allclose(res[:5], rp, rtol=1e-4)
+        np.testing.assert_allclose(res[5:], rd, rtol=1e-4)
+        want = oracle.adaptive_rho(rho0, rp, rd)
+        np.testing.assert_allclose(rho1, want, rtol=1e-6)
+        changed += int((np.asarray(rho1) != np.float32(rho0)).sum())
+        ru2, rw2 = oracle.rescale_duals(ru, rz, ptr, idx, G, rho0 / np.asarray(rho1, np.float64))
+        gu, gw = tr.u.cpu().numpy(), tr.w.cpu().numpy()
+        mag = 1.0 + np.abs(x[:, held]) + np.abs(rz).max()         # FP32 cancellation scale of u and w
+        assert (np.abs(gu[:, held] - ru2[:, held]) <= 1e-5 * mag).all()
+        assert (np.abs(gw[:, held] - rw2[:, held]) <= 1e-5 * mag).all()
+        tr.t += 1
+    assert changed >= 3
+
+
 def test_autograd_function_fp64_against_finite_differences():
     """GaussianRasterize in FP64 (200 Gaussians, SH 3, 64x64): backward
     through torch.autograd equals central differences of the forward on a

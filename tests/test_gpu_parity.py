@@ -326,37 +326,104 @@ def test_adam_admm_matches_oracle():
     assert (np.abs(sub.cpu().numpy() - rx) <= bx).all()
 
 
-def test_consensus_matches_oracle():
-    rng = np.random.default_rng(32)
-    K, G, A = 4, 3000, 14
-    held = [sorted(rng.choice(K, rng.integers(1, 3), replace=False)) for _ in range(G)]
-    locs, local_of = [], {}
+def _random_holders(rng, K, G, max_holders, unheld=0.0):
+    """Holder CSR over K blocks: each global id is held by 1..max_holders
+    blocks (a fraction ``unheld`` by none), locals laid out block by block in
+    ascending global id with a padding column after every 97th local copy
+    (a column no holder set names)."""
+    held = []
+    for _ in range(G):
+        n = 0 if rng.random() < unheld else int(rng.integers(1, max_holders + 1))
+        held.append(sorted(rng.choice(K, n, replace=False)) if n else [])
+    cols, local_of, L = [], {}, 0
     for k in range(K):
         for gid in range(G):
             if k in held[gid]:
-                local_of[(gid, k)] = len(locs)
-                locs.append(gid)
+                local_of[(gid, k)] = L
+                cols.append(L)
+                L += 1
+                if L % 97 == 0:
+                    L += 1
     ptr = np.zeros(G + 1, np.int64)
     idx = []
     for gid in range(G):
         idx += [local_of[(gid, k)] for k in held[gid]]
         ptr[gid + 1] = len(idx)
-    idx = np.asarray(idx, np.int64)
-    L = len(locs)
+    return ptr, np.asarray(idx, np.int64), L
+
+
+@pytest.mark.parametrize("deg,max_holders", [(0, 2), (1, 4), (2, 6), (3, 2), (3, 5)])
+def test_consensus_matches_oracle(deg, max_holders):
+    """z, u, w and the per-group residual sums against the oracle for every
+    SH degree (plane count), the 1-2 / 3-4 / more-holder paths, with and
+    without over-relaxation and residuals; single-holder duals and columns
+    of no holder set keep their values."""
+    rng = np.random.default_rng(32 + deg)
+    K, G = 6, 2500
+    A = 11 + 3 * (deg + 1) ** 2
+    ptr, idx, L = _random_holders(rng, K, G, max_holders, unheld=0.02)
     x = rng.standard_normal((A, L)).astype(np.float32)
     u = (0.1 * rng.standard_normal((A, L))).astype(np.float32)
     zp = rng.standard_normal((A, G)).astype(np.float32)
+    w0 = rng.standard_normal((A, L)).astype(np.float32)
+    held = np.sort(idx)
+    free = np.setdiff1d(np.arange(L), held)
+    unheld_g = np.nonzero(np.diff(ptr) == 0)[0]
+    single = idx[ptr[:-1][np.diff(ptr) == 1]]
+    assert len(free) and len(unheld_g) and len(single)
+    dptr, didx = torch.from_numpy(ptr).cuda(), torch.from_numpy(idx).cuda()
     for relax in (1.0, 1.6):
-        tx, tu = torch.from_numpy(x).cuda(), torch.from_numpy(u.copy()).cuda()
-        tw, tz = torch.zeros_like(tu), torch.from_numpy(zp.copy()).cuda()
-        res = torch.zeros(10, device="cuda")
-        gs.consensus(tx, tu, tw, tz, torch.from_numpy(ptr).cuda(), torch.from_numpy(idx).cuda(), relax, res)
-        rz, ru, rw = oracle.consensus(x, u, ptr, idx, G, relax=relax, z_prev=zp)
-        np.testing.assert_allclose(tz.cpu().numpy(), rz, rtol=1e-6, atol=1e-6)
-        np.testing.assert_allclose(tu.cpu().numpy(), ru, rtol=1e-6, atol=1e-6)
-        np.testing.assert_allclose(tw.cpu().numpy(), rw, rtol=1e-6, atol=1e-6)
-        rp = sum(((x[:, idx[ptr[g]:ptr[g + 1]]] - rz[:, g:g + 1]) ** 2).sum() for g in range(G))
-        assert abs(res[:5].sum().item() / rp - 1) < 1e-4
+        for want_resid in (True, False):
+            tx, tu = torch.from_numpy(x).cuda(), torch.from_numpy(u.copy()).cuda()
+            tw, tz = torch.from_numpy(w0.copy()).cuda(), torch.from_numpy(zp.copy()).cuda()
+            res = torch.zeros(10, device="cuda") if want_resid else None
+            gs.consensus(tx, tu, tw, tz, dptr, didx, relax, res)
+            rz, ru, rw = oracle.consensus(x, u, ptr, idx, G, relax=relax, z_prev=zp)
+            gz, gu, gw = (t.cpu().numpy() for t in (tz, tu, tw))
+            hg = np.diff(ptr) > 0
+            np.testing.assert_allclose(gz[:, hg], rz[:, hg], rtol=1e-6, atol=1e-6)
+            np.testing.assert_allclose(gu[:, held], ru[:, held], rtol=1e-6, atol=1e-6)
+            np.testing.assert_allclose(gw[:, held], rw[:, held], rtol=1e-6, atol=1e-6)
+            # untouched: columns of no holder, z of unheld ids, u of single holders (bitwise)
+            assert np.array_equal(gu[:, free], u[:, free]) and np.array_equal(gw[:, free], w0[:, free])
+            assert np.array_equal(gz[:, unheld_g], zp[:, unheld_g])
+            assert np.array_equal(gu[:, single], u[:, single])
+            if want_resid:
+                rp, rd = oracle.residual_sums(x, rz, zp, ptr, idx, G)
+                got = res.cpu().numpy().astype(np.float64)
+                np.testing.assert_allclose(got[:5], rp, rtol=2e-5)
+                np.testing.assert_allclose(got[5:], rd, rtol=2e-5)
+
+
+def test_dual_rescale_matches_oracle():
+    """u *= scale per group, w = z - u over held copies after a consensus
+    (groups at scale 1 and zero duals untouched bitwise)."""
+    rng = np.random.default_rng(40)
+    K, G, deg = 4, 3000, 3
+    A = 11 + 3 * (deg + 1) ** 2
+    ptr, idx, L = _random_holders(rng, K, G, 3)
+    x = rng.standard_normal((A, L)).astype(np.float32)
+    u = (0.1 * rng.standard_normal((A, L))).astype(np.float32)
+    u[:, idx[ptr[:-1][np.diff(ptr) == 1]]] = 0                  # single holders: duals stay zero
+    zp = rng.standard_normal((A, G)).astype(np.float32)
+    tx, tu = torch.from_numpy(x).cuda(), torch.from_numpy(u.copy()).cuda()
+    tw, tz = torch.zeros_like(tu), torch.from_numpy(zp.copy()).cuda()
+    dptr, didx = torch.from_numpy(ptr).cuda(), torch.from_numpy(idx).cuda()
+    gs.consensus(tx, tu, tw, tz, dptr, didx, 1.0, None)
+    u1, w1, z1 = tu.cpu().numpy(), tw.cpu().numpy(), tz.cpu().numpy()
+    scale = (2.0, 0.5, 1.0, 4.0, 0.25)
+    gs.dual_rescale(tu, tw, tz, dptr, didx, scale)
+    ru, rw = oracle.rescale_duals(u1, z1, ptr, idx, G, scale)
+    held = np.sort(idx)
+    gu, gw = tu.cpu().numpy(), tw.cpu().numpy()
+    np.testing.assert_allclose(gu[:, held], ru[:, held], rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gw[:, held], rw[:, held], rtol=1e-6, atol=1e-6)
+    s_planes = np.asarray(oracle.penalty_groups(A)) == 2          # group s has scale 1
+    assert np.array_equal(gu[s_planes], u1[s_planes]) and np.array_equal(gw[s_planes], w1[s_planes])
+    zero = u1 == 0
+    assert zero.sum() > 0 and np.array_equal(gw[zero], w1[zero])
+    with pytest.raises(gs.GsError, match="scale"):
+        gs.dual_rescale(tu, tw, tz, dptr, didx, (1.0, 0.0, 1.0, 1.0, 1.0))
 
 
 def test_capacity_overflow_reported_then_grown(cfg1):
