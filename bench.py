@@ -38,15 +38,22 @@ LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)       # mean, rotation, scale, SH, opaci
 RHO = (1e-3,) * 5
 
 
-def kernel_sources_sha256():
-    """Fingerprint of the HIP sources (kernels and their headers)."""
-    import glob
+# sources each measured kernel is built from (its translation unit and headers)
+KERNEL_SOURCES = {
+    "k_project_bwd_adam": ("project.hip", "adam.hpp", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
+    "k_render_bwd": ("render.hip", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
+    "k_consensus": ("optim.hip", "adam.hpp", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
+}
+
+
+def kernel_sources_sha256(kernel):
+    """Fingerprint of the sources a kernel is built from."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2405_13943_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(d, "*.hip")) + glob.glob(os.path.join(d, "*.hpp"))):
+    for f in KERNEL_SOURCES[kernel]:
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+        with open(os.path.normpath(os.path.join(d, f)), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -54,15 +61,74 @@ def kernel_sources_sha256():
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a copy of known size), or None
-    when the kernel sources have changed since those counters were taken."""
+    when the kernel's sources have changed since those counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh).get(kernel)
-    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_sha256(kernel):
         return None
     return int(rec["traffic_bytes_per_launch"])
+
+
+def _counter_per_dispatch(csv_dir, kernel, counter):
+    """Mean value of a rocprofv3 counter over a kernel's dispatches (KiB)."""
+    import csv
+    import glob
+    vals = []
+    for path in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter and (kernel is None or f"gs::{kernel}<" in r["Kernel_Name"]
+                                                     or f"gs::{kernel}(" in r["Kernel_Name"]):
+                    vals.append(float(r["Counter_Value"]))
+    return sum(vals) / len(vals) if vals else None
+
+
+def record_traffic(kernel, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, commands):
+    """Write the kernel's measured HBM bytes per launch into
+    profiles/hbm_traffic.json: FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
+    one rocprofv3 --pmc run each) scaled so that the copy probe of 1 GiB
+    reads and writes exactly 1 GiB."""
+    import csv
+    import glob
+
+    def copy_value(d, counter):
+        best = 0.0
+        for path in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]:
+                        best = max(best, float(r["Counter_Value"]))
+        if best <= 0:
+            raise SystemExit(f"no copy-probe {counter} under {d}")
+        return best
+
+    gib_kib = float(1 << 20)
+    f_scale = round(gib_kib / copy_value(copy_fetch_dir, "FETCH_SIZE"), 2)
+    w_scale = round(gib_kib / copy_value(copy_write_dir, "WRITE_SIZE"), 2)
+    fk = _counter_per_dispatch(fetch_dir, kernel, "FETCH_SIZE")
+    wk = _counter_per_dispatch(write_dir, kernel, "WRITE_SIZE")
+    if fk is None or wk is None:
+        log(f"[record-traffic] no samples of {kernel}; left as it was")
+        return
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    data[kernel] = {
+        "workload": workload,
+        "kernel_sources_sha256": kernel_sources_sha256(kernel),
+        "fetch_size_kib_per_launch": round(fk, 1),
+        "write_size_kib_per_launch": round(wk, 1),
+        "fetch_scale": f_scale,
+        "write_scale": w_scale,
+        "traffic_bytes_per_launch": int(1024 * (fk * f_scale + wk * w_scale)),
+        "copy_probe": f"1 GiB device copy: FETCH_SIZE x{f_scale}, WRITE_SIZE x{w_scale}",
+        "commands": commands,
+    }
+    with open(path, "w") as fh:
+        json.dump(data, fh, indent=1)
+    print(json.dumps(data[kernel]), flush=True)
 
 
 def log(msg):
@@ -308,6 +374,63 @@ def consensus_roofline(model, tr, c_ms, kernels):
             "copies": copies, "multi_holder_copies": multi, "held_global": g_held}
 
 
+def run_consensus(args):
+    """The consensus step alone on the K = 4 block store (7.5M global
+    Gaussians SH3, 8.25M local copies; global ids numbered by holder set):
+    local copies drawn around the global model, then ``--block-steps``
+    rounds of gs_consensus with the residual sums (over-relaxation
+    ``--relax``), each followed by the penalty update and, when rho moves,
+    gs_dual_rescale, as the trainer does before the freeze.  Timed with the
+    library's HIP events per kernel."""
+    import torch
+    from paper_2405_13943_amd import admm, gs, scenes
+    t0 = time.time()
+    bs = scenes.block_scene(n_cams=1)
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+    del bs
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    noise = torch.randn(model.x.shape, generator=gen, device="cuda")
+    model.x.add_(noise, alpha=1e-2)
+    del noise
+    u = torch.zeros_like(model.x)
+    w = model.x.clone()
+    resid = torch.zeros(10, device="cuda")
+    rho = RHO
+    log(f"[consensus] setup {time.time() - t0:.1f}s: store {tuple(model.x.shape)}, global {model.z.shape[1]}")
+    calls = max(2, args.block_steps // 100)
+    gs.profile_set(["k_consensus", "k_dual_rescale"])
+    torch.cuda.synchronize()
+    t1 = time.time()
+    rescaled = 0
+    for i in range(calls):
+        resid.zero_()
+        gs.consensus(model.x, u, w, model.z, model.holder_ptr, model.holder_idx, args.relax, resid)
+        new, scale = gs.penalty_update(resid, rho)
+        if any(f != 1.0 for f in scale):
+            gs.dual_rescale(u, w, model.z, model.holder_ptr, model.holder_idx, scale)
+            rescaled += 1
+        rho = new
+        model.x.lerp_(w, 0.5)                      # stand-in for the local steps between rounds
+    torch.cuda.synchronize()
+    wall = time.time() - t1
+    kernels = {k: gs.profile_get(k) for k in ("k_consensus", "k_dual_rescale")}
+    gs.profile_set(None)
+
+    class _Tr:
+        relax = args.relax
+    cons = consensus_roofline(model, _Tr, [1.0], kernels)
+    cons.pop("call_ms")
+    cons["traffic"] = measured_traffic("k_consensus")
+    return {"metric": "consensus rounds/s (z, u, w and residual sums over 8.25M local copies, SH3)",
+            "value": kernels["k_consensus"][1] / (kernels["k_consensus"][0] * 1e-3), "unit": "rounds/s",
+            "n_gpus": 1, "steps": calls, "warmup": 0, "ms_per_step": kernels["k_consensus"][0] / calls,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (seeded slab blocks, copies = global model + N(0, 0.01))",
+            "config": {"workload": "K=4 block store, 7.5M global Gaussians SH3, 8.25M local copies, "
+                                   f"relax {args.relax}, residual sums and penalty update every round"},
+            "roofline": cons, "rescales": rescaled, "wall_s": round(wall, 3), "final_rho": list(rho)}
+
+
 def run_blocks4(args):
     """K = 4 uneven blocks (0.8M/1.5M/2.2M/3.0M own Gaussians, 10% shared with
     a neighbour), 32 ring views per block at 1600x1066: the batched trainer
@@ -528,8 +651,9 @@ def main():
                     help="backward compositing wavefronts per tile: 1, 2, 4, or -1 per tile from its list length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="backward and optimiser as two calls (gradient in HBM)")
-    ap.add_argument("--workload", choices=("train", "blocks4", "serve"), default="train",
-                    help="train: single block at scale (+ serve leg); blocks4: batched K=4 blocks; serve: serving only")
+    ap.add_argument("--workload", choices=("train", "blocks4", "serve", "consensus"), default="train",
+                    help="train: single block at scale (+ serve leg); blocks4: batched K=4 blocks; serve: serving "
+                         "only; consensus: the consensus step alone on the K=4 block store")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the train workload")
     ap.add_argument("--serve-n", type=int, default=6_000_000)
     ap.add_argument("--rate", type=float, default=200.0)
@@ -544,9 +668,25 @@ def main():
     ap.add_argument("--adaptive", action="store_true", help="blocks4: residual-balancing penalty (until 2000)")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="host only: write profiles/hbm_traffic.json for the measured kernels from rocprofv3 --pmc "
+                         "output directories (the bench runs, then the copy probe's)")
+    ap.add_argument("--traffic-args", default="--steps 4 --warmup 2 --no-cpu-baseline --no-serve",
+                    help="with --record-traffic: the bench arguments the counter runs used")
+    ap.add_argument("--traffic-workload", default="plain single block, 500k Gaussians SH3, 1600x1066, 16x16 tiles, "
+                                                  "wavefronts per tile from list length (forward and backward)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.record_traffic:
+        fd, wd, cfd, cwd = args.record_traffic
+        cmds = [f"rocprofv3 --pmc FETCH_SIZE -f csv -d {fd} -o bench -- python bench.py {args.traffic_args}",
+                f"rocprofv3 --pmc WRITE_SIZE -f csv -d {wd} -o bench -- python bench.py {args.traffic_args}",
+                f"rocprofv3 --pmc FETCH_SIZE -f csv -d {cfd} -o copy -- python bench.py --copy-probe",
+                f"rocprofv3 --pmc WRITE_SIZE -f csv -d {cwd} -o copy -- python bench.py --copy-probe"]
+        for kernel in KERNEL_SOURCES:
+            record_traffic(kernel, fd, wd, cfd, cwd, args.traffic_workload, cmds)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path holds all K blocks in one GPU's HBM and this build has no "
@@ -554,6 +694,9 @@ def main():
         sys.exit(2)
     if args.workload == "blocks4":
         print(json.dumps(run_blocks4(args)), flush=True)
+        return
+    if args.workload == "consensus":
+        print(json.dumps(run_consensus(args)), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps({"serve": run_serve(args)}), flush=True)
@@ -589,7 +732,8 @@ def main():
         "kernel_ms": {k: round(v, 5) for k, v in r["kernel_ms"].items()},
         "roofline": {"bound": "alu", "kernel": "k_render_bwd", "achieved": round(r["bwd_tflops"], 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(r["bwd_tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(r["bwd_tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "traffic": measured_traffic("k_render_bwd"),
                      "work": f"{BWD_FLOPS} flops x {r['kept']:.4g} (pixel, Gaussian) contributions per launch"},
         "roofline_stream": {"bound": "hbm", "kernel": r["opt_kernel"], "achieved": round(r["opt_gbs"], 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["opt_gbs"] / HBM_PEAK_GBS, 4),
