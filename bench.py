@@ -191,11 +191,20 @@ def run_gpu(args):
     log(f"[bench] max pairs over views {pmax}, capacity {buf.capacity}")
     loss = torch.zeros(1, device="cuda")
     buf.counters.zero_()
+    lam = args.ssim
+    if lam > 0:
+        # Eq. 3 with the D-SSIM term: dL/dC from gs_ssim_loss_grad, then the
+        # backward takes it as an external gradient
+        dl = torch.empty(3 * max(f.n_pixels for f in frames), device="cuda")
+        ssim_ws = torch.empty(int(gs.lib.gs_ssim_workspace_size(max(f.n_pixels for f in frames))),
+                              dtype=torch.uint8, device="cuda")
 
     if args.unfused:
         names = ["project", "bin_sort", "render_fwd", "render_bwd", "adam_admm", "end"]
     else:
         names = ["project", "bin_sort", "render_fwd", "render_bwd_adam", "end"]
+    if lam > 0:
+        names.insert(3, "ssim")
 
     def step(t, timer=None):
         f = frames[t % len(frames)]
@@ -207,15 +216,19 @@ def run_gpu(args):
         mark("render_fwd")
         gs.render_fwd(f, cfg, buf)
         acfg = gs.adam_cfg(LR, RHO, t + 1)
+        mode, gin = gs.LOSS_L1, targets[t % len(frames)]
+        if lam > 0:
+            mark("ssim")
+            gs.ssim_loss_grad(f, cfg, buf.rgb, gin, lam, grad_out=dl, loss_out=loss, ws=ssim_ws)
+            mode, gin = gs.LOSS_EXTERNAL, dl
         if args.unfused:
             mark("render_bwd")
-            gs.render_bwd(st["x"], f, cfg, buf, st["g"], gs.LOSS_L1, targets[t % len(frames)], loss)
+            gs.render_bwd(st["x"], f, cfg, buf, st["g"], mode, gin, loss)
             mark("adam_admm")
             gs.adam_admm(st["x"], st["g"], st["m"], st["v"], st["w"], None, acfg)
         else:
             mark("render_bwd_adam")
-            gs.render_bwd_adam(st["x"], f, cfg, buf, st["m"], st["v"], st["w"], None, acfg, gs.LOSS_L1,
-                               targets[t % len(frames)], loss)
+            gs.render_bwd_adam(st["x"], f, cfg, buf, st["m"], st["v"], st["w"], None, acfg, mode, gin, loss)
         mark("end")
 
     for t in range(args.warmup):
@@ -229,6 +242,8 @@ def run_gpu(args):
     # the library times the launches of these kernels with its own HIP events
     # on the launch stream (fused calls hold several kernels)
     kernels = ["k_render_bwd", "k_render_fwd", "k_adam_admm" if args.unfused else "k_project_bwd_adam"]
+    if lam > 0:
+        kernels += ["k_ssim_fwd", "k_ssim_bwd"]
     gs.profile_set(kernels)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -276,7 +291,19 @@ def run_gpu(args):
     # (pixel, Gaussian) contribution (alpha recomputed, transmittance, colour
     # behind, dL/dalpha, colour and moment accumulations; an FMA counts 2)
     bwd_flops = BWD_FLOPS * kept
+    ssim = None
+    if lam > 0:
+        # algorithmic bytes of the two SSIM passes per colour value: the
+        # forward reads image and target and writes three derivative maps
+        # (20 B), the backward reads the maps, image and target and writes
+        # dL/dC (24 B)
+        px = 3 * args.width * args.height
+        ssim_ms = kern["k_ssim_fwd"] + kern["k_ssim_bwd"]
+        ssim = {"bound": "hbm", "kernel": "k_ssim_fwd + k_ssim_bwd", "achieved": round(44 * px / (ssim_ms * 1e-3) / 1e9, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(44 * px / (ssim_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "bytes": 44 * px, "ms": round(ssim_ms, 5), "lambda": lam}
     return dict(ms_per_step=ms / args.steps, steps=args.steps, stage_ms=stage, kernel_ms=kern, opt_kernel=opt_kernel,
+                ssim=ssim,
                 opt_bytes=opt_bytes, opt_gbs=opt_bytes / (opt_ms * 1e-3) / 1e9, pairs_max=pmax, pairs=pairs,
                 kept=kept, bwd_flops=bwd_flops, bwd_tflops=bwd_flops / (kern["k_render_bwd"] * 1e-3) / 1e12, N=N, A=A,
                 scene=scene)
@@ -655,6 +682,8 @@ def main():
                     help="train: single block at scale (+ serve leg); blocks4: batched K=4 blocks; serve: serving "
                          "only; consensus: the consensus step alone on the K=4 block store")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the train workload")
+    ap.add_argument("--ssim", type=float, default=0.0,
+                    help="train: weight lambda of the D-SSIM term of the loss (0: the L1 loss alone)")
     ap.add_argument("--serve-n", type=int, default=6_000_000)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=8.0)
@@ -741,6 +770,9 @@ def main():
         "cpu_baseline": cpu,
         "serve": srv,
     }
+    if r["ssim"] is not None:
+        out["roofline_ssim"] = r["ssim"]
+        out["config"]["workload"] = out["config"]["workload"].replace("L1 +", f"L1 + {r['ssim']['lambda']} D-SSIM +")
     print(json.dumps(out), flush=True)
 
 

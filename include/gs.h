@@ -252,6 +252,28 @@ gs_status gs_render_bwd_f64(const gs_params *params, const gs_frame *frame, cons
                             double *loss_out_dev, gs_params *grad, void *ws_dev, size_t ws_bytes,
                             gs_stream stream);
 
+/* Photometric loss of Eq. 3 with its structural term, per job j:
+ *   L_j = w_j (mean |C - target| + lambda (1 - mean SSIM)),
+ * w_j = jobs[j].loss_weight, means over the job's 3 H W colour values.  SSIM
+ * is that of Wang et al. (cited by the paper for its SSIM metric) under an
+ * 11 x 11 Gaussian window of sigma 1.5 normalised to 1, zero outside the
+ * image (a "same" correlation), per colour channel, C1 = 0.01^2,
+ * C2 = 0.03^2; L_ssim = 1 - SSIM is the D-SSIM of the splatting recipe the
+ * paper trains with.  rgb_dev / target_dev: planar [3][H][W] images at
+ * 3 * px0 (as gs_render_fwd writes them).  grad_out_dev (same layout)
+ * receives dL/dC (sign(0) = 0 for the L1 part): pass it to gs_render_bwd /
+ * gs_render_bwd_adam with GS_LOSS_EXTERNAL.  loss_out_dev (float[n_jobs],
+ * may be NULL) accumulates L_j; the caller zeroes it; its float additions
+ * run in no fixed order.  cfg gives the binning tiles the frame was planned
+ * with (its wavefront fields are not used).  Workspace:
+ * gs_ssim_workspace_size(frame->n_pixels) bytes (three FP32 derivative maps
+ * per colour value).  lambda >= 0 and finite; lambda = 0 gives the L1 loss
+ * alone. */
+size_t gs_ssim_workspace_size(int64_t n_pixels);
+gs_status gs_ssim_loss_grad(const gs_frame *frame, const gs_raster_cfg *cfg, const float *rgb_dev,
+                            const float *target_dev, float lambda, float *grad_out_dev, float *loss_out_dev,
+                            void *ws_dev, size_t ws_bytes, gs_stream stream);
+
 /* x-update step of Eq. 8a: Adam (bias-corrected) on g + rho_a (x - w), where
  * w = z - u is the consensus target and rho_a the per-attribute penalty
  * (supplementary Sec. C).  w == NULL: no penalty.  mask (device float [n],

@@ -158,7 +158,7 @@ class AdmmTrainer:
 
     def __init__(self, model: BlockModel, cams, targets, cfg: gs.GsRasterCfg, lr=DEFAULT_LR, rho=(1e-3,) * 5,
                  intv=100, relax=1.0, beta1=0.9, beta2=0.999, eps=1e-8, capacity=None, mask=None, fused=True,
-                 adaptive: AdaptivePenalty | None = None):
+                 adaptive: AdaptivePenalty | None = None, lambda_ssim=0.0):
         """cams[k]: list of cameras of block k; targets[k][v]: device tensor
         [3*H*W] (or a callable (k, v) -> tensor) for block k, view v.
         fused: backward and optimiser in one call (gs_render_bwd_adam, the
@@ -166,7 +166,8 @@ class AdmmTrainer:
         then gs_adam_admm.  relax: over-relaxation alpha of the consensus
         (1: none; the paper uses 1.5-1.8).  adaptive: residual-balancing
         penalty (one host read of the residual sums per consensus while it
-        is active)."""
+        is active).  lambda_ssim: weight of the D-SSIM term of Eq. 3 (0: the
+        L1 term alone, fused into the backward)."""
         self.model, self.cfg = model, cfg
         self.lr, self.rho, self.intv, self.relax = tuple(lr), tuple(rho), int(intv), float(relax)
         self.beta1, self.beta2, self.eps = beta1, beta2, eps
@@ -188,6 +189,8 @@ class AdmmTrainer:
         self.capacity = capacity
         self.loss = torch.zeros(model.K, device=x.device)
         self.adaptive = adaptive
+        self.lambda_ssim = float(lambda_ssim)
+        self._dl = self._ssim_ws = None
         self.resid = torch.zeros(10, device=x.device)
         self.history = []        # (t, residual sums, rho after the update) per adaptive consensus
 
@@ -235,13 +238,22 @@ class AdmmTrainer:
         tgt = self.target_buffer(views) if target is None else target
         self.loss.zero_()
         acfg = gs.adam_cfg(self.lr, self.rho, self.t + 1, self.beta1, self.beta2, self.eps)
+        mode, gin, loss = gs.LOSS_L1, tgt, self.loss
+        if self.lambda_ssim > 0:
+            n = 3 * f.n_pixels
+            if self._dl is None or self._dl.numel() < n:
+                self._dl = torch.empty(n, device=x.device)
+                self._ssim_ws = torch.empty(int(gs.lib.gs_ssim_workspace_size(f.n_pixels)), dtype=torch.uint8,
+                                            device=x.device)
+            gs.ssim_loss_grad(f, self.cfg, buf.rgb, tgt, self.lambda_ssim, grad_out=self._dl, loss_out=self.loss,
+                              ws=self._ssim_ws)
+            mode, gin, loss = gs.LOSS_EXTERNAL, self._dl, None
         if self.fused and f.jobs_disjoint:
-            gs.render_bwd_adam(x, f, self.cfg, buf, self.m, self.v, self.w, self.mask, acfg, gs.LOSS_L1, tgt,
-                               self.loss)
+            gs.render_bwd_adam(x, f, self.cfg, buf, self.m, self.v, self.w, self.mask, acfg, mode, gin, loss)
         else:
             if self.g is None:
                 self.g = torch.empty_like(x)
-            gs.render_bwd(x, f, self.cfg, buf, self.g, gs.LOSS_L1, tgt, self.loss)
+            gs.render_bwd(x, f, self.cfg, buf, self.g, mode, gin, loss)
             gs.adam_admm(x, self.g, self.m, self.v, self.w, self.mask, acfg)
 
     def consensus(self):

@@ -249,6 +249,22 @@ gs_status gs_render_fwd_f64(const gs_frame* frame, const gs_raster_cfg* cfg, con
 
 size_t gs_render_bwd_workspace_size(uint64_t capacity, int32_t f64) { return bwd_ws(capacity, f64); }
 
+size_t gs_ssim_workspace_size(int64_t n_pixels) { return n_pixels > 0 ? gs::ssim_workspace_size(n_pixels) : 0; }
+
+gs_status gs_ssim_loss_grad(const gs_frame* frame, const gs_raster_cfg* cfg, const float* rgb, const float* tgt,
+                            float lambda, float* grad, float* loss, void* ws, size_t ws_bytes, gs_stream stream) {
+    gs_status st;
+    if ((st = check_frame(frame, cfg)) != GS_OK) return st;
+    if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(GS_E_INVALID, "lambda %g not finite and >= 0", double(lambda));
+    if (frame->n_pixels == 0) return GS_OK;
+    if (!rgb || !tgt || !grad) return fail(GS_E_INVALID, "null image, target or gradient");
+    if (!ws || ws_bytes < gs::ssim_workspace_size(frame->n_pixels))
+        return fail(GS_E_CAPACITY, "ssim workspace %zu bytes < %zu", ws_bytes, gs::ssim_workspace_size(frame->n_pixels));
+    return check_hip(gs::launch_ssim_loss_grad(*frame, *cfg, rgb, tgt, lambda, grad, loss, static_cast<float*>(ws),
+                                               (hipStream_t)stream),
+                     "gs_ssim_loss_grad");
+}
+
 gs_status gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
                         const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
                         const void* gin, float* loss, gs_params* grad, void* ws, size_t ws_bytes, gs_stream stream) {

@@ -99,6 +99,9 @@ def _load():
                                 ctypes.c_size_t, c_vp], c_i32),
         "gs_consensus": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, c_f, c_vp, c_vp], c_i32),
         "gs_penalty_update": ([P(c_f), P(c_f), c_f, c_f, c_f, P(c_f)], c_i32),
+        "gs_ssim_workspace_size": ([c_i64], ctypes.c_size_t),
+        "gs_ssim_loss_grad": ([P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_f, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp],
+                              c_i32),
         "gs_dual_rescale": ([P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, P(c_f), c_vp], c_i32),
         "gs_profile_set": ([ctypes.c_char_p], c_i32),
         "gs_profile_get": ([ctypes.c_char_p, P(ctypes.c_double), P(c_i64)], c_i32),
@@ -308,6 +311,21 @@ def render_bwd(params: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffer
     _check(fn(ctypes.byref(p), ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.rec), _ptr(buf.meta),
               ctypes.byref(b), _ptr(buf.rgb), mode, _ptr(grad_in), _ptr(loss_out), ctypes.byref(g),
               _ptr(buf.bwd_ws), buf.bwd_ws.numel(), _stream()), "gs_render_bwd")
+
+
+def ssim_loss_grad(frame: Frame, cfg: GsRasterCfg, rgb: torch.Tensor, target: torch.Tensor, lam: float,
+                   grad_out: torch.Tensor = None, loss_out: torch.Tensor = None, ws: torch.Tensor = None):
+    """Eq. 3 with the D-SSIM term (gs_ssim_loss_grad): dL/dC into grad_out
+    (allocated when None; pass it to the backward with LOSS_EXTERNAL) and
+    the per-job loss added into loss_out.  ws: a uint8 device buffer of at
+    least gs_ssim_workspace_size bytes (allocated when None)."""
+    if grad_out is None:
+        grad_out = torch.empty_like(rgb)
+    if ws is None:
+        ws = torch.empty(int(lib.gs_ssim_workspace_size(frame.n_pixels)), dtype=torch.uint8, device=rgb.device)
+    _check(lib.gs_ssim_loss_grad(ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(rgb), _ptr(target), float(lam),
+                                 _ptr(grad_out), _ptr(loss_out), _ptr(ws), ws.numel(), _stream()), "gs_ssim_loss_grad")
+    return grad_out
 
 
 def adam_cfg(lr, rho, step, beta1=0.9, beta2=0.999, eps=1e-8) -> GsAdamCfg:

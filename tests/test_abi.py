@@ -202,3 +202,18 @@ def test_penalty_update_host_only_matches_oracle(gs):
         gs.penalty_update([-1.0] + [1.0] * 9, [1.0] * 5)
     with pytest.raises(gs.GsError, match="rho"):
         gs.penalty_update([1.0] * 10, [0.0] + [1.0] * 4)
+
+
+def test_ssim_entry_host_checks(gs):
+    """Workspace size and argument checks of gs_ssim_loss_grad, no launch."""
+    assert gs.lib.gs_ssim_workspace_size(1000) == 1000 * 3 * 3 * 4
+    assert gs.lib.gs_ssim_workspace_size(0) == 0
+    f = gs.GsFrame()
+    cfg = gs.raster_cfg()
+    call = lambda lam: gs.lib.gs_ssim_loss_grad(ctypes.byref(f), ctypes.byref(cfg), None, None, lam, None, None,  # noqa: E731
+                                                None, 0, None)
+    assert call(-0.5) == gs.GS_E_INVALID and "lambda" in gs.lib.gs_last_error().decode()
+    assert call(float("inf")) == gs.GS_E_INVALID
+    assert call(0.2) == gs.GS_OK                   # empty frame: nothing to do
+    f.n_pixels = 10
+    assert call(0.2) == gs.GS_E_INVALID            # null images
