@@ -265,10 +265,10 @@ gs_status gs_render_bwd_f64(const gs_params *params, const gs_frame *frame, cons
  * gs_render_bwd_adam with GS_LOSS_EXTERNAL.  loss_out_dev (float[n_jobs],
  * may be NULL) accumulates L_j; the caller zeroes it; its float additions
  * run in no fixed order.  cfg gives the binning tiles the frame was planned
- * with (its wavefront fields are not used).  Workspace:
- * gs_ssim_workspace_size(frame->n_pixels) bytes (three FP32 derivative maps
- * per colour value).  lambda >= 0 and finite; lambda = 0 gives the L1 loss
- * alone. */
+ * with (its wavefront fields are not used).  Workspace (device, 4-byte
+ * aligned): gs_ssim_workspace_size(frame->n_pixels) bytes (three FP32
+ * derivative maps per colour value).  lambda >= 0 and finite; lambda = 0
+ * gives the L1 loss alone. */
 size_t gs_ssim_workspace_size(int64_t n_pixels);
 gs_status gs_ssim_loss_grad(const gs_frame *frame, const gs_raster_cfg *cfg, const float *rgb_dev,
                             const float *target_dev, float lambda, float *grad_out_dev, float *loss_out_dev,

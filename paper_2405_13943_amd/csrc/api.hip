@@ -258,10 +258,11 @@ gs_status gs_ssim_loss_grad(const gs_frame* frame, const gs_raster_cfg* cfg, con
     if (!(lambda >= 0.f) || !std::isfinite(lambda)) return fail(GS_E_INVALID, "lambda %g not finite and >= 0", double(lambda));
     if (frame->n_pixels == 0) return GS_OK;
     if (!rgb || !tgt || !grad) return fail(GS_E_INVALID, "null image, target or gradient");
-    if (!ws || ws_bytes < gs::ssim_workspace_size(frame->n_pixels))
-        return fail(GS_E_CAPACITY, "ssim workspace %zu bytes < %zu", ws_bytes, gs::ssim_workspace_size(frame->n_pixels));
-    return check_hip(gs::launch_ssim_loss_grad(*frame, *cfg, rgb, tgt, lambda, grad, loss, static_cast<float*>(ws),
-                                               (hipStream_t)stream),
+    if (frame->n_tiles == 0) return GS_OK;
+    const size_t need = gs::ssim_workspace_size(frame->n_pixels);
+    if (!ws || ws_bytes < need) return fail(GS_E_CAPACITY, "ssim workspace %zu bytes < %zu", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(ws) & 3) != 0) return fail(GS_E_INVALID, "ssim workspace not 4-byte aligned");
+    return check_hip(gs::launch_ssim_loss_grad(*frame, *cfg, rgb, tgt, lambda, grad, loss, ws, (hipStream_t)stream),
                      "gs_ssim_loss_grad");
 }
 

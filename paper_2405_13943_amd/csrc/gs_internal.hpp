@@ -67,7 +67,7 @@ hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const 
 // ssim.hip
 size_t ssim_workspace_size(int64_t n_pixels);
 hipError_t launch_ssim_loss_grad(const gs_frame& f, const gs_raster_cfg& cfg, const float* rgb, const float* tgt,
-                                 float lambda, float* grad, float* loss, float* ws, hipStream_t s);
+                                 float lambda, float* grad, float* loss, void* ws, hipStream_t s);
 
 // optim.hip
 hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_params& v, const gs_params* w,
