@@ -5,8 +5,9 @@ CPU-baseline leg of the benchmark may import this package; the product path
 never does.  It shares no code with the GPU implementation: the rasterizer is
 plain C (``orc.c``, per-pixel brute force in FP64), the optimiser and the
 consensus step are plain NumPy in FP64 (``admm.py``), the structural
-similarity term of the loss is NumPy in FP64 (``ssim.py``), and the
-tile-binning reference is a stable sort (``binning.py``).
+similarity term of the loss is NumPy in FP64 (``ssim.py``), the scene
+splitting is plain Python (``split.py``), and the tile-binning reference is a
+stable sort (``binning.py``).
 
 Every function says which passage of the paper it follows.  Pinned by the
 ``-m "not gpu"`` tests (closed forms, invariants, library routines, finite
@@ -17,4 +18,4 @@ from .raster import (Camera, RasterConfig, project, render, backward, sh_basis, 
 from .admm import (adam_admm, adaptive_rho, consensus, consensus_full, penalty_groups,  # noqa: F401
                    rescale_duals, residual_sums, scaled_lagrangian, unscaled_lagrangian)
 from .binning import bin_reference  # noqa: F401
-from . import ssim  # noqa: F401
+from . import split, ssim  # noqa: F401
