@@ -350,6 +350,37 @@ gs_status gs_dual_rescale(gs_params *u_local, gs_params *w_local, const gs_param
                           const int64_t *holder_ptr_dev, const int64_t *holder_idx_dev, const float *scale_host,
                           gs_stream stream);
 
+/* Scene splitting into K blocks (Alg. 1; host only, no device work).
+ * points (host double [n][3]): the initial point cloud.  Starting from the
+ * tight box of all points, rounds cut every current cell (first in, first
+ * out) in two along its longer ground axis and append the two re-tightened
+ * halves, until there are K cells (the last round stops at K).  The cut
+ * puts the floor(m/2) points of a cell with the smallest (coordinate, point
+ * id) in the first half (a median cut: blocks of similar point counts).
+ * ground_axes: bit mask of the axes that may be cut (the paper assumes one
+ * axis is aligned with the ground; 5 = x and z with y up).  Ties between
+ * axis extents go to the lower axis.  boxes (host double [K][6], lo xyz then
+ * hi xyz) receives the cells' tight boxes in the algorithm's order;
+ * cell_of (host int64 [n], may be NULL) each point's cell.  Requires
+ * 1 <= K <= n and finite coordinates. */
+gs_status gs_split_scene(const double *points_host, int64_t n, int32_t K, int32_t ground_axes,
+                         double *boxes_host, int64_t *cell_of_host);
+
+/* Overlap grouping (Sec. 3.2, scene splitting): block k holds every point
+ * (or camera centre) covered by its cell box scaled by `scale` (>= 1; the
+ * paper uses 1.4) about the box centre, computed as each side moved out by
+ * (scale - 1) / 2 of the box extent, bounds inclusive, on the axes of the
+ * test_axes bit mask (7 for points; the ground axes for camera centres,
+ * which lie above the point cloud, so that views follow their ground-plane
+ * cell as the paper assigns them).  counts (host int64
+ * [K]) and *total receive the block sizes; members (host int64, may be
+ * NULL), when capacity >= *total, receives block 0's point ids ascending,
+ * then block 1's, ...; a smaller non-NULL buffer gives GS_E_CAPACITY after
+ * the counts are written. */
+gs_status gs_split_group(const double *boxes_host, int32_t K, double scale, int32_t test_axes,
+                         const double *points_host, int64_t n, int64_t *counts_host, int64_t *members_host,
+                         int64_t capacity, int64_t *total_host);
+
 #ifdef __cplusplus
 }
 #endif

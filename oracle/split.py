@@ -65,12 +65,15 @@ def expand_box(box, s):
     return [lo[a] - g[a] for a in range(3)] + [hi[a] + g[a] for a in range(3)]
 
 
-def group(boxes, s, points):
-    """Per block, the ascending ids of the points its scaled box covers."""
+def group(boxes, s, points, axes=(0, 1, 2)):
+    """Per block, the ascending ids of the points its scaled box covers on
+    the given axes (all three for points; the ground axes for camera
+    centres, which sit above the point cloud: the paper assigns views by
+    their ground-plane cell)."""
     pts = np.asarray(points, np.float64)
     out = []
     for box in boxes:
         e = expand_box(box, s)
         out.append([i for i in range(len(pts))
-                    if all(e[a] <= pts[i][a] <= e[3 + a] for a in range(3))])
+                    if all(e[a] <= pts[i][a] <= e[3 + a] for a in axes)])
     return out

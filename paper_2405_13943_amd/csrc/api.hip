@@ -384,6 +384,28 @@ gs_status gs_penalty_update(const float* resid, float* rho, float mu, float tau_
     return GS_OK;
 }
 
+gs_status gs_split_scene(const double* points, int64_t n, int32_t K, int32_t ground_axes, double* boxes,
+                         int64_t* cell_of) {
+    if (!points || !boxes) return fail(GS_E_INVALID, "null points or boxes");
+    if (n < 1 || K < 1 || int64_t(K) > n) return fail(GS_E_INVALID, "need 1 <= K (%d) <= points (%lld)", K, (long long)n);
+    if (ground_axes <= 0 || ground_axes > 7) return fail(GS_E_INVALID, "ground axis mask %d not in 1..7", ground_axes);
+    for (int64_t i = 0; i < 3 * n; i++)
+        if (!std::isfinite(points[i])) return fail(GS_E_INVALID, "point coordinate %lld not finite", (long long)i);
+    return gs::split_scene(points, n, K, ground_axes, boxes, cell_of);
+}
+
+gs_status gs_split_group(const double* boxes, int32_t K, double scale, int32_t test_axes, const double* points,
+                         int64_t n, int64_t* counts, int64_t* members, int64_t capacity, int64_t* total) {
+    if (!boxes || !counts || !total || (n > 0 && !points)) return fail(GS_E_INVALID, "null boxes, points, counts or total");
+    if (K < 1 || n < 0) return fail(GS_E_INVALID, "need K >= 1 and n >= 0");
+    if (!(scale >= 1.0) || !std::isfinite(scale)) return fail(GS_E_INVALID, "scale %g not finite and >= 1", scale);
+    if (test_axes <= 0 || test_axes > 7) return fail(GS_E_INVALID, "test axis mask %d not in 1..7", test_axes);
+    gs::split_group(boxes, K, scale, test_axes, points, n, counts, members, capacity, total);
+    if (members && capacity < *total)
+        return fail(GS_E_CAPACITY, "members capacity %lld < %lld", (long long)capacity, (long long)*total);
+    return GS_OK;
+}
+
 gs_status gs_dual_rescale(gs_params* u, gs_params* w, const gs_params* z, const int64_t* hptr, const int64_t* hidx,
                           const float* scale, gs_stream stream) {
     gs_status st;

@@ -69,6 +69,11 @@ size_t ssim_workspace_size(int64_t n_pixels);
 hipError_t launch_ssim_loss_grad(const gs_frame& f, const gs_raster_cfg& cfg, const float* rgb, const float* tgt,
                                  float lambda, float* grad, float* loss, void* ws, hipStream_t s);
 
+// split.hip (host)
+gs_status split_scene(const double* points, int64_t n, int32_t K, int32_t axes, double* boxes, int64_t* cell_of);
+void split_group(const double* boxes, int32_t K, double s, int32_t axes, const double* points, int64_t n,
+                 int64_t* counts, int64_t* members, int64_t capacity, int64_t* total);
+
 // optim.hip
 hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_params& v, const gs_params* w,
                             const float* mask, const gs_adam_cfg& cfg, hipStream_t s);

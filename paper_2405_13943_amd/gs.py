@@ -100,6 +100,8 @@ def _load():
         "gs_consensus": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, c_f, c_vp, c_vp], c_i32),
         "gs_penalty_update": ([P(c_f), P(c_f), c_f, c_f, c_f, P(c_f)], c_i32),
         "gs_ssim_workspace_size": ([c_i64], ctypes.c_size_t),
+        "gs_split_scene": ([c_vp, c_i64, c_i32, c_i32, c_vp, c_vp], c_i32),
+        "gs_split_group": ([c_vp, c_i32, ctypes.c_double, c_i32, c_vp, c_i64, c_vp, c_vp, c_i64, P(c_i64)], c_i32),
         "gs_ssim_loss_grad": ([P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_f, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp],
                               c_i32),
         "gs_dual_rescale": ([P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, P(c_f), c_vp], c_i32),
@@ -326,6 +328,39 @@ def ssim_loss_grad(frame: Frame, cfg: GsRasterCfg, rgb: torch.Tensor, target: to
     _check(lib.gs_ssim_loss_grad(ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(rgb), _ptr(target), float(lam),
                                  _ptr(grad_out), _ptr(loss_out), _ptr(ws), ws.numel(), _stream()), "gs_ssim_loss_grad")
     return grad_out
+
+
+def split_scene(points, K, ground_axes=(0, 2)):
+    """Alg. 1 (gs_split_scene): the K cells' tight boxes [K][6] (lo xyz, hi
+    xyz) and each point's cell, from host points [n][3]."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n = pts.shape[0]
+    boxes = np.zeros((K, 6), np.float64)
+    cell = np.zeros(n, np.int64)
+    mask = sum(1 << a for a in ground_axes)
+    _check(lib.gs_split_scene(pts.ctypes.data, n, int(K), mask, boxes.ctypes.data, cell.ctypes.data),
+           "gs_split_scene")
+    return boxes, cell
+
+
+def split_group(boxes, scale, points, axes=(0, 1, 2)):
+    """Overlap grouping (gs_split_group): per block, the ascending ids of the
+    points its box scaled by ``scale`` covers on ``axes`` (all three for
+    points, the ground axes for camera centres)."""
+    b = np.ascontiguousarray(boxes, dtype=np.float64)
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    K = b.shape[0]
+    mask = sum(1 << a for a in axes)
+    counts = np.zeros(K, np.int64)
+    total = c_i64()
+    _check(lib.gs_split_group(b.ctypes.data, K, float(scale), mask, pts.ctypes.data, pts.shape[0],
+                              counts.ctypes.data, None, 0, ctypes.byref(total)), "gs_split_group")
+    members = np.zeros(max(total.value, 1), np.int64)
+    _check(lib.gs_split_group(b.ctypes.data, K, float(scale), mask, pts.ctypes.data, pts.shape[0],
+                              counts.ctypes.data, members.ctypes.data, members.size, ctypes.byref(total)),
+           "gs_split_group")
+    ends = np.cumsum(counts)
+    return [members[e - c:e] for c, e in zip(counts, ends)]
 
 
 def adam_cfg(lr, rho, step, beta1=0.9, beta2=0.999, eps=1e-8) -> GsAdamCfg:
