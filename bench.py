@@ -458,6 +458,85 @@ def run_consensus(args):
             "roofline": cons, "rescales": rescaled, "wall_s": round(wall, 3), "final_rho": list(rho)}
 
 
+def run_split4(args):
+    """K = 4 blocks made from the scene (Alg. 1 on 7.5M Gaussian means of uneven
+    density, overlap factor ``--split-scale``; views grouped by the same
+    boxes): split time and balance, then the batched trainer (adaptive
+    penalty and over-relaxation as given, consensus every 100 steps), one view
+    per block per step."""
+    import torch
+    from paper_2405_13943_amd import admm, gs, scenes
+    t0 = time.time()
+    si = scenes.split_input()
+    log(f"[split4] scene {time.time() - t0:.1f}s")
+    t1 = time.time()
+    model, boxes, groups = admm.BlockModel.from_split(si.params_global, 4, scale=args.split_scale)
+    split_s = time.time() - t1
+    cams = admm.split_cameras(boxes, si.cams, scale=args.split_scale)
+    K = len(groups)
+    sizes = [len(g) for g in groups]
+    n_global = si.params_global.shape[1]
+    log(f"[split4] split + store {split_s:.1f}s: local {sizes}, views {[len(c) for c in cams]}")
+    dev = torch.device("cuda", 0)
+    tg = {}
+
+    def target(k, v):
+        if (k, v) not in tg:
+            c = cams[k][v]
+            tg[(k, v)] = torch.from_numpy(scenes.rng(si.seed * 1000 + 100 * k + v).random(
+                (3, c.height, c.width)).astype(np.float32)).reshape(-1).to(dev)
+        return tg[(k, v)]
+    n_views = min(len(c) for c in cams)
+    for k in range(K):
+        for v in range(n_views):
+            target(k, v)
+    del si
+    tile = (args.tile, args.tile, args.fwd_waves, args.bwd_waves)
+    adaptive = admm.AdaptivePenalty() if args.adaptive else None
+    tr = admm.AdmmTrainer(model, cams, target, gs.raster_cfg(tile), lr=LR, rho=RHO, intv=100, relax=args.relax,
+                          adaptive=adaptive)
+    tr.calibrate()
+    for _ in range(args.warmup):
+        tr.step()
+    cons = []
+    gs.profile_set(["k_consensus", "k_dual_rescale"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    steps = args.block_steps
+    for _ in range(steps):
+        tr.local_step()
+        if tr.t % tr.intv == 0:
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            tr.consensus()
+            b.record()
+            cons.append((a, b))
+        tr.t += 1
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    kernels = {k: gs.profile_get(k) for k in ("k_consensus", "k_dual_rescale")}
+    gs.profile_set(None)
+    if not tr.check(grow=False):
+        raise SystemExit("pair capacity overflowed during the timed steps")
+    c_ms = [a.elapsed_time(b) for a, b in cons]
+    roof = consensus_roofline(model, tr, c_ms, kernels)
+    return {"metric": "K-block ADMM train steps/s on Alg. 1 blocks (4 blocks, 1 view each, consensus/100)",
+            "value": 1000.0 * steps / ms, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic (7.5M Gaussians, 70% uniform + 30% cluster; 8x8 view lattice; U(0,1) "
+                                    "targets)",
+            "config": {"workload": f"Alg. 1 split of 7.5M Gaussians SH3 into 4 blocks, overlap scale "
+                                   f"{args.split_scale}, 1600x1066, consensus every 100 steps",
+                       "tile": "x".join(map(str, tile[:2])), "waves_per_tile_fwd_bwd": list(tile[2:]),
+                       "relax": args.relax, "adaptive_penalty": bool(args.adaptive)},
+            "split_s": round(split_s, 2), "local_copies": sizes, "global": n_global,
+            "shared_fraction": round(sum(sizes) / n_global - 1.0, 4),
+            "balance_max_over_min": round(max(sizes) / min(sizes), 4),
+            "views_per_block": [len(c) for c in cams], "consensus_ms": c_ms, "consensus_roofline": roof}
+
+
 def run_blocks4(args):
     """K = 4 uneven blocks (0.8M/1.5M/2.2M/3.0M own Gaussians, 10% shared with
     a neighbour), 32 ring views per block at 1600x1066: the batched trainer
@@ -678,9 +757,10 @@ def main():
                     help="backward compositing wavefronts per tile: 1, 2, 4, or -1 per tile from its list length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="backward and optimiser as two calls (gradient in HBM)")
-    ap.add_argument("--workload", choices=("train", "blocks4", "serve", "consensus"), default="train",
+    ap.add_argument("--workload", choices=("train", "blocks4", "serve", "consensus", "split4"), default="train",
                     help="train: single block at scale (+ serve leg); blocks4: batched K=4 blocks; serve: serving "
-                         "only; consensus: the consensus step alone on the K=4 block store")
+                         "only; consensus: the consensus step alone on the K=4 block store; split4: K=4 blocks from "
+                         "the scene by Alg. 1")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the train workload")
     ap.add_argument("--ssim", type=float, default=0.0,
                     help="train: weight lambda of the D-SSIM term of the loss (0: the L1 loss alone)")
@@ -695,6 +775,7 @@ def main():
     ap.add_argument("--no-tile-auto", action="store_true", help="blocks4: use --tile instead of the autotuner")
     ap.add_argument("--relax", type=float, default=1.0, help="blocks4: over-relaxation alpha of the consensus")
     ap.add_argument("--adaptive", action="store_true", help="blocks4: residual-balancing penalty (until 2000)")
+    ap.add_argument("--split-scale", type=float, default=1.4, help="split4: overlap scale factor of the blocks")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -723,6 +804,9 @@ def main():
         sys.exit(2)
     if args.workload == "blocks4":
         print(json.dumps(run_blocks4(args)), flush=True)
+        return
+    if args.workload == "split4":
+        print(json.dumps(run_split4(args)), flush=True)
         return
     if args.workload == "consensus":
         print(json.dumps(run_consensus(args)), flush=True)

@@ -59,6 +59,14 @@ def holder_csr(local_gid, n_global, local_index=None):
     return ptr, cols[order].astype(np.int64)
 
 
+def split_cameras(boxes, cams, scale=1.4, ground_axes=(0, 2)):
+    """Per block, the views whose centres its cell box, scaled by ``scale``,
+    covers in the ground plane (Sec. 3.2: views are split with the points)."""
+    centres = np.stack([-np.asarray(c.R, np.float64).T @ np.asarray(c.t, np.float64) for c in cams])
+    groups = gs.split_group(boxes, scale, centres, ground_axes)
+    return [[cams[i] for i in g] for g in groups]
+
+
 def holder_order(local_gid, n_global):
     """Numbering of the global ids grouped by holder set: ids held by the
     same blocks become consecutive, groups ordered by (first holder, number
@@ -134,6 +142,17 @@ class BlockModel:
         ends = [offs[k] + len(local_gid[k]) for k in range(len(local_gid))]
         return cls(deg, z, x, offs[:-1] + [offs[-1]], torch.from_numpy(ptr).to(device),
                    torch.from_numpy(idx).to(device), [np.asarray(g) for g in local_gid], ends, perm)
+
+    @classmethod
+    def from_split(cls, params_global: np.ndarray, K: int, scale=1.4, ground_axes=(0, 2), device="cuda", align=64):
+        """K blocks from the scene itself (Alg. 1 on the Gaussian means, then
+        the overlap grouping with factor ``scale``; the paper uses 1.4):
+        returns (model, cell boxes [K][6], per-block global ids in the
+        caller's numbering)."""
+        pts = np.ascontiguousarray(params_global[0:3].T, dtype=np.float64)
+        boxes, _ = gs.split_scene(pts, K, ground_axes)
+        groups = gs.split_group(boxes, scale, pts)
+        return cls.from_global(params_global, groups, device=device, align=align), boxes, groups
 
     @property
     def K(self):

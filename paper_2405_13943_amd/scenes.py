@@ -244,6 +244,42 @@ def block_scene(counts=BLOCK_COUNTS, bounds=SLAB_BOUNDS, share=0.10, n_cams=32,
     return BlockScene(params_global, sh_degree, local_gid, list(counts), cams, seed)
 
 
+@dataclass
+class SplitInput:
+    """A global model and a global camera set, to be split into blocks."""
+    params_global: np.ndarray        # [A][N]
+    sh_degree: int
+    cams: list                       # global training views
+    seed: int
+
+
+def split_input(n=7_500_000, n_grid=8, width=1600, height=1066, sh_degree=3, seed=1005) -> SplitInput:
+    """Global Gaussians with uneven density, 70% uniform over the
+    100 x 20 x 100 m box and 30% in a cluster around (15, 0, -20) with
+    standard deviations (8, 3, 8) (drawn in chunks of 1M with seed
+    seed * 1000 + chunk); views on an n_grid x n_grid lattice 25 m above the
+    ground plane over x, z in [-45, 45], each looking at the ground 15 m ahead
+    along +z."""
+    n_u = int(round(0.7 * n))
+    step = 1_000_000
+    parts = []
+    for a in range(0, n, step):
+        m = min(step, n - a)
+        sd = seed * 1000 + a // step
+        p = gaussians(m, sh_degree, sd, [-50, -10, -50], [50, 10, 50], -3.0, 0.7)
+        lo_c = max(a, n_u) - a                  # entries of this chunk that belong to the cluster
+        if lo_c < m:
+            g = rng(sd + 500)
+            k = m - lo_c
+            p[MEAN:MEAN + 3, lo_c:] = (np.array([15.0, 0.0, -20.0])[:, None]
+                                       + g.normal(0.0, 1.0, (3, k)) * np.array([8.0, 3.0, 8.0])[:, None])
+        parts.append(p)
+    params = np.concatenate(parts, axis=1)
+    xs = np.linspace(-45.0, 45.0, n_grid)
+    cams = [look_at([x, 25.0, z], [x, 0.0, z + 15.0], width, height) for z in xs for x in xs]
+    return SplitInput(params, sh_degree, cams, seed)
+
+
 def poisson_arrivals(rate, duration, seed):
     g = rng(seed)
     t, out = 0.0, []

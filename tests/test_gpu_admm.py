@@ -254,3 +254,43 @@ def test_autotuner_picks_a_candidate_and_caches(tmp_path):
     best = admm.autotune_tile(run, "tiny-3blocks", path, reps=2)
     assert best in admm.TILES
     assert admm.autotune_tile(lambda t: (_ for _ in ()).throw(AssertionError), "tiny-3blocks", path) == best
+
+
+def test_trainer_on_alg1_blocks():
+    """Blocks made by Alg. 1 (K = 3, overlap 1.4) from a small uneven scene:
+    the batched frame renders each block as its own render, the holder CSR
+    covers every Gaussian the grouping assigned, and after steps with
+    consensus the duals of shared Gaussians average to zero."""
+    si = scenes.split_input(n=3000, n_grid=3, width=64, height=48)
+    model, boxes, groups = admm.BlockModel.from_split(si.params_global, 3)
+    cams = admm.split_cameras(boxes, si.cams)
+    assert all(len(c) > 0 for c in cams)
+    ptr = model.holder_ptr.cpu().numpy()
+    cnt = np.diff(ptr)
+    assert cnt.sum() == sum(len(g) for g in groups) and (cnt >= 1).all() and (cnt > 1).sum() > 100
+    targets = [[torch.from_numpy(t).reshape(-1).cuda() for t in scenes.target_images(970 + 10 * k, cams[k])]
+               for k in range(3)]
+    cfg = gs.raster_cfg((16, 16))
+    tr = admm.AdmmTrainer(model, cams, targets, cfg, lr=(1e-3, 2e-3, 3e-3, 4e-3, 5e-3), rho=(1e-2,) * 5, intv=2,
+                          capacity=1 << 18, relax=1.6, adaptive=admm.AdaptivePenalty(until=10))
+    views = [0, 0, 0]
+    f = tr.frame(views)
+    buf = gs.Buffers(f, 1 << 18)
+    gs.rasterize(model.x, f, cfg, buf)
+    for k in range(3):
+        a, b = model.block(k)
+        fk = gs.Frame([cams[k][0]], [gs.JobSpec(0, 0, b - a, 1.0)], cfg)
+        bk = gs.rasterize(model.x[:, a:b].contiguous(), fk, cfg)
+        assert torch.equal(f.image(buf.rgb, k), fk.image(bk.rgb, 0))
+    for _ in range(5):
+        tr.step()
+    assert tr.check()
+    idx = model.holder_idx.cpu().numpy()
+    u = tr.u.cpu().numpy().astype(np.float64)
+    x = model.x.cpu().numpy().astype(np.float64)
+    for g in np.nonzero(cnt > 1)[0][:300]:
+        hs = idx[ptr[g]:ptr[g + 1]]
+        # FP32 rounding of u = x - z at the copies' magnitude (means reach ~50)
+        tol = 8 * 2.0 ** -24 * (1.0 + np.abs(x[:, hs]).max(axis=1))
+        assert (np.abs(u[:, hs].mean(axis=1)) <= tol).all(), g
+    assert len(tr.history) >= 2
