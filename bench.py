@@ -43,6 +43,8 @@ KERNEL_SOURCES = {
     "k_project_bwd_adam": ("project.hip", "adam.hpp", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
     "k_render_bwd": ("render.hip", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
     "k_consensus": ("optim.hip", "adam.hpp", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
+    "k_ssim_fwd": ("ssim.hip", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
+    "k_ssim_bwd": ("ssim.hip", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
 }
 
 
@@ -80,8 +82,9 @@ def _counter_per_dispatch(csv_dir, kernel, counter):
     for path in glob.glob(os.path.join(csv_dir, "*counter_collection.csv")):
         with open(path) as fh:
             for r in csv.DictReader(fh):
-                if r["Counter_Name"] == counter and (kernel is None or f"gs::{kernel}<" in r["Kernel_Name"]
-                                                     or f"gs::{kernel}(" in r["Kernel_Name"]):
+                name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+                if r["Counter_Name"] == counter and (kernel is None or f"gs::{kernel}<" in name
+                                                     or f"gs::{kernel}(" in name):
                     vals.append(float(r["Counter_Value"]))
     return sum(vals) / len(vals) if vals else None
 
@@ -302,6 +305,8 @@ def run_gpu(args):
         ssim = {"bound": "hbm", "kernel": "k_ssim_fwd + k_ssim_bwd", "achieved": round(44 * px / (ssim_ms * 1e-3) / 1e9, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(44 * px / (ssim_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "bytes": 44 * px, "ms": round(ssim_ms, 5), "lambda": lam}
+        tf, tb = measured_traffic("k_ssim_fwd"), measured_traffic("k_ssim_bwd")
+        ssim["traffic"] = tf + tb if tf is not None and tb is not None else None
     return dict(ms_per_step=ms / args.steps, steps=args.steps, stage_ms=stage, kernel_ms=kern, opt_kernel=opt_kernel,
                 ssim=ssim,
                 opt_bytes=opt_bytes, opt_gbs=opt_bytes / (opt_ms * 1e-3) / 1e9, pairs_max=pmax, pairs=pairs,
@@ -781,6 +786,9 @@ def main():
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="host only: write profiles/hbm_traffic.json for the measured kernels from rocprofv3 --pmc "
                          "output directories (the bench runs, then the copy probe's)")
+    ap.add_argument("--traffic-kernels", default=None,
+                    help="with --record-traffic: comma-separated kernels to record (default: every measured kernel "
+                         "with samples)")
     ap.add_argument("--traffic-args", default="--steps 4 --warmup 2 --no-cpu-baseline --no-serve",
                     help="with --record-traffic: the bench arguments the counter runs used")
     ap.add_argument("--traffic-workload", default="plain single block, 500k Gaussians SH3, 1600x1066, 16x16 tiles, "
@@ -795,7 +803,7 @@ def main():
                 f"rocprofv3 --pmc WRITE_SIZE -f csv -d {wd} -o bench -- python bench.py {args.traffic_args}",
                 f"rocprofv3 --pmc FETCH_SIZE -f csv -d {cfd} -o copy -- python bench.py --copy-probe",
                 f"rocprofv3 --pmc WRITE_SIZE -f csv -d {cwd} -o copy -- python bench.py --copy-probe"]
-        for kernel in KERNEL_SOURCES:
+        for kernel in (args.traffic_kernels.split(",") if args.traffic_kernels else KERNEL_SOURCES):
             record_traffic(kernel, fd, wd, cfd, cwd, args.traffic_workload, cmds)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
