@@ -3,14 +3,15 @@
 // (its rasterizer is cited, not specified); this is an exact acceleration of
 // the per-pixel compositing order (depth, index).
 //
-// Two stable LSD radix sorts instead of one sort of 64-bit (tile, depth) keys:
-//   1. compact the visible records (scan of n_tiles > 0) and sort them by the
-//      FP32 bits of their depth (positive floats order like their bits);
-//   2. emit one (tile id, record) pair per covered tile in that depth order
-//      and sort the pairs by tile id only (ceil(log2 tiles) bits).
-// Stability makes each tile's list come out in (depth bits, record) order,
-// exactly what one stable sort of (tile, depth) keys on record-ordered
-// emission gives, while moving 32-bit keys over far fewer passes.
+//   1. compact the visible records (scan of n_tiles > 0), in record order;
+//   2. scan their tile counts: each record's pairs are contiguous from its
+//      first pair (pair_off), the layout the backward's per-pair partials use;
+//   3. emit one (tile id, record) pair per covered tile and sort the pairs by
+//      tile id (LSD radix, ceil(log2 tiles) bits);
+//   4. sort each tile's list by the unique key (depth bits, record) on chip
+//      (k_tile_sort: positive floats order like their bits).
+// Sorting every tile's short list in LDS replaces four global radix passes
+// over all visible records by their depth.
 //
 // Every count that depends on the data (visible records V, pairs P) stays on
 // the device: kernels read it from the counters and size their loops from
@@ -31,14 +32,13 @@ constexpr int kMaxGrid = 1024;
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BinWs {
-    uint32_t* dkey[2];    // depth keys, [n_records] each
-    uint32_t* dval[2];    // record ids, [n_records] each
+    uint32_t* dval[1];    // visible record ids, [n_records]
     uint32_t* tkey[2];    // tile keys, [capacity] each
     uint32_t* tval;       // alternate record-id buffer, [capacity]
     uint32_t* part;       // scan partials, [kMaxGrid + 1]
     uint32_t* hist;       // radix histograms, [256 * kMaxGrid]
     uint32_t* coltot;     // per-digit totals of one radix pass, [256]
-    uint32_t* poff;       // first pair of each visible record in depth order, [n_records]
+    uint32_t* poff;       // first pair of each visible record in compacted order, [n_records]
     size_t bytes;
 };
 
@@ -48,8 +48,7 @@ static BinWs carve(void* base, int64_t n_records, uint64_t capacity) {
     size_t off = 0;
     auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return reinterpret_cast<uint32_t*>(q); };
     const size_t nr = size_t(n_records > 0 ? n_records : 1) * 4, nc = size_t(capacity > 0 ? capacity : 1) * 4;
-    w.dkey[0] = take(nr); w.dkey[1] = take(nr);
-    w.dval[0] = take(nr); w.dval[1] = take(nr);
+    w.dval[0] = take(nr);
     w.tkey[0] = take(nc); w.tkey[1] = take(nc);
     w.tval = take(nc);
     w.part = take(size_t(kMaxGrid + 1) * 4);
@@ -101,18 +100,16 @@ __device__ inline void block_range(uint32_t n, int G, int b, uint32_t granule, u
 // ---------------------------------------------------------------------------
 // reduce-then-scan over a device-sized sequence; two flavours of input/output
 
-struct VisibleFlag {      // item i: record i is visible; output: compact (depth key, record)
+struct VisibleFlag {      // item i: record i is visible; output: the compacted record ids
     const uint4* meta;
-    uint32_t* key_out;
     uint32_t* val_out;
     __device__ uint32_t value(uint32_t i) const { return meta_tiles(meta[i].y) > 0 ? 1u : 0u; }
     __device__ void emit(uint32_t i, uint32_t pre) const {
-        const uint4 m = meta[i];
-        if (meta_tiles(m.y) > 0) { key_out[pre] = m.x; val_out[pre] = i; }
+        if (meta_tiles(meta[i].y) > 0) val_out[pre] = i;
     }
 };
 
-struct PairCount {        // item s: sorted visible record; output: its first pair
+struct PairCount {        // item s: visible record s; output: its first pair
     const uint4* meta;
     const uint32_t* sorted_rec;
     uint32_t* pair_off;       // by record
@@ -351,6 +348,102 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// per-tile depth order: each tile's list (record ids, any order) sorted by the
+// unique key (depth bits, record id).  Short lists: a rank sort in LDS (each
+// thread counts the smaller keys of its entries); up to kSortChunk: a bitonic
+// sort in LDS; longer lists: chunks of kSortChunk sorted in LDS, then
+// pairwise merges of sorted runs through a scratch range (each entry's place
+// is its index in its run plus the number of smaller keys in the other run,
+// found by binary search).  A persistent grid walks the tiles.
+
+constexpr int kSortBlock = 256;
+constexpr int kSortChunk = 2048;
+
+__device__ __forceinline__ uint64_t depth_key(const uint4* __restrict__ meta, uint32_t r) {
+    return (uint64_t(meta[r].x) << 32) | r;
+}
+
+// number of keys in run[0, n) smaller than k (the run is sorted)
+__device__ __forceinline__ uint32_t count_less(const uint4* __restrict__ meta, const uint32_t* run, uint32_t n,
+                                               uint64_t k) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (depth_key(meta, run[mid]) < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restrict__ meta,
+                                                          const uint2* __restrict__ ranges, int n_tiles,
+                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ scratch) {
+    __shared__ uint64_t sk[kSortChunk];
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint2 rg = ranges[tile];
+        const uint32_t n = rg.y - rg.x;
+        if (n < 2) continue;                                   // uniform per workgroup
+        uint32_t* v = vals + rg.x;
+        if (n <= kSortBlock) {
+            const uint32_t i = threadIdx.x;
+            const uint64_t k = i < n ? depth_key(meta, v[i]) : 0;
+            if (i < n) sk[i] = k;
+            __syncthreads();
+            if (i < n) {
+                uint32_t rank = 0;
+                for (uint32_t j = 0; j < n; j++) rank += sk[j] < k ? 1u : 0u;
+                v[rank] = uint32_t(k);
+            }
+            __syncthreads();
+            continue;
+        }
+        // chunks of kSortChunk: bitonic sort in LDS (padded with the largest key)
+        for (uint32_t c0 = 0; c0 < n; c0 += kSortChunk) {
+            const uint32_t m = min(uint32_t(kSortChunk), n - c0);
+            uint32_t p = 1;
+            while (p < m) p <<= 1;
+            for (uint32_t i = threadIdx.x; i < p; i += kSortBlock) sk[i] = i < m ? depth_key(meta, v[c0 + i]) : ~0ull;
+            __syncthreads();
+            for (uint32_t k = 2; k <= p; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = threadIdx.x; i < p; i += kSortBlock) {
+                        const uint32_t ij = i ^ j;
+                        if (ij > i) {
+                            const uint64_t a = sk[i], b = sk[ij];
+                            const bool up = (i & k) == 0;
+                            if ((a > b) == up) { sk[i] = b; sk[ij] = a; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t i = threadIdx.x; i < m; i += kSortBlock) v[c0 + i] = uint32_t(sk[i]);
+            __syncthreads();
+        }
+        // pairwise merges of sorted runs, ping-ponging with the scratch range
+        uint32_t* src = v;
+        uint32_t* dst = scratch + rg.x;
+        for (uint32_t run = kSortChunk; run < n; run <<= 1) {
+            for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) {
+                const uint32_t a0 = (i / (2 * run)) * (2 * run), b0 = a0 + run, b1 = min(a0 + 2 * run, n);
+                const uint32_t r = src[i];
+                if (b0 >= n) { dst[i] = r; continue; }
+                const uint64_t k = depth_key(meta, r);
+                if (i < b0) dst[i + count_less(meta, src + b0, b1 - b0, k)] = r;
+                else dst[a0 + (i - b0) + count_less(meta, src + a0, run, k)] = r;
+            }
+            __syncthreads();
+            uint32_t* t = src;
+            src = dst;
+            dst = t;
+        }
+        if (src != v) {
+            for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) v[i] = src[i];
+            __syncthreads();
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ counters,
                                                 uint64_t capacity, uint2* __restrict__ ranges) {
     const uint32_t P = uint32_t(min(uint64_t(counters[GS_CTR_PAIRS]), capacity));
@@ -462,29 +555,25 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
         return hipGetLastError();
     }
 
-    // 1. compact visible records as (depth bits, record)
+    // 1. compact the visible records (record order)
     const int Gs = grid_for(nrec, kScanBlock * 8);
-    VisibleFlag vf{meta, w.dkey[0], w.dval[0]};
+    VisibleFlag vf{meta, w.dval[0]};
     GS_LAUNCH("k_scan_reduce", k_scan_reduce<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
     GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_VISIBLE,
                        uint64_t(0));
     GS_LAUNCH("k_scan_apply", k_scan_apply<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
-
-    // 2. stable sort by depth bits (32 bits, 4 passes: the result is in buffer 0)
-    uint32_t* dk_final;
     const uint32_t* n_vis = bins.counters + GS_CTR_VISIBLE;
-    hipError_t e = radix_sort(w.dkey[0], w.dval[0], w.dkey[1], w.dval[1], n_vis, nrec, 32, &dk_final, s, w);
-    if (e != hipSuccess) return e;
-    const uint32_t* sorted_rec = (dk_final == w.dkey[0]) ? w.dval[0] : w.dval[1];
+    const uint32_t* sorted_rec = w.dval[0];
+    hipError_t e;
 
-    // 3. first pair of each visible record, in depth order; total pairs
+    // 2. first pair of each visible record; total pairs
     PairCount pc{meta, sorted_rec, bins.pair_off, w.poff};
     GS_LAUNCH("k_scan_reduce", k_scan_reduce<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
     GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_PAIRS,
                        bins.capacity);
     GS_LAUNCH("k_scan_apply", k_scan_apply<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
 
-    // 4. emit (tile, record) pairs in depth order, then stable sort by tile id
+    // 3. emit (tile, record) pairs, then sort them by tile id
     int bits = 0;
     while ((1ll << bits) < int64_t(f.n_tiles)) bits++;
     const int passes = (bits + 7) / 8;
@@ -500,9 +589,14 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
         if (e != hipSuccess) return e;
     }
 
-    // 5. per-tile [start, end)
+    // 4. per-tile [start, end)
     GS_LAUNCH("k_ranges", k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity,
                        reinterpret_cast<uint2*>(bins.ranges));
+    // 5. each tile's list in (depth bits, record) order (the tile sort leaves
+    //    the values in bins.vals, so the other value buffer is free scratch)
+    if (f.n_tiles > 0)
+        GS_LAUNCH("k_tile_sort", k_tile_sort, dim3(unsigned(std::min(f.n_tiles, 4096))), dim3(kSortBlock), 0, s, meta,
+                  reinterpret_cast<const uint2*>(bins.ranges), f.n_tiles, bins.vals, w.tval);
     // 6. compositing plan, when a pass splits tiles adaptively
     plan();
     return hipGetLastError();

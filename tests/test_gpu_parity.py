@@ -128,6 +128,24 @@ def test_bins_bit_exact(gpu1):
     _bins_check(frame, buf)
 
 
+@pytest.mark.parametrize("n", [300, 2500, 6000])
+def test_bins_bit_exact_long_tile_lists(n):
+    """Large Gaussians in front of a small view put n entries in every tile
+    (above 256: the in-LDS bitonic sort; above 2048: chunks and merges), with
+    many equal depths (ties ordered by record), against the reference."""
+    p = scenes.gaussians(n, 0, 4100 + n, [-0.3, -0.3, -0.3], [0.3, 0.3, 0.3], 0.0, 0.1)
+    p[scenes.MEAN + 2, ::3] = 0.25                  # every third Gaussian at the same depth
+    params = torch.from_numpy(p).cuda()
+    cam = scenes.look_at([0.0, 0.0, 3.0], [0, 0, 0], 64, 48, 60.0, 60.0)
+    for tile in [(16, 16), (8, 8)]:
+        cfg = gs.raster_cfg(tile)
+        frame = gs.Frame([cam], [gs.JobSpec(0, 0, n, 1.0)], cfg)
+        buf = gs.rasterize(params, frame, cfg, capacity=n * frame.n_tiles + 1024)
+        lens = np.diff(buf.ranges.view(-1, 2).cpu().numpy().view(np.uint32), axis=1)
+        assert lens.max() > min(n - 10, 256)
+        _bins_check(frame, buf)
+
+
 @pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 8)])
 def test_bins_bit_exact_other_tiles(cfg1, tile):
     cfg = gs.raster_cfg(tile)
