@@ -38,25 +38,38 @@ LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)       # mean, rotation, scale, SH, opaci
 RHO = (1e-3,) * 5
 
 
-# sources each measured kernel is built from (its translation unit and headers)
+# sources each measured kernel's code comes from: its translation unit and the
+# device headers it includes; of the public header only the type and constant
+# definitions count (declarations of other entry points do not change a kernel)
 KERNEL_SOURCES = {
-    "k_project_bwd_adam": ("project.hip", "adam.hpp", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
-    "k_render_bwd": ("render.hip", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
-    "k_consensus": ("optim.hip", "adam.hpp", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
-    "k_ssim_fwd": ("ssim.hip", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
-    "k_ssim_bwd": ("ssim.hip", "gs_device.hpp", "gs_internal.hpp", "../../include/gs.h"),
+    "k_project_bwd_adam": ("project.hip", "adam.hpp", "gs_device.hpp"),
+    "k_render_bwd": ("render.hip", "gs_device.hpp"),
+    "k_consensus": ("optim.hip", "adam.hpp", "gs_device.hpp"),
+    "k_ssim_fwd": ("ssim.hip", "gs_device.hpp"),
+    "k_ssim_bwd": ("ssim.hip", "gs_device.hpp"),
 }
 
 
+def _header_definitions():
+    """The typedefs (structs, enums) and #defines of include/gs.h, in order."""
+    import re
+    with open(os.path.join(ROOT, "include", "gs.h")) as fh:
+        text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+    defs = re.findall(r"typedef\s+(?:struct|enum)\s*\{.*?\}\s*\w+\s*;", text, flags=re.S)
+    defs += re.findall(r"^#define\s+GS_\w+.*$", text, flags=re.M)
+    return "\n".join(" ".join(d.split()) for d in defs)
+
+
 def kernel_sources_sha256(kernel):
-    """Fingerprint of the sources a kernel is built from."""
+    """Fingerprint of the sources a kernel's code comes from."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2405_13943_amd", "csrc")
     for f in KERNEL_SOURCES[kernel]:
-        h.update(os.path.basename(f).encode())
-        with open(os.path.normpath(os.path.join(d, f)), "rb") as fh:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
+    h.update(_header_definitions().encode())
     return h.hexdigest()
 
 

@@ -39,6 +39,7 @@ struct BinWs {
     uint32_t* hist;       // radix histograms, [256 * kMaxGrid]
     uint32_t* coltot;     // per-digit totals of one radix pass, [256]
     uint32_t* poff;       // first pair of each visible record in compacted order, [n_records]
+    uint64_t* key[2];     // sort keys of long tile lists, [capacity] each
     size_t bytes;
 };
 
@@ -55,6 +56,8 @@ static BinWs carve(void* base, int64_t n_records, uint64_t capacity) {
     w.hist = take(size_t(256) * kMaxGrid * 4);
     w.coltot = take(256 * 4);
     w.poff = take(nr);
+    w.key[0] = reinterpret_cast<uint64_t*>(take(nc * 2));
+    w.key[1] = reinterpret_cast<uint64_t*>(take(nc * 2));
     w.bytes = off;
     return w;
 }
@@ -350,12 +353,11 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, co
 
 // ---------------------------------------------------------------------------
 // per-tile depth order: each tile's list (record ids, any order) sorted by the
-// unique key (depth bits, record id).  Short lists: a rank sort in LDS (each
-// thread counts the smaller keys of its entries); up to kSortChunk: a bitonic
-// sort in LDS; longer lists: chunks of kSortChunk sorted in LDS, then
-// pairwise merges of sorted runs through a scratch range (each entry's place
-// is its index in its run plus the number of smaller keys in the other run,
-// found by binary search).  A persistent grid walks the tiles.
+// unique key (depth bits, record id).  k_tile_sort (persistent grid) takes
+// lists of up to kSortChunk entries: up to one workgroup's width a rank sort
+// in LDS (each thread counts the keys smaller than its own), longer ones a
+// bitonic sort in LDS.  k_tile_sort_long takes the longer lists (dense
+// views), one large workgroup each.
 
 constexpr int kSortBlock = 256;
 constexpr int kSortChunk = 2048;
@@ -365,19 +367,36 @@ __device__ __forceinline__ uint64_t depth_key(const uint4* __restrict__ meta, ui
 }
 
 // number of keys in run[0, n) smaller than k (the run is sorted)
-__device__ __forceinline__ uint32_t count_less(const uint4* __restrict__ meta, const uint32_t* run, uint32_t n,
-                                               uint64_t k) {
+__device__ __forceinline__ uint32_t count_less(const uint64_t* run, uint32_t n, uint64_t k) {
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (depth_key(meta, run[mid]) < k) lo = mid + 1; else hi = mid;
+        if (run[mid] < k) lo = mid + 1; else hi = mid;
     }
     return lo;
 }
 
+// ascending bitonic sort of sk[0, p), p a power of two, by a workgroup of B
+template <int B>
+__device__ __forceinline__ void bitonic_lds(uint64_t* sk, uint32_t p) {
+    for (uint32_t k = 2; k <= p; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < p; i += B) {
+                const uint32_t ij = i ^ j;
+                if (ij > i) {
+                    const uint64_t a = sk[i], b = sk[ij];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) { sk[i] = b; sk[ij] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 __global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restrict__ meta,
                                                           const uint2* __restrict__ ranges, int n_tiles,
-                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ scratch) {
+                                                          uint32_t* __restrict__ vals) {
     __shared__ uint64_t sk[kSortChunk];
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint2 rg = ranges[tile];
@@ -397,50 +416,68 @@ __global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restric
             __syncthreads();
             continue;
         }
-        // chunks of kSortChunk: bitonic sort in LDS (padded with the largest key)
-        for (uint32_t c0 = 0; c0 < n; c0 += kSortChunk) {
-            const uint32_t m = min(uint32_t(kSortChunk), n - c0);
+        if (n > uint32_t(kSortChunk)) continue;                 // k_tile_sort_long takes it
+        // bitonic sort in LDS (padded with the largest key)
+        uint32_t p = 1;
+        while (p < n) p <<= 1;
+        for (uint32_t i = threadIdx.x; i < p; i += kSortBlock) sk[i] = i < n ? depth_key(meta, v[i]) : ~0ull;
+        __syncthreads();
+        bitonic_lds<kSortBlock>(sk, p);
+        for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) v[i] = uint32_t(sk[i]);
+        __syncthreads();
+    }
+}
+
+// Lists longer than kSortChunk: one workgroup of kLongBlock threads per list,
+// chunks of kLongChunk keys bitonic-sorted in LDS, then (lists longer than a
+// chunk) pairwise merges of sorted key runs through two scratch ranges (each
+// key's place is its index in its run plus the number of smaller keys in the
+// other run, by binary search).
+constexpr int kLongBlock = 1024;
+constexpr int kLongChunk = 8192;
+
+__global__ __launch_bounds__(kLongBlock) void k_tile_sort_long(const uint4* __restrict__ meta,
+                                                               const uint2* __restrict__ ranges, int n_tiles,
+                                                               uint32_t* __restrict__ vals, uint64_t* __restrict__ ka,
+                                                               uint64_t* __restrict__ kb) {
+    __shared__ uint64_t sk[kLongChunk];
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint2 rg = ranges[tile];
+        const uint32_t n = rg.y - rg.x;
+        if (n <= uint32_t(kSortChunk)) continue;                // uniform per workgroup
+        uint32_t* v = vals + rg.x;
+        uint64_t* src = ka + rg.x;
+        uint64_t* dst = kb + rg.x;
+        for (uint32_t c0 = 0; c0 < n; c0 += kLongChunk) {
+            const uint32_t m = min(uint32_t(kLongChunk), n - c0);
             uint32_t p = 1;
             while (p < m) p <<= 1;
-            for (uint32_t i = threadIdx.x; i < p; i += kSortBlock) sk[i] = i < m ? depth_key(meta, v[c0 + i]) : ~0ull;
+            for (uint32_t i = threadIdx.x; i < p; i += kLongBlock) sk[i] = i < m ? depth_key(meta, v[c0 + i]) : ~0ull;
             __syncthreads();
-            for (uint32_t k = 2; k <= p; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t i = threadIdx.x; i < p; i += kSortBlock) {
-                        const uint32_t ij = i ^ j;
-                        if (ij > i) {
-                            const uint64_t a = sk[i], b = sk[ij];
-                            const bool up = (i & k) == 0;
-                            if ((a > b) == up) { sk[i] = b; sk[ij] = a; }
-                        }
-                    }
-                    __syncthreads();
-                }
+            bitonic_lds<kLongBlock>(sk, p);
+            if (n <= uint32_t(kLongChunk)) {
+                for (uint32_t i = threadIdx.x; i < m; i += kLongBlock) v[i] = uint32_t(sk[i]);
+            } else {
+                for (uint32_t i = threadIdx.x; i < m; i += kLongBlock) src[c0 + i] = sk[i];
             }
-            for (uint32_t i = threadIdx.x; i < m; i += kSortBlock) v[c0 + i] = uint32_t(sk[i]);
             __syncthreads();
         }
-        // pairwise merges of sorted runs, ping-ponging with the scratch range
-        uint32_t* src = v;
-        uint32_t* dst = scratch + rg.x;
-        for (uint32_t run = kSortChunk; run < n; run <<= 1) {
-            for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) {
+        if (n <= uint32_t(kLongChunk)) continue;
+        for (uint32_t run = kLongChunk; run < n; run <<= 1) {
+            for (uint32_t i = threadIdx.x; i < n; i += kLongBlock) {
                 const uint32_t a0 = (i / (2 * run)) * (2 * run), b0 = a0 + run, b1 = min(a0 + 2 * run, n);
-                const uint32_t r = src[i];
-                if (b0 >= n) { dst[i] = r; continue; }
-                const uint64_t k = depth_key(meta, r);
-                if (i < b0) dst[i + count_less(meta, src + b0, b1 - b0, k)] = r;
-                else dst[a0 + (i - b0) + count_less(meta, src + a0, run, k)] = r;
+                const uint64_t k = src[i];
+                if (b0 >= n) { dst[i] = k; continue; }
+                if (i < b0) dst[i + count_less(src + b0, b1 - b0, k)] = k;
+                else dst[a0 + (i - b0) + count_less(src + a0, run, k)] = k;
             }
             __syncthreads();
-            uint32_t* t = src;
+            uint64_t* t = src;
             src = dst;
             dst = t;
         }
-        if (src != v) {
-            for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) v[i] = src[i];
-            __syncthreads();
-        }
+        for (uint32_t i = threadIdx.x; i < n; i += kLongBlock) v[i] = uint32_t(src[i]);
+        __syncthreads();
     }
 }
 
@@ -592,11 +629,13 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     // 4. per-tile [start, end)
     GS_LAUNCH("k_ranges", k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity,
                        reinterpret_cast<uint2*>(bins.ranges));
-    // 5. each tile's list in (depth bits, record) order (the tile sort leaves
-    //    the values in bins.vals, so the other value buffer is free scratch)
-    if (f.n_tiles > 0)
+    // 5. each tile's list in (depth bits, record) order
+    if (f.n_tiles > 0) {
         GS_LAUNCH("k_tile_sort", k_tile_sort, dim3(unsigned(std::min(f.n_tiles, 4096))), dim3(kSortBlock), 0, s, meta,
-                  reinterpret_cast<const uint2*>(bins.ranges), f.n_tiles, bins.vals, w.tval);
+                  reinterpret_cast<const uint2*>(bins.ranges), f.n_tiles, bins.vals);
+        GS_LAUNCH("k_tile_sort_long", k_tile_sort_long, dim3(unsigned(std::min(f.n_tiles, 256))), dim3(kLongBlock), 0,
+                  s, meta, reinterpret_cast<const uint2*>(bins.ranges), f.n_tiles, bins.vals, w.key[0], w.key[1]);
+    }
     // 6. compositing plan, when a pass splits tiles adaptively
     plan();
     return hipGetLastError();

@@ -75,6 +75,13 @@ class Arena:
                                                            self.tile_order, self.rgb, self.T, self.ncontrib,
                                                            self.vals, self.bin_ws))
 
+    @staticmethod
+    def bytes_for(n_gauss, max_jobs, max_pixels, max_tiles, capacity):
+        """nbytes() of an arena of these sizes, without allocating it."""
+        R = n_gauss * max_jobs
+        return (R * (gs.REC_WORDS * 4 + gs.META_WORDS * 4 + 4) + max_tiles * 8 + (max_tiles + 4) * 4
+                + max_pixels * 20 + capacity * 4 + int(gs.lib.gs_bin_sort_workspace_size(R, capacity, max_tiles)))
+
     @property
     def bins(self) -> gs.GsBins:
         return gs.GsBins(self.vals.data_ptr(), self.ranges.data_ptr(), self.pair_off.data_ptr(),
@@ -103,10 +110,14 @@ class RenderServer:
         max_px = max(w * h for w, h in self.resolutions)
         tw, th = cfg.tile_w, cfg.tile_h
         max_tiles_view = max(((w + tw - 1) // tw) * ((h + th - 1) // th) for w, h in self.resolutions)
-        per_view = self._view_bytes(max_px, max_tiles_view)
         slot_budget = hbm_budget / n_slots
-        self.max_batch = int(max(1, min(max_batch, slot_budget // per_view)))
-        cap = int(self.pairs_per_px * max_px * self.max_batch) + 4096
+        # the largest batch whose arena fits one slot's share (at least one view)
+        cap_of = lambda b: int(self.pairs_per_px * max_px * b) + 4096  # noqa: E731
+        b = max(1, int(max_batch))
+        while b > 1 and Arena.bytes_for(self.G, b, max_px * b, max_tiles_view * b, cap_of(b)) > slot_budget:
+            b -= 1
+        self.max_batch = b
+        cap = cap_of(b)
         self.slots = [Slot(Arena(self.G, self.max_batch, max_px * self.max_batch, max_tiles_view * self.max_batch,
                                  cap, self.device)) for _ in range(n_slots)]
         self.queue = []
@@ -120,11 +131,6 @@ class RenderServer:
                     torch.empty((3, h, w), dtype=torch.float32).pin_memory())
 
     # -- sizing ---------------------------------------------------------
-    def _view_bytes(self, px, tiles):
-        rec = self.G * (gs.REC_WORDS * 4 + gs.META_WORDS * 4 + 4 + 16 + 4)   # records, pair_off, depth sort, poff
-        pairs = self.pairs_per_px * px * (4 + 12)
-        return rec + px * 20 + tiles * 8 + pairs
-
     def _calibrate_pairs(self, headroom):
         """Tile pairs per pixel at each served resolution (one render each,
         on a ring view), with headroom."""

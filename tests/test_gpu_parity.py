@@ -128,11 +128,12 @@ def test_bins_bit_exact(gpu1):
     _bins_check(frame, buf)
 
 
-@pytest.mark.parametrize("n", [300, 2500, 6000])
+@pytest.mark.parametrize("n", [300, 1500, 6000, 9000])
 def test_bins_bit_exact_long_tile_lists(n):
     """Large Gaussians in front of a small view put n entries in every tile
-    (above 256: the in-LDS bitonic sort; above 2048: chunks and merges), with
-    many equal depths (ties ordered by record), against the reference."""
+    (above 256: the in-LDS bitonic sort; above 2048: the long-list kernel;
+    above 8192: its chunks and merges), with many equal depths (ties ordered
+    by record), against the reference."""
     p = scenes.gaussians(n, 0, 4100 + n, [-0.3, -0.3, -0.3], [0.3, 0.3, 0.3], 0.0, 0.1)
     p[scenes.MEAN + 2, ::3] = 0.25                  # every third Gaussian at the same depth
     params = torch.from_numpy(p).cuda()

@@ -57,7 +57,9 @@ def test_small_budget_queues_instead_of_failing():
     params = small_model()
     cfg = gs.raster_cfg((16, 16))
     probe = serve.RenderServer(params, cfg, hbm_budget=2e9, n_slots=1, max_batch=1, resolutions=RES)
-    one_view = probe.slots[0].arena.nbytes()
+    a = probe.slots[0].arena
+    one_view = a.nbytes()
+    assert one_view == serve.Arena.bytes_for(a.n_gauss, a.max_jobs, a.max_pixels, a.max_tiles, a.capacity)
     del probe
     srv = serve.RenderServer(params, cfg, hbm_budget=1.2 * one_view * 2, n_slots=2, max_batch=8, resolutions=RES)
     assert srv.max_batch == 1
