@@ -370,8 +370,8 @@ def run_serve(args):
     return out
 
 
-KERNELS = ("k_project", "k_fill_u32", "k_scan_reduce", "k_scan_spine", "k_scan_apply", "k_rs_hist", "k_rs_colscan",
-           "k_rs_scatter", "k_emit", "k_ranges", "k_render_fwd", "k_render_bwd", "k_project_bwd_rec",
+KERNELS = ("k_project", "k_fill_u32", "k_scan_reduce", "k_scan_spine", "k_scan_apply", "k_emit", "k_rs_hist", "k_rs_colscan", "k_rs_scatter", "k_ranges",
+           "k_tile_sort", "k_tile_sort_long", "k_tile_plan", "k_render_fwd", "k_render_bwd", "k_project_bwd_rec",
            "k_zero_uncovered", "k_project_bwd_adam", "k_adam_uncovered", "k_adam_admm", "k_consensus")
 
 

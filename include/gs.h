@@ -204,12 +204,16 @@ gs_status gs_project_f64(const gs_params *params, const gs_frame *frame, const g
                          void *rec_dev, uint32_t *meta_dev, gs_stream stream);
 
 /* Tile binning (no counterpart in the paper; an exact acceleration of the
- * per-pixel definition).  Emits one pair per (covered tile, record) in
- * ascending (depth bits, record) order and sorts the pairs stably by global
- * tile id with an LSD radix sort, so each tile's list is ordered by
- * (depth, record).  Writes vals, ranges, pair_off and counters.  When the
- * pairs exceed bins->capacity, sets GS_STATUS_PAIR_OVERFLOW, stores the
- * needed count in counters[GS_CTR_PAIRS] and leaves vals/ranges invalid. */
+ * per-pixel definition).  Emits one pair per (covered tile, record), sorts
+ * the pairs by global tile id (LSD radix) and then each tile's list by the
+ * unique key (depth bits, record), so every list is ordered by
+ * (depth, record).  Writes vals, ranges, pair_off (the first pair of each
+ * visible record in record order: the layout of the backward's per-pair
+ * partials) and counters.  When the pairs exceed bins->capacity, sets
+ * GS_STATUS_PAIR_OVERFLOW, stores the needed count in counters[GS_CTR_PAIRS]
+ * (saturating at 2^32 - 1) and leaves vals/ranges invalid.  The workspace
+ * (device, caller-owned, at least gs_bin_sort_workspace_size bytes) holds
+ * 8 bytes per record and 16 per pair of capacity, plus about 1 MiB. */
 size_t gs_bin_sort_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles);
 gs_status gs_bin_sort(const gs_frame *frame, const gs_raster_cfg *cfg, const uint32_t *meta_dev,
                       const gs_bins *bins, void *ws_dev, size_t ws_bytes, gs_stream stream);

@@ -3,15 +3,15 @@
 // (its rasterizer is cited, not specified); this is an exact acceleration of
 // the per-pixel compositing order (depth, index).
 //
-//   1. compact the visible records (scan of n_tiles > 0), in record order;
-//   2. scan their tile counts: each record's pairs are contiguous from its
-//      first pair (pair_off), the layout the backward's per-pair partials use;
-//   3. emit one (tile id, record) pair per covered tile and sort the pairs by
-//      tile id (LSD radix, ceil(log2 tiles) bits);
+//   1. one scan over the records: the visible ones (at least one covered
+//      tile) compacted in record order, and each one's first pair
+//      (pair_off), the layout the backward's per-pair partials use;
+//   2. emit one (tile id, record) pair per covered tile and sort the pairs by
+//      tile id (LSD radix, ceil(log2 tiles) bits in one or more passes of at
+//      most 8, each staged through LDS so that writes leave in runs);
+//   3. per-tile [start, end);
 //   4. sort each tile's list by the unique key (depth bits, record) on chip
-//      (k_tile_sort: positive floats order like their bits).
-// Sorting every tile's short list in LDS replaces four global radix passes
-// over all visible records by their depth.
+//      (positive floats order like their bits).
 //
 // Every count that depends on the data (visible records V, pairs P) stays on
 // the device: kernels read it from the counters and size their loops from
@@ -25,45 +25,52 @@ namespace gs {
 
 constexpr int kScanBlock = 256;
 constexpr int kRsBlock = 256;
-constexpr int kRsItems = 4;
-constexpr int kRsTile = kRsBlock * kRsItems;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsBlock * kRsItems;     // keys per workgroup and iteration of a radix pass
 constexpr int kMaxGrid = 1024;
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BinWs {
-    uint32_t* dval[1];    // visible record ids, [n_records]
+    uint32_t* vis;        // visible record ids in record order, [n_records]
+    uint32_t* poff;       // first pair of each visible record in that order, [n_records]
     uint32_t* tkey[2];    // tile keys, [capacity] each
     uint32_t* tval;       // alternate record-id buffer, [capacity]
-    uint32_t* part;       // scan partials, [kMaxGrid + 1]
+    uint64_t* key[2];     // sort keys of tile lists longer than one LDS chunk, [capacity] each
     uint32_t* hist;       // radix histograms, [256 * kMaxGrid]
     uint32_t* coltot;     // per-digit totals of one radix pass, [256]
-    uint32_t* poff;       // first pair of each visible record in compacted order, [n_records]
-    uint64_t* key[2];     // sort keys of long tile lists, [capacity] each
+    uint32_t* longq;      // lists longer than one LDS chunk: count, then tile ids, [1 + n_tiles]
+    void* part;           // scan partials, [kMaxGrid + 1] x 8 bytes
     size_t bytes;
 };
 
-static BinWs carve(void* base, int64_t n_records, uint64_t capacity) {
+// key[0] overlays the two tile-key buffers and key[1] the alternate values:
+// the long-list sort runs after the tile sort and the ranges are done
+static BinWs carve(void* base, int64_t n_records, uint64_t capacity, int32_t n_tiles) {
     BinWs w;
     char* p = static_cast<char*>(base);
     size_t off = 0;
-    auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return reinterpret_cast<uint32_t*>(q); };
-    const size_t nr = size_t(n_records > 0 ? n_records : 1) * 4, nc = size_t(capacity > 0 ? capacity : 1) * 4;
-    w.dval[0] = take(nr);
-    w.tkey[0] = take(nc); w.tkey[1] = take(nc);
-    w.tval = take(nc);
-    w.part = take(size_t(kMaxGrid + 1) * 4);
-    w.hist = take(size_t(256) * kMaxGrid * 4);
-    w.coltot = take(256 * 4);
-    w.poff = take(nr);
-    w.key[0] = reinterpret_cast<uint64_t*>(take(nc * 2));
-    w.key[1] = reinterpret_cast<uint64_t*>(take(nc * 2));
+    auto take = [&](size_t bytes) { char* q = p ? p + off : nullptr; off += align256(bytes); return q; };
+    const size_t nr = size_t(n_records > 0 ? n_records : 1) * 4, nc = size_t(capacity > 0 ? capacity : 1);
+    w.vis = reinterpret_cast<uint32_t*>(take(nr));
+    w.poff = reinterpret_cast<uint32_t*>(take(nr));
+    char* a = take(nc * 8);
+    char* b = take(nc * 8);
+    w.key[0] = reinterpret_cast<uint64_t*>(a);
+    w.key[1] = reinterpret_cast<uint64_t*>(b);
+    w.tkey[0] = reinterpret_cast<uint32_t*>(a);
+    w.tkey[1] = a ? reinterpret_cast<uint32_t*>(a + nc * 4) : nullptr;
+    w.tval = reinterpret_cast<uint32_t*>(b);
+    w.hist = reinterpret_cast<uint32_t*>(take(size_t(256) * kMaxGrid * 4));
+    w.coltot = reinterpret_cast<uint32_t*>(take(256 * 4));
+    w.longq = reinterpret_cast<uint32_t*>(take((size_t(n_tiles > 0 ? n_tiles : 0) + 1) * 4));
+    w.part = take(size_t(kMaxGrid + 1) * 8);
     w.bytes = off;
     return w;
 }
 
-size_t bin_workspace_size(int64_t n_records, uint64_t capacity, int32_t) {
-    return carve(nullptr, n_records, capacity).bytes;
+size_t bin_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles) {
+    return carve(nullptr, n_records, capacity, n_tiles).bytes;
 }
 
 // ---------------------------------------------------------------------------
@@ -74,22 +81,47 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
         p[i] = v;
 }
 
-// exclusive scan of one value per thread over a 256-thread block
-__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+// (visible records, pairs): the pair sum saturates at 2^32 - 1, which is
+// above every capacity, so an oversized frame is reported, never wrapped
+struct VisPairs {
+    uint32_t v, p;
+};
+
+__device__ inline uint32_t scan_add(uint32_t a, uint32_t b) { return a + b; }
+__device__ inline VisPairs scan_add(VisPairs a, VisPairs b) {
+    const uint32_t p = a.p + b.p;
+    return {a.v + b.v, p < a.p ? 0xffffffffu : p};
+}
+__device__ inline uint32_t shfl_up_v(uint32_t x, int off) { return __shfl_up(x, off, kWave); }
+__device__ inline VisPairs shfl_up_v(VisPairs x, int off) {
+    return {__shfl_up(x.v, off, kWave), __shfl_up(x.p, off, kWave)};
+}
+
+// exclusive scan of one value per thread over a kScanBlock-thread block;
+// total = the block's sum.  Only the (associative) scan_add is used.
+template <typename T>
+__device__ inline T block_excl_scan(T v, T* s_wave, T& total) {
     const int lane = lane_id(), wave = threadIdx.x / kWave;
-    const uint32_t inc = wave_incl_scan(v);
+    T inc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const T t = shfl_up_v(inc, off);
+        if (lane >= off) inc = scan_add(t, inc);
+    }
+    T ex = shfl_up_v(inc, 1);
+    if (lane == 0) ex = T{};
     if (lane == kWave - 1) s_wave[wave] = inc;
     __syncthreads();
-    uint32_t before = 0;
-    total = 0;
+    T before{};
+    total = T{};
 #pragma unroll
     for (int w = 0; w < kScanBlock / kWave; w++) {
-        const uint32_t s = s_wave[w];
-        if (w < wave) before += s;
-        total += s;
+        const T s = s_wave[w];
+        if (w < wave) before = scan_add(before, s);
+        total = scan_add(total, s);
     }
     __syncthreads();
-    return before + inc - v;
+    return scan_add(before, ex);
 }
 
 // chunk of items [lo, hi) that block b of G handles when n items are split
@@ -101,87 +133,103 @@ __device__ inline void block_range(uint32_t n, int G, int b, uint32_t granule, u
 }
 
 // ---------------------------------------------------------------------------
-// reduce-then-scan over a device-sized sequence; two flavours of input/output
+// reduce-then-scan over a sequence of n items (three launches: per-block
+// sums, a one-block scan of those, then each block's exclusive prefixes)
 
-struct VisibleFlag {      // item i: record i is visible; output: the compacted record ids
+struct RecordScan {       // item i: record i; output: compacted ids and first pairs
+    using T = VisPairs;
     const uint4* meta;
-    uint32_t* val_out;
-    __device__ uint32_t value(uint32_t i) const { return meta_tiles(meta[i].y) > 0 ? 1u : 0u; }
-    __device__ void emit(uint32_t i, uint32_t pre) const {
-        if (meta_tiles(meta[i].y) > 0) val_out[pre] = i;
-    }
-};
-
-struct PairCount {        // item s: visible record s; output: its first pair
-    const uint4* meta;
-    const uint32_t* sorted_rec;
+    uint32_t* vis;
     uint32_t* pair_off;       // by record
-    uint32_t* poff;           // by depth rank
-    __device__ uint32_t value(uint32_t s) const { return meta_tiles(meta[sorted_rec[s]].y); }
-    __device__ void emit(uint32_t s, uint32_t pre) const {
-        pair_off[sorted_rec[s]] = pre;
-        poff[s] = pre;
+    uint32_t* poff;           // by visible rank
+    __device__ T value(uint32_t i) const {
+        const uint32_t n = meta_tiles(meta[i].y);
+        return {n > 0 ? 1u : 0u, n};
+    }
+    __device__ void emit(uint32_t i, T pre, T v) const {
+        if (v.v) {
+            vis[pre.v] = i;
+            poff[pre.v] = pre.p;
+            pair_off[i] = pre.p;
+        }
+    }
+    __device__ static void finish(T total, uint32_t* counters, uint64_t capacity) {
+        counters[GS_CTR_VISIBLE] = total.v;
+        counters[GS_CTR_PAIRS] = total.p;
+        if (uint64_t(total.p) > capacity) counters[GS_CTR_STATUS] |= GS_STATUS_PAIR_OVERFLOW;
     }
 };
 
+// The reduce also zeroes `clear[0, n_clear)` (grid-stride) and the word
+// `*clear1` (when not null), for buffers the later steps fill in part or
+// count into: it saves launches.
 template <typename F>
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, const uint32_t* __restrict__ n_dev, uint32_t n_host,
-                                                            uint32_t* __restrict__ part, int G) {
-    __shared__ uint32_t s_wave[kScanBlock / kWave];
-    const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, uint32_t n, typename F::T* __restrict__ part, int G,
+                                                            uint32_t* __restrict__ clear, int64_t n_clear,
+                                                            uint32_t* __restrict__ clear1) {
+    using T = typename F::T;
+    __shared__ T s_wave[kScanBlock / kWave];
+    for (int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x; i < n_clear; i += int64_t(G) * kScanBlock)
+        clear[i] = 0u;
+    if (clear1 != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *clear1 = 0u;
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kScanBlock, lo, hi);
-    uint32_t acc = 0;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kScanBlock) acc += f.value(i);
-    uint32_t tot;
+    T acc{};
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kScanBlock) acc = scan_add(acc, f.value(i));
+    T tot;
     block_excl_scan(acc, s_wave, tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// single block: exclusive scan of the G partials in place; total to counters
-__global__ __launch_bounds__(kScanBlock) void k_scan_spine(uint32_t* __restrict__ part, int G,
-                                                           uint32_t* __restrict__ counters, int total_idx,
-                                                           uint64_t capacity) {
-    __shared__ uint32_t s_wave[kScanBlock / kWave];
-    uint32_t carry = 0;
+// single block: exclusive scan of the G partials in place; the total goes to
+// F::finish
+template <typename F>
+__global__ __launch_bounds__(kScanBlock) void k_scan_spine(typename F::T* __restrict__ part, int G,
+                                                           uint32_t* __restrict__ counters, uint64_t capacity) {
+    using T = typename F::T;
+    __shared__ T s_wave[kScanBlock / kWave];
+    T carry{};
     for (int base = 0; base < G; base += kScanBlock) {
         const int i = base + threadIdx.x;
-        const uint32_t v = i < G ? part[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, s_wave, tot);
-        if (i < G) part[i] = carry + ex;
-        carry += tot;
+        const T v = i < G ? part[i] : T{};
+        T tot;
+        const T ex = block_excl_scan(v, s_wave, tot);
+        if (i < G) part[i] = scan_add(carry, ex);
+        carry = scan_add(carry, tot);
     }
-    if (threadIdx.x == 0) {
-        counters[total_idx] = carry;
-        if (capacity && uint64_t(carry) > capacity) counters[GS_CTR_STATUS] |= GS_STATUS_PAIR_OVERFLOW;
-    }
+    if (threadIdx.x == 0) F::finish(carry, counters, capacity);
 }
 
 template <typename F>
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(F f, const uint32_t* __restrict__ n_dev, uint32_t n_host,
-                                                           const uint32_t* __restrict__ part, int G) {
-    __shared__ uint32_t s_wave[kScanBlock / kWave];
-    const uint32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(F f, uint32_t n, const typename F::T* __restrict__ part,
+                                                           int G) {
+    using T = typename F::T;
+    __shared__ T s_wave[kScanBlock / kWave];
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kScanBlock, lo, hi);
-    uint32_t carry = part[blockIdx.x];
+    T carry = part[blockIdx.x];
     for (uint32_t base = lo; base < hi; base += kScanBlock) {
         const uint32_t i = base + threadIdx.x;
-        const uint32_t v = i < hi ? f.value(i) : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, s_wave, tot);
-        if (i < hi) f.emit(i, carry + ex);
-        carry += tot;
+        const T v = i < hi ? f.value(i) : T{};
+        T tot;
+        const T ex = block_excl_scan(v, s_wave, tot);
+        if (i < hi) f.emit(i, scan_add(carry, ex), v);
+        carry = scan_add(carry, tot);
     }
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort of (uint32 key, uint32 value), 8-bit digits,
-// reduce-then-scan with a fixed grid of G blocks over device-sized n
+// stable LSD radix sort of (uint32 key, uint32 value) by digits of `bits`
+// bits (at most 8), reduce-then-scan with a fixed grid of G workgroups over a
+// device-sized n; each workgroup takes a contiguous range of the keys
+
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift, int bits) {
+    return (k >> shift) & ((1u << bits) - 1u);
+}
 
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-                                                      uint32_t n_host, int shift, uint32_t* __restrict__ hist, int G) {
+                                                      uint32_t n_host, int shift, int bits, uint32_t* __restrict__ hist,
+                                                      int G) {
     __shared__ uint32_t h[kRsBlock / kWave][256];
     const int wave = threadIdx.x / kWave;
     for (int i = threadIdx.x; i < 256 * (kRsBlock / kWave); i += kRsBlock) (&h[0][0])[i] = 0;
@@ -189,7 +237,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint32_t* __restrict
     const uint32_t n = min(*n_dev, n_host);
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kRsTile, lo, hi);
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kRsBlock) atomicAdd(&h[wave][(keys[i] >> shift) & 255u], 1u);
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kRsBlock) atomicAdd(&h[wave][digit_of(keys[i], shift, bits)], 1u);
     __syncthreads();
     const int d = threadIdx.x;
     uint32_t s = 0;
@@ -198,9 +246,9 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint32_t* __restrict
     hist[d * G + blockIdx.x] = s;
 }
 
-// one block per digit: exclusive scan of that digit's counts over the G
-// blocks (in place) and the digit's total; the digits' base offsets are
-// then an exclusive scan of 256 totals, done by every scatter block
+// one workgroup per digit: exclusive scan of that digit's counts over the G
+// workgroups (in place) and the digit's total; the digits' base offsets are
+// then an exclusive scan of 256 totals, done by every scatter workgroup
 __global__ __launch_bounds__(kRsBlock) void k_rs_colscan(uint32_t* __restrict__ hist, int G,
                                                          uint32_t* __restrict__ coltot) {
     __shared__ uint32_t s_wave[kRsBlock / kWave];
@@ -224,21 +272,27 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_colscan(uint32_t* __restrict__ 
     if (threadIdx.x == 0) coltot[blockIdx.x] = tot;
 }
 
+// Scatter: per iteration kRsTile keys are ranked by digit (wave ballots for
+// the rank among equal digits, LDS counts across waves), staged in LDS in
+// digit order, then written out by consecutive threads to consecutive
+// addresses of each digit's output run.
 __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
-                                                         const uint32_t* __restrict__ hist, int G,
+                                                         int bits, const uint32_t* __restrict__ hist, int G,
                                                          const uint32_t* __restrict__ coltot) {
     constexpr int NW = kRsBlock / kWave;
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[NW][256];
-    __shared__ uint32_t wpre[NW][256];
+    constexpr int PER_WAVE = kWave * kRsItems;
+    __shared__ uint32_t run[256];          // next output index of each digit
+    __shared__ uint32_t loc[256];          // first staging slot of each digit
+    __shared__ uint32_t wcnt[NW][256];     // per wave: count, then first rank, of each digit
+    __shared__ uint32_t s_wave[NW];
+    __shared__ uint32_t sk[kRsTile], sv[kRsTile];
     const int tid = threadIdx.x, lane = lane_id(), wave = tid / kWave;
     const uint32_t n = min(*n_dev, n_host);
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kRsTile, lo, hi);
     {
-        __shared__ uint32_t s_wave[NW];
         uint32_t tot;
         const uint32_t base = block_excl_scan(coltot[tid], s_wave, tot);
         run[tid] = base + hist[tid * G + blockIdx.x];
@@ -249,15 +303,14 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
         uint32_t key[kRsItems], val[kRsItems], rank[kRsItems];
 #pragma unroll
         for (int k = 0; k < kRsItems; k++) {
-            const uint32_t i = base + wave * (kWave * kRsItems) + k * kWave + lane;
+            const uint32_t i = base + wave * PER_WAVE + k * kWave + lane;
             key[k] = 0; val[k] = 0; rank[k] = 0;
             if (i < hi) {
                 key[k] = kin[i];
                 val[k] = vin[i];
-                const uint32_t dg = (key[k] >> shift) & 255u;
+                const uint32_t dg = digit_of(key[k], shift, bits);
                 uint64_t peers = __ballot(1);
-#pragma unroll
-                for (int bit = 0; bit < 8; bit++) {
+                for (int bit = 0; bit < bits; bit++) {
                     const uint64_t m = __ballot((dg >> bit) & 1u);
                     peers &= ((dg >> bit) & 1u) ? m : ~m;
                 }
@@ -269,25 +322,37 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
+        // thread d: the waves' first ranks of digit d, then the digit's first slot
         uint32_t tot = 0;
         {
             const int d = tid;
 #pragma unroll
             for (int w = 0; w < NW; w++) {
-                wpre[w][d] = tot;
-                tot += wcnt[w][d];
+                const uint32_t c = wcnt[w][d];
+                wcnt[w][d] = tot;
+                tot += c;
             }
+            uint32_t all;
+            loc[d] = block_excl_scan(tot, s_wave, all);
         }
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kRsItems; k++) {
-            const uint32_t i = base + wave * (kWave * kRsItems) + k * kWave + lane;
+            const uint32_t i = base + wave * PER_WAVE + k * kWave + lane;
             if (i < hi) {
-                const uint32_t dg = (key[k] >> shift) & 255u;
-                const uint32_t pos = run[dg] + wpre[wave][dg] + rank[k];
-                kout[pos] = key[k];
-                vout[pos] = val[k];
+                const uint32_t dg = digit_of(key[k], shift, bits);
+                const uint32_t pos = loc[dg] + wcnt[wave][dg] + rank[k];
+                sk[pos] = key[k];
+                sv[pos] = val[k];
             }
+        }
+        __syncthreads();
+        const uint32_t m = min(uint32_t(kRsTile), hi - base);
+        for (uint32_t j = tid; j < m; j += kRsBlock) {
+            const uint32_t k = sk[j], dg = digit_of(k, shift, bits);
+            const uint32_t o = run[dg] + (j - loc[dg]);
+            kout[o] = k;
+            vout[o] = sv[j];
         }
         __syncthreads();
         run[tid] += tot;
@@ -299,12 +364,12 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
 // pair emission and tile ranges
 
 // Pair-parallel emission: block-sized chunks of the P pairs; each chunk finds
-// the depth-ordered records it spans by binary search over their first-pair
+// the visible records it spans by binary search over their first-pair
 // offsets (staged in LDS), so a Gaussian covering thousands of tiles is
 // spread over many threads instead of serialising one.
 constexpr int kEmitChunk = 2048;
 
-__global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ sorted_rec,
+__global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ vis,
                                               const uint32_t* __restrict__ poff, const uint32_t* __restrict__ counters,
                                               gs_frame frame, uint64_t capacity, uint32_t* __restrict__ tkey,
                                               uint32_t* __restrict__ tval) {
@@ -330,7 +395,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, co
         const uint32_t lo = s_lo, n = s_hi - s_lo + 1;
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
             s_off[i] = poff[lo + i];
-            s_rec[i] = sorted_rec[lo + i];
+            s_rec[i] = vis[lo + i];
         }
         __syncthreads();
         for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
@@ -351,16 +416,39 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, co
     }
 }
 
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ counters,
+                                                uint64_t capacity, uint2* __restrict__ ranges) {
+    const uint32_t P = uint32_t(min(uint64_t(counters[GS_CTR_PAIRS]), capacity));
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < P; e += gridDim.x * blockDim.x) {
+        const uint32_t t = tkey[e];
+        if (e == 0 || tkey[e - 1] != t) ranges[t].x = e;
+        if (e + 1 == P || tkey[e + 1] != t) ranges[t].y = e + 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // per-tile depth order: each tile's list (record ids, any order) sorted by the
-// unique key (depth bits, record id).  k_tile_sort (persistent grid) takes
-// lists of up to kSortChunk entries: up to one workgroup's width a rank sort
-// in LDS (each thread counts the keys smaller than its own), longer ones a
-// bitonic sort in LDS.  k_tile_sort_long takes the longer lists (dense
-// views), one large workgroup each.
+// unique key (depth bits, record id).  k_tile_sort (persistent grid, one
+// list per workgroup at a time) takes lists of up to kSortChunk entries: up
+// to one workgroup's width a rank sort in LDS (each thread counts the keys
+// below its own), longer ones a merge sort in LDS (4 keys per thread up to
+// 1024 entries, 16 beyond).  k_tile_sort_long takes
+// the longer lists (dense views), one large workgroup each.
+//
+// The merge sort: every thread sorts E consecutive keys in registers (a
+// sorting network), then rounds of pairwise merges double the sorted runs;
+// in a round each thread produces E consecutive outputs of its pair of runs,
+// finding where they start in the two inputs by binary search along the
+// merge path and then merging sequentially (ties go to the first run).  The
+// work is O(n log n) with one LDS read and write per key and round.
 
 constexpr int kSortBlock = 256;
-constexpr int kSortChunk = 2048;
+constexpr int kSortItems = 16;
+constexpr int kSortItemsShort = 4;                      // lists up to 1024: more threads, shorter merges
+constexpr int kSortChunk = kSortBlock * kSortItems;     // 4096
+constexpr int kLongBlock = 1024;
+constexpr int kLongItems = 8;
+constexpr int kLongChunk = kLongBlock * kLongItems;     // 8192
 
 __device__ __forceinline__ uint64_t depth_key(const uint4* __restrict__ meta, uint32_t r) {
     return (uint64_t(meta[r].x) << 32) | r;
@@ -376,32 +464,95 @@ __device__ __forceinline__ uint32_t count_less(const uint64_t* run, uint32_t n, 
     return lo;
 }
 
-// ascending bitonic sort of sk[0, p), p a power of two, by a workgroup of B
-template <int B>
-__device__ __forceinline__ void bitonic_lds(uint64_t* sk, uint32_t p) {
-    for (uint32_t k = 2; k <= p; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < p; i += B) {
-                const uint32_t ij = i ^ j;
-                if (ij > i) {
-                    const uint64_t a = sk[i], b = sk[ij];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) { sk[i] = b; sk[ij] = a; }
+// ascending bitonic network over E keys in registers
+template <int E>
+__device__ __forceinline__ void sort_registers(uint64_t (&r)[E]) {
+#pragma unroll
+    for (int k = 2; k <= E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < E; i++) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = r[i], b = r[l];
+                    const bool swap = (a > b) == ((i & k) == 0);
+                    r[i] = swap ? b : a;
+                    r[l] = swap ? a : b;
                 }
             }
-            __syncthreads();
         }
+    }
+}
+
+// Sorts sk[0, n) ascending in LDS, n <= B * E, by a workgroup of B threads;
+// the keys must be visible to the workgroup (a barrier after they were
+// written).  sk must hold ceil(n / E) * E keys (the tail is padded with the
+// largest key).  Ends with a barrier.
+template <int B, int E>
+__device__ void block_merge_sort(uint64_t* sk, uint32_t n) {
+    const uint32_t np = (n + E - 1) / E * E;
+    const uint32_t base = threadIdx.x * E;
+    const bool active = base < np;
+    for (uint32_t i = n + threadIdx.x; i < np; i += B) sk[i] = ~0ull;
+    __syncthreads();
+    uint64_t r[E];
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < E; j++) r[j] = sk[base + j];
+        sort_registers<E>(r);
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < E; j++) sk[base + j] = r[j];
+    }
+    __syncthreads();
+    for (uint32_t run = E; run < np; run <<= 1) {
+        if (active) {
+            const uint32_t a0 = base / (2 * run) * (2 * run);
+            const uint32_t a1 = min(a0 + run, np), b1 = min(a0 + 2 * run, np);
+            const uint32_t la = a1 - a0, lb = b1 - a1, d = base - a0;
+            // outputs [d, d + E) of this pair: how many come from the first run
+            uint32_t lo = d > lb ? d - lb : 0u, hi = min(d, la);
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (sk[a0 + mid] <= sk[a1 + d - mid - 1]) lo = mid + 1; else hi = mid;
+            }
+            uint32_t ia = lo, ib = d - lo;
+            uint64_t ka = sk[a0 + min(ia, la - 1)];
+            uint64_t kb = lb ? sk[a1 + min(ib, lb - 1)] : 0ull;
+#pragma unroll
+            for (int j = 0; j < E; j++) {
+                const bool from_a = ia < la && (ib >= lb || ka <= kb);
+                r[j] = from_a ? ka : kb;
+                if (from_a) ia++; else ib++;
+                const uint32_t next = from_a ? a0 + min(ia, la - 1) : a1 + min(ib, lb - 1);
+                const uint64_t nk = sk[next];
+                if (from_a) ka = nk; else kb = nk;
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < E; j++) sk[base + j] = r[j];
+        }
+        __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restrict__ meta,
                                                           const uint2* __restrict__ ranges, int n_tiles,
-                                                          uint32_t* __restrict__ vals) {
+                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ longq) {
     __shared__ uint64_t sk[kSortChunk];
     for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint2 rg = ranges[tile];
         const uint32_t n = rg.y - rg.x;
         if (n < 2) continue;                                   // uniform per workgroup
+        if (n > uint32_t(kSortChunk)) {                         // for k_tile_sort_long
+            if (threadIdx.x == 0) longq[1 + atomicAdd(&longq[0], 1u)] = uint32_t(tile);
+            continue;
+        }
         uint32_t* v = vals + rg.x;
         if (n <= kSortBlock) {
             const uint32_t i = threadIdx.x;
@@ -416,45 +567,39 @@ __global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restric
             __syncthreads();
             continue;
         }
-        if (n > uint32_t(kSortChunk)) continue;                 // k_tile_sort_long takes it
-        // bitonic sort in LDS (padded with the largest key)
-        uint32_t p = 1;
-        while (p < n) p <<= 1;
-        for (uint32_t i = threadIdx.x; i < p; i += kSortBlock) sk[i] = i < n ? depth_key(meta, v[i]) : ~0ull;
+        for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) sk[i] = depth_key(meta, v[i]);
         __syncthreads();
-        bitonic_lds<kSortBlock>(sk, p);
+        if (n <= kSortBlock * kSortItemsShort) block_merge_sort<kSortBlock, kSortItemsShort>(sk, n);
+        else block_merge_sort<kSortBlock, kSortItems>(sk, n);
         for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) v[i] = uint32_t(sk[i]);
         __syncthreads();
     }
 }
 
-// Lists longer than kSortChunk: one workgroup of kLongBlock threads per list,
-// chunks of kLongChunk keys bitonic-sorted in LDS, then (lists longer than a
-// chunk) pairwise merges of sorted key runs through two scratch ranges (each
+// Lists longer than kSortChunk (queued by k_tile_sort, in any order): one
+// workgroup of kLongBlock threads per list,
+// chunks of kLongChunk keys merge-sorted in LDS, then (lists longer than a
+// chunk) pairwise merges of sorted runs through two scratch ranges (each
 // key's place is its index in its run plus the number of smaller keys in the
 // other run, by binary search).
-constexpr int kLongBlock = 1024;
-constexpr int kLongChunk = 8192;
-
 __global__ __launch_bounds__(kLongBlock) void k_tile_sort_long(const uint4* __restrict__ meta,
-                                                               const uint2* __restrict__ ranges, int n_tiles,
+                                                               const uint2* __restrict__ ranges,
+                                                               const uint32_t* __restrict__ longq,
                                                                uint32_t* __restrict__ vals, uint64_t* __restrict__ ka,
                                                                uint64_t* __restrict__ kb) {
     __shared__ uint64_t sk[kLongChunk];
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint2 rg = ranges[tile];
+    const uint32_t nq = longq[0];
+    for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const uint2 rg = ranges[longq[1 + q]];
         const uint32_t n = rg.y - rg.x;
-        if (n <= uint32_t(kSortChunk)) continue;                // uniform per workgroup
         uint32_t* v = vals + rg.x;
         uint64_t* src = ka + rg.x;
         uint64_t* dst = kb + rg.x;
         for (uint32_t c0 = 0; c0 < n; c0 += kLongChunk) {
             const uint32_t m = min(uint32_t(kLongChunk), n - c0);
-            uint32_t p = 1;
-            while (p < m) p <<= 1;
-            for (uint32_t i = threadIdx.x; i < p; i += kLongBlock) sk[i] = i < m ? depth_key(meta, v[c0 + i]) : ~0ull;
+            for (uint32_t i = threadIdx.x; i < m; i += kLongBlock) sk[i] = depth_key(meta, v[c0 + i]);
             __syncthreads();
-            bitonic_lds<kLongBlock>(sk, p);
+            block_merge_sort<kLongBlock, kLongItems>(sk, m);
             if (n <= uint32_t(kLongChunk)) {
                 for (uint32_t i = threadIdx.x; i < m; i += kLongBlock) v[i] = uint32_t(sk[i]);
             } else {
@@ -478,16 +623,6 @@ __global__ __launch_bounds__(kLongBlock) void k_tile_sort_long(const uint4* __re
         }
         for (uint32_t i = threadIdx.x; i < n; i += kLongBlock) v[i] = uint32_t(src[i]);
         __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tkey, const uint32_t* __restrict__ counters,
-                                                uint64_t capacity, uint2* __restrict__ ranges) {
-    const uint32_t P = uint32_t(min(uint64_t(counters[GS_CTR_PAIRS]), capacity));
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < P; e += gridDim.x * blockDim.x) {
-        const uint32_t t = tkey[e];
-        if (e == 0 || tkey[e - 1] != t) ranges[t].x = e;
-        if (e + 1 == P || tkey[e + 1] != t) ranges[t].y = e + 1;
     }
 }
 
@@ -543,6 +678,7 @@ __global__ __launch_bounds__(1024) void k_tile_plan(const uint2* __restrict__ ra
     }
 }
 
+
 // ---------------------------------------------------------------------------
 
 static int grid_for(uint64_t n_max, int per_block) {
@@ -552,15 +688,20 @@ static int grid_for(uint64_t n_max, int per_block) {
     return int(g);
 }
 
+// sorts by the low `bits` bits of the keys in passes of at most 8 bits;
+// returns (in k_final) the buffer that holds the sorted keys
 static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
                              uint32_t n_max, int bits, uint32_t** k_final, hipStream_t s, BinWs& w) {
-    const int G = grid_for(n_max, kRsTile * 4);
+    const int G = grid_for(n_max, kRsTile);
+    const int passes = (bits + 7) / 8;
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
-    for (int shift = 0; shift < bits; shift += 8) {
-        GS_LAUNCH("k_rs_hist", k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, w.hist, G);
+    for (int p = 0, shift = 0; p < passes; p++) {
+        const int b = (bits - shift) / (passes - p);          // near-equal digit widths
+        GS_LAUNCH("k_rs_hist", k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, b, w.hist, G);
         GS_LAUNCH("k_rs_colscan", k_rs_colscan, dim3(256), dim3(kRsBlock), 0, s, w.hist, G, w.coltot);
-        GS_LAUNCH("k_rs_scatter", k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, w.hist, G,
-                           w.coltot);
+        GS_LAUNCH("k_rs_scatter", k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, b,
+                  w.hist, G, w.coltot);
+        shift += b;
         uint32_t* t;
         t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -571,72 +712,66 @@ static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
 
 hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta_u32, const gs_bins& bins,
                            void* ws, size_t ws_bytes, hipStream_t s) {
-    (void)cfg;
     (void)ws_bytes;
-    BinWs w = carve(ws, f.n_records, bins.capacity);
+    BinWs w = carve(ws, f.n_records, bins.capacity, f.n_tiles);
     const uint4* meta = reinterpret_cast<const uint4*>(meta_u32);
     const uint32_t nrec = uint32_t(f.n_records);
-    // counts restart every call; the status bits are sticky until the caller clears them
-    GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, bins.counters, 0u, int64_t(GS_CTR_STATUS));
-    const int64_t nr2 = int64_t(f.n_tiles) * 2;
-    GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(std::min<int64_t>((nr2 + 255) / 256, 2048))), dim3(256), 0, s,
-                       bins.ranges, 0u, nr2);
+    uint2* ranges = reinterpret_cast<uint2*>(bins.ranges);
+    // counts restart every call (the record scan writes them); the status
+    // bits are sticky until the caller clears them
+    const int64_t nt = f.n_tiles;
     auto plan = [&]() {
         if (bins.tile_order && (fwd_waves(cfg) == 0 || bwd_waves(cfg) == 0))
-            GS_LAUNCH("k_tile_plan", k_tile_plan, dim3(1), dim3(1024), 0, s,
-                      reinterpret_cast<const uint2*>(bins.ranges), bins.counters, f.n_tiles,
+            GS_LAUNCH("k_tile_plan", k_tile_plan, dim3(1), dim3(1024), 0, s, ranges, bins.counters, f.n_tiles,
                       (cfg.tile_w / 8) * (cfg.tile_h / 8), bins.tile_order);
     };
     if (nrec == 0) {
+        GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, bins.counters, 0u, int64_t(GS_CTR_STATUS));
+        GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(std::min<int64_t>((2 * nt + 255) / 256, 2048))), dim3(256), 0,
+                  s, bins.ranges, 0u, 2 * nt);
         plan();
         return hipGetLastError();
     }
 
-    // 1. compact the visible records (record order)
-    const int Gs = grid_for(nrec, kScanBlock * 8);
-    VisibleFlag vf{meta, w.dval[0]};
-    GS_LAUNCH("k_scan_reduce", k_scan_reduce<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
-    GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_VISIBLE,
-                       uint64_t(0));
-    GS_LAUNCH("k_scan_apply", k_scan_apply<VisibleFlag>, dim3(Gs), dim3(kScanBlock), 0, s, vf, nullptr, nrec, w.part, Gs);
-    const uint32_t* n_vis = bins.counters + GS_CTR_VISIBLE;
-    const uint32_t* sorted_rec = w.dval[0];
-    hipError_t e;
-
-    // 2. first pair of each visible record; total pairs
-    PairCount pc{meta, sorted_rec, bins.pair_off, w.poff};
-    GS_LAUNCH("k_scan_reduce", k_scan_reduce<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
-    GS_LAUNCH("k_scan_spine", k_scan_spine, dim3(1), dim3(kScanBlock), 0, s, w.part, Gs, bins.counters, GS_CTR_PAIRS,
-                       bins.capacity);
-    GS_LAUNCH("k_scan_apply", k_scan_apply<PairCount>, dim3(Gs), dim3(kScanBlock), 0, s, pc, n_vis, nrec, w.part, Gs);
-
-    // 3. emit (tile, record) pairs, then sort them by tile id
+    // 1. visible records in record order, their first pairs; V and P (the
+    //    reduce clears the tile ranges, which step 3 fills for tiles with
+    //    pairs; and the long-list queue count, which follows the ranges)
+    static_assert(sizeof(uint2) == 8, "ranges are pairs of 32-bit words");
+    {
+        const int G = grid_for(nrec, kScanBlock * 8);
+        RecordScan rs{meta, w.vis, bins.pair_off, w.poff};
+        VisPairs* part = static_cast<VisPairs*>(w.part);
+        GS_LAUNCH("k_scan_reduce", k_scan_reduce<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G,
+                  bins.ranges, 2 * nt, w.longq);
+        GS_LAUNCH("k_scan_spine", k_scan_spine<RecordScan>, dim3(1), dim3(kScanBlock), 0, s, part, G, bins.counters,
+                  bins.capacity);
+        GS_LAUNCH("k_scan_apply", k_scan_apply<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G);
+    }
+    // 2. emit (tile, record) pairs in record order, then sort them by tile id
     int bits = 0;
-    while ((1ll << bits) < int64_t(f.n_tiles)) bits++;
+    while ((1ll << bits) < nt) bits++;
     const int passes = (bits + 7) / 8;
     uint32_t* emit_val = (passes & 1) ? w.tval : bins.vals;
     uint32_t* other_val = (passes & 1) ? bins.vals : w.tval;
-    GS_LAUNCH("k_emit", k_emit, dim3(unsigned(grid_for(bins.capacity, kEmitChunk))), dim3(256), 0, s, meta, sorted_rec,
-                       w.poff, bins.counters, f, bins.capacity, w.tkey[0], emit_val);
+    GS_LAUNCH("k_emit", k_emit, dim3(unsigned(grid_for(bins.capacity, kEmitChunk))), dim3(256), 0, s, meta, w.vis,
+              w.poff, bins.counters, f, bins.capacity, w.tkey[0], emit_val);
     const uint32_t pmax = uint32_t(std::min<uint64_t>(bins.capacity, 0xffffffffull));
     uint32_t* tk_final = w.tkey[0];
     if (passes > 0) {
-        e = radix_sort(w.tkey[0], emit_val, w.tkey[1], other_val, bins.counters + GS_CTR_PAIRS, pmax, passes * 8,
-                       &tk_final, s, w);
+        const hipError_t e = radix_sort(w.tkey[0], emit_val, w.tkey[1], other_val, bins.counters + GS_CTR_PAIRS, pmax,
+                                        bits, &tk_final, s, w);
         if (e != hipSuccess) return e;
     }
-
-    // 4. per-tile [start, end)
-    GS_LAUNCH("k_ranges", k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity,
-                       reinterpret_cast<uint2*>(bins.ranges));
-    // 5. each tile's list in (depth bits, record) order
-    if (f.n_tiles > 0) {
-        GS_LAUNCH("k_tile_sort", k_tile_sort, dim3(unsigned(std::min(f.n_tiles, 4096))), dim3(kSortBlock), 0, s, meta,
-                  reinterpret_cast<const uint2*>(bins.ranges), f.n_tiles, bins.vals);
-        GS_LAUNCH("k_tile_sort_long", k_tile_sort_long, dim3(unsigned(std::min(f.n_tiles, 256))), dim3(kLongBlock), 0,
-                  s, meta, reinterpret_cast<const uint2*>(bins.ranges), f.n_tiles, bins.vals, w.key[0], w.key[1]);
+    // 3. per-tile [start, end)
+    GS_LAUNCH("k_ranges", k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity, ranges);
+    // 4. each tile's list in (depth bits, record) order
+    if (nt > 0) {
+        GS_LAUNCH("k_tile_sort", k_tile_sort, dim3(unsigned(std::min<int64_t>(nt, 4096))), dim3(kSortBlock), 0, s, meta,
+                  ranges, f.n_tiles, bins.vals, w.longq);
+        GS_LAUNCH("k_tile_sort_long", k_tile_sort_long, dim3(unsigned(std::min<int64_t>(nt, 256))), dim3(kLongBlock), 0,
+                  s, meta, ranges, w.longq, bins.vals, w.key[0], w.key[1]);
     }
-    // 6. compositing plan, when a pass splits tiles adaptively
+    // 5. compositing plan, when a pass splits tiles adaptively
     plan();
     return hipGetLastError();
 }
