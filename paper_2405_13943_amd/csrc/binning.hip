@@ -25,8 +25,9 @@ namespace gs {
 
 constexpr int kScanBlock = 256;
 constexpr int kRsBlock = 256;
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kRsBlock * kRsItems;     // keys per workgroup and iteration of a radix pass
+constexpr int kRsItemsLarge = 16;                // keys per thread and iteration of a radix pass: large
+constexpr int kRsItemsSmall = 4;                 // and small sorts (more workgroups)
+constexpr uint32_t kRsSmallMax = 1u << 22;       // pair capacity up to which the small form is used
 constexpr int kMaxGrid = 1024;
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -229,14 +230,14 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, int shift, int bits) {
 
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
                                                       uint32_t n_host, int shift, int bits, uint32_t* __restrict__ hist,
-                                                      int G) {
+                                                      int G, uint32_t granule) {
     __shared__ uint32_t h[kRsBlock / kWave][256];
     const int wave = threadIdx.x / kWave;
     for (int i = threadIdx.x; i < 256 * (kRsBlock / kWave); i += kRsBlock) (&h[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = min(*n_dev, n_host);
     uint32_t lo, hi;
-    block_range(n, G, blockIdx.x, kRsTile, lo, hi);
+    block_range(n, G, blockIdx.x, granule, lo, hi);
     for (uint32_t i = lo + threadIdx.x; i < hi; i += kRsBlock) atomicAdd(&h[wave][digit_of(keys[i], shift, bits)], 1u);
     __syncthreads();
     const int d = threadIdx.x;
@@ -272,17 +273,19 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_colscan(uint32_t* __restrict__ 
     if (threadIdx.x == 0) coltot[blockIdx.x] = tot;
 }
 
-// Scatter: per iteration kRsTile keys are ranked by digit (wave ballots for
+// Scatter: per iteration kRsBlock * ITEMS keys are ranked by digit (wave ballots for
 // the rank among equal digits, LDS counts across waves), staged in LDS in
 // digit order, then written out by consecutive threads to consecutive
 // addresses of each digit's output run.
+template <int ITEMS>
 __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
                                                          int bits, const uint32_t* __restrict__ hist, int G,
                                                          const uint32_t* __restrict__ coltot) {
     constexpr int NW = kRsBlock / kWave;
-    constexpr int PER_WAVE = kWave * kRsItems;
+    constexpr int PER_WAVE = kWave * ITEMS;
+    constexpr int kRsTile = kRsBlock * ITEMS;
     __shared__ uint32_t run[256];          // next output index of each digit
     __shared__ uint32_t loc[256];          // first staging slot of each digit
     __shared__ uint32_t wcnt[NW][256];     // per wave: count, then first rank, of each digit
@@ -300,9 +303,9 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
     for (uint32_t base = lo; base < hi; base += kRsTile) {
         for (int d = lane; d < 256; d += kWave) wcnt[wave][d] = 0;
         __builtin_amdgcn_wave_barrier();
-        uint32_t key[kRsItems], val[kRsItems], rank[kRsItems];
+        uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-        for (int k = 0; k < kRsItems; k++) {
+        for (int k = 0; k < ITEMS; k++) {
             const uint32_t i = base + wave * PER_WAVE + k * kWave + lane;
             key[k] = 0; val[k] = 0; rank[k] = 0;
             if (i < hi) {
@@ -337,7 +340,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kRsItems; k++) {
+        for (int k = 0; k < ITEMS; k++) {
             const uint32_t i = base + wave * PER_WAVE + k * kWave + lane;
             if (i < hi) {
                 const uint32_t dg = digit_of(key[k], shift, bits);
@@ -692,15 +695,21 @@ static int grid_for(uint64_t n_max, int per_block) {
 // returns (in k_final) the buffer that holds the sorted keys
 static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
                              uint32_t n_max, int bits, uint32_t** k_final, hipStream_t s, BinWs& w) {
-    const int G = grid_for(n_max, kRsTile);
+    const bool small = n_max <= kRsSmallMax;
+    const uint32_t tile = kRsBlock * (small ? kRsItemsSmall : kRsItemsLarge);
+    const int G = grid_for(n_max, int(tile));
     const int passes = (bits + 7) / 8;
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     for (int p = 0, shift = 0; p < passes; p++) {
         const int b = (bits - shift) / (passes - p);          // near-equal digit widths
-        GS_LAUNCH("k_rs_hist", k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, b, w.hist, G);
+        GS_LAUNCH("k_rs_hist", k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, b, w.hist, G, tile);
         GS_LAUNCH("k_rs_colscan", k_rs_colscan, dim3(256), dim3(kRsBlock), 0, s, w.hist, G, w.coltot);
-        GS_LAUNCH("k_rs_scatter", k_rs_scatter, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev, n_max, shift, b,
-                  w.hist, G, w.coltot);
+        if (small)
+            GS_LAUNCH("k_rs_scatter", k_rs_scatter<kRsItemsSmall>, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev,
+                      n_max, shift, b, w.hist, G, w.coltot);
+        else
+            GS_LAUNCH("k_rs_scatter", k_rs_scatter<kRsItemsLarge>, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev,
+                      n_max, shift, b, w.hist, G, w.coltot);
         shift += b;
         uint32_t* t;
         t = ki; ki = ko; ko = t;

@@ -131,9 +131,10 @@ def test_bins_bit_exact(gpu1):
 @pytest.mark.parametrize("n", [300, 1500, 6000, 9000])
 def test_bins_bit_exact_long_tile_lists(n):
     """Large Gaussians in front of a small view put n entries in every tile
-    (above 256: the in-LDS bitonic sort; above 2048: the long-list kernel;
-    above 8192: its chunks and merges), with many equal depths (ties ordered
-    by record), against the reference."""
+    (above 256: the in-LDS merge sort, 4 keys per thread up to 1024 and 16
+    beyond; above 4096: the long-list kernel; above 8192: its chunks and
+    merges), with many equal depths (ties ordered by record), against the
+    reference."""
     p = scenes.gaussians(n, 0, 4100 + n, [-0.3, -0.3, -0.3], [0.3, 0.3, 0.3], 0.0, 0.1)
     p[scenes.MEAN + 2, ::3] = 0.25                  # every third Gaussian at the same depth
     params = torch.from_numpy(p).cuda()
@@ -145,6 +146,21 @@ def test_bins_bit_exact_long_tile_lists(n):
         lens = np.diff(buf.ranges.view(-1, 2).cpu().numpy().view(np.uint32), axis=1)
         assert lens.max() > min(n - 10, 256)
         _bins_check(frame, buf)
+
+
+def test_bins_bit_exact_large_pair_capacity():
+    """A pair capacity above 2^22 takes the tile radix sort's large form (16
+    keys per thread and iteration, here over many iterations and a ragged
+    last one); the bins do not change."""
+    n = 1500
+    p = scenes.gaussians(n, 0, 4200, [-0.3, -0.3, -0.3], [0.3, 0.3, 0.3], 0.0, 0.1)
+    params = torch.from_numpy(p).cuda()
+    cam = scenes.look_at([0.0, 0.0, 3.0], [0, 0, 0], 64, 48, 60.0, 60.0)
+    cfg = gs.raster_cfg((8, 8))
+    frame = gs.Frame([cam], [gs.JobSpec(0, 0, n, 1.0)], cfg)
+    buf = gs.rasterize(params, frame, cfg, capacity=(1 << 22) + 4096)
+    assert gs.read_counters(buf)["pairs"] > 4096 * 8
+    _bins_check(frame, buf)
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 8), (32, 8)])
