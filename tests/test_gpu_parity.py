@@ -148,6 +148,22 @@ def test_bins_bit_exact_long_tile_lists(n):
         _bins_check(frame, buf)
 
 
+@pytest.mark.parametrize("size", [(16, 16), (17, 16), (48, 16), (200, 16)])
+def test_bins_bit_exact_few_tiles(size):
+    """1, 2, 3 and 13 tiles: no radix pass at all, then one pass of a 1-, 2-
+    and 4-bit digit; every Gaussian in front of the camera."""
+    n = 400
+    p = scenes.gaussians(n, 0, 4300, [-0.4, -0.2, -0.2], [0.4, 0.2, 0.2], 0.0, 0.3)
+    params = torch.from_numpy(p).cuda()
+    w, h = size
+    cam = scenes.look_at([0.0, 0.0, 3.0], [0, 0, 0], w, h, 40.0, 40.0)
+    cfg = gs.raster_cfg((16, 16))
+    frame = gs.Frame([cam], [gs.JobSpec(0, 0, n, 1.0)], cfg)
+    buf = gs.rasterize(params, frame, cfg)
+    assert frame.n_tiles == (w + 15) // 16 and gs.read_counters(buf)["pairs"] > 0
+    _bins_check(frame, buf)
+
+
 def test_bins_bit_exact_large_pair_capacity():
     """A pair capacity above 2^22 takes the tile radix sort's large form (16
     keys per thread and iteration, here over many iterations and a ragged
