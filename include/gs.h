@@ -385,6 +385,20 @@ gs_status gs_split_group(const double *boxes_host, int32_t K, double scale, int3
                          const double *points_host, int64_t n, int64_t *counts_host, int64_t *members_host,
                          int64_t capacity, int64_t *total_host);
 
+/* Storage order for a Gaussian store (no counterpart in the paper; a memory
+ * layout).  perm_host (int64 [n]) receives the Gaussians in Z-order
+ * (Morton order) of their means: mean_host holds the three mean planes
+ * (host FP32, plane a at mean_host + a * stride, stride >= n); each
+ * coordinate is quantised to `bits` (1..21) bits over the bounding box of
+ * the means, the bits are interleaved (x lowest, then y, then z, from the
+ * least significant level up) and ties keep index order.  Storing a model
+ * as params[:, perm] puts Gaussians that are close in space close in
+ * memory: what one view sees then forms long runs, which the projection and
+ * the compositing read in whole cache lines.  Renders of the permuted model
+ * equal those of the original except where two Gaussians have the same
+ * depth bits (their order follows the index). */
+gs_status gs_spatial_order(const float *mean_host, int64_t n, int64_t stride, int32_t bits, int64_t *perm_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,9 +99,17 @@ class Slot:
 
 class RenderServer:
     def __init__(self, params: torch.Tensor, cfg: gs.GsRasterCfg, hbm_budget: float = 32e9, n_slots: int = 3,
-                 max_batch: int = 16, resolutions=None, pair_headroom: float = 1.5):
+                 max_batch: int = 16, resolutions=None, pair_headroom: float = 1.5, spatial_order: bool = True):
         """params: global model [A][G] resident on the GPU.  The HBM budget
-        (bytes, transient buffers only) is split over n_slots arenas."""
+        (bytes, transient buffers only) is split over n_slots arenas.
+        spatial_order: serve a copy of the model stored in Z-order of the
+        means (gs_spatial_order), so that what a view sees forms long runs
+        in memory; images are the same except between Gaussians of equal
+        depth bits."""
+        self.perm = None
+        if spatial_order:
+            self.perm = torch.from_numpy(gs.spatial_order(params)).to(params.device)
+            params = params.index_select(1, self.perm).contiguous()
         self.params, self.cfg = params, cfg
         self.device = params.device
         self.G = params.shape[1]

@@ -217,3 +217,39 @@ def test_ssim_entry_host_checks(gs):
     assert call(0.2) == gs.GS_OK                   # empty frame: nothing to do
     f.n_pixels = 10
     assert call(0.2) == gs.GS_E_INVALID            # null images
+
+
+def _morton_ref(means, bits):
+    """Z-order by brute force: quantise, interleave bit by bit, sort by
+    (code, index)."""
+    m = np.asarray(means, np.float64)
+    lo, hi = m.min(1), m.max(1)
+    cells = 1 << bits
+    q = np.clip(np.floor((m - lo[:, None]) / np.maximum(hi - lo, 1e-30)[:, None] * cells), 0, cells - 1)
+    q = q.astype(np.int64)
+    codes = []
+    for i in range(m.shape[1]):
+        c = 0
+        for b in range(bits):
+            for a in range(3):
+                c |= ((int(q[a, i]) >> b) & 1) << (3 * b + a)
+        codes.append((c, i))
+    return [i for _, i in sorted(codes)]
+
+
+def test_spatial_order(gs):
+    """gs_spatial_order against a brute-force Z-order, a hand-worked 1-bit
+    case (octants x + 2y + 4z, ties by index), and argument checks."""
+    r = np.random.default_rng(2)
+    means = (r.random((3, 700)) * [[100], [20], [100]] - [[50], [10], [50]]).astype(np.float32)
+    for bits in (1, 3, 10):
+        assert gs.spatial_order(means, bits).tolist() == _morton_ref(means, bits)
+    pts = np.array([[1, 0, 1, 0, 1], [1, 1, 0, 0, 1], [0, 0, 0, 0, 1]], np.float32)
+    # octant codes: 3, 2, 1, 0, 7
+    assert gs.spatial_order(pts, 1).tolist() == [3, 2, 1, 0, 4]
+    with pytest.raises(gs.GsError, match="bits"):
+        gs.spatial_order(means, 0)
+    bad = means.copy()
+    bad[1, 5] = np.inf
+    with pytest.raises(gs.GsError, match="finite"):
+        gs.spatial_order(bad)

@@ -68,3 +68,29 @@ def test_small_budget_queues_instead_of_failing():
     stats, reqs = srv.run_open_loop(cams, arrivals, keep=[0, 29])
     assert stats["requests"] == 30
     assert torch.equal(srv.kept[29], srv.render_alone(cams[29]))
+
+
+def test_spatial_order_serves_the_same_images():
+    """The server's Z-ordered copy of the model is a permutation of the
+    model's columns, and its images match the FP64 oracle on the model in
+    its own order (1e-4 relative; pixels the oracle flags, e.g. two kept
+    Gaussians at nearly the same depth, whose order follows the index, are
+    left out), as do those of a server on the unpermuted model."""
+    import oracle
+    p = scenes.gaussians(1500, 3, 4343, [-5, -1, -5], [5, 1, 5], -2.5, 0.6)
+    params = torch.from_numpy(p).cuda()
+    cfg = gs.raster_cfg((16, 16))
+    a = serve.RenderServer(params, cfg, hbm_budget=2e9, n_slots=1, max_batch=2, resolutions=RES)
+    b = serve.RenderServer(params, cfg, hbm_budget=2e9, n_slots=1, max_batch=2, resolutions=RES, spatial_order=False)
+    assert a.perm is not None and b.perm is None
+    assert torch.equal(torch.sort(a.perm).values, torch.arange(params.shape[1], device=a.perm.device))
+    assert torch.equal(a.params, params[:, a.perm])
+    for cam in requests(3, 21):
+        ref = oracle.render(p, cam)
+        ok = ref["flags"] == 0
+        assert ok.mean() > 0.95
+        for srv in (a, b):
+            img = srv.render_alone(cam).numpy().astype(np.float64)
+            err = np.abs(img - ref["rgb"])
+            bad = (err > 1e-4 * np.abs(ref["rgb"]) + 1e-6) & ok[None]
+            assert not bad.any(), f"{bad.sum()} pixel-channels off"
