@@ -212,8 +212,9 @@ gs_status gs_project_f64(const gs_params *params, const gs_frame *frame, const g
  * partials) and counters.  When the pairs exceed bins->capacity, sets
  * GS_STATUS_PAIR_OVERFLOW, stores the needed count in counters[GS_CTR_PAIRS]
  * (saturating at 2^32 - 1) and leaves vals/ranges invalid.  The workspace
- * (device, caller-owned, at least gs_bin_sort_workspace_size bytes) holds
- * 8 bytes per record and 16 per pair of capacity, plus about 1 MiB. */
+ * (device, caller-owned, at least gs_bin_sort_workspace_size bytes for the
+ * frame's records, the bins' capacity and the frame's tiles) holds 8 bytes
+ * per record, 16 per pair of capacity and 4 per tile, plus about 1 MiB. */
 size_t gs_bin_sort_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles);
 gs_status gs_bin_sort(const gs_frame *frame, const gs_raster_cfg *cfg, const uint32_t *meta_dev,
                       const gs_bins *bins, void *ws_dev, size_t ws_bytes, gs_stream stream);
