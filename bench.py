@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 BWD_FLOPS = 46
+ORDER_STRANDS = 1024     # strands of the default training storage order (see setup)
 LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)       # mean, rotation, scale, SH, opacity
 RHO = (1e-3,) * 5
 
@@ -73,10 +74,11 @@ def kernel_sources_sha256(kernel):
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE / WRITE_SIZE scaled by a copy of known size), or None
-    when the kernel's sources have changed since those counters were taken."""
+    when the kernel's sources have changed since those counters were taken,
+    or when `workload` is given and the counters were taken on another."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -84,7 +86,15 @@ def measured_traffic(kernel):
         rec = json.load(fh).get(kernel)
     if not rec or rec.get("kernel_sources_sha256") != kernel_sources_sha256(kernel):
         return None
+    if workload is not None and rec.get("workload") != workload:
+        return None
     return int(rec["traffic_bytes_per_launch"])
+
+
+def train_workload_label(order):
+    """Name of the default training workload in the traffic records."""
+    return ("plain single block, 500k Gaussians SH3, 1600x1066, 16x16 tiles, wavefronts per tile from list length "
+            f"(forward and backward), storage order {order}")
 
 
 def _counter_per_dispatch(csv_dir, kernel, counter):
@@ -147,14 +157,24 @@ def record_traffic(kernel, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir,
     print(json.dumps(data[kernel]), flush=True)
 
 
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup(n, n_cams, width, height, tile):
+def setup(n, n_cams, width, height, tile, order="generator"):
     import torch
     from paper_2405_13943_amd import gs, scenes
     scene = scenes.config2(n=n, n_cams=n_cams, width=width, height=height)
+    if order != "generator":
+        # storage layout only (the same Gaussians): Z-order of the means, by
+        # default in 16-Gaussian chunks (one 64-byte line of a plane) dealt
+        # over ORDER_STRANDS strands, so that a view's culled Gaussians leave
+        # whole lines unread while each optimiser workgroup still mixes seen
+        # and unseen Gaussians
+        strands = ORDER_STRANDS if order == "z-strands" else 1
+        perm = gs.spatial_order(scene.params[0:3], chunk=16, strands=strands)
+        scene.params = np.ascontiguousarray(scene.params[:, perm])
     cfg = gs.raster_cfg(tile)
     dev = torch.device("cuda", 0)
     x = torch.from_numpy(scene.params).to(dev)
@@ -200,7 +220,7 @@ def run_gpu(args):
     torch.cuda.set_device(0)
     t0 = time.time()
     scene, cfg, st, frames, targets = setup(args.n, args.cams, args.width, args.height,
-                                            (args.tile, args.tile, args.fwd_waves, args.bwd_waves))
+                                            (args.tile, args.tile, args.fwd_waves, args.bwd_waves), args.order)
     A, N = st["x"].shape
     log(f"[bench] setup {time.time() - t0:.1f}s: N={N} A={A} views={len(frames)} {args.width}x{args.height}")
     buf, pmax = calibrate_capacity(gs, st, frames, cfg)
@@ -784,6 +804,9 @@ def main():
                     help="backward compositing wavefronts per tile: 1, 2, 4, or -1 per tile from its list length")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="backward and optimiser as two calls (gradient in HBM)")
+    ap.add_argument("--order", choices=("z-strands", "z", "generator"), default="z-strands",
+                    help="storage order of the training scene's Gaussians (a layout: the scene is the same): Z-order "
+                         "of the means in 16-Gaussian chunks over 1024 strands, plain Z-order, or as drawn")
     ap.add_argument("--inline-stage-timing", action="store_true",
                     help="record the per-stage events inside the timed loop (adds their cost to the step time)")
     ap.add_argument("--workload", choices=("train", "blocks4", "serve", "consensus", "split4"), default="train",
@@ -815,8 +838,8 @@ def main():
                          "with samples)")
     ap.add_argument("--traffic-args", default="--steps 4 --warmup 2 --no-cpu-baseline --no-serve",
                     help="with --record-traffic: the bench arguments the counter runs used")
-    ap.add_argument("--traffic-workload", default="plain single block, 500k Gaussians SH3, 1600x1066, 16x16 tiles, "
-                                                  "wavefronts per tile from list length (forward and backward)")
+    ap.add_argument("--traffic-workload", default=None,
+                    help="workload name stored with recorded traffic (default: the training workload and --order)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -828,7 +851,7 @@ def main():
                 f"rocprofv3 --pmc FETCH_SIZE -f csv -d {cfd} -o copy -- python bench.py --copy-probe",
                 f"rocprofv3 --pmc WRITE_SIZE -f csv -d {cwd} -o copy -- python bench.py --copy-probe"]
         for kernel in (args.traffic_kernels.split(",") if args.traffic_kernels else KERNEL_SOURCES):
-            record_traffic(kernel, fd, wd, cfd, cwd, args.traffic_workload, cmds)
+            record_traffic(kernel, fd, wd, cfd, cwd, args.traffic_workload or train_workload_label(args.order), cmds)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path holds all K blocks in one GPU's HBM and this build has no "
@@ -872,17 +895,18 @@ def main():
         "config": {"workload": f"single block, {r['N']} Gaussians SH3, {args.width}x{args.height}, "
                                f"{args.cams} ring views, one view per step, L1 + Adam/ADMM rho=1e-3",
                    "tile": f"{args.tile}x{args.tile}", "waves_per_tile_fwd_bwd": [args.fwd_waves, args.bwd_waves],
-                   "max_pairs": r["pairs_max"]},
+                   "max_pairs": r["pairs_max"], "storage_order": args.order},
         "stage_ms": {k: round(v, 5) for k, v in r["stage_ms"].items()},
         "kernel_ms": {k: round(v, 5) for k, v in r["kernel_ms"].items()},
         "roofline": {"bound": "alu", "kernel": "k_render_bwd", "achieved": round(r["bwd_tflops"], 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(r["bwd_tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic("k_render_bwd"),
+                     "traffic": measured_traffic("k_render_bwd", train_workload_label(args.order)),
                      "work": f"{BWD_FLOPS} flops x {r['kept']:.4g} (pixel, Gaussian) contributions per launch"},
         "roofline_stream": {"bound": "hbm", "kernel": r["opt_kernel"], "achieved": round(r["opt_gbs"], 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["opt_gbs"] / HBM_PEAK_GBS, 4),
-                            "traffic": measured_traffic(r["opt_kernel"]), "bytes": int(r["opt_bytes"])},
+                            "traffic": measured_traffic(r["opt_kernel"], train_workload_label(args.order)),
+                            "bytes": int(r["opt_bytes"])},
         "cpu_baseline": cpu,
         "serve": srv,
     }

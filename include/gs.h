@@ -392,13 +392,19 @@ gs_status gs_split_group(const double *boxes_host, int32_t K, double scale, int3
  * (host FP32, plane a at mean_host + a * stride, stride >= n); each
  * coordinate is quantised to `bits` (1..21) bits over the bounding box of
  * the means, the bits are interleaved (x lowest, then y, then z, from the
- * least significant level up) and ties keep index order.  Storing a model
- * as params[:, perm] puts Gaussians that are close in space close in
- * memory: what one view sees then forms long runs, which the projection and
- * the compositing read in whole cache lines.  Renders of the permuted model
- * equal those of the original except where two Gaussians have the same
- * depth bits (their order follows the index). */
-gs_status gs_spatial_order(const float *mean_host, int64_t n, int64_t stride, int32_t bits, int64_t *perm_host);
+ * least significant level up) and ties keep index order.  With strands > 1
+ * the Z-ordered sequence is cut into chunks of `chunk` Gaussians (the tail
+ * of n mod chunk stays last) and strand s (0 .. strands-1) takes chunks
+ * s, s + strands, s + 2 strands, ..., the strands one after another.
+ * Storing a model as params[:, perm] puts Gaussians that are close in space
+ * close in memory: what one view sees then forms long runs (or, with
+ * strands, whole chunks), which the projection and the compositing read in
+ * whole cache lines; the strands spread each region over the store, so that
+ * a workgroup's consecutive Gaussians mix seen and unseen ones.  Renders of
+ * the permuted model equal those of the original except where two Gaussians
+ * have the same depth bits (their order follows the index). */
+gs_status gs_spatial_order(const float *mean_host, int64_t n, int64_t stride, int32_t bits, int32_t chunk,
+                           int32_t strands, int64_t *perm_host);
 
 #ifdef __cplusplus
 }

@@ -384,17 +384,19 @@ gs_status gs_penalty_update(const float* resid, float* rho, float mu, float tau_
     return GS_OK;
 }
 
-gs_status gs_spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, int64_t* perm) {
+gs_status gs_spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, int32_t chunk, int32_t strands,
+                           int64_t* perm) {
     if (n < 0) return fail(GS_E_INVALID, "negative n");
     if (n == 0) return GS_OK;
     if (!mean || !perm) return fail(GS_E_INVALID, "null means or permutation");
     if (stride < n) return fail(GS_E_INVALID, "stride %lld below n %lld", (long long)stride, (long long)n);
     if (bits < 1 || bits > 21) return fail(GS_E_INVALID, "bits %d not in 1..21", bits);
+    if (chunk < 1 || strands < 1) return fail(GS_E_INVALID, "chunk %d and strands %d must be >= 1", chunk, strands);
     for (int a = 0; a < 3; a++)
         for (int64_t i = 0; i < n; i++)
             if (!std::isfinite(mean[a * stride + i]))
                 return fail(GS_E_INVALID, "mean %d of Gaussian %lld not finite", a, (long long)i);
-    gs::spatial_order(mean, n, stride, bits, perm);
+    gs::spatial_order(mean, n, stride, bits, chunk, strands, perm);
     return GS_OK;
 }
 

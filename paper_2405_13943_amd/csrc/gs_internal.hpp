@@ -72,7 +72,8 @@ hipError_t launch_ssim_loss_grad(const gs_frame& f, const gs_raster_cfg& cfg, co
 // split.hip (host)
 gs_status split_scene(const double* points, int64_t n, int32_t K, int32_t axes, double* boxes, int64_t* cell_of);
 // layout.hip
-void spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, int64_t* perm);
+void spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, int32_t chunk, int32_t strands,
+                   int64_t* perm);
 void split_group(const double* boxes, int32_t K, double s, int32_t axes, const double* points, int64_t n,
                  int64_t* counts, int64_t* members, int64_t capacity, int64_t* total);
 

@@ -5,6 +5,13 @@
 // Gaussians close in space become close in memory, so the set one view sees
 // forms long runs: the projection's loads of culled Gaussians then skip
 // whole cache lines, and a tile's records share lines.
+//
+// Optionally the Z-ordered sequence is cut into chunks of `chunk` Gaussians
+// (one cache line of a plane at 16) that are dealt over `strands` strands:
+// strand s takes chunks s, s + strands, ..., and the strands follow one
+// another.  Lines stay coherent in space, while a run of consecutive chunks
+// (one optimiser workgroup's Gaussians) comes from regions far apart, so
+// every such run mixes Gaussians the view sees and Gaussians it does not.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -14,7 +21,8 @@
 
 namespace gs {
 
-void spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, int64_t* perm) {
+void spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, int32_t chunk, int32_t strands,
+                   int64_t* perm) {
     double lo[3], hi[3];
     for (int a = 0; a < 3; a++) {
         lo[a] = hi[a] = double(mean[a * stride]);
@@ -39,7 +47,16 @@ void spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, i
         key[size_t(i)] = {code, i};
     }
     std::sort(key.begin(), key.end());
-    for (int64_t i = 0; i < n; i++) perm[i] = key[size_t(i)].second;
+    const int64_t nch = n / chunk;
+    if (strands <= 1 || nch == 0) {
+        for (int64_t i = 0; i < n; i++) perm[i] = key[size_t(i)].second;
+        return;
+    }
+    int64_t o = 0;
+    for (int64_t s = 0; s < strands; s++)
+        for (int64_t c = s; c < nch; c += strands)
+            for (int64_t j = 0; j < chunk; j++) perm[o++] = key[size_t(c * chunk + j)].second;
+    for (int64_t i = nch * chunk; i < n; i++) perm[o++] = key[size_t(i)].second;
 }
 
 }  // namespace gs

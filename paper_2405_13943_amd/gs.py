@@ -102,7 +102,7 @@ def _load():
         "gs_penalty_update": ([P(c_f), P(c_f), c_f, c_f, c_f, P(c_f)], c_i32),
         "gs_ssim_workspace_size": ([c_i64], ctypes.c_size_t),
         "gs_split_scene": ([c_vp, c_i64, c_i32, c_i32, c_vp, c_vp], c_i32),
-        "gs_spatial_order": ([c_vp, c_i64, c_i64, c_i32, c_vp], c_i32),
+        "gs_spatial_order": ([c_vp, c_i64, c_i64, c_i32, c_i32, c_i32, c_vp], c_i32),
         "gs_split_group": ([c_vp, c_i32, ctypes.c_double, c_i32, c_vp, c_i64, c_vp, c_vp, c_i64, P(c_i64)], c_i32),
         "gs_ssim_loss_grad": ([P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_f, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp],
                               c_i32),
@@ -332,17 +332,19 @@ def ssim_loss_grad(frame: Frame, cfg: GsRasterCfg, rgb: torch.Tensor, target: to
     return grad_out
 
 
-def spatial_order(means, bits=10):
+def spatial_order(means, bits=10, chunk=16, strands=1):
     """Z-order of the Gaussians' means (gs_spatial_order): a permutation
-    (int64 numpy array) for storing a model as params[:, perm].  means: the
-    three mean planes [3][n] (host array, or the parameter tensor's first
-    three rows on any device)."""
+    (int64 numpy array) for storing a model as params[:, perm]; with
+    strands > 1, chunks of `chunk` Gaussians of the Z-order dealt over that
+    many strands.  means: the three mean planes [3][n] (host array, or the
+    parameter tensor's first three rows on any device)."""
     if isinstance(means, torch.Tensor):
         means = means[MEAN_PLANE:MEAN_PLANE + 3].detach().float().cpu().numpy()
     m = np.ascontiguousarray(means, dtype=np.float32)
     n = m.shape[1]
     perm = np.zeros(n, np.int64)
-    _check(lib.gs_spatial_order(m.ctypes.data, n, n, int(bits), perm.ctypes.data), "gs_spatial_order")
+    _check(lib.gs_spatial_order(m.ctypes.data, n, n, int(bits), int(chunk), int(strands), perm.ctypes.data),
+           "gs_spatial_order")
     return perm
 
 

@@ -253,3 +253,19 @@ def test_spatial_order(gs):
     bad[1, 5] = np.inf
     with pytest.raises(gs.GsError, match="finite"):
         gs.spatial_order(bad)
+
+
+def test_spatial_order_strands(gs):
+    """Chunks of the Z-order dealt over strands: strand s takes chunks s,
+    s + k, ...; the tail shorter than a chunk stays last."""
+    r = np.random.default_rng(4)
+    means = r.random((3, 1000)).astype(np.float32)
+    z = gs.spatial_order(means, 10)
+    got = gs.spatial_order(means, 10, chunk=16, strands=5)
+    chunks = z[:992].reshape(62, 16)
+    want = np.concatenate([chunks[s::5].reshape(-1) for s in range(5)] + [z[992:]])
+    assert np.array_equal(got, want)
+    assert np.array_equal(np.sort(got), np.arange(1000))
+    assert np.array_equal(gs.spatial_order(means, 10, chunk=16, strands=1), z)
+    with pytest.raises(gs.GsError, match="strands"):
+        gs.spatial_order(means, 10, chunk=16, strands=0)
