@@ -517,7 +517,8 @@ def run_split4(args):
     si = scenes.split_input()
     log(f"[split4] scene {time.time() - t0:.1f}s")
     t1 = time.time()
-    model, boxes, groups = admm.BlockModel.from_split(si.params_global, 4, scale=args.split_scale)
+    model, boxes, groups = admm.BlockModel.from_split(si.params_global, 4, scale=args.split_scale,
+                                                      spatial_strands=args.block_strands)
     split_s = time.time() - t1
     cams = admm.split_cameras(boxes, si.cams, scale=args.split_scale)
     K = len(groups)
@@ -577,7 +578,8 @@ def run_split4(args):
             "config": {"workload": f"Alg. 1 split of 7.5M Gaussians SH3 into 4 blocks, overlap scale "
                                    f"{args.split_scale}, 1600x1066, consensus every 100 steps",
                        "tile": "x".join(map(str, tile[:2])), "waves_per_tile_fwd_bwd": list(tile[2:]),
-                       "relax": args.relax, "adaptive_penalty": bool(args.adaptive)},
+                       "relax": args.relax, "adaptive_penalty": bool(args.adaptive),
+                       "block_strands": args.block_strands},
             "split_s": round(split_s, 2), "local_copies": sizes, "global": n_global,
             "shared_fraction": round(sum(sizes) / n_global - 1.0, 4),
             "balance_max_over_min": round(max(sizes) / min(sizes), 4),
@@ -610,7 +612,7 @@ def run_blocks4(args):
     for k in range(K):
         for v in range(args.block_cams):
             target(k, v)
-    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid, spatial_strands=args.block_strands)
     log(f"[blocks4] setup {time.time() - t0:.1f}s: local {[len(g) for g in bs.local_gid]}, store "
         f"{tuple(model.x.shape)}, global {model.z.shape[1]}")
     x0 = model.x.clone()
@@ -650,7 +652,7 @@ def run_blocks4(args):
     # sequential baseline: each block as its own plain single-block model
     seq = []
     for k in range(K):
-        mk = admm.BlockModel.from_global(bs.params_global, [bs.local_gid[k]])
+        mk = admm.BlockModel.from_global(bs.params_global, [bs.local_gid[k]], spatial_strands=args.block_strands)
         tk = admm.AdmmTrainer(mk, [bs.cams[k]], (lambda kk: (lambda _k, v: target(kk, v)))(k), cfg, lr=LR, rho=RHO,
                               intv=1 << 30)
         tk.calibrate()
@@ -724,7 +726,8 @@ def run_blocks4(args):
            "config": {"workload": "batched K=4 blocks 0.8M/1.5M/2.2M/3.0M own Gaussians SH3 + 10% shared copies "
                                   f"({model.x.shape[1]} local slots), {args.block_cams} ring views per block at "
                                   "1600x1066, consensus every 100 steps",
-                      "tile": "x".join(map(str, tile[:2])), "waves_per_tile_fwd_bwd": list(tile[2:])},
+                      "tile": "x".join(map(str, tile[:2])), "waves_per_tile_fwd_bwd": list(tile[2:]),
+                      "block_strands": args.block_strands},
            "sequential_ms_per_step": ms_s / steps, "batched_speedup": ms_s / ms_b,
            "consensus_ms": c_ms, "consensus_calls": len(c_ms), "consensus_roofline": cons,
            "relax": args.relax, "adaptive_penalty": bool(args.adaptive), "images_equal_per_block": same,
@@ -828,6 +831,9 @@ def main():
     ap.add_argument("--relax", type=float, default=1.0, help="blocks4: over-relaxation alpha of the consensus")
     ap.add_argument("--adaptive", action="store_true", help="blocks4: residual-balancing penalty (until 2000)")
     ap.add_argument("--split-scale", type=float, default=1.4, help="split4: overlap scale factor of the blocks")
+    ap.add_argument("--block-strands", type=int, default=1024,
+                    help="blocks4/split4: inside each holder group, Z-order of the means in 16-Gaussian chunks over "
+                         "this many strands (0: the drawn order); a storage layout")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),

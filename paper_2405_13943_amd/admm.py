@@ -67,12 +67,13 @@ def split_cameras(boxes, cams, scale=1.4, ground_axes=(0, 2)):
     return [[cams[i] for i in g] for g in groups]
 
 
-def holder_order(local_gid, n_global):
+def holder_order(local_gid, n_global, within=None):
     """Numbering of the global ids grouped by holder set: ids held by the
     same blocks become consecutive, groups ordered by (first holder, number
-    of holders, holder set), original order kept inside a group, ids held by
-    no block last.  Returns (perm, inv): new id j is original id perm[j];
-    original id i becomes inv[i].
+    of holders, holder set), inside a group by ``within`` (a rank per
+    original id; default the original order), ids held by no block last.
+    Returns (perm, inv): new id j is original id perm[j]; original id i
+    becomes inv[i].
 
     With every block's copies stored in this order, the copies of one
     holder group are consecutive columns in each of its blocks, so the
@@ -91,7 +92,8 @@ def holder_order(local_gid, n_global):
         bit = (mask >> np.uint64(k)) & np.uint64(1)
         count += bit.astype(np.int64)
         first[bit.astype(bool)] = k
-    perm = np.lexsort((np.arange(n_global), mask, count, first)).astype(np.int64)
+    inner = np.arange(n_global) if within is None else np.asarray(within, np.int64)
+    perm = np.lexsort((inner, mask, count, first)).astype(np.int64)
     inv = np.empty_like(perm)
     inv[perm] = np.arange(n_global, dtype=np.int64)
     return perm, inv
@@ -111,18 +113,27 @@ class BlockModel:
     perm: np.ndarray = None           # store id j is the caller's global id perm[j] (None: identity)
 
     @classmethod
-    def from_global(cls, params_global: np.ndarray, local_gid, device="cuda", align=64, group_holders=True):
+    def from_global(cls, params_global: np.ndarray, local_gid, device="cuda", align=64, group_holders=True,
+                    spatial_strands=0):
         """Local copies of each block start on a multiple of ``align``
         columns (16-byte aligned slices for per-block streaming); the padding
         columns belong to no block and no holder set.  With
         ``group_holders`` the global ids are renumbered by holder set
         (``holder_order``) and each block's copies stored in that order;
-        ``global_params`` returns z in the caller's order."""
+        ``global_params`` returns z in the caller's order.  With
+        ``spatial_strands`` > 0 the ids inside a holder group follow the
+        Z-order of their means in 16-Gaussian chunks dealt over that many
+        strands (``gs.spatial_order``; a storage layout)."""
         A, G = params_global.shape
         deg = gs.sh_degree_of(A)
         perm = None
         if group_holders:
-            perm, inv = holder_order(local_gid, G)
+            within = None
+            if spatial_strands > 0:
+                order = gs.spatial_order(params_global[0:3], chunk=16, strands=int(spatial_strands))
+                within = np.empty(G, np.int64)
+                within[order] = np.arange(G, dtype=np.int64)
+            perm, inv = holder_order(local_gid, G, within)
             params_global = params_global[:, perm]
             local_gid = [np.sort(inv[np.asarray(g, np.int64)]) for g in local_gid]
         z = torch.from_numpy(np.ascontiguousarray(params_global)).to(device)
@@ -144,7 +155,8 @@ class BlockModel:
                    torch.from_numpy(idx).to(device), [np.asarray(g) for g in local_gid], ends, perm)
 
     @classmethod
-    def from_split(cls, params_global: np.ndarray, K: int, scale=1.4, ground_axes=(0, 2), device="cuda", align=64):
+    def from_split(cls, params_global: np.ndarray, K: int, scale=1.4, ground_axes=(0, 2), device="cuda", align=64,
+                   spatial_strands=0):
         """K blocks from the scene itself (Alg. 1 on the Gaussian means, then
         the overlap grouping with factor ``scale``; the paper uses 1.4):
         returns (model, cell boxes [K][6], per-block global ids in the
@@ -152,7 +164,8 @@ class BlockModel:
         pts = np.ascontiguousarray(params_global[0:3].T, dtype=np.float64)
         boxes, _ = gs.split_scene(pts, K, ground_axes)
         groups = gs.split_group(boxes, scale, pts)
-        return cls.from_global(params_global, groups, device=device, align=align), boxes, groups
+        return (cls.from_global(params_global, groups, device=device, align=align, spatial_strands=spatial_strands),
+                boxes, groups)
 
     @property
     def K(self):

@@ -30,24 +30,26 @@ def targets_for(bs):
             for k in range(len(bs.cams))]
 
 
-def make_trainer(bs, intv=2, rho=(1e-2,) * 5, relax=1.0, fused=True):
-    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+def make_trainer(bs, intv=2, rho=(1e-2,) * 5, relax=1.0, fused=True, strands=0):
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid, spatial_strands=strands)
     cfg = gs.raster_cfg((16, 16))
     return admm.AdmmTrainer(model, bs.cams, targets_for(bs), cfg, lr=(1e-3, 2e-3, 3e-3, 4e-3, 5e-3), rho=rho,
                             intv=intv, relax=relax, capacity=1 << 16, fused=fused)
 
 
-def test_batched_blocks_equal_single_block_runs():
+@pytest.mark.parametrize("strands", [0, 4])
+def test_batched_blocks_equal_single_block_runs(strands):
     """All blocks in one launch per stage give bit-identical images and
-    gradients to rendering each block alone."""
+    gradients to rendering each block alone (store in the drawn order inside
+    the holder groups, and in Z-order chunks over strands)."""
     bs = tiny_blocks()
-    tr = make_trainer(bs, fused=False)
+    tr = make_trainer(bs, fused=False, strands=strands)
     views = [1, 0, 1]
     tr.local_step(views)
     f = tr.frame(views)
     imgs = [f.image(tr.buf.rgb, k).clone() for k in range(3)]
     g_all = tr.g.clone()
-    x0 = admm.BlockModel.from_global(bs.params_global, bs.local_gid).x
+    x0 = admm.BlockModel.from_global(bs.params_global, bs.local_gid, spatial_strands=strands).x
     for k in range(3):
         a, b = tr.model.block(k)
         pk = x0[:, a:b].contiguous()
@@ -59,13 +61,15 @@ def test_batched_blocks_equal_single_block_runs():
         assert torch.equal(gk, g_all[:, a:b])
 
 
-def test_trainer_step_matches_oracle_composition():
+@pytest.mark.parametrize("strands", [0, 4])
+def test_trainer_step_matches_oracle_composition(strands):
     """One trainer step (t = 0: local step for all blocks, then consensus)
     equals the oracle composed from the paper's pieces: per-block image
     gradient (FP64 render/backward), Adam on g + rho (x - w) with w = z - u
-    and u = 0, then z = mean over holders, u = x - z, w = z - u."""
+    and u = 0, then z = mean over holders, u = x - z, w = z - u.  Also with
+    the store in Z-order chunks inside the holder groups."""
     bs = tiny_blocks()
-    tr = make_trainer(bs, intv=1)
+    tr = make_trainer(bs, intv=1, strands=strands)
     x0 = tr.model.x.cpu().numpy().copy()
     tr.local_step()
     # the trainer's step (backward and optimiser fused) used the L1 gradient of

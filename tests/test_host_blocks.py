@@ -58,3 +58,22 @@ def test_block_model_store_order_and_round_trip():
     np.testing.assert_array_equal(model.global_params().numpy(), params)
     plain = admm.BlockModel.from_global(params, local_gid, device="cpu", group_holders=False)
     np.testing.assert_array_equal(plain.global_params().numpy(), params)
+
+
+def test_holder_groups_ordered_inside_by_rank():
+    """A rank inside the holder groups reorders each group and nothing else:
+    the groups keep their places and sizes."""
+    r = np.random.default_rng(8)
+    G = 400
+    local_gid = [np.sort(r.choice(G, 150, replace=False)), np.sort(r.choice(G, 220, replace=False))]
+    perm0, _ = admm.holder_order(local_gid, G)
+    rank = r.permutation(G)
+    perm1, inv1 = admm.holder_order(local_gid, G, within=rank)
+    mask = np.zeros(G, np.int64)
+    for k, g in enumerate(local_gid):
+        mask[g] |= 1 << k
+    assert np.array_equal(mask[perm0], mask[perm1])            # same group at every position
+    for m in np.unique(mask):
+        ids = perm1[mask[perm1] == m]
+        assert np.all(np.diff(rank[ids]) > 0)                  # rank order inside the group
+    assert np.array_equal(inv1[perm1], np.arange(G))
