@@ -269,3 +269,17 @@ def test_spatial_order_strands(gs):
     assert np.array_equal(gs.spatial_order(means, 10, chunk=16, strands=1), z)
     with pytest.raises(gs.GsError, match="strands"):
         gs.spatial_order(means, 10, chunk=16, strands=0)
+
+
+def test_spatial_order_degenerate_clouds(gs):
+    """Equal means (a zero-extent box on every axis) keep the index order; a
+    single Gaussian and an empty store are permutations too; a flat cloud
+    (zero extent on one axis) orders by the other two."""
+    same = np.ones((3, 50), np.float32)
+    assert gs.spatial_order(same).tolist() == list(range(50))
+    assert gs.spatial_order(np.zeros((3, 1), np.float32)).tolist() == [0]
+    assert gs.spatial_order(np.zeros((3, 0), np.float32)).tolist() == []
+    r = np.random.default_rng(9)
+    flat = r.random((3, 300)).astype(np.float32)
+    flat[1] = 2.0
+    assert gs.spatial_order(flat, 6).tolist() == _morton_ref(flat, 6)
