@@ -38,7 +38,7 @@
 namespace gs {
 
 constexpr int kRenderWaves = 4;
-constexpr int kBwdBatch = 32;   // records staged per backward batch
+constexpr int kBwdBatch = 48;   // records staged per backward batch (of the 64 lanes)
 
 // record words as produced by the projection
 enum { R_MX = 0, R_MY, R_QA, R_QB, R_QC, R_LO, R_CR, R_CG, R_CB, R_DEPTH, R_HX, R_HY };
