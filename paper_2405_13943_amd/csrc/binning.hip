@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
 // the visible records it spans by binary search over their first-pair
 // offsets (staged in LDS), so a Gaussian covering thousands of tiles is
 // spread over many threads instead of serialising one.
-constexpr int kEmitChunk = 2048;
+constexpr int kEmitChunk = 1024;
 
 __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ vis,
                                               const uint32_t* __restrict__ poff, const uint32_t* __restrict__ counters,

@@ -571,7 +571,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P
 // with 16-byte accesses, else one Gaussian per thread.  The gradient never
 // reaches HBM and the parameters read by the chain are still in cache for the
 // update.  Same arithmetic as k_project_bwd_rec followed by k_adam_admm.
-constexpr int kFusedBlock = 128;
+constexpr int kFusedBlock = 256;
 
 // gradient of plane a of the block's Gaussian i from the phase-1 LDS arrays
 // (geo [11][kFusedBlock], Y [NK][kFusedBlock], dc [3][kFusedBlock])
