@@ -300,9 +300,39 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     int tile = 0, sub = 0, nwaves = NSD;
     uint32_t owned = (1u << PPL) - 1u;
     bool valid = true;   // adaptive: no early return, the workgroup may meet at a barrier below
+    // L1 loss, adaptive: the workgroup's wavefronts leave their sums in LDS
+    // and the last to arrive adds them per job, one global atomic per job
+    // and workgroup instead of one per wavefront (same-address atomics from
+    // every wavefront of the launch cost it about a sixth of its time)
+    __shared__ T s_loss[kRenderWaves];
+    __shared__ int s_ljob[kRenderWaves];
+    __shared__ uint32_t s_larrived;
+    const bool wg_loss = ADAPT && mode == GS_LOSS_L1 && loss_out != nullptr;
+    auto arrive = [&](T l, int jl) {
+        if (lane != 0) return;
+        s_loss[wave] = l;
+        s_ljob[wave] = jl;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (atomicAdd(&s_larrived, 1u) != uint32_t(kRenderWaves - 1)) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        for (int a = 0; a < kRenderWaves; a++) {
+            const int ja = s_ljob[a];
+            bool first = ja >= 0;
+            for (int b = 0; b < a; b++) first = first && s_ljob[b] != ja;
+            if (!first) continue;
+            T sum = T(0);
+            for (int b = a; b < kRenderWaves; b++) sum += s_ljob[b] == ja ? s_loss[b] : T(0);
+            atomicAdd(loss_out + ja, sum);
+        }
+    };
+    if (wg_loss) {
+        if (threadIdx.x == 0) s_larrived = 0u;
+        __syncthreads();
+    }
     if (ADAPT) {
         valid = plan_wave(order, frame.n_tiles, blockIdx.x * kRenderWaves + wave, tile, sub, nwaves);
         owned = valid ? owned_quadrants(PPL, nwaves, sub) : 0u;
+        if (wg_loss && !valid) arrive(T(0), -1);
     } else {
         const int gw = xcd_block(blockIdx.x, gridDim.x) * kRenderWaves + wave;
         tile = gw / NSD;
@@ -361,7 +391,8 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     }
     if (mode == GS_LOSS_L1 && loss_out) {
         const T l = wave_sum(loss);
-        if (lane == 0) atomicAdd(loss_out + j, l);
+        if (wg_loss) arrive(l, j);
+        else if (lane == 0) atomicAdd(loss_out + j, l);
     }
 
     const uint2 range = ranges[tile];

@@ -298,10 +298,16 @@ def test_render_bwd_sub_tile_waves_match_oracle(cfg1, ref1, tile):
     assert torch.equal(grad, grad2)
 
 
-def test_l1_loss_mode(cfg1, gpu1):
+@pytest.mark.parametrize("tile", [(16, 16), (16, 16, -1), (32, 8, -1), (8, 8, -1)])
+def test_l1_loss_mode(cfg1, tile):
     """GS_LOSS_L1 equals the external mode fed sign(C - target) * w / (3HW),
-    and the loss is w * mean |C - target|."""
-    cfg, frame, params, buf = gpu1
+    and the loss is w * mean |C - target| per job: with one wavefront per
+    tile, and with the wavefronts from the plan (whose workgroups mix tiles
+    of the four jobs and add their sums per job)."""
+    cfg = gs.raster_cfg(tile)
+    frame = make_frame(cfg1, cfg)
+    params = torch.from_numpy(cfg1.params).cuda()
+    buf = gs.rasterize(params, frame, cfg)
     target = frame_target(frame, cfg1, range(4))
     loss = torch.zeros(4, dtype=torch.float32, device="cuda")
     g1 = torch.empty_like(params)
