@@ -232,6 +232,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_ssim_fwd(gs_frame f, int tw, in
         vb[it] = tgt[t.px + si.off[it]];
     }
     const int c = int(threadIdx.x) % kTile, r0 = (int(threadIdx.x) / kTile) * kBlk;
+    // loss sums of the workgroup's tiles of one job, added to loss_out when
+    // the job changes or the workgroup is done (one atomic per job and
+    // workgroup: per-tile atomics on one word would serialise)
+    float s_sum = 0.f, l1_sum = 0.f;
+    int firsts = 0;
     while (true) {
         const gs_job job = f.jobs[t.job];
         const float n = 3.f * float(t.W) * float(t.H);
@@ -239,7 +244,6 @@ __global__ __launch_bounds__(kThreads, 3) void k_ssim_fwd(gs_frame f, int tw, in
         const uint32_t inext = i + gridDim.x;
         SsimTile tn = t;
         StageIdx sn = si;
-        float s_sum = 0.f, l1_sum = 0.f;
         for (int ch = 0; ch < 3; ch++) {
             const int64_t base = t.px + ch * t.plane;
 #pragma unroll
@@ -296,15 +300,18 @@ __global__ __launch_bounds__(kThreads, 3) void k_ssim_fwd(gs_frame f, int tw, in
             }
             __syncthreads();                   // st and hs are rewritten by the next item
         }
-        if (loss_out != nullptr) {             // uniform: the loss is optional
+        if (t.x0 == 0 && t.y0 == 0) firsts++;
+        // uniform: the loss is optional, and the next tile is the same for the workgroup
+        if (loss_out != nullptr && (inext >= cnt || tn.job != t.job)) {
             const float ss = block_sum(s_sum, red);
             const float ls = block_sum(l1_sum, red);
             if (threadIdx.x == 0) {
                 // w (mean |d| - lambda mean S), plus w lambda once per job for the 1 of 1 - mean S
-                float add = job.loss_weight * (ls - lambda * ss) / n;
-                if (t.x0 == 0 && t.y0 == 0) add += job.loss_weight * lambda;
+                const float add = job.loss_weight * (ls - lambda * ss) / n + float(firsts) * job.loss_weight * lambda;
                 atomicAdd(loss_out + t.job, add);
             }
+            s_sum = l1_sum = 0.f;
+            firsts = 0;
         }
         if (inext >= cnt) break;
         i = inext;
