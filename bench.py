@@ -46,6 +46,7 @@ KERNEL_SOURCES = {
     "k_project_bwd_adam": ("project.hip", "adam.hpp", "gs_device.hpp"),
     "k_render_bwd": ("render.hip", "gs_device.hpp"),
     "k_consensus": ("optim.hip", "adam.hpp", "gs_device.hpp"),
+    "k_adam_admm": ("optim.hip", "adam.hpp", "gs_device.hpp"),
     "k_ssim_fwd": ("ssim.hip", "gs_device.hpp"),
     "k_ssim_bwd": ("ssim.hip", "gs_device.hpp"),
 }

@@ -10,6 +10,19 @@ namespace gs {
 
 constexpr int kWave = 64;
 
+// 16-byte accesses with the non-temporal hint, for state that one step
+// touches once (the optimiser's moments and the consensus target): they
+// keep it from evicting the lines that the same kernel reads again
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ inline float4 load_stream4(const float* p) {
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ inline void store_stream4(float* p, float4 v) {
+    const f32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
+}
+
 // ---------------------------------------------------------------------------
 // scalar-type traits: FP32 product path, FP64 instantiation for adjoint checks
 

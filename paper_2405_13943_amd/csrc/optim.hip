@@ -33,19 +33,20 @@ __global__ __launch_bounds__(256) void k_adam_admm(float* __restrict__ x, const 
     const float* Wp = PEN ? w + a * sw : nullptr;
     if (VEC && i4 + 4 <= n) {
         float4 xv = *reinterpret_cast<const float4*>(X + i4);
-        const float4 gv = *reinterpret_cast<const float4*>(G + i4);
-        float4 mv = *reinterpret_cast<const float4*>(M + i4);
-        float4 vv = *reinterpret_cast<const float4*>(Vv + i4);
+        // g, m, v and w are touched once per step: streamed past the caches
+        const float4 gv = load_stream4(G + i4);
+        float4 mv = load_stream4(M + i4);
+        float4 vv = load_stream4(Vv + i4);
         float4 wv = make_float4(0.f, 0.f, 0.f, 0.f), kv = make_float4(1.f, 1.f, 1.f, 1.f);
-        if (PEN) wv = *reinterpret_cast<const float4*>(Wp + i4);
+        if (PEN) wv = load_stream4(Wp + i4);
         if (MASK) kv = *reinterpret_cast<const float4*>(mask + i4);
         adam_one(xv.x, gv.x, mv.x, vv.x, wv.x, PEN ? rho * kv.x : 0.f, lr, c);
         adam_one(xv.y, gv.y, mv.y, vv.y, wv.y, PEN ? rho * kv.y : 0.f, lr, c);
         adam_one(xv.z, gv.z, mv.z, vv.z, wv.z, PEN ? rho * kv.z : 0.f, lr, c);
         adam_one(xv.w, gv.w, mv.w, vv.w, wv.w, PEN ? rho * kv.w : 0.f, lr, c);
         *reinterpret_cast<float4*>(X + i4) = xv;
-        *reinterpret_cast<float4*>(M + i4) = mv;
-        *reinterpret_cast<float4*>(Vv + i4) = vv;
+        store_stream4(M + i4, mv);
+        store_stream4(Vv + i4, vv);
     } else {
         for (int64_t i = i4; i < n && i < i4 + 4; i++) {
             float xs = X[i], ms = M[i], vs = Vv[i];

@@ -581,7 +581,8 @@ __device__ inline float staged_grad(const float* geo, const float* Y, const floa
 }
 
 // phase 2 over contiguous, 16-byte aligned Gaussians g0 .. g0 + kFusedBlock - 1:
-// items (plane, 4 Gaussians), 16-byte accesses
+// items (plane, 4 Gaussians), 16-byte accesses; m, v and w stream past the
+// caches (x stays cached: the chain rule has just read part of it)
 template <int A, bool PEN, bool MASK>
 __device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* __restrict__ M, int64_t sm,
                                       float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
@@ -598,10 +599,10 @@ __device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* 
         const int grp = plane_group(a);
         const float lr = c.lr[grp], rho = c.rho[grp];
         float4 xv = *reinterpret_cast<const float4*>(X + a * sx + gv);
-        float4 mv = *reinterpret_cast<const float4*>(M + a * sm + gv);
-        float4 vv = *reinterpret_cast<const float4*>(V + a * sv + gv);
+        float4 mv = load_stream4(M + a * sm + gv);
+        float4 vv = load_stream4(V + a * sv + gv);
         float4 wv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (PEN) wv = *reinterpret_cast<const float4*>(Wp + a * sw + gv);
+        if (PEN) wv = load_stream4(Wp + a * sw + gv);
         // the four Gaussians' gradients of plane a: one 16-byte LDS read per array
         float4 gq;
         if (a < 11) {
@@ -616,8 +617,8 @@ __device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* 
         adam_one(xv.z, gq.z, mv.z, vv.z, wv.z, PEN ? rho * kv.z : 0.f, lr, c);
         adam_one(xv.w, gq.w, mv.w, vv.w, wv.w, PEN ? rho * kv.w : 0.f, lr, c);
         *reinterpret_cast<float4*>(X + a * sx + gv) = xv;
-        *reinterpret_cast<float4*>(M + a * sm + gv) = mv;
-        *reinterpret_cast<float4*>(V + a * sv + gv) = vv;
+        store_stream4(M + a * sm + gv, mv);
+        store_stream4(V + a * sv + gv, vv);
     }
 }
 
