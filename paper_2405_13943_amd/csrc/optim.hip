@@ -116,6 +116,11 @@ __device__ __forceinline__ float& at(float* base, uint32_t off) {
 __device__ __forceinline__ float at(const float* base, uint32_t off) {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
 }
+// store with the non-temporal hint: z, u and w are written once per round and
+// not read again by it, so they need not take cache lines from the loads
+__device__ __forceinline__ void store_stream(float* base, uint32_t off, float v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off));
+}
 
 // Planes [A0, A0 + NP) (clipped to A) of one global id (byte offset og in the
 // z planes) whose nh <= NH holders sit at byte offsets ol[0..NH) in the local
@@ -151,13 +156,13 @@ __device__ __forceinline__ void consensus_chunk(const float* __restrict__ x, flo
             if (j == 0 || j < nh) acc += xh[j];
         }
         const float zn = acc / cnt;
-        at(z + a * sz, og) = zn;
+        store_stream(z + a * sz, og, zn);
 #pragma unroll
         for (int j = 0; j < NH; j++) {
             if (j == 0 || j < nh) {
                 const float un = uv[i][j] + xh[j] - zn;
-                if (nh > 1) at(u + a * su, ol[j]) = un;
-                at(w + a * sw, ol[j]) = zn - un;
+                if (nh > 1) store_stream(u + a * su, ol[j], un);
+                store_stream(w + a * sw, ol[j], zn - un);
                 rp[grp] += (xv[i][j] - zn) * (xv[i][j] - zn);
             }
         }
@@ -367,8 +372,8 @@ __device__ __forceinline__ void rescale_chunk(float* __restrict__ u, float* __re
         for (int j = 0; j < NH; j++) {
             const float us = uv[i][j] * f;
             if ((j == 0 || j < n) && us != uv[i][j]) {
-                at(u + a * su, ol[j]) = us;
-                at(w + a * sw, ol[j]) = zv[i] - us;
+                store_stream(u + a * su, ol[j], us);
+                store_stream(w + a * sw, ol[j], zv[i] - us);
             }
         }
     }
