@@ -70,6 +70,22 @@ def test_single_job_with_culled_gaussians(w, mask):
     assert not torch.equal(a[0], x)        # the step moved the parameters
 
 
+def test_job_at_unaligned_column_with_uncovered_gaussians():
+    """A job over Gaussians [3, n): its workgroups are not 16-byte aligned, so
+    every one takes the per-Gaussian optimiser path, and the three Gaussians
+    outside the job get the zero-gradient update of the uncovered kernel."""
+    s = scenes.config1()
+    x = torch.from_numpy(s.params).cuda()
+    n = x.shape[1]
+    cfg = gs.raster_cfg((16, 16))
+    frame = gs.Frame([s.cams[1]], [gs.JobSpec(0, 3, n, 1.0)], cfg)
+    assert frame.jobs_disjoint
+    target = torch.from_numpy(s.targets[1]).reshape(-1).cuda()
+    a, b = both_paths(x, frame, cfg, target, True, True, step=5, seed=3)
+    assert_same(a, b)
+    assert not torch.equal(a[0][:, :3], x[:, :3])   # the penalty moved the uncovered ones too
+
+
 def test_disjoint_blocks_with_padding_columns():
     bs = scenes.block_scene(counts=(300, 400, 350), bounds=(-1.5, -0.5, 0.5, 1.5), n_cams=2, width=64, height=48,
                             y_range=(-0.5, 0.5), z_range=(-0.5, 0.5), logscale=(-3.5, 0.4), ring_radius=3.0,
