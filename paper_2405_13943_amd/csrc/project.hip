@@ -249,7 +249,9 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     const int tx0 = int(x0) / cfg.tile_w, tx1 = int(x1) / cfg.tile_w;
     const int ty0 = int(y0) / cfg.tile_h, ty1 = int(y1) / cfg.tile_h;
 
-    // colour from the SH coefficients at the view direction
+    // colour from the SH coefficients at the view direction (read with the
+    // non-temporal hint: 48 of the 59 planes, not needed again until the
+    // optimiser, so they leave the cache to the geometry planes and records)
     T dir[3];
     view_dir(G, cam, dir);
     T Y[16];
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     for (int ch = 0; ch < 3; ch++) {
         T s = 0;
 #pragma unroll
-        for (int k = 0; k < NK; k++) s += Y[k] * plane(P, stride, 11 + 3 * k + ch, g);
+        for (int k = 0; k < NK; k++) s += Y[k] * __builtin_nontemporal_load(P + int64_t(11 + 3 * k + ch) * stride + g);
         s += T(0.5);
         col[ch] = s > T(0) ? s : T(0);
         clamp |= s > T(0) ? 0u : (1u << ch);
