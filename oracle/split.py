@@ -14,7 +14,10 @@ Alg. 1, as read here:
     balance constraint); the "longer axis" is the longer of the ground
     axes (the paper assumes one axis is aligned with the ground and splits
     the ground plane), ties to the lower axis index; when K is not a power
-    of two the last round stops as soon as there are K cells.
+    of two the last round stops as soon as there are K cells; a cell of a
+    single point cannot be cut in two non-empty halves, so its turn takes
+    it out and appends it again unchanged (K <= n still ends with K cells,
+    since some cell holds two points while there are fewer than n cells).
 Overlap (Sec. 3.2): every cell box is scaled by s about its centre and a
 point (or a camera centre) belongs to every block whose scaled box covers it
 (inclusive bounds), so points near a cut are shared by both sides.  The
@@ -46,6 +49,9 @@ def split_cells(points, K, ground_axes=(0, 2)):
         while current and len(cells) < K:
             box, ids = current.pop(0)
             cells.remove((box, ids))
+            if len(ids) < 2:
+                cells.append((box, ids))
+                continue
             ext = {a: box[3 + a] - box[a] for a in ground_axes}
             axis = max(ground_axes, key=lambda a: (ext[a], -a))
             order = sorted(ids, key=lambda i: (pts[i][axis], i))

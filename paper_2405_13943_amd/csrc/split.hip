@@ -5,12 +5,14 @@
 // Alg. 1: start from the tight box of all points; in rounds, every current
 // cell (first in, first out) is removed, cut in two along its longer ground
 // axis, and the two halves re-tightened and appended, until there are K
-// cells (the last round stops at K).  The cut is the median: the floor(n/2)
-// points with the smallest (coordinate, point id) form the first half, so
-// blocks hold similar numbers of points.  Grouping: a point (or camera
-// centre) belongs to every block whose cell box, grown by (s - 1) / 2 of its
-// extent on each side (the box scaled by s about its centre), covers it on
-// the tested axes (all three for points, the ground axes for cameras).
+// cells (the last round stops at K); a cell of one point cannot be cut into
+// two non-empty halves, so its turn appends it again unchanged.  The cut is
+// the median: the floor(n/2) points with the smallest (coordinate, point id)
+// form the first half, so blocks hold similar numbers of points.  Grouping:
+// a point (or camera centre) belongs to every block whose cell box, grown by
+// (s - 1) / 2 of its extent on each side (the box scaled by s about its
+// centre), covers it on the tested axes (all three for points, the ground
+// axes for cameras).
 #include <algorithm>
 #include <cstdint>
 #include <deque>
@@ -77,6 +79,10 @@ gs_status split_scene(const double* p, int64_t n, int32_t K, int32_t axes, doubl
             Cell c = std::move(cells.front());
             cells.pop_front();
             round--;
+            if (c.ids.size() < 2) {
+                cells.push_back(std::move(c));
+                continue;
+            }
             int axis = ground[0];
             for (int a : ground)
                 if (c.box[3 + a] - c.box[a] > c.box[3 + axis] - c.box[axis]) axis = a;

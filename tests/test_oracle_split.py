@@ -83,3 +83,25 @@ def test_rounds_split_every_cell_first_in_first_out():
     assert [[pts[i][0] for i in c] for _, c in cells] == [[1.0, 0.0], [3.0, 2.0], [5.0, 4.0], [7.0, 6.0]]
     three = split.split_cells(pts, 3)
     assert [sorted(pts[i][0] for i in c) for _, c in three] == [[4.0, 5.0, 6.0, 7.0], [0.0, 1.0], [2.0, 3.0]]
+
+
+def test_single_point_cells_wait_their_turn():
+    """Three points on the x axis, K = 3 (worked by hand).  Round 1 cuts
+    {0, 1, 2} at the median: {0} and {1, 2}.  Round 2 takes {0} first; it
+    cannot be cut, so it is appended again unchanged; then {1, 2} is cut
+    into {1} and {2}.  Cells in order: {0}, {1}, {2}."""
+    pts = [[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [2.0, 0.0, 0.0]]
+    cells = split.split_cells(pts, 3)
+    assert [ids for _, ids in cells] == [[0], [1], [2]]
+    assert [box for box, _ in cells] == [[0.0, 0, 0, 0.0, 0, 0], [1.0, 0, 0, 1.0, 0, 0], [2.0, 0, 0, 2.0, 0, 0]]
+    # five points, K = 5.  Round 1: {0,1} {2,3,4}.  Round 2: {2,3,4} {0} {1},
+    # then {0} {1} {2} {3,4}.  Round 3: {0}, {1} and {2} are appended again
+    # in turn, leaving {3,4} {0} {1} {2}; the cut of {3,4} gives the order
+    # {0} {1} {2} {3} {4}
+    pts5 = [[float(i), 0.0, 0.0] for i in range(5)]
+    got = [ids for _, ids in split.split_cells(pts5, 5)]
+    assert got == [[0], [1], [2], [3], [4]]
+    # six points, K = 5: round 2 leaves {0} {1,2} {3} {4,5}; round 3 appends
+    # {0} again, then cuts {1,2}: {3} {4,5} {0} {1} {2}
+    pts6 = [[float(i), 0.0, 0.0] for i in range(6)]
+    assert [ids for _, ids in split.split_cells(pts6, 5)] == [[3], [4, 5], [0], [1], [2]]

@@ -92,3 +92,18 @@ def test_argument_checks(gs):
     boxes, _ = gs.split_scene(np.random.default_rng(0).random((10, 3)), 2)
     with pytest.raises(gs.GsError, match="scale"):
         gs.split_group(boxes, 0.5, pts)
+
+
+@pytest.mark.parametrize("n,K", [(3, 3), (5, 5), (6, 5), (2, 2), (7, 7), (9, 8)])
+def test_k_close_to_n(gs, n, K):
+    """K close to the number of points: cells of one point are not cut (their
+    turn appends them again), so K <= n always ends with K non-empty cells,
+    equal to the oracle's."""
+    r = np.random.default_rng(100 + n * 10 + K)
+    for pts in (r.random((n, 3)) * [10, 1, 10], np.repeat(r.random((1, 3)), n, axis=0)):
+        boxes, cell = gs.split_scene(pts, K)
+        ref = osplit.split_cells(pts, K)
+        assert len(ref) == K and all(len(ids) >= 1 for _, ids in ref)
+        for k, (box, ids) in enumerate(ref):
+            assert list(boxes[k]) == box
+            assert list(np.nonzero(cell == k)[0]) == ids
