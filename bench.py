@@ -567,7 +567,7 @@ def run_split4(args):
     ms = e0.elapsed_time(e1)
     kernels = {k: gs.profile_get(k) for k in ("k_consensus", "k_dual_rescale")}
     gs.profile_set(None)
-    if not tr.check(grow=False):
+    if gs.read_counters(tr.buf)["status"] & gs.GS_STATUS_PAIR_OVERFLOW:
         raise SystemExit("pair capacity overflowed during the timed steps")
     c_ms = [a.elapsed_time(b) for a, b in cons]
     roof = consensus_roofline(model, tr, c_ms, kernels)
@@ -709,7 +709,7 @@ def run_blocks4(args):
     cons_kernels = {k: gs.profile_get(k) for k in ("k_consensus", "k_dual_rescale")}
     gs.profile_set(None)
     ms_s = timed(seq_step, steps)
-    ok = all(b.check(grow=False) for b in [tr] + seq)
+    ok = all(not gs.read_counters(b.buf)["status"] & gs.GS_STATUS_PAIR_OVERFLOW for b in [tr] + seq)
     if not ok:
         raise SystemExit("pair capacity overflowed during the timed steps; rerun with more headroom")
     c_ms = [a.elapsed_time(b) for a, b in cons_ms]

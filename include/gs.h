@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 2
+#define GS_ABI_VERSION 3
 
 typedef enum {
     GS_OK = 0,
@@ -53,14 +53,19 @@ typedef enum {
     GS_E_UNSUPPORTED = 4   /* valid request this build does not implement */
 } gs_status;
 
-/* status bits OR-ed into gs_bins.counters[GS_CTR_STATUS]; sticky: gs_bin_sort
- * never clears them, so one check after many steps covers all of them */
-#define GS_STATUS_PAIR_OVERFLOW 1u
+/* status bits OR-ed into a device status word (gs_bins.counters[GS_CTR_STATUS],
+ * or the status_dev argument of gs_project and gs_adam_admm); sticky: no call
+ * clears them, so one check after many steps covers all of them */
+#define GS_STATUS_PAIR_OVERFLOW 1u   /* gs_bin_sort: more pairs than bins.capacity */
+#define GS_STATUS_NONFINITE 2u       /* gs_project / the optimiser met a NaN or Inf */
 
 /* indices into gs_bins.counters (device, uint32[GS_N_COUNTERS]) */
 #define GS_CTR_VISIBLE 0   /* records with at least one covered tile */
 #define GS_CTR_PAIRS 1     /* (tile, record) pairs required (may exceed capacity) */
 #define GS_CTR_STATUS 2
+#define GS_CTR_OVERFLOWED 3  /* gs_bin_sort calls that ended with GS_STATUS_PAIR_OVERFLOW
+                                set (counted until the caller clears it): the steps whose
+                                optimiser updates were skipped */
 #define GS_N_COUNTERS 4
 
 typedef void *gs_stream;   /* hipStream_t */
@@ -197,11 +202,15 @@ gs_status gs_frame_plan(const gs_camera *cams_host, int32_t n_cams, gs_job *jobs
  *                bits 0..23 with the colour-clamp flags of r, g, b in bits 24..26,
  *                tile rectangle lo (x | y << 16) and hi (inclusive).
  * The rectangle is conservative: every pixel where alpha >= alpha_min lies
- * inside it. */
+ * inside it.  status_dev (device uint32, may be NULL; e.g. the bins'
+ * counters + GS_CTR_STATUS): GS_STATUS_NONFINITE is OR-ed in when a
+ * parameter value the projection reads is NaN or Inf (the mean of every
+ * Gaussian of a job; its other geometry planes when it passes the near
+ * plane; its SH planes when its rectangle meets the image). */
 gs_status gs_project(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
-                     void *rec_dev, uint32_t *meta_dev, gs_stream stream);
+                     void *rec_dev, uint32_t *meta_dev, uint32_t *status_dev, gs_stream stream);
 gs_status gs_project_f64(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
-                         void *rec_dev, uint32_t *meta_dev, gs_stream stream);
+                         void *rec_dev, uint32_t *meta_dev, uint32_t *status_dev, gs_stream stream);
 
 /* Tile binning (no counterpart in the paper; an exact acceleration of the
  * per-pixel definition).  Emits one pair per (covered tile, record), sorts
@@ -211,7 +220,11 @@ gs_status gs_project_f64(const gs_params *params, const gs_frame *frame, const g
  * visible record in record order: the layout of the backward's per-pair
  * partials) and counters.  When the pairs exceed bins->capacity, sets
  * GS_STATUS_PAIR_OVERFLOW, stores the needed count in counters[GS_CTR_PAIRS]
- * (saturating at 2^32 - 1) and leaves vals/ranges invalid.  The workspace
+ * (saturating at 2^32 - 1) and leaves vals/ranges truncated to the first
+ * `capacity` pairs (in bounds, but not the frame's lists).  Every call that
+ * ends with the overflow bit set (this call's or an earlier, uncleared one)
+ * adds 1 to counters[GS_CTR_OVERFLOWED]: with the sticky bit, the optimiser
+ * updates of that many steps were skipped and are to be redone.  The workspace
  * (device, caller-owned, at least gs_bin_sort_workspace_size bytes for the
  * frame's records, the bins' capacity and the frame's tiles) holds 8 bytes
  * per record, 16 per pair of capacity and 4 per tile, plus about 1 MiB. */
@@ -283,9 +296,15 @@ gs_status gs_ssim_loss_grad(const gs_frame *frame, const gs_raster_cfg *cfg, con
  * w = z - u is the consensus target and rho_a the per-attribute penalty
  * (supplementary Sec. C).  w == NULL: no penalty.  mask (device float [n],
  * may be NULL): per-Gaussian penalty weight.  Updates x, m, v in place over
- * all x->n Gaussians; all five gs_params must share n and sh_degree. */
+ * all x->n Gaussians; all five gs_params must share n and sh_degree.
+ * status_dev (device uint32, may be NULL; e.g. the bins' counters +
+ * GS_CTR_STATUS): while GS_STATUS_PAIR_OVERFLOW is set in it the update is
+ * skipped (x, m, v untouched: a gradient from truncated tile lists must not
+ * move the parameters); GS_STATUS_NONFINITE is OR-ed in when an updated
+ * parameter or second moment is NaN or Inf, which any NaN or Inf among x, g,
+ * m, v, w and mask leads to. */
 gs_status gs_adam_admm(gs_params *x, const gs_params *g, gs_params *m, gs_params *v, const gs_params *w,
-                       const float *mask_dev, const gs_adam_cfg *cfg, gs_stream stream);
+                       const float *mask_dev, const gs_adam_cfg *cfg, uint32_t *status_dev, gs_stream stream);
 
 /* Backward and x-update of one local step in one call: gs_render_bwd in
  * FP32 followed by gs_adam_admm, with the gradient of each parameter plane
@@ -295,7 +314,9 @@ gs_status gs_adam_admm(gs_params *x, const gs_params *g, gs_params *m, gs_params
  * disjoint Gaussian ranges (frame->jobs_disjoint; otherwise GS_E_UNSUPPORTED:
  * use the two calls); Gaussians in no job take the update with a zero
  * gradient.  x is read by the backward and updated in place; m, v, w, mask
- * and acfg as in gs_adam_admm; the other arguments and the workspace as in
+ * and acfg as in gs_adam_admm, with bins->counters[GS_CTR_STATUS] as the
+ * status word (the update is skipped after a pair overflow; non-finite
+ * updates are flagged); the other arguments and the workspace as in
  * gs_render_bwd. */
 gs_status gs_render_bwd_adam(gs_params *x, const gs_frame *frame, const gs_raster_cfg *cfg,
                              const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,

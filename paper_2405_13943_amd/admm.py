@@ -224,6 +224,7 @@ class AdmmTrainer:
         self.lambda_ssim = float(lambda_ssim)
         self._dl = self._ssim_ws = None
         self.resid = torch.zeros(10, device=x.device)
+        self.redone = 0          # local steps redone after pair-capacity overflows
         self.history = []        # (t, residual sums, rho after the update) per adaptive consensus
 
     # -- frames ----------------------------------------------------------
@@ -286,7 +287,7 @@ class AdmmTrainer:
             if self.g is None:
                 self.g = torch.empty_like(x)
             gs.render_bwd(x, f, self.cfg, buf, self.g, mode, gin, loss)
-            gs.adam_admm(x, self.g, self.m, self.v, self.w, self.mask, acfg)
+            gs.adam_admm(x, self.g, self.m, self.v, self.w, self.mask, acfg, status=buf)
 
     def consensus(self):
         """z = mean of holders' copies; u += x - z; w = z - u (Eq. 8b-c);
@@ -305,23 +306,45 @@ class AdmmTrainer:
             self.history.append((self.t, res, rho))
 
     def step(self):
-        """Alg. 2: local step for all blocks, then consensus when t mod intv == 0."""
+        """Alg. 2: local step for all blocks, then consensus when t mod intv
+        == 0.  Before a consensus reads x, the device counters are checked
+        once and steps skipped after a pair-capacity overflow are redone, so
+        a consensus never sees a block behind its step count."""
         self.local_step()
         if self.t % self.intv == 0:
+            self.check()
             self.consensus()
         self.t += 1
 
-    def check(self, grow=True):
-        """Read the device counters once; on a pair-capacity overflow grow the
-        buffers (the steps since the last check must be redone by the caller)."""
-        c = gs.read_counters(self.buf)
-        if c["status"] & gs.GS_STATUS_PAIR_OVERFLOW:
-            if grow:
-                self.capacity = int(c["pairs"] * 1.3) + 4096
-                self.buf.grow(self.capacity)
-                self.buf.counters.zero_()
-            return False
-        return True
+    MAX_REGROW = 8
+
+    def check(self):
+        """Read the device counters once.  After a pair-capacity overflow the
+        device skipped the optimiser update of the overflowing step and of
+        every step after it (the status bit is sticky; counters[OVERFLOWED]
+        counts them), so x, m and v are exactly as they were before the
+        first of them.  Grow the pair buffers to what was needed, clear the
+        status and redo those steps (their views follow from the step
+        index).  Returns the number of steps redone."""
+        redone = 0
+        for _ in range(self.MAX_REGROW):
+            c = gs.read_counters(self.buf)
+            if c["status"] & gs.GS_STATUS_NONFINITE:
+                raise FloatingPointError(f"non-finite parameter or optimiser state before step {self.t + 1}")
+            if not c["status"] & gs.GS_STATUS_PAIR_OVERFLOW:
+                return redone
+            skipped = c["overflowed"]
+            self.capacity = max(int(c["pairs"] * 1.3) + 4096, self.buf.capacity)
+            self.buf.grow(self.capacity)
+            self.buf.counters.zero_()
+            t_now = self.t
+            for t in range(t_now - skipped + 1, t_now + 1):
+                self.t = t
+                self.local_step()
+                redone += 1
+                self.redone += 1
+            self.t = t_now
+        raise RuntimeError("pair capacity still overflowing after growing the buffers")
 
     def calibrate(self, headroom=1.3):
         """Size the pair capacity from every view combination once (untimed)."""

@@ -44,4 +44,22 @@ __device__ inline float adam_one(float& x, float g, float& m, float& v, float w,
     return x;
 }
 
+// Non-finite detection for the optimiser: fin += x * 0 + v * 0 stays 0
+// while the updated parameter and second moment are finite, and turns NaN
+// otherwise.  A NaN or Inf in any of x, g, m, v, w (or the mask) reaches the
+// updated x or v through the update above, so checking the two outputs
+// covers every input.
+__device__ inline void adam_finite(float& fin, float x, float v) { fin += x * 0.0f + v * 0.0f; }
+
+// Device status word handed to the optimiser kernels (may be null): the
+// update is skipped while GS_STATUS_PAIR_OVERFLOW is set (a gradient from
+// truncated tile lists must not move the parameters), and
+// GS_STATUS_NONFINITE is OR-ed in when an update meets a NaN or Inf.
+__device__ inline bool adam_skipped(const uint32_t* status) {
+    return status != nullptr && (*status & GS_STATUS_PAIR_OVERFLOW) != 0u;
+}
+__device__ inline void adam_flag(uint32_t* status, float fin) {
+    if (status != nullptr && !(fin == 0.0f)) atomicOr(status, GS_STATUS_NONFINITE);
+}
+
 }  // namespace gs

@@ -80,14 +80,15 @@ gs_status check_bins(const gs_bins* b, const gs_frame* f, const gs_raster_cfg* c
 
 template <typename T>
 gs_status project_impl(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, void* rec,
-                       uint32_t* meta, gs_stream stream) {
+                       uint32_t* meta, uint32_t* status, gs_stream stream) {
     gs_status st;
     if ((st = check_params(params, "params")) != GS_OK) return st;
     if ((st = check_frame(frame, cfg)) != GS_OK) return st;
     if (frame->g_max > params->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
                                               (long long)frame->g_max, (long long)params->n);
     if (frame->n_records > 0 && (!rec || !meta)) return fail(GS_E_INVALID, "null record buffers");
-    return check_hip(gs::launch_project<T>(*params, *frame, *cfg, static_cast<T*>(rec), meta, (hipStream_t)stream),
+    return check_hip(gs::launch_project<T>(*params, *frame, *cfg, static_cast<T*>(rec), meta, status,
+                                           (hipStream_t)stream),
                      "gs_project");
 }
 
@@ -207,13 +208,13 @@ gs_status gs_frame_plan(const gs_camera* cams, int32_t n_cams, gs_job* jobs, int
 }
 
 gs_status gs_project(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, void* rec,
-                     uint32_t* meta, gs_stream stream) {
-    return project_impl<float>(params, frame, cfg, rec, meta, stream);
+                     uint32_t* meta, uint32_t* status, gs_stream stream) {
+    return project_impl<float>(params, frame, cfg, rec, meta, status, stream);
 }
 
 gs_status gs_project_f64(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, void* rec,
-                         uint32_t* meta, gs_stream stream) {
-    return project_impl<double>(params, frame, cfg, rec, meta, stream);
+                         uint32_t* meta, uint32_t* status, gs_stream stream) {
+    return project_impl<double>(params, frame, cfg, rec, meta, status, stream);
 }
 
 size_t gs_bin_sort_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles) {
@@ -306,11 +307,12 @@ gs_status check_adam(const gs_params* x, const gs_params* g, const gs_params* m,
 }  // namespace
 
 gs_status gs_adam_admm(gs_params* x, const gs_params* g, gs_params* m, gs_params* v, const gs_params* w,
-                       const float* mask, const gs_adam_cfg* cfg, gs_stream stream) {
+                       const float* mask, const gs_adam_cfg* cfg, uint32_t* status, gs_stream stream) {
     gs_status st;
     if (!g) return fail(GS_E_INVALID, "g: null gs_params");
     if ((st = check_adam(x, g, m, v, w, mask, cfg)) != GS_OK) return st;
-    return check_hip(gs::launch_adam_admm(*x, *g, *m, *v, w, mask, *cfg, (hipStream_t)stream), "gs_adam_admm");
+    return check_hip(gs::launch_adam_admm(*x, *g, *m, *v, w, mask, *cfg, status, (hipStream_t)stream),
+                     "gs_adam_admm");
 }
 
 gs_status gs_render_bwd_adam(gs_params* x, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,

@@ -77,6 +77,16 @@ size_t bin_workspace_size(int64_t n_records, uint64_t capacity, int32_t n_tiles)
 // ---------------------------------------------------------------------------
 // small helpers
 
+// counters of a frame without records: no visible record, no pair; an
+// uncleared overflow still counts the call (its step's update is skipped)
+__global__ void k_counters_empty(uint32_t* __restrict__ counters) {
+    if (threadIdx.x == 0) {
+        counters[GS_CTR_VISIBLE] = 0u;
+        counters[GS_CTR_PAIRS] = 0u;
+        if (counters[GS_CTR_STATUS] & GS_STATUS_PAIR_OVERFLOW) counters[GS_CTR_OVERFLOWED] += 1u;
+    }
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
         p[i] = v;
@@ -158,6 +168,7 @@ struct RecordScan {       // item i: record i; output: compacted ids and first p
         counters[GS_CTR_VISIBLE] = total.v;
         counters[GS_CTR_PAIRS] = total.p;
         if (uint64_t(total.p) > capacity) counters[GS_CTR_STATUS] |= GS_STATUS_PAIR_OVERFLOW;
+        if (counters[GS_CTR_STATUS] & GS_STATUS_PAIR_OVERFLOW) counters[GS_CTR_OVERFLOWED] += 1u;
     }
 };
 
@@ -735,7 +746,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
                       (cfg.tile_w / 8) * (cfg.tile_h / 8), bins.tile_order);
     };
     if (nrec == 0) {
-        GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(1), dim3(64), 0, s, bins.counters, 0u, int64_t(GS_CTR_STATUS));
+        GS_LAUNCH("k_counters_empty", k_counters_empty, dim3(1), dim3(64), 0, s, bins.counters);
         GS_LAUNCH("k_fill_u32", k_fill_u32, dim3(unsigned(std::min<int64_t>((2 * nt + 255) / 256, 2048))), dim3(256), 0,
                   s, bins.ranges, 0u, 2 * nt);
         plan();

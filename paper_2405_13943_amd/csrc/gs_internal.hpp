@@ -40,7 +40,7 @@ struct KernelTimer {
 // project.hip
 template <typename T>
 hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, T* rec,
-                          uint32_t* meta, hipStream_t s);
+                          uint32_t* meta, uint32_t* status, hipStream_t s);
 template <typename T>
 hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
                               const uint32_t* meta, const gs_bins& bins, const T* pg, gs_params& grad, hipStream_t s);
@@ -79,7 +79,7 @@ void split_group(const double* boxes, int32_t K, double s, int32_t axes, const d
 
 // optim.hip
 hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_params& v, const gs_params* w,
-                            const float* mask, const gs_adam_cfg& cfg, hipStream_t s);
+                            const float* mask, const gs_adam_cfg& cfg, uint32_t* status, hipStream_t s);
 hipError_t launch_consensus(const gs_params& x, gs_params& u, gs_params& w, gs_params& z, const int64_t* hptr,
                             const int64_t* hidx, float relax, float* resid, hipStream_t s);
 hipError_t launch_dual_rescale(gs_params& u, gs_params& w, const gs_params& z, const int64_t* hptr,

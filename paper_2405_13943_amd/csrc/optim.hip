@@ -20,7 +20,8 @@ __global__ __launch_bounds__(256) void k_adam_admm(float* __restrict__ x, const 
                                                     float* __restrict__ m, float* __restrict__ v,
                                                     const float* __restrict__ w, const float* __restrict__ mask,
                                                     int64_t n, int64_t sx, int64_t sg, int64_t sm, int64_t sv,
-                                                    int64_t sw, AdamConsts c) {
+                                                    int64_t sw, AdamConsts c, uint32_t* __restrict__ status) {
+    if (adam_skipped(status)) return;
     const int a = blockIdx.y;
     const int grp = plane_group(a);
     const float lr = c.lr[grp], rho = c.rho[grp];
@@ -47,31 +48,42 @@ __global__ __launch_bounds__(256) void k_adam_admm(float* __restrict__ x, const 
         *reinterpret_cast<float4*>(X + i4) = xv;
         store_stream4(M + i4, mv);
         store_stream4(Vv + i4, vv);
+        float fin = 0.f;
+        adam_finite(fin, xv.x, vv.x);
+        adam_finite(fin, xv.y, vv.y);
+        adam_finite(fin, xv.z, vv.z);
+        adam_finite(fin, xv.w, vv.w);
+        adam_flag(status, fin);
     } else {
+        float fin = 0.f;
         for (int64_t i = i4; i < n && i < i4 + 4; i++) {
             float xs = X[i], ms = M[i], vs = Vv[i];
             const float ws = PEN ? Wp[i] : 0.f;
             const float r = PEN ? rho * (MASK ? mask[i] : 1.f) : 0.f;
             adam_one(xs, G[i], ms, vs, ws, r, lr, c);
             X[i] = xs; M[i] = ms; Vv[i] = vs;
+            adam_finite(fin, xs, vs);
         }
+        adam_flag(status, fin);
     }
 }
 
 template <bool PEN, bool MASK>
 static void adam_launch(bool vec, dim3 grid, hipStream_t s, float* x, const float* g, float* m, float* v,
                         const float* w, const float* mask, int64_t n, int64_t sx, int64_t sg, int64_t sm, int64_t sv,
-                        int64_t sw, const AdamConsts& c) {
+                        int64_t sw, const AdamConsts& c, uint32_t* status) {
     if (vec)
-        GS_LAUNCH("k_adam_admm", (k_adam_admm<PEN, MASK, true>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg, sm, sv, sw, c);
+        GS_LAUNCH("k_adam_admm", (k_adam_admm<PEN, MASK, true>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg,
+                  sm, sv, sw, c, status);
     else
-        GS_LAUNCH("k_adam_admm", (k_adam_admm<PEN, MASK, false>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg, sm, sv, sw, c);
+        GS_LAUNCH("k_adam_admm", (k_adam_admm<PEN, MASK, false>), grid, dim3(256), 0, s, x, g, m, v, w, mask, n, sx, sg,
+                  sm, sv, sw, c, status);
 }
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_params& v, const gs_params* w,
-                            const float* mask, const gs_adam_cfg& cfg, hipStream_t s) {
+                            const float* mask, const gs_adam_cfg& cfg, uint32_t* status, hipStream_t s) {
     const int64_t n = x.n;
     if (n == 0) return hipSuccess;
     const int A = 11 + 3 * (x.sh_degree + 1) * (x.sh_degree + 1);
@@ -87,9 +99,15 @@ hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_p
     float* V = static_cast<float*>(v.data);
     const float* Wd = w ? static_cast<const float*>(w->data) : nullptr;
     const int64_t sw = w ? w->stride : 0;
-    if (w && mask) adam_launch<true, true>(vec, grid, s, X, G, M, V, Wd, mask, n, x.stride, g.stride, m.stride, v.stride, sw, c);
-    else if (w) adam_launch<true, false>(vec, grid, s, X, G, M, V, Wd, mask, n, x.stride, g.stride, m.stride, v.stride, sw, c);
-    else adam_launch<false, false>(vec, grid, s, X, G, M, V, Wd, mask, n, x.stride, g.stride, m.stride, v.stride, sw, c);
+    if (w && mask)
+        adam_launch<true, true>(vec, grid, s, X, G, M, V, Wd, mask, n, x.stride, g.stride, m.stride, v.stride, sw, c,
+                                status);
+    else if (w)
+        adam_launch<true, false>(vec, grid, s, X, G, M, V, Wd, mask, n, x.stride, g.stride, m.stride, v.stride, sw, c,
+                                 status);
+    else
+        adam_launch<false, false>(vec, grid, s, X, G, M, V, Wd, mask, n, x.stride, g.stride, m.stride, v.stride, sw, c,
+                                  status);
     return hipGetLastError();
 }
 

@@ -125,24 +125,37 @@ __device__ inline T plane(const T* __restrict__ P, int64_t stride, int a, int64_
     return P[int64_t(a) * stride + g];
 }
 
+// v * 0 is 0 for finite v and NaN for NaN or +-Inf: a sum of such products
+// stays 0 exactly while every value added is finite
+template <typename T>
+__device__ inline void finite_acc(T& acc, T v) { acc += v * T(0); }
+
 // Returns false when culled by the near plane or the opacity threshold.
+// fin (may be null): every parameter value read is added as v * 0.
 template <typename T>
 __device__ inline bool geometry(const T* __restrict__ P, int64_t stride, int64_t g, const Cam<T>& cam,
-                                const gs_raster_cfg& cfg, Geo<T>& G) {
+                                const gs_raster_cfg& cfg, Geo<T>& G, T* fin = nullptr) {
     using N = Num<T>;
 #pragma unroll
     for (int k = 0; k < 3; k++) G.u[k] = plane(P, stride, k, g);
+    if (fin)
+#pragma unroll
+        for (int k = 0; k < 3; k++) finite_acc(*fin, G.u[k]);
 #pragma unroll
     for (int r = 0; r < 3; r++)
         G.t[r] = cam.R[3 * r] * G.u[0] + cam.R[3 * r + 1] * G.u[1] + cam.R[3 * r + 2] * G.u[2] + cam.t[r];
     if (!(G.t[2] > T(cfg.near_z))) return false;
     const T logit = plane(P, stride, 10, g);
+    if (fin) finite_acc(*fin, logit);
     G.o = T(1) / (T(1) + N::exp(-logit));
     if (G.o < T(cfg.alpha_min)) return false;
 
     T q[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) q[k] = plane(P, stride, 3 + k, g);
+    if (fin)
+#pragma unroll
+        for (int k = 0; k < 4; k++) finite_acc(*fin, q[k]);
     G.qinv = N::rsqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
 #pragma unroll
     for (int k = 0; k < 4; k++) G.qn[k] = q[k] * G.qinv;
@@ -151,7 +164,11 @@ __device__ inline bool geometry(const T* __restrict__ P, int64_t stride, int64_t
     G.R[3] = T(2) * (x * y + w * z); G.R[4] = T(1) - T(2) * (x * x + z * z); G.R[5] = T(2) * (y * z - w * x);
     G.R[6] = T(2) * (x * z - w * y); G.R[7] = T(2) * (y * z + w * x); G.R[8] = T(1) - T(2) * (x * x + y * y);
 #pragma unroll
-    for (int k = 0; k < 3; k++) G.s[k] = N::exp(plane(P, stride, 7 + k, g));
+    for (int k = 0; k < 3; k++) {
+        const T ls = plane(P, stride, 7 + k, g);
+        if (fin) finite_acc(*fin, ls);
+        G.s[k] = N::exp(ls);
+    }
     // Sigma = R diag(s^2) R^T
     T M[9];
 #pragma unroll
@@ -217,10 +234,18 @@ __device__ inline T view_dir(const Geo<T>& G, const Cam<T>& cam, T* dir) {
 // ---------------------------------------------------------------------------
 // forward
 
+// status (may be null): GS_STATUS_NONFINITE is OR-ed in when a parameter value
+// the projection reads is NaN or Inf (the mean of every Gaussian; the rest
+// of those that pass the near plane; the SH planes of those on screen)
+template <typename T>
+__device__ inline void flag_nonfinite(uint32_t* status, T fin) {
+    if (status && !(fin == T(0))) atomicOr(status, GS_STATUS_NONFINITE);
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_t stride, gs_frame frame,
                                                   gs_raster_cfg cfg, T* __restrict__ rec,
-                                                  uint4* __restrict__ meta) {
+                                                  uint4* __restrict__ meta, uint32_t* __restrict__ status) {
     constexpr int NK = (D + 1) * (D + 1);
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= frame.n_records) return;
@@ -231,7 +256,12 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     load_cam(frame.cams[job.cam], cam);
     Geo<T> G;
     uint4 m = make_uint4(0xffffffffu, 0u, 0u, 0u);
-    if (!geometry(P, stride, g, cam, cfg, G)) { meta[r] = m; return; }
+    T fin = T(0);
+    if (!geometry(P, stride, g, cam, cfg, G, &fin)) {
+        meta[r] = m;
+        flag_nonfinite(status, fin);
+        return;
+    }
 
     // conservative pixel rectangle of {alpha >= alpha_min}: the ellipse
     // d^T A d <= 2 ln(o / alpha_min) has half-extents sqrt(thr * Sigma'_xx), ...
@@ -245,7 +275,11 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     y0 = y0 < T(0) ? T(0) : y0;
     x1 = x1 > T(cam.W - 1) ? T(cam.W - 1) : x1;
     y1 = y1 > T(cam.H - 1) ? T(cam.H - 1) : y1;
-    if (!(x0 <= x1 && y0 <= y1)) { meta[r] = m; return; }
+    if (!(x0 <= x1 && y0 <= y1)) {
+        meta[r] = m;
+        flag_nonfinite(status, fin);
+        return;
+    }
     const int tx0 = int(x0) / cfg.tile_w, tx1 = int(x1) / cfg.tile_w;
     const int ty0 = int(y0) / cfg.tile_h, ty1 = int(y1) / cfg.tile_h;
 
@@ -262,7 +296,11 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     for (int ch = 0; ch < 3; ch++) {
         T s = 0;
 #pragma unroll
-        for (int k = 0; k < NK; k++) s += Y[k] * __builtin_nontemporal_load(P + int64_t(11 + 3 * k + ch) * stride + g);
+        for (int k = 0; k < NK; k++) {
+            const T f = __builtin_nontemporal_load(P + int64_t(11 + 3 * k + ch) * stride + g);
+            finite_acc(fin, f);
+            s += Y[k] * f;
+        }
         s += T(0.5);
         col[ch] = s > T(0) ? s : T(0);
         clamp |= s > T(0) ? 0u : (1u << ch);
@@ -286,6 +324,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     m.z = uint32_t(tx0) | (uint32_t(ty0) << 16);
     m.w = uint32_t(tx1) | (uint32_t(ty1) << 16);
     meta[r] = m;
+    flag_nonfinite(status, fin);
 }
 
 // ---------------------------------------------------------------------------
@@ -589,7 +628,7 @@ template <int A, bool PEN, bool MASK>
 __device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* __restrict__ M, int64_t sm,
                                       float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
                                       const float* __restrict__ mask, int64_t g0, const float* geo, const float* Y,
-                                      const float* dc, const AdamConsts& c) {
+                                      const float* dc, const AdamConsts& c, float& fin) {
     constexpr int kCols = kFusedBlock / 4;
     const int t = threadIdx.x;
     const int col = t % kCols;
@@ -621,6 +660,10 @@ __device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* 
         *reinterpret_cast<float4*>(X + a * sx + gv) = xv;
         store_stream4(M + a * sm + gv, mv);
         store_stream4(V + a * sv + gv, vv);
+        adam_finite(fin, xv.x, vv.x);
+        adam_finite(fin, xv.y, vv.y);
+        adam_finite(fin, xv.z, vv.z);
+        adam_finite(fin, xv.w, vv.w);
     }
 }
 
@@ -629,7 +672,7 @@ template <int A, bool PEN, bool MASK>
 __device__ inline void adam_block_one(float* __restrict__ X, int64_t sx, float* __restrict__ M, int64_t sm,
                                       float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
                                       const float* __restrict__ mask, int64_t g, int i, const float* geo,
-                                      const float* Y, const float* dc, const AdamConsts& c) {
+                                      const float* Y, const float* dc, const AdamConsts& c, float& fin) {
     const float k = MASK ? mask[g] : 1.f;
     for (int a = 0; a < A; a++) {
         const int grp = plane_group(a);
@@ -639,6 +682,7 @@ __device__ inline void adam_block_one(float* __restrict__ X, int64_t sx, float* 
         X[a * sx + g] = xv;
         M[a * sm + g] = mv;
         V[a * sv + g] = vv;
+        adam_finite(fin, xv, vv);
     }
 }
 
@@ -648,9 +692,10 @@ __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     const uint32_t* __restrict__ pair_off, uint64_t capacity, PartialLayout L, const float* __restrict__ pg,
     float* __restrict__ M,
     int64_t sm, float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
-    const float* __restrict__ mask, AdamConsts c) {
+    const float* __restrict__ mask, AdamConsts c, uint32_t* __restrict__ status) {
     constexpr int NK = (D + 1) * (D + 1);
     constexpr int A = 11 + 3 * NK;
+    if (adam_skipped(status)) return;   // uniform over the grid: no wavefront reaches the barrier
     __shared__ __align__(16) float s_geo[11][kFusedBlock];
     __shared__ __align__(16) float s_Y[NK][kFusedBlock];
     __shared__ __align__(16) float s_dc[3][kFusedBlock];
@@ -689,11 +734,14 @@ __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     const bool contiguous = __syncthreads_and(active && j == j0) != 0;
 
     // phase 2: optimiser over the planes
+    float fin = 0.f;
     if (VEC && contiguous && (g0 & 3) == 0)
-        adam_block_vec<A, PEN, MASK>(X, sx, M, sm, V, sv, Wp, sw, mask, g0, &s_geo[0][0], &s_Y[0][0], &s_dc[0][0], c);
+        adam_block_vec<A, PEN, MASK>(X, sx, M, sm, V, sv, Wp, sw, mask, g0, &s_geo[0][0], &s_Y[0][0], &s_dc[0][0], c,
+                                     fin);
     else if (active)
         adam_block_one<A, PEN, MASK>(X, sx, M, sm, V, sv, Wp, sw, mask, g, t, &s_geo[0][0], &s_Y[0][0], &s_dc[0][0],
-                                     c);
+                                     c, fin);
+    adam_flag(status, fin);
 }
 
 // Adam/ADMM with a zero gradient for Gaussians outside every job (disjoint
@@ -703,12 +751,14 @@ __global__ __launch_bounds__(256) void k_adam_uncovered(int64_t n, gs_frame fram
                                                         int64_t sx, float* __restrict__ M, int64_t sm,
                                                         float* __restrict__ V, int64_t sv,
                                                         const float* __restrict__ Wp, int64_t sw,
-                                                        const float* __restrict__ mask, AdamConsts c) {
+                                                        const float* __restrict__ mask, AdamConsts c,
+                                                        uint32_t* __restrict__ status) {
     const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= n) return;
+    if (g >= n || adam_skipped(status)) return;
     for (int j = 0; j < frame.n_jobs; j++)
         if (g >= frame.jobs[j].g0 && g < frame.jobs[j].g1) return;
     const float k = MASK ? mask[g] : 1.f;
+    float fin = 0.f;
     for (int a = 0; a < A; a++) {
         const int grp = plane_group(a);
         float xv = X[a * sx + g], mv = M[a * sm + g], vv = V[a * sv + g];
@@ -717,7 +767,9 @@ __global__ __launch_bounds__(256) void k_adam_uncovered(int64_t n, gs_frame fram
         X[a * sx + g] = xv;
         M[a * sm + g] = mv;
         V[a * sv + g] = vv;
+        adam_finite(fin, xv, vv);
     }
+    adam_flag(status, fin);
 }
 
 // zeros for Gaussians outside every job (disjoint jobs that do not cover [0, n))
@@ -735,17 +787,17 @@ __global__ __launch_bounds__(256) void k_zero_uncovered(int64_t n, gs_frame fram
 
 template <typename T>
 hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, T* rec,
-                          uint32_t* meta, hipStream_t s) {
+                          uint32_t* meta, uint32_t* status, hipStream_t s) {
     const int64_t n = f.n_records;
     if (n == 0) return hipSuccess;
     dim3 grid(unsigned((n + 255) / 256)), block(256);
     const T* P = static_cast<const T*>(p.data);
     uint4* M = reinterpret_cast<uint4*>(meta);
     switch (p.sh_degree) {
-        case 0: GS_LAUNCH("k_project", (k_project<T, 0>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
-        case 1: GS_LAUNCH("k_project", (k_project<T, 1>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
-        case 2: GS_LAUNCH("k_project", (k_project<T, 2>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
-        default: GS_LAUNCH("k_project", (k_project<T, 3>), grid, block, 0, s, P, p.stride, f, cfg, rec, M); break;
+        case 0: GS_LAUNCH("k_project", (k_project<T, 0>), grid, block, 0, s, P, p.stride, f, cfg, rec, M, status); break;
+        case 1: GS_LAUNCH("k_project", (k_project<T, 1>), grid, block, 0, s, P, p.stride, f, cfg, rec, M, status); break;
+        case 2: GS_LAUNCH("k_project", (k_project<T, 2>), grid, block, 0, s, P, p.stride, f, cfg, rec, M, status); break;
+        default: GS_LAUNCH("k_project", (k_project<T, 3>), grid, block, 0, s, P, p.stride, f, cfg, rec, M, status); break;
     }
     return hipGetLastError();
 }
@@ -800,7 +852,7 @@ template <int D, bool PEN, bool MASK>
 static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
                                     const uint32_t* pair_off, uint64_t capacity, const PartialLayout& L,
                                     const float* pg, gs_params& m, gs_params& v, const gs_params* w,
-                                    const float* mask, const AdamConsts& c, hipStream_t s) {
+                                    const float* mask, const AdamConsts& c, uint32_t* status, hipStream_t s) {
     float* X = static_cast<float*>(x.data);
     float* Mo = static_cast<float*>(m.data);
     float* Vo = static_cast<float*>(v.data);
@@ -809,27 +861,28 @@ static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_ra
     const bool covers = f.n_records == x.n && f.g_max == x.n;
     if (!covers)
         GS_LAUNCH("k_adam_uncovered", (k_adam_uncovered<PEN, MASK>), dim3(unsigned((x.n + 255) / 256)), dim3(256), 0, s, x.n, f,
-                           11 + 3 * (D + 1) * (D + 1), X, x.stride, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+                           11 + 3 * (D + 1) * (D + 1), X, x.stride, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c,
+                           status);
     const bool vec = aligned16(X) && aligned16(Mo) && aligned16(Vo) && (!Wd || aligned16(Wd)) &&
                      (!mask || aligned16(mask)) && x.stride % 4 == 0 && m.stride % 4 == 0 && v.stride % 4 == 0 &&
                      sw % 4 == 0;
     const dim3 grid(unsigned((f.n_records + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
     if (f.n_records > 0 && vec)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, true>), grid, block, 0, s, X, x.stride, f,
-                  cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+                  cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c, status);
     else if (f.n_records > 0)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, false>), grid, block, 0, s, X, x.stride,
-                  f, cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c);
+                  f, cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c, status);
 }
 
 template <int D>
 static void project_bwd_adam_pen(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
                                  const uint32_t* po, uint64_t cap, const PartialLayout& L, const float* pg,
                                  gs_params& m, gs_params& v, const gs_params* w, const float* mask,
-                                 const AdamConsts& c, hipStream_t s) {
-    if (w && mask) project_bwd_adam_launch<D, true, true>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s);
-    else if (w) project_bwd_adam_launch<D, true, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s);
-    else project_bwd_adam_launch<D, false, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s);
+                                 const AdamConsts& c, uint32_t* st, hipStream_t s) {
+    if (w && mask) project_bwd_adam_launch<D, true, true>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s);
+    else if (w) project_bwd_adam_launch<D, true, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s);
+    else project_bwd_adam_launch<D, false, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s);
 }
 
 hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta,
@@ -841,17 +894,18 @@ hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_ras
     const PartialLayout L = partial_layout(cfg, bins, pg);
     const uint32_t* po = bins.pair_off;
     const uint64_t cap = bins.capacity;
+    uint32_t* st = bins.counters + GS_CTR_STATUS;
     switch (x.sh_degree) {
-        case 0: project_bwd_adam_pen<0>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
-        case 1: project_bwd_adam_pen<1>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
-        case 2: project_bwd_adam_pen<2>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
-        default: project_bwd_adam_pen<3>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, s); break;
+        case 0: project_bwd_adam_pen<0>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
+        case 1: project_bwd_adam_pen<1>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
+        case 2: project_bwd_adam_pen<2>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
+        default: project_bwd_adam_pen<3>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
     }
     return hipGetLastError();
 }
 
-template hipError_t launch_project<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, float*, uint32_t*, hipStream_t);
-template hipError_t launch_project<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, double*, uint32_t*, hipStream_t);
+template hipError_t launch_project<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, float*, uint32_t*, uint32_t*, hipStream_t);
+template hipError_t launch_project<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, double*, uint32_t*, uint32_t*, hipStream_t);
 template hipError_t launch_project_bwd<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const gs_bins&, const float*, gs_params&, hipStream_t);
 template hipError_t launch_project_bwd<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const gs_bins&, const double*, gs_params&, hipStream_t);
 

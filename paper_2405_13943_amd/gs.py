@@ -22,9 +22,9 @@ from . import build as _build
 c_f, c_i32, c_i64, c_u64, c_vp = ctypes.c_float, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
 
 GS_OK, GS_E_INVALID, GS_E_CAPACITY, GS_E_DEVICE, GS_E_UNSUPPORTED = range(5)
-GS_STATUS_PAIR_OVERFLOW = 1
+GS_STATUS_PAIR_OVERFLOW, GS_STATUS_NONFINITE = 1, 2
 GS_WAVES_ADAPTIVE = -1
-CTR_VISIBLE, CTR_PAIRS, CTR_STATUS, N_COUNTERS = 0, 1, 2, 4
+CTR_VISIBLE, CTR_PAIRS, CTR_STATUS, CTR_OVERFLOWED, N_COUNTERS = 0, 1, 2, 3, 4
 LOSS_L1, LOSS_EXTERNAL = 0, 1
 REC_WORDS, META_WORDS = 12, 4
 MEAN_PLANE = 0            # the three mean planes lead the parameter layout
@@ -81,8 +81,8 @@ def _load():
         "gs_raster_cfg_default": ([P(GsRasterCfg)], None),
         "gs_frame_plan": ([P(GsCamera), c_i32, P(GsJob), c_i32, P(GsRasterCfg), P(c_i64), P(c_i64), P(c_i32),
                            P(c_i64), P(c_i32)], c_i32),
-        "gs_project": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_vp], c_i32),
-        "gs_project_f64": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_vp], c_i32),
+        "gs_project": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_vp, c_vp], c_i32),
+        "gs_project_f64": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_bin_sort_workspace_size": ([c_i64, c_u64, c_i32], ctypes.c_size_t),
         "gs_bin_sort": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, ctypes.c_size_t, c_vp], c_i32),
         "gs_render_fwd": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp], c_i32),
@@ -94,7 +94,7 @@ def _load():
         "gs_render_bwd_f64": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_i32, c_vp,
                                c_vp, P(GsParams), c_vp, ctypes.c_size_t, c_vp], c_i32),
         "gs_adam_admm": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg),
-                          c_vp], c_i32),
+                          c_vp, c_vp], c_i32),
         "gs_render_bwd_adam": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_i32, c_vp,
                                 c_vp, P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg), c_vp,
                                 ctypes.c_size_t, c_vp], c_i32),
@@ -273,11 +273,18 @@ class Buffers:
 # ---------------------------------------------------------------------------
 # entry points
 
+def status_ptr(buf):
+    """Device address of a buffer's status word (its counters[CTR_STATUS])."""
+    return c_vp(buf.counters.data_ptr() + 4 * CTR_STATUS)
+
+
 def project(params: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffers):
+    """Projection into buf's records; non-finite parameters it reads set
+    GS_STATUS_NONFINITE in buf's status word."""
     p = params_struct(params)
     fn = lib.gs_project_f64 if params.dtype == torch.float64 else lib.gs_project
     _check(fn(ctypes.byref(p), ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.rec), _ptr(buf.meta),
-              _stream()), "gs_project")
+              status_ptr(buf), _stream()), "gs_project")
 
 
 def bin_sort(frame: Frame, cfg: GsRasterCfg, buf: Buffers):
@@ -389,11 +396,14 @@ def adam_cfg(lr, rho, step, beta1=0.9, beta2=0.999, eps=1e-8) -> GsAdamCfg:
     return c
 
 
-def adam_admm(x, g, m, v, w=None, mask=None, cfg: GsAdamCfg = None):
+def adam_admm(x, g, m, v, w=None, mask=None, cfg: GsAdamCfg = None, status: Buffers = None):
+    """status: a Buffers whose status word gates the update (skipped after a
+    pair overflow) and receives GS_STATUS_NONFINITE; None: no status."""
     px, pg, pm, pv = (params_struct(t) for t in (x, g, m, v))
     pw = params_struct(w) if w is not None else None
     _check(lib.gs_adam_admm(ctypes.byref(px), ctypes.byref(pg), ctypes.byref(pm), ctypes.byref(pv),
-                            ctypes.byref(pw) if pw is not None else None, _ptr(mask), ctypes.byref(cfg), _stream()),
+                            ctypes.byref(pw) if pw is not None else None, _ptr(mask), ctypes.byref(cfg),
+                            status_ptr(status) if status is not None else None, _stream()),
            "gs_adam_admm")
 
 
@@ -442,7 +452,8 @@ def dual_rescale(u, w, z, holder_ptr, holder_idx, scale):
 
 def read_counters(buf: Buffers):
     c = buf.counters.cpu().numpy().astype(np.uint32)
-    return {"visible": int(c[CTR_VISIBLE]), "pairs": int(c[CTR_PAIRS]), "status": int(c[CTR_STATUS])}
+    return {"visible": int(c[CTR_VISIBLE]), "pairs": int(c[CTR_PAIRS]), "status": int(c[CTR_STATUS]),
+            "overflowed": int(c[CTR_OVERFLOWED])}
 
 
 def rasterize(params: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffers = None, capacity=None):

@@ -41,6 +41,7 @@ class Request:
     started: float = None
     done: float = None
     image: torch.Tensor = None        # pinned host [3][H][W] FP32
+    tries: int = 0                    # launches that overflowed the pair budget
 
     @property
     def pixels(self):
@@ -63,12 +64,22 @@ class Arena:
         self.rgb = torch.empty(max_pixels * 3, dtype=torch.float32, device=device)
         self.T = torch.empty(max_pixels, dtype=torch.float32, device=device)
         self.ncontrib = torch.empty(max_pixels, dtype=torch.int32, device=device)
-        self.vals = torch.empty(capacity, dtype=torch.int32, device=device)
-        nb = gs.lib.gs_bin_sort_workspace_size(R, capacity, max_tiles)
-        self.bin_ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        self._alloc_pairs(capacity)
         self.counters_host = torch.zeros(gs.N_COUNTERS, dtype=torch.int32).pin_memory()
         self.f64 = False
         self.frame = None
+
+    def _alloc_pairs(self, capacity):
+        self.capacity = int(capacity)
+        self.vals = torch.empty(self.capacity, dtype=torch.int32, device=self.rec.device)
+        nb = gs.lib.gs_bin_sort_workspace_size(self.n_gauss * self.max_jobs, self.capacity, self.max_tiles)
+        self.bin_ws = torch.empty(nb, dtype=torch.uint8, device=self.rec.device)
+
+    def grow_pairs(self, capacity):
+        """Reallocate the pair buffers for a larger capacity (only while the
+        slot is idle: its last batch has completed)."""
+        if capacity > self.capacity:
+            self._alloc_pairs(capacity)
 
     def nbytes(self):
         return sum(t.numel() * t.element_size() for t in (self.rec, self.meta, self.pair_off, self.ranges,
@@ -98,6 +109,8 @@ class Slot:
 
 
 class RenderServer:
+    MAX_TRIES = 4      # overflowing launches of one request before the server gives up
+
     def __init__(self, params: torch.Tensor, cfg: gs.GsRasterCfg, hbm_budget: float = 32e9, n_slots: int = 3,
                  max_batch: int = 16, resolutions=None, pair_headroom: float = 1.5, spatial_order: bool = True):
         """params: global model [A][G] resident on the GPU.  The HBM budget
@@ -131,6 +144,8 @@ class RenderServer:
         self.queue = []
         self.finished = []
         self.retries = 0
+        self.largest_batch = 0        # most requests in one launched batch
+        self.most_in_flight = 0       # most slots holding a batch at one time
         self.pool = {}
         # pre-fill the pinned pool for requests in flight (it grows on demand)
         for w, h in self.resolutions:
@@ -192,15 +207,24 @@ class RenderServer:
         for r in batch:
             r.started = now
         slot.batch, slot.event, slot.frame = batch, ev, f
+        self.largest_batch = max(self.largest_batch, len(batch))
+        self.most_in_flight = max(self.most_in_flight, sum(s.batch is not None for s in self.slots))
 
     def _admit(self, slot: Slot):
-        """Greedy admission of waiting requests into the slot's arena."""
+        """Greedy admission of waiting requests into the slot's arena.  A
+        request whose pair estimate alone exceeds the arena (the estimate
+        grows after an overflow) gets the arena's pair buffers grown for it
+        and is launched alone."""
         a = slot.arena
         batch, px = [], 0
         for r in self.queue:
-            if len(batch) >= self.max_batch:
+            if len(batch) >= self.max_batch or px + r.pixels > a.max_pixels:
                 break
-            if px + r.pixels > a.max_pixels or self.pairs_per_px * (px + r.pixels) > a.capacity:
+            if self.pairs_per_px * (px + r.pixels) > a.capacity:
+                if batch:
+                    break
+                a.grow_pairs(int(self.pairs_per_px * r.pixels) + 4096)
+                batch.append(r)
                 break
             batch.append(r)
             px += r.pixels
@@ -213,8 +237,20 @@ class RenderServer:
             if s.batch is not None and s.event.query():
                 st = int(s.arena.counters_host[gs.CTR_STATUS].item())
                 if st & gs.GS_STATUS_PAIR_OVERFLOW:
-                    # more pairs than budgeted: put the batch back in front
+                    # more pairs than budgeted: raise the pairs-per-pixel
+                    # estimate to what this batch needed, so that admission
+                    # makes the batch smaller (or grows the arena for a
+                    # single request), and put the batch back in front
                     self.retries += 1
+                    need = int(s.arena.counters_host[gs.CTR_PAIRS].item()) & 0xFFFFFFFF
+                    px = sum(r.pixels for r in s.batch)
+                    self.pairs_per_px = max(self.pairs_per_px, 1.1 * need / px)
+                    for r in s.batch:
+                        self.release(r)
+                        r.tries += 1
+                        if r.tries > self.MAX_TRIES:
+                            raise RuntimeError(f"request {r.rid} overflowed its pair budget {r.tries} times "
+                                               f"({need} pairs needed)")
                     self.queue[:0] = s.batch
                 else:
                     t = time.perf_counter()
@@ -264,7 +300,8 @@ class RenderServer:
         return {"requests": len(meas), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "frames_per_s": len(meas) / span, "mpx_per_s": px / span / 1e6,
                 "wall_s": t_end - t0, "retries": self.retries, "max_batch": self.max_batch,
-                "slots": len(self.slots)}, reqs
+                "slots": len(self.slots), "largest_batch": self.largest_batch,
+                "most_in_flight": self.most_in_flight}, reqs
 
     def render_alone(self, cam):
         """Render one view by itself (reference for the batching check)."""

@@ -104,23 +104,23 @@ def test_invalid_arguments_rejected_without_launch(gs):
     cfg = gs.raster_cfg()
     f = gs.GsFrame()
     bad = gs.GsParams(None, -1, 0, 0, 0)
-    assert gs.lib.gs_project(ctypes.byref(bad), ctypes.byref(f), ctypes.byref(cfg), None, None, None) == gs.GS_E_INVALID
+    assert gs.lib.gs_project(ctypes.byref(bad), ctypes.byref(f), ctypes.byref(cfg), None, None, None, None) == gs.GS_E_INVALID
     assert "negative" in gs.lib.gs_last_error().decode()
     deg4 = gs.GsParams(None, 0, 0, 4, 0)
-    assert gs.lib.gs_project(ctypes.byref(deg4), ctypes.byref(f), ctypes.byref(cfg), None, None, None) == gs.GS_E_INVALID
+    assert gs.lib.gs_project(ctypes.byref(deg4), ctypes.byref(f), ctypes.byref(cfg), None, None, None, None) == gs.GS_E_INVALID
     cfg_bad = gs.raster_cfg((12, 12))
     ok = gs.GsParams(None, 0, 0, 0, 0)
-    assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(cfg_bad), None, None, None) == gs.GS_E_INVALID
+    assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(cfg_bad), None, None, None, None) == gs.GS_E_INVALID
     for tile in [(8, 8, 2), (16, 8, 4), (16, 16, 3), (32, 8, 8), (16, 16, 2, 3), (8, 8, 1, 2), (16, 16, 2, -2)]:
         c = gs.raster_cfg(tile)
-        assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None) == gs.GS_E_INVALID
+        assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None, None) == gs.GS_E_INVALID
     for tile in [(16, 16, 4), (32, 8, 2), (16, 8, 2), (16, 16, 2, 1), (32, 8, 4, 2), (16, 16, 2, -1), (8, 8, -1, -1)]:
         c = gs.raster_cfg(tile)
-        assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None) == gs.GS_OK
+        assert gs.lib.gs_project(ctypes.byref(ok), ctypes.byref(f), ctypes.byref(c), None, None, None, None) == gs.GS_OK
     # jobs reaching past the parameter planes
     f2 = gs.GsFrame(1, 1, 1, 1, 10, 10, 11, 1, 0)
     p10 = gs.GsParams(1, 10, 10, 0, 0)
-    assert gs.lib.gs_project(ctypes.byref(p10), ctypes.byref(f2), ctypes.byref(cfg), 1, 1, None) == gs.GS_E_INVALID
+    assert gs.lib.gs_project(ctypes.byref(p10), ctypes.byref(f2), ctypes.byref(cfg), 1, 1, None, None) == gs.GS_E_INVALID
     # backward workspace too small
     bins = gs.GsBins(1, 1, 1, 1, 1000, 1)
     rc = gs.lib.gs_render_bwd(ctypes.byref(p10), ctypes.byref(gs.GsFrame(1, 1, 1, 1, 10, 10, 10, 1, 0)), ctypes.byref(cfg),
@@ -131,10 +131,10 @@ def test_invalid_arguments_rejected_without_launch(gs):
     b = gs.GsParams(1, 11, 11, 0, 0)
     acfg = gs.adam_cfg([1e-3] * 5, [0] * 5, 1)
     assert gs.lib.gs_adam_admm(ctypes.byref(a), ctypes.byref(b), ctypes.byref(a), ctypes.byref(a), None, None,
-                               ctypes.byref(acfg), None) == gs.GS_E_INVALID
+                               ctypes.byref(acfg), None, None) == gs.GS_E_INVALID
     acfg0 = gs.adam_cfg([1e-3] * 5, [0] * 5, 0)
     assert gs.lib.gs_adam_admm(ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), None, None,
-                               ctypes.byref(acfg0), None) == gs.GS_E_INVALID
+                               ctypes.byref(acfg0), None, None) == gs.GS_E_INVALID
     # consensus relaxation outside (0, 2)
     assert gs.lib.gs_consensus(ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), ctypes.byref(a), 1, 1,
                                2.5, None, None) == gs.GS_E_INVALID

@@ -162,7 +162,7 @@ def test_trainer_loop_invariants_and_penalty():
             np.testing.assert_allclose(u[:, hs].mean(axis=1), 0, atol=1e-6)
             np.testing.assert_allclose(w[:, hs], z[:, gid:gid + 1] - u[:, hs], atol=1e-6)
         spread[rho] = np.mean([np.abs(x[:, idx[ptr[g]:ptr[g + 1]]] - z[:, g:g + 1]).max() for g in shared])
-        assert tr.check()
+        assert tr.check() == 0
     assert spread[1.0] < spread[0.0]
 
 
@@ -288,7 +288,7 @@ def test_trainer_on_alg1_blocks():
         assert torch.equal(f.image(buf.rgb, k), fk.image(bk.rgb, 0))
     for _ in range(5):
         tr.step()
-    assert tr.check()
+    assert tr.check() == 0
     idx = model.holder_idx.cpu().numpy()
     u = tr.u.cpu().numpy().astype(np.float64)
     x = model.x.cpu().numpy().astype(np.float64)

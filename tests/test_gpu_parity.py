@@ -300,10 +300,12 @@ def test_render_bwd_sub_tile_waves_match_oracle(cfg1, ref1, tile):
 
 @pytest.mark.parametrize("tile", [(16, 16), (16, 16, -1), (32, 8, -1), (8, 8, -1)])
 def test_l1_loss_mode(cfg1, tile):
-    """GS_LOSS_L1 equals the external mode fed sign(C - target) * w / (3HW),
-    and the loss is w * mean |C - target| per job: with one wavefront per
-    tile, and with the wavefronts from the plan (whose workgroups mix tiles
-    of the four jobs and add their sums per job)."""
+    """GS_LOSS_L1 equals the external mode fed the oracle's dL/dC of the
+    L1 part of Eq. 3 (w sign(C - target) / 3HW on the GPU's own image), and
+    the fused loss equals the oracle's w mean |C - target| per job: with one
+    wavefront per tile, and with the wavefronts from the plan (whose
+    workgroups mix tiles of the four jobs and add their sums per job)."""
+    from oracle.raster import l1_loss_and_grad
     cfg = gs.raster_cfg(tile)
     frame = make_frame(cfg1, cfg)
     params = torch.from_numpy(cfg1.params).cuda()
@@ -312,14 +314,14 @@ def test_l1_loss_mode(cfg1, tile):
     loss = torch.zeros(4, dtype=torch.float32, device="cuda")
     g1 = torch.empty_like(params)
     gs.render_bwd(params, frame, cfg, buf, g1, gs.LOSS_L1, target, loss)
-    d = buf.rgb - target
     n = 3 * 128 * 128
-    dl = 0.25 * torch.sign(d) / n
+    rgb, tg = buf.rgb.cpu().numpy(), target.cpu().numpy()
+    ref = [l1_loss_and_grad(rgb[i * n:(i + 1) * n], tg[i * n:(i + 1) * n], 0.25) for i in range(4)]
+    dl = torch.from_numpy(np.concatenate([r[1] for r in ref]).astype(np.float32)).cuda()
     g2 = torch.empty_like(params)
     gs.render_bwd(params, frame, cfg, buf, g2, gs.LOSS_EXTERNAL, dl)
     torch.testing.assert_close(g1, g2, rtol=1e-6, atol=1e-12)
-    want = [0.25 * d[i * n:(i + 1) * n].abs().mean().item() for i in range(4)]
-    np.testing.assert_allclose(loss.cpu().numpy(), want, rtol=1e-5)
+    np.testing.assert_allclose(loss.cpu().numpy(), [r[0] for r in ref], rtol=1e-5)
 
 
 def _adam_bounds(x, g, m, v, w, lr, rho, step, mask, b1, b2, eps):

@@ -46,6 +46,9 @@ def test_mixed_batches_equal_alone_and_all_complete():
     assert srv.idle()
     batched = [r for r in reqs if r.started is not None]
     assert len(batched) == n
+    # continuous batching, not a serial queue: some launch held several
+    # requests and several slots were on the GPU at once
+    assert stats["largest_batch"] > 1 and stats["most_in_flight"] > 1, stats
     for rid in keep:
         alone = srv.render_alone(cams[rid])
         assert torch.equal(srv.kept[rid], alone), rid
@@ -94,3 +97,25 @@ def test_spatial_order_serves_the_same_images():
             err = np.abs(img - ref["rgb"])
             bad = (err > 1e-4 * np.abs(ref["rgb"]) + 1e-6) & ok[None]
             assert not bad.any(), f"{bad.sum()} pixel-channels off"
+
+
+def test_pair_overflow_is_retried_and_completes():
+    """A pair budget far below what the views need (calibration headroom
+    0.05): batches overflow on the device, the server raises its
+    pairs-per-pixel estimate, re-admits smaller batches (growing an arena
+    for a request that alone exceeds it) and every request completes with
+    the image it has alone."""
+    params = small_model()
+    cfg = gs.raster_cfg((16, 16))
+    srv = serve.RenderServer(params, cfg, hbm_budget=2e9, n_slots=2, max_batch=4, resolutions=RES,
+                             pair_headroom=0.05)
+    n = 24
+    cams = requests(n, 13)
+    arrivals = np.linspace(0.0, 0.005, n)
+    keep = list(range(n))
+    stats, reqs = srv.run_open_loop(cams, arrivals, keep=keep)
+    assert stats["requests"] == n and all(r.done is not None for r in reqs)
+    assert stats["retries"] >= 1
+    assert all(r.tries <= srv.MAX_TRIES for r in reqs)
+    for rid in keep:
+        assert torch.equal(srv.kept[rid], srv.render_alone(cams[rid])), rid

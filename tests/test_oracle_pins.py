@@ -341,3 +341,44 @@ def test_listed_pixels_equal_full_render():
     part = oracle.render(s.params, s.cams[3], pixels=pix)
     np.testing.assert_array_equal(part["rgb"], full["rgb"].reshape(3, -1)[:, pix])
     np.testing.assert_array_equal(part["n"], full["n"].ravel()[pix])
+
+
+def test_l1_loss_worked_example():
+    """L1 part of Eq. 3 on a hand-worked 3 x 1 x 2 image: C - target =
+    [[0.1, -0.2], [0, 0.3], [-0.5, 0]], so sum |d| = 1.1 over 3HW = 6 values:
+    L = w 1.1 / 6 and dL/dC = w sign(d) / 6 (sign(0) = 0)."""
+    from oracle.raster import l1_loss_and_grad
+    C = np.array([[[0.5, 0.2]], [[0.1, 0.9]], [[0.3, 0.3]]])
+    t = np.array([[[0.4, 0.4]], [[0.1, 0.6]], [[0.8, 0.3]]])
+    for w in (1.0, 0.25):
+        L, g = l1_loss_and_grad(C, t, w)
+        assert abs(L - w * 1.1 / 6) < 1e-15
+        want = w * np.array([[[1, -1]], [[0, 1]], [[-1, 0]]]) / 6
+        np.testing.assert_array_equal(g, want)
+
+
+def test_l1_loss_against_autograd_and_differences():
+    """The oracle's L1 loss and gradient against torch autograd of
+    w * mean |C - target| (an independent reverse mode; its |.| has zero
+    gradient at 0 as well), and against central differences away from the
+    kinks, on a 3 x 7 x 5 image with exact zeros in C - target."""
+    torch = pytest.importorskip("torch")
+    from oracle.raster import l1_loss_and_grad
+    r = np.random.default_rng(41)
+    C = r.random((3, 7, 5))
+    t = r.random((3, 7, 5))
+    t[0, 2, 3] = C[0, 2, 3]
+    t[2, 6, 0] = C[2, 6, 0]
+    w = 0.37
+    L, g = l1_loss_and_grad(C, t, w)
+    Ct = torch.tensor(C, dtype=torch.float64, requires_grad=True)
+    Lt = w * (Ct - torch.tensor(t, dtype=torch.float64)).abs().mean()
+    Lt.backward()
+    assert abs(L - Lt.item()) < 1e-15
+    np.testing.assert_allclose(g, Ct.grad.numpy(), rtol=0, atol=1e-18)
+    h = 1e-7
+    for idx in [(0, 0, 0), (1, 3, 4), (2, 5, 2), (0, 6, 1)]:
+        e = np.zeros_like(C)
+        e[idx] = h
+        fd = (l1_loss_and_grad(C + e, t, w)[0] - l1_loss_and_grad(C - e, t, w)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-7 * abs(g[idx]), idx
