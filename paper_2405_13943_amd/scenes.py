@@ -196,6 +196,47 @@ def config4a() -> Scene:
     return Scene("adjoint-200-sh3-64x64", p, 3, cams, [], seed)
 
 
+def edge_cases():
+    """A 64x64 view (fx = fy = 60, camera at (0, 0, 3) looking at the origin)
+    of 60 config-4a-style Gaussians (SH degree 3, seed 1200) plus eight
+    placed ones, each making one rule of the rasterizer act (Gaussians 60..67):
+      60, 61  negative SH DC: colour clamped at zero (all channels; red only);
+      62, 63  opacity logit 10 and 9 at a few pixels' distance scale: the
+              alpha clamp at 0.99 acts at the pixels nearest their centres;
+      64, 65  beyond 1.3x the half field of view (x/z = 0.86, y/z = 0.75)
+              and large: the Jacobian clamp acts, their footprints reach the
+              image;
+      66      camera depth 0.23, just past the near plane at 0.2;
+      67      camera depth 0.15, before the near plane (culled).
+    Depths are all distinct.  Returns (planes [A][68] FP32, camera); render
+    with a non-black background."""
+    base = gaussians(60, 3, 1200, [-0.5] * 3, [0.5] * 3, -2.5, 0.3).astype(np.float64)
+    A = base.shape[0]
+    placed = []
+
+    def add(mean, logscale, logit, dc, q=(1.0, 0.0, 0.0, 0.0), seed=0):
+        g = np.zeros(A, np.float64)
+        g[MEAN:MEAN + 3] = mean
+        g[QUAT:QUAT + 4] = q
+        g[LOGSCALE:LOGSCALE + 3] = logscale
+        g[OPACITY] = logit
+        g[SH:SH + 3] = dc
+        g[SH + 3:] = rng(1277 + seed).normal(0.0, 0.02, A - SH - 3)
+        placed.append(g)
+
+    add((-0.3, 0.2, 0.0), (-2.3, -2.1, -2.4), 0.5, (-2.5, -2.5, -2.5), seed=1)
+    add((0.1, -0.25, 0.2), (-2.2, -2.2, -2.0), 0.8, (-2.5, 1.0, -1.5), q=(0.9, 0.3, -0.2, 0.1), seed=2)
+    add((0.0, 0.0, 0.3), (-1.0, -1.1, -1.0), 10.0, (1.0, 0.5, 0.2), seed=3)
+    add((-0.25, -0.3, 0.1), (-0.9, -1.3, -1.0), 9.0, (0.2, 1.2, 0.4), q=(0.8, 0.0, 0.5, 0.3), seed=4)
+    add((2.55, 0.0, 0.05), (0.0, -0.2, -0.1), 0.0, (0.8, 0.6, 0.4), seed=5)
+    add((0.1, -2.4, -0.2), (-0.3, -0.1, -0.3), -0.5, (0.3, 0.9, 0.7), q=(0.7, 0.1, 0.1, 0.7), seed=6)
+    add((0.05, -0.03, 2.77), (-4.5, -4.4, -4.6), 1.0, (0.9, 0.1, 0.6), seed=7)
+    add((-0.02, 0.04, 2.85), (-4.0, -4.0, -4.0), 1.0, (0.9, 0.9, 0.9), seed=8)
+    p = np.concatenate([base, np.stack(placed, 1)], 1).astype(np.float32)
+    cam = look_at([0.0, 0.0, 3.0], [0, 0, 0], 64, 64, 60.0, 60.0)
+    return p, cam
+
+
 SLAB_BOUNDS = (-50.0, -39.333, -19.333, 10.0, 50.0)
 BLOCK_COUNTS = (800_000, 1_500_000, 2_200_000, 3_000_000)
 
