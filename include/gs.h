@@ -232,6 +232,23 @@ size_t gs_bin_sort_workspace_size(int64_t n_records, uint64_t capacity, int32_t 
 gs_status gs_bin_sort(const gs_frame *frame, const gs_raster_cfg *cfg, const uint32_t *meta_dev,
                       const gs_bins *bins, void *ws_dev, size_t ws_bytes, gs_stream stream);
 
+/* gs_bin_sort for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * kernels and results, with the workspace taken from a static device array
+ * of the library (gs_bin_sort_noalloc_max_bytes() = 64 MiB per GPU, held
+ * from the library's load to the end of the process) instead of a caller
+ * buffer.  The caller still passes meta and the bins.  A frame whose
+ * workspace (gs_bin_sort_workspace_size) exceeds that size gets
+ * GS_E_CAPACITY and nothing is launched.  The call allocates nothing; its
+ * first call on a device (the current one) looks up that device's copy of
+ * the array.  Every call on one GPU shares the array, so calls that overlap
+ * on one GPU (concurrent streams, or threads on one stream without ordering)
+ * race and give undefined bins; calls ordered on one stream are safe.  No
+ * content of the array carries from one call to the next. */
+size_t gs_bin_sort_noalloc_max_bytes(void);
+gs_status gs_bin_sort_noalloc(const gs_frame *frame, const gs_raster_cfg *cfg, const uint32_t *meta_dev,
+                              const gs_bins *bins, gs_stream stream);
+
 /* Forward compositing (Eq. 2) per pixel over its tile's list.  Writes
  * rgb [3][H][W] per job at 3*px0 (C + T bg), T_final [H][W] at px0 and
  * n_contrib (list position after the last contributor) at px0. */

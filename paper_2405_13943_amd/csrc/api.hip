@@ -232,6 +232,67 @@ gs_status gs_bin_sort(const gs_frame* frame, const gs_raster_cfg* cfg, const uin
     return check_hip(gs::launch_bin_sort(*frame, *cfg, meta, *bins, ws, ws_bytes, (hipStream_t)stream), "gs_bin_sort");
 }
 
+// ---------------------------------------------------------------------------
+// Binning without a caller workspace: the workspace lives in `scratch`, a
+// device array of this file that each GPU holds from the library's load to
+// the end of the process.  Host code never passes `scratch` itself (on the
+// host the name stands for a host-side shadow, not a device address): the
+// device address is looked up once per device, with that device current, and
+// kept in g_scratch_dev.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// device address of the current device's scratch (looked up on first use)
+gs_status scratch_address(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(GS_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GS_E_UNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GS_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return GS_OK;
+}
+
+}  // namespace
+
+size_t gs_bin_sort_noalloc_max_bytes(void) { return kScratchBytes; }
+
+gs_status gs_bin_sort_noalloc(const gs_frame* frame, const gs_raster_cfg* cfg, const uint32_t* meta,
+                              const gs_bins* bins, gs_stream stream) {
+    gs_status st;
+    if ((st = check_frame(frame, cfg)) != GS_OK) return st;
+    if ((st = check_bins(bins, frame, cfg)) != GS_OK) return st;
+    if (frame->n_records > 0 && !meta) return fail(GS_E_INVALID, "null meta");
+    const size_t need = gs::bin_workspace_size(frame->n_records, bins->capacity, frame->n_tiles);
+    if (need > kScratchBytes)
+        return fail(GS_E_CAPACITY, "binning needs %zu workspace bytes for %lld records, %llu pairs and %d tiles; "
+                    "the static scratch holds %zu: use gs_bin_sort with a caller workspace", need,
+                    (long long)frame->n_records, (unsigned long long)bins->capacity, frame->n_tiles, kScratchBytes);
+    void* ws = nullptr;
+    if ((st = scratch_address(&ws)) != GS_OK) return st;
+    return check_hip(gs::launch_bin_sort(*frame, *cfg, meta, *bins, ws, kScratchBytes, (hipStream_t)stream),
+                     "gs_bin_sort_noalloc");
+}
+
 gs_status gs_render_fwd(const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec, const gs_bins* bins, void* rgb,
                         void* T, uint32_t* nc, gs_stream stream) {
     return render_fwd_impl<float>(frame, cfg, rec, bins, rgb, T, nc, stream);

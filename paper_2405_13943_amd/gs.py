@@ -85,6 +85,8 @@ def _load():
         "gs_project_f64": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_bin_sort_workspace_size": ([c_i64, c_u64, c_i32], ctypes.c_size_t),
         "gs_bin_sort": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, ctypes.c_size_t, c_vp], c_i32),
+        "gs_bin_sort_noalloc_max_bytes": ([], ctypes.c_size_t),
+        "gs_bin_sort_noalloc": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp], c_i32),
         "gs_render_fwd": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_render_fwd_f64": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_render_fwd_stats": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
@@ -291,6 +293,13 @@ def bin_sort(frame: Frame, cfg: GsRasterCfg, buf: Buffers):
     b = buf.bins
     _check(lib.gs_bin_sort(ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.meta), ctypes.byref(b),
                            _ptr(buf.bin_ws), buf.bin_ws.numel(), _stream()), "gs_bin_sort")
+
+
+def bin_sort_noalloc(frame: Frame, cfg: GsRasterCfg, buf: Buffers):
+    """gs_bin_sort with the library's static workspace (buf.bin_ws unused)."""
+    b = buf.bins
+    _check(lib.gs_bin_sort_noalloc(ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.meta), ctypes.byref(b),
+                                   _stream()), "gs_bin_sort_noalloc")
 
 
 def render_fwd(frame: Frame, cfg: GsRasterCfg, buf: Buffers):

@@ -156,6 +156,22 @@ def test_invalid_arguments_rejected_without_launch(gs):
     assert rc == gs.GS_E_CAPACITY
 
 
+def test_bin_sort_noalloc_size_limit_host_only(gs):
+    """Binning with the static workspace refuses a frame whose workspace
+    exceeds the array (16 bytes per pair of capacity: 5 Mi pairs need more
+    than 64 MiB) with GS_E_CAPACITY, on the host, before touching a device;
+    bad arguments are refused as by gs_bin_sort."""
+    assert gs.lib.gs_bin_sort_noalloc_max_bytes() == 64 << 20
+    cfg = gs.raster_cfg()
+    fr = gs.GsFrame(1, 1, 1, 1, 1000, 4096, 1000, 1, 0)
+    big = gs.GsBins(1, 1, 1, 1, 5 << 20, 1)
+    assert gs.lib.gs_bin_sort_workspace_size(1000, 5 << 20, 1) > 64 << 20
+    rc = gs.lib.gs_bin_sort_noalloc(ctypes.byref(fr), ctypes.byref(cfg), 1, ctypes.byref(big), None)
+    assert rc == gs.GS_E_CAPACITY and "static scratch" in gs.lib.gs_last_error().decode()
+    assert gs.lib.gs_bin_sort_noalloc(ctypes.byref(fr), ctypes.byref(cfg), None, ctypes.byref(big), None) == gs.GS_E_INVALID
+    assert gs.lib.gs_bin_sort_noalloc(ctypes.byref(fr), ctypes.byref(cfg), 1, None, None) == gs.GS_E_INVALID
+
+
 def test_profile_registry_host_only(gs):
     """Selecting kernels to time launches nothing; kernels never launched
     report zero."""
