@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 3
+#define GS_ABI_VERSION 4
 
 typedef enum {
     GS_OK = 0,
@@ -195,7 +195,10 @@ gs_status gs_frame_plan(const gs_camera *cams_host, int32_t n_cams, gs_job *jobs
 /* Projection (Sec. 3.1: Eq. 1, Sigma = R S S^T R^T, alpha = o X^proj(p), SH
  * colour).  For every (job, Gaussian) slot r = rec0 + g - g0 writes
  *   rec [r][12]: mean2d x, y; the conic scaled for exp2 (-a/2, -b, -c/2
- *                times log2 e); log2 opacity; colour r, g, b; depth; the
+ *                times log2 e); log2 opacity; colour r, g, b; the axis of
+ *                the conic's largest eigenvalue as tan(theta / 2) of its
+ *                direction (cos theta, sin theta), cos theta >= 0 (the frame
+ *                in which the backward sums its second moments); the
  *                conservative half-extents (x, y) in pixels of the region
  *                where alpha >= alpha_min
  *   meta[r][4]:  FP32 bits of the depth, number of covered tiles (0 = culled) in
@@ -270,22 +273,25 @@ gs_status gs_render_fwd_stats(const gs_frame *frame, const gs_raster_cfg *cfg, c
  * parameter planes.  GS_LOSS_L1: L = sum_jobs loss_weight * mean |C - target|
  * over 3HW (the L1 part of Eq. 3), target laid out like rgb; the per-job
  * loss is added to loss_out[job] (may be NULL).  GS_LOSS_EXTERNAL: grad_in is
- * dL/dC laid out like rgb.  The transmittance is recomputed front to back
- * (never stored per pair).  grad->data receives dense gradient planes
- * (zero for Gaussians in no job or culled); grad must cover params->n.
- * Workspace: gs_render_bwd_workspace_size bytes (nine partials per tile pair
- * and compositing wavefront, sized for up to 4 wavefronts per tile). */
+ * dL/dC laid out like rgb.  rgb_dev and n_contrib_dev are the outputs of
+ * gs_render_fwd for the same frame, records and bins (the contributor counts
+ * carry the forward's stop decisions).  The transmittance is recomputed
+ * front to back (never stored per pair).  grad->data receives dense gradient
+ * planes (zero for Gaussians in no job or culled); grad must cover
+ * params->n.  Workspace: gs_render_bwd_workspace_size bytes (nine partials
+ * per tile pair and compositing wavefront, sized for up to 4 wavefronts per
+ * tile). */
 size_t gs_render_bwd_workspace_size(uint64_t capacity, int32_t f64);
 gs_status gs_render_bwd(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
                         const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,
-                        const void *rgb_dev, gs_loss_mode mode, const void *grad_in_dev,
-                        float *loss_out_dev, gs_params *grad, void *ws_dev, size_t ws_bytes,
-                        gs_stream stream);
+                        const void *rgb_dev, const uint32_t *n_contrib_dev, gs_loss_mode mode,
+                        const void *grad_in_dev, float *loss_out_dev, gs_params *grad, void *ws_dev,
+                        size_t ws_bytes, gs_stream stream);
 gs_status gs_render_bwd_f64(const gs_params *params, const gs_frame *frame, const gs_raster_cfg *cfg,
                             const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,
-                            const void *rgb_dev, gs_loss_mode mode, const void *grad_in_dev,
-                            double *loss_out_dev, gs_params *grad, void *ws_dev, size_t ws_bytes,
-                            gs_stream stream);
+                            const void *rgb_dev, const uint32_t *n_contrib_dev, gs_loss_mode mode,
+                            const void *grad_in_dev, double *loss_out_dev, gs_params *grad, void *ws_dev,
+                            size_t ws_bytes, gs_stream stream);
 
 /* Photometric loss of Eq. 3 with its structural term, per job j:
  *   L_j = w_j (mean |C - target| + lambda (1 - mean SSIM)),
@@ -337,10 +343,10 @@ gs_status gs_adam_admm(gs_params *x, const gs_params *g, gs_params *m, gs_params
  * gs_render_bwd. */
 gs_status gs_render_bwd_adam(gs_params *x, const gs_frame *frame, const gs_raster_cfg *cfg,
                              const void *rec_dev, const uint32_t *meta_dev, const gs_bins *bins,
-                             const void *rgb_dev, gs_loss_mode mode, const void *grad_in_dev,
-                             float *loss_out_dev, gs_params *m, gs_params *v, const gs_params *w,
-                             const float *mask_dev, const gs_adam_cfg *acfg, void *ws_dev, size_t ws_bytes,
-                             gs_stream stream);
+                             const void *rgb_dev, const uint32_t *n_contrib_dev, gs_loss_mode mode,
+                             const void *grad_in_dev, float *loss_out_dev, gs_params *m, gs_params *v,
+                             const gs_params *w, const float *mask_dev, const gs_adam_cfg *acfg, void *ws_dev,
+                             size_t ws_bytes, gs_stream stream);
 
 /* Per-kernel timing with HIP events (measurement tooling; off by default).
  * gs_profile_set(names): comma-separated kernel names to time, "*" for all,
@@ -351,6 +357,40 @@ gs_status gs_render_bwd_adam(gs_params *x, const gs_frame *frame, const gs_raste
  * 0 for a kernel never launched). */
 gs_status gs_profile_set(const char *names);
 gs_status gs_profile_get(const char *name, double *total_ms, int64_t *launches);
+
+/* Tile-shape autotuner (no counterpart in the paper: a choice of launch
+ * shapes for the batched K-block step of Alg. 2, S1).  A candidate is a
+ * binning tile and the wavefronts per tile of the forward and the backward
+ * compositing passes (the fields of gs_raster_cfg they set; each must be a
+ * combination gs_raster_cfg accepts).  The workgroup is always 4
+ * wavefronts: the adaptive split puts a tile's wavefronts in one workgroup. */
+typedef struct {
+    int32_t tile_w, tile_h;
+    int32_t fwd_waves, bwd_waves;
+} gs_tune_choice;
+
+/* One step of the caller's workload with the given launch shapes, enqueued on
+ * the stream handed to gs_autotune (or synchronous); returns 0 on success. */
+typedef int32_t (*gs_tune_step_fn)(const gs_tune_choice *choice, void *user);
+
+/* Cache of tuned choices: path of a JSON file ({"<key>": {"tile": [w, h,
+ * fwd, bwd], "ms": {...}}}) read now and rewritten after each new tuning, or
+ * NULL for an in-memory cache only.  Clears the in-memory cache first.
+ * GS_E_INVALID for a file that is not such JSON (the cache is then empty).
+ * Without a call, the cache is in memory only. */
+gs_status gs_set_tune_cache(const char *path);
+
+/* Fastest of n_candidates launch shapes for the workload named shape_key:
+ * when the key is cached, *best (and *best_ms, the cached time or -1) come
+ * from the cache and step is never called.  Otherwise, per candidate, step is
+ * called once untimed, then reps times between two HIP events on `stream`;
+ * the candidate with the least time per step wins (ties: the first), is
+ * cached under shape_key and returned.  best_ms (may be NULL) receives its
+ * milliseconds per step.  Errors: GS_E_INVALID for null or empty arguments,
+ * n_candidates or reps below 1, an invalid candidate or a step that returns
+ * non-zero; GS_E_DEVICE when the events fail. */
+gs_status gs_autotune(const char *shape_key, const gs_tune_choice *candidates, int32_t n_candidates, int32_t reps,
+                      gs_tune_step_fn step, void *user, gs_stream stream, gs_tune_choice *best, double *best_ms);
 
 /* Consensus step (Eq. 8b-c, Alg. 2) over K blocks held in one parameter
  * store.  For each global id gid with local holders

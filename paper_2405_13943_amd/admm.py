@@ -17,9 +17,7 @@ arithmetic step runs in libgs.
 """
 from __future__ import annotations
 
-import json
 import os
-import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -371,31 +369,12 @@ TILES = ((16, 16, -1, -1), (32, 8, -1, -1), (16, 16, 2, 1), (16, 16, 2, -1), (16
 
 
 def autotune_tile(run_step, key: str, cache_path=None, candidates=TILES, reps=5):
-    """Time ``run_step(tile)`` (one full training step with that tile shape)
-    for each candidate with HIP events and return the fastest; results are
-    cached in a JSON file keyed by ``key`` (workload shape)."""
-    cache = {}
-    if cache_path and os.path.exists(cache_path):
-        with open(cache_path) as fh:
-            cache = json.load(fh)
-    if key in cache:
-        return tuple(cache[key]["tile"])
-    times = {}
-    for tile in candidates:
-        run_step(tile)                         # warm-up (and capacity sizing)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            run_step(tile)
-        e1.record()
-        torch.cuda.synchronize()
-        times[tile] = e0.elapsed_time(e1) / reps
-    best = min(times, key=times.get)
-    cache[key] = {"tile": list(best), "ms": {"x".join(map(str, t)): v for t, v in times.items()},
-                  "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    """The fastest launch shape for ``run_step(tile)`` (one full training step
+    with that tile shape) from libgs's tuner (gs_autotune: HIP-event timing
+    of each candidate on the current stream, choices cached per workload key,
+    in ``cache_path`` when given)."""
     if cache_path:
         os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
-        with open(cache_path, "w") as fh:
-            json.dump(cache, fh, indent=1)
-    return best
+    gs.set_tune_cache(cache_path)
+    best, _ = gs.autotune(key, candidates, run_step, reps)
+    return tuple(best)

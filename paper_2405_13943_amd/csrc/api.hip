@@ -114,8 +114,9 @@ size_t bwd_ws(uint64_t capacity, int f64) {
 
 template <typename T>
 gs_status render_bwd_impl(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
-                          const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
-                          const void* gin, T* loss, gs_params* grad, void* ws, size_t ws_bytes, gs_stream stream) {
+                          const uint32_t* meta, const gs_bins* bins, const void* rgb, const uint32_t* nc,
+                          gs_loss_mode mode, const void* gin, T* loss, gs_params* grad, void* ws, size_t ws_bytes,
+                          gs_stream stream) {
     gs_status st;
     if ((st = check_params(params, "params")) != GS_OK) return st;
     if ((st = check_params(grad, "grad")) != GS_OK) return st;
@@ -126,7 +127,8 @@ gs_status render_bwd_impl(const gs_params* params, const gs_frame* frame, const 
     if (frame->g_max > params->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
                                               (long long)frame->g_max, (long long)params->n);
     if (mode != GS_LOSS_L1 && mode != GS_LOSS_EXTERNAL) return fail(GS_E_INVALID, "unknown loss mode");
-    if (frame->n_pixels > 0 && (!rgb || !gin)) return fail(GS_E_INVALID, "null image or gradient input");
+    if (frame->n_pixels > 0 && (!rgb || !nc || !gin))
+        return fail(GS_E_INVALID, "null image, contributor count or gradient input");
     if (frame->n_records > 0 && (!rec || !meta)) return fail(GS_E_INVALID, "null record buffers");
     if (!ws || ws_bytes < bwd_ws(bins->capacity, sizeof(T) == 8))
         return fail(GS_E_CAPACITY, "backward workspace too small (%zu < %zu)", ws_bytes,
@@ -134,9 +136,11 @@ gs_status render_bwd_impl(const gs_params* params, const gs_frame* frame, const 
     T* pg = static_cast<T*>(ws);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gs::launch_render_bwd<T>(*frame, *cfg, static_cast<const T*>(rec), meta, *bins,
-                                            static_cast<const T*>(rgb), mode, static_cast<const T*>(gin), loss, pg, s);
+                                            static_cast<const T*>(rgb), nc, mode, static_cast<const T*>(gin), loss,
+                                            pg, s);
     if (e != hipSuccess) return check_hip(e, "gs_render_bwd (composite)");
-    return check_hip(gs::launch_project_bwd<T>(*params, *frame, *cfg, meta, *bins, pg, *grad, s),
+    return check_hip(gs::launch_project_bwd<T>(*params, *frame, *cfg, static_cast<const T*>(rec), meta, *bins, pg,
+                                               *grad, s),
                      "gs_render_bwd (projection)");
 }
 
@@ -274,6 +278,36 @@ gs_status scratch_address(void** out) {
 
 }  // namespace
 
+gs_status gs_set_tune_cache(const char* path) {
+    std::string err;
+    const gs_status st = gs::tune_set_cache(path, err);
+    return st == GS_OK ? GS_OK : fail(st, "%s", err.c_str());
+}
+
+gs_status gs_autotune(const char* key, const gs_tune_choice* cand, int32_t n, int32_t reps, gs_tune_step_fn step,
+                      void* user, gs_stream stream, gs_tune_choice* best, double* best_ms) {
+    if (!key || !*key || !cand || !step || !best) return fail(GS_E_INVALID, "null or empty autotune argument");
+    if (n < 1 || reps < 1) return fail(GS_E_INVALID, "autotune needs at least one candidate and one repetition");
+    for (int32_t i = 0; i < n; i++) {
+        gs_raster_cfg c;
+        gs_raster_cfg_default(&c);
+        c.tile_w = cand[i].tile_w;
+        c.tile_h = cand[i].tile_h;
+        c.fwd_waves = int16_t(cand[i].fwd_waves);
+        c.bwd_waves = int16_t(cand[i].bwd_waves);
+        if (cand[i].fwd_waves != c.fwd_waves || cand[i].bwd_waves != c.bwd_waves || !tile_ok(&c))
+            return fail(GS_E_INVALID, "candidate %d: tile %dx%d with %d/%d wavefronts is not a valid launch shape", i,
+                        cand[i].tile_w, cand[i].tile_h, cand[i].fwd_waves, cand[i].bwd_waves);
+    }
+    std::string err;
+    bool found = false;
+    gs_status st = gs::tune_lookup(key, best, best_ms, &found, err);
+    if (st != GS_OK) return fail(st, "%s", err.c_str());
+    if (found) return GS_OK;
+    st = gs::tune_run(key, cand, n, reps, step, user, (hipStream_t)stream, best, best_ms, err);
+    return st == GS_OK ? GS_OK : fail(st, "%s", err.c_str());
+}
+
 size_t gs_bin_sort_noalloc_max_bytes(void) { return kScratchBytes; }
 
 gs_status gs_bin_sort_noalloc(const gs_frame* frame, const gs_raster_cfg* cfg, const uint32_t* meta,
@@ -329,17 +363,19 @@ gs_status gs_ssim_loss_grad(const gs_frame* frame, const gs_raster_cfg* cfg, con
 }
 
 gs_status gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
-                        const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
-                        const void* gin, float* loss, gs_params* grad, void* ws, size_t ws_bytes, gs_stream stream) {
-    return render_bwd_impl<float>(params, frame, cfg, rec, meta, bins, rgb, mode, gin, loss, grad, ws, ws_bytes, stream);
+                        const uint32_t* meta, const gs_bins* bins, const void* rgb, const uint32_t* n_contrib,
+                        gs_loss_mode mode, const void* gin, float* loss, gs_params* grad, void* ws, size_t ws_bytes,
+                        gs_stream stream) {
+    return render_bwd_impl<float>(params, frame, cfg, rec, meta, bins, rgb, n_contrib, mode, gin, loss, grad, ws,
+                                  ws_bytes, stream);
 }
 
 gs_status gs_render_bwd_f64(const gs_params* params, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
-                            const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
-                            const void* gin, double* loss, gs_params* grad, void* ws, size_t ws_bytes,
-                            gs_stream stream) {
-    return render_bwd_impl<double>(params, frame, cfg, rec, meta, bins, rgb, mode, gin, loss, grad, ws, ws_bytes,
-                                   stream);
+                            const uint32_t* meta, const gs_bins* bins, const void* rgb, const uint32_t* n_contrib,
+                            gs_loss_mode mode, const void* gin, double* loss, gs_params* grad, void* ws,
+                            size_t ws_bytes, gs_stream stream) {
+    return render_bwd_impl<double>(params, frame, cfg, rec, meta, bins, rgb, n_contrib, mode, gin, loss, grad, ws,
+                                   ws_bytes, stream);
 }
 
 namespace {
@@ -377,8 +413,9 @@ gs_status gs_adam_admm(gs_params* x, const gs_params* g, gs_params* m, gs_params
 }
 
 gs_status gs_render_bwd_adam(gs_params* x, const gs_frame* frame, const gs_raster_cfg* cfg, const void* rec,
-                             const uint32_t* meta, const gs_bins* bins, const void* rgb, gs_loss_mode mode,
-                             const void* gin, float* loss, gs_params* m, gs_params* v, const gs_params* w,
+                             const uint32_t* meta, const gs_bins* bins, const void* rgb, const uint32_t* n_contrib,
+                             gs_loss_mode mode, const void* gin, float* loss, gs_params* m, gs_params* v,
+                             const gs_params* w,
                              const float* mask, const gs_adam_cfg* acfg, void* ws, size_t ws_bytes,
                              gs_stream stream) {
     gs_status st;
@@ -390,17 +427,19 @@ gs_status gs_render_bwd_adam(gs_params* x, const gs_frame* frame, const gs_raste
     if (frame->g_max > x->n) return fail(GS_E_INVALID, "jobs reach Gaussian %lld, params hold %lld",
                                          (long long)frame->g_max, (long long)x->n);
     if (mode != GS_LOSS_L1 && mode != GS_LOSS_EXTERNAL) return fail(GS_E_INVALID, "unknown loss mode");
-    if (frame->n_pixels > 0 && (!rgb || !gin)) return fail(GS_E_INVALID, "null image or gradient input");
+    if (frame->n_pixels > 0 && (!rgb || !n_contrib || !gin))
+        return fail(GS_E_INVALID, "null image, contributor count or gradient input");
     if (frame->n_records > 0 && (!rec || !meta)) return fail(GS_E_INVALID, "null record buffers");
     if (!ws || ws_bytes < bwd_ws(bins->capacity, 0))
         return fail(GS_E_CAPACITY, "backward workspace too small (%zu < %zu)", ws_bytes, bwd_ws(bins->capacity, 0));
     float* pg = static_cast<float*>(ws);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gs::launch_render_bwd<float>(*frame, *cfg, static_cast<const float*>(rec), meta, *bins,
-                                                static_cast<const float*>(rgb), mode, static_cast<const float*>(gin),
-                                                loss, pg, s);
+                                                static_cast<const float*>(rgb), n_contrib, mode,
+                                                static_cast<const float*>(gin), loss, pg, s);
     if (e != hipSuccess) return check_hip(e, "gs_render_bwd_adam (composite)");
-    return check_hip(gs::launch_project_bwd_adam(*x, *frame, *cfg, meta, *bins, pg, *m, *v, w, mask, *acfg, s),
+    return check_hip(gs::launch_project_bwd_adam(*x, *frame, *cfg, static_cast<const float*>(rec), meta, *bins, pg,
+                                                 *m, *v, w, mask, *acfg, s),
                      "gs_render_bwd_adam (projection + optimiser)");
 }
 

@@ -55,6 +55,47 @@ template <typename T> __device__ constexpr T kLn2() { return T(0.693147180559945
 template <typename T> __device__ constexpr T kLog2e() { return T(1.44269504088896340736); }
 
 // ---------------------------------------------------------------------------
+// Frame of the compositing backward's second moments.  A footprint much
+// longer than it is wide puts almost all of sum ge (p - m)(p - m)^T along its
+// long axis, while the gradient of the screen covariance is dominated by the
+// part across it; taken from pixel-frame sums, that part would come out of a
+// near-cancellation.  So the backward accumulates the moments in the
+// footprint's axes: e1 along the axis of the conic's largest eigenvalue (the
+// narrow one) and e2 across it.  The projection stores that axis as one word,
+// t = tan(theta / 2) of its direction (cos theta, sin theta) with
+// cos theta >= 0, and every user decodes the same word with the same
+// operations, so all of them rotate by the same matrix.
+
+// code of the narrow axis of the conic [[a, b], [b, c]] (any axis when a = c
+// and b = 0)
+template <typename T>
+__device__ inline T narrow_axis_code(T a, T b, T c) {
+    const T h = T(0.5) * (a - c);
+    const T r = Num<T>::sqrt(Num<T>::fma(h, h, b * b));
+    // eigenvector of the eigenvalue (a + c) / 2 + r, from the better-conditioned row
+    T vx = h >= T(0) ? h + r : b;
+    T vy = h >= T(0) ? b : r - h;
+    const T n2 = Num<T>::fma(vx, vx, vy * vy);
+    if (!(n2 > T(0))) return T(0);
+    const T inv = Num<T>::rsqrt(n2);
+    vx *= inv;
+    vy *= inv;
+    if (vx < T(0)) {
+        vx = -vx;
+        vy = -vy;
+    }
+    return vy / (T(1) + vx);
+}
+
+// (cos theta, sin theta) of a narrow-axis code
+template <typename T>
+__device__ inline void narrow_axis(T t, T& c, T& s) {
+    const T w = T(1) / Num<T>::fma(t, t, T(1));
+    c = Num<T>::fma(-t, t, T(1)) * w;
+    s = (t + t) * w;
+}
+
+// ---------------------------------------------------------------------------
 // per-record metadata word 1: covered tiles in the low 24 bits, the colour
 // clamp of each channel (SH sum + 0.5 <= 0) in bits 24..26
 
@@ -216,6 +257,14 @@ __device__ inline double wave_sum(double v) {
 
 __device__ inline uint32_t wave_sum_u32(uint32_t v) {
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
     return v;
 }
 

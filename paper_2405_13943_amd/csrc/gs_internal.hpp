@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "gs.h"
 
 namespace gs {
@@ -42,11 +44,12 @@ template <typename T>
 hipError_t launch_project(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, T* rec,
                           uint32_t* meta, uint32_t* status, hipStream_t s);
 template <typename T>
-hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
+hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, const T* rec,
                               const uint32_t* meta, const gs_bins& bins, const T* pg, gs_params& grad, hipStream_t s);
 
 // fused projection backward + Adam/ADMM (FP32, jobs over disjoint ranges)
-hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta,
+hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const float* rec,
+                                   const uint32_t* meta,
                                    const gs_bins& bins, const float* pg, gs_params& m, gs_params& v,
                                    const gs_params* w, const float* mask, const gs_adam_cfg& acfg, hipStream_t s);
 
@@ -61,8 +64,8 @@ hipError_t launch_render_fwd(const gs_frame& f, const gs_raster_cfg& cfg, const 
                              T* rgb, T* Tfin, uint32_t* ncontrib, unsigned long long* kept, hipStream_t s);
 template <typename T>
 hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
-                             const gs_bins& bins, const T* rgb, gs_loss_mode mode, const T* grad_in, T* loss_out,
-                             T* pg, hipStream_t s);
+                             const gs_bins& bins, const T* rgb, const uint32_t* ncontrib, gs_loss_mode mode,
+                             const T* grad_in, T* loss_out, T* pg, hipStream_t s);
 
 // ssim.hip
 size_t ssim_workspace_size(int64_t n_pixels);
@@ -76,6 +79,12 @@ void spatial_order(const float* mean, int64_t n, int64_t stride, int32_t bits, i
                    int64_t* perm);
 void split_group(const double* boxes, int32_t K, double s, int32_t axes, const double* points, int64_t n,
                  int64_t* counts, int64_t* members, int64_t capacity, int64_t* total);
+
+// tune.hip (host)
+gs_status tune_set_cache(const char* path, std::string& err);
+gs_status tune_lookup(const char* key, gs_tune_choice* best, double* best_ms, bool* found, std::string& err);
+gs_status tune_run(const char* key, const gs_tune_choice* cand, int32_t n, int32_t reps, gs_tune_step_fn step,
+                   void* user, hipStream_t stream, gs_tune_choice* best, double* best_ms, std::string& err);
 
 // optim.hip
 hipError_t launch_adam_admm(gs_params& x, const gs_params& g, gs_params& m, gs_params& v, const gs_params* w,

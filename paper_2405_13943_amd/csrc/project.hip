@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256) void k_project(const T* __restrict__ P, int64_
     o[6] = col[0];
     o[7] = col[1];
     o[8] = col[2];
-    o[9] = G.t[2];
+    o[9] = narrow_axis_code(G.a, G.b, G.c);   // frame of the backward's moments
     o[10] = hx;   // conservative half-extents of {alpha >= alpha_min} in pixels
     o[11] = hy;
     m.x = __float_as_uint(float(G.t[2]));
@@ -404,7 +404,7 @@ __device__ inline void record_partials(const T* __restrict__ pg, const PartialLa
 // gradients.
 template <typename T, int D, typename Emit>
 __device__ inline void record_chain(const T* P, int64_t stride, int64_t g, const gs_camera& camera,
-                                    const gs_raster_cfg& cfg, uint32_t meta_y, const T* d, Emit emit,
+                                    const gs_raster_cfg& cfg, uint32_t meta_y, const T* d, T axis, Emit emit,
                                     T* sh_basis_out = nullptr, T* sh_dc_out = nullptr) {
     constexpr int NK = (D + 1) * (D + 1);
     const uint4 m = make_uint4(0u, meta_y, 0u, 0u);
@@ -414,15 +414,41 @@ __device__ inline void record_chain(const T* P, int64_t stride, int64_t g, const
     geometry(P, stride, g, cam, cfg, G);
 
     // The compositing backward hands over, per record, the moments of
-    // ge = dL/dalpha * alpha over the covered pixels (offsets dx, dy from
-    // the mean): d[0] = sum ge, d[1] = sum ge dx, d[2] = sum ge dy,
-    // d[3..5] = sum ge (dx^2, dx dy, dy^2); and dL/dcolour in d[6..8].
-    // With alpha = o exp(-(a dx^2 + 2 b dx dy + c dy^2) / 2):
-    //   dL/dlogit = sum ge (1 - o);  dL/dmean2d = (a m1 + b m2, b m1 + c m2);
-    //   dL/da = -m3 / 2, dL/db = -m4, dL/dc = -m5 / 2.
+    // ge = dL/dalpha * alpha over the covered pixels, with the offset
+    // delta = pixel - mean in the axes R = [v w] of the record's moment frame
+    // (v = (cs, sn) the conic's narrow axis, w = (-sn, cs); e = R^T delta):
+    // d[0] = sum ge, d[1..2] = sum ge e, d[3..5] = sum ge (e1^2, e1 e2, e2^2);
+    // and dL/dcolour in d[6..8].  With alpha = o exp(-delta^T A delta / 2):
+    //   dL/dlogit = sum ge (1 - o);
+    //   dL/dmean2d = A sum ge delta = R Dg (d1, d2)  with Dg = R^T A R;
+    //   dL/dA = -(1/2) sum ge delta delta^T, so the screen covariance
+    //   Sigma' = A^-1 gets dL/dSigma' = -A dL/dA A = (1/2) R Dg Se Dg R^T,
+    //   Se = [[d3, d4], [d4, d5]].
+    // Dg is diagonal up to rounding; R is exactly the rotation the moments
+    // were taken in, so nothing here subtracts the large along-axis moments
+    // from the small across-axis ones.
     emit(10, d[0] * (T(1) - G.o));
-    const T dmx = G.a * d[1] + G.b * d[2];
-    const T dmy = G.b * d[1] + G.c * d[2];
+    // in the moment frame; what the later steps need (the mean gradient, the
+    // rotation and P = Dg Se Dg / 2) replaces the conic and the moments
+    // before the SH planes are read, which keeps the values live across
+    // those loads few
+    T cs, sn;
+    narrow_axis(axis, cs, sn);
+    T dmx, dmy, P11, P12, P22;
+    {
+        const T cs2 = cs * cs, sn2 = sn * sn, csn = cs * sn;
+        const T D11 = G.a * cs2 + T(2) * G.b * csn + G.c * sn2;
+        const T D22 = G.a * sn2 - T(2) * G.b * csn + G.c * cs2;
+        const T D12 = (G.c - G.a) * csn + G.b * (cs2 - sn2);
+        const T q1 = D11 * d[1] + D12 * d[2], q2 = D12 * d[1] + D22 * d[2];
+        dmx = cs * q1 - sn * q2;
+        dmy = sn * q1 + cs * q2;
+        const T E11 = D11 * d[3] + D12 * d[4], E12 = D11 * d[4] + D12 * d[5];
+        const T E21 = D12 * d[3] + D22 * d[4], E22 = D12 * d[4] + D22 * d[5];
+        P11 = T(0.5) * (E11 * D11 + E12 * D12);
+        P12 = T(0.5) * (E11 * D12 + E12 * D22);
+        P22 = T(0.5) * (E21 * D12 + E22 * D22);
+    }
 
     // colour: c = max(0, sum_k Y_k f_k + 0.5)
     T dir[3];
@@ -458,14 +484,11 @@ __device__ inline void record_chain(const T* P, int64_t stride, int64_t g, const
 #pragma unroll
     for (int k = 0; k < 3; k++) du[k] = (ddir[k] - dir[k] * dd) * vinv;
 
-    // conic -> screen covariance: dS = -A dA A
-    const T da = T(-0.5) * d[3];
-    const T db = -d[4];
-    const T dcn = T(-0.5) * d[5];
-    const T a = G.a, b = G.b, c = G.c;
-    const T S00 = -(a * a * da + a * b * db + b * b * dcn);
-    const T S01 = -(a * b * da + T(0.5) * (a * c + b * b) * db + b * c * dcn);
-    const T S11 = -(b * b * da + b * c * db + c * c * dcn);
+    // moments -> screen covariance: dSigma' = R P R^T
+    const T cs2 = cs * cs, sn2 = sn * sn, csn = cs * sn;
+    const T S00 = cs2 * P11 - T(2) * csn * P12 + sn2 * P22;
+    const T S01 = csn * (P11 - P22) + (cs2 - sn2) * P12;
+    const T S11 = sn2 * P11 + T(2) * csn * P12 + cs2 * P22;
 
     // screen covariance -> Sigma and the rows t0, t1 of J W
     T St0[3], St1[3];
@@ -547,7 +570,8 @@ __device__ inline void record_chain(const T* P, int64_t stride, int64_t g, const
 // plane stored once, as soon as it is known.  Culled records get zeros.
 template <typename T, int D>
 __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P, int64_t stride, gs_frame frame,
-                                                          gs_raster_cfg cfg, const uint4* __restrict__ meta,
+                                                          gs_raster_cfg cfg, const T* __restrict__ rec,
+                                                          const uint4* __restrict__ meta,
                                                           const uint32_t* __restrict__ pair_off, uint64_t capacity,
                                                           PartialLayout L, const T* __restrict__ pg, T* __restrict__ grad,
                                                           int64_t gstride) {
@@ -559,6 +583,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P
     const int64_t g = job.g0 + (r - job.rec0);
     const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t ntiles = meta_tiles(m.y);
+    const T axis = ntiles ? rec[r * GS_REC_WORDS + 9] : T(0);   // moment frame, loaded early
     T d[9];
     record_partials(pg, L, m, ntiles ? pair_off[r] : 0u, capacity, d);
     if (!active) return;
@@ -568,7 +593,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P
         for (int a = 0; a < A; a++) gout[int64_t(a) * gstride] = T(0);
         return;
     }
-    record_chain<T, D>(P, stride, g, frame.cams[job.cam], cfg, m.y, d,
+    record_chain<T, D>(P, stride, g, frame.cams[job.cam], cfg, m.y, d, axis,
                        [&](int a, T v) { gout[int64_t(a) * gstride] = v; });
 }
 
@@ -577,7 +602,7 @@ __global__ __launch_bounds__(128) void k_project_bwd_rec(const T* __restrict__ P
 template <typename T, int D>
 __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P, int64_t stride, int64_t n,
                                                           gs_frame frame, gs_raster_cfg cfg,
-                                                          const uint4* __restrict__ meta,
+                                                          const T* __restrict__ rec, const uint4* __restrict__ meta,
                                                           const uint32_t* __restrict__ pair_off, uint64_t capacity,
                                                           PartialLayout L, const T* __restrict__ pg, T* __restrict__ grad,
                                                           int64_t gstride) {
@@ -593,10 +618,11 @@ __global__ __launch_bounds__(128) void k_project_bwd_acc(const T* __restrict__ P
         const int64_t r = in_job ? job.rec0 + (g - job.g0) : 0;
         const uint4 m = in_job ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
         const uint32_t ntiles = meta_tiles(m.y);
+        const T axis = ntiles ? rec[r * GS_REC_WORDS + 9] : T(0);
         T d[9];
         record_partials(pg, L, m, ntiles ? pair_off[r] : 0u, capacity, d);
         if (ntiles == 0) continue;
-        record_chain<T, D>(P, stride, g, frame.cams[job.cam], cfg, m.y, d,
+        record_chain<T, D>(P, stride, g, frame.cams[job.cam], cfg, m.y, d, axis,
                            [&](int a, T v) { gout[int64_t(a) * gstride] += v; });
     }
 }
@@ -688,8 +714,9 @@ __device__ inline void adam_block_one(float* __restrict__ X, int64_t sx, float* 
 
 template <int D, bool PEN, bool MASK, bool VEC>
 __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
-    float* X, int64_t sx, gs_frame frame, gs_raster_cfg cfg, const uint4* __restrict__ meta,
-    const uint32_t* __restrict__ pair_off, uint64_t capacity, PartialLayout L, const float* __restrict__ pg,
+    float* X, int64_t sx, gs_frame frame, gs_raster_cfg cfg, const float* __restrict__ rec,
+    const uint4* __restrict__ meta, const uint32_t* __restrict__ pair_off, uint64_t capacity, PartialLayout L,
+    const float* __restrict__ pg,
     float* __restrict__ M,
     int64_t sm, float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
     const float* __restrict__ mask, AdamConsts c, uint32_t* __restrict__ status) {
@@ -708,6 +735,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     const int64_t g = job.g0 + (r - job.rec0);
     const uint4 m = active ? meta[r] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t ntiles = meta_tiles(m.y);
+    const float axis = ntiles ? rec[r * GS_REC_WORDS + 9] : 0.f;   // moment frame, loaded early
     float d[9];
     record_partials(pg, L, m, ntiles ? pair_off[r] : 0u, capacity, d);
 
@@ -719,7 +747,7 @@ __global__ __launch_bounds__(kFusedBlock) void k_project_bwd_adam(
     for (int q = 0; q < NK; q++) Y[q] = 0.f;
     dc[0] = dc[1] = dc[2] = 0.f;
     if (active && ntiles != 0)
-        record_chain<float, D>(X, sx, g, frame.cams[job.cam], cfg, m.y, d,
+        record_chain<float, D>(X, sx, g, frame.cams[job.cam], cfg, m.y, d, axis,
                                [&](int a, float v) {
                                    if (a < 11) s_geo[a][t] = v;
                                },
@@ -810,7 +838,8 @@ static PartialLayout partial_layout(const gs_raster_cfg& cfg, const gs_bins&, co
 }
 
 template <typename T, int D>
-static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
+static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, const T* rec,
+                                 const uint4* M,
                                  const uint32_t* pair_off, uint64_t capacity, const PartialLayout& L, const T* pg,
                                  gs_params& grad, hipStream_t s) {
     const T* P = static_cast<const T*>(p.data);
@@ -822,15 +851,15 @@ static void project_bwd_dispatch(const gs_params& p, const gs_frame& f, const gs
                                11 + 3 * (D + 1) * (D + 1), Gd, grad.stride);
         if (f.n_records > 0)
             GS_LAUNCH("k_project_bwd_rec", (k_project_bwd_rec<T, D>), dim3(unsigned((f.n_records + 127) / 128)), dim3(128), 0, s,
-                               P, p.stride, f, cfg, M, pair_off, capacity, L, pg, Gd, grad.stride);
+                               P, p.stride, f, cfg, rec, M, pair_off, capacity, L, pg, Gd, grad.stride);
     } else {
         GS_LAUNCH("k_project_bwd_acc", (k_project_bwd_acc<T, D>), dim3(unsigned((p.n + 127) / 128)), dim3(128), 0, s, P,
-                           p.stride, p.n, f, cfg, M, pair_off, capacity, L, pg, Gd, grad.stride);
+                           p.stride, p.n, f, cfg, rec, M, pair_off, capacity, L, pg, Gd, grad.stride);
     }
 }
 
 template <typename T>
-hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg,
+hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_raster_cfg& cfg, const T* rec,
                               const uint32_t* meta, const gs_bins& bins, const T* pg, gs_params& grad, hipStream_t s) {
     if (p.n == 0) return hipSuccess;
     const uint4* M = reinterpret_cast<const uint4*>(meta);
@@ -838,10 +867,10 @@ hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_ra
     const uint32_t* po = bins.pair_off;
     const uint64_t cap = bins.capacity;
     switch (p.sh_degree) {
-        case 0: project_bwd_dispatch<T, 0>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
-        case 1: project_bwd_dispatch<T, 1>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
-        case 2: project_bwd_dispatch<T, 2>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
-        default: project_bwd_dispatch<T, 3>(p, f, cfg, M, po, cap, L, pg, grad, s); break;
+        case 0: project_bwd_dispatch<T, 0>(p, f, cfg, rec, M, po, cap, L, pg, grad, s); break;
+        case 1: project_bwd_dispatch<T, 1>(p, f, cfg, rec, M, po, cap, L, pg, grad, s); break;
+        case 2: project_bwd_dispatch<T, 2>(p, f, cfg, rec, M, po, cap, L, pg, grad, s); break;
+        default: project_bwd_dispatch<T, 3>(p, f, cfg, rec, M, po, cap, L, pg, grad, s); break;
     }
     return hipGetLastError();
 }
@@ -849,7 +878,8 @@ hipError_t launch_project_bwd(const gs_params& p, const gs_frame& f, const gs_ra
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 template <int D, bool PEN, bool MASK>
-static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
+static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const float* rec,
+                                    const uint4* M,
                                     const uint32_t* pair_off, uint64_t capacity, const PartialLayout& L,
                                     const float* pg, gs_params& m, gs_params& v, const gs_params* w,
                                     const float* mask, const AdamConsts& c, uint32_t* status, hipStream_t s) {
@@ -869,23 +899,25 @@ static void project_bwd_adam_launch(gs_params& x, const gs_frame& f, const gs_ra
     const dim3 grid(unsigned((f.n_records + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
     if (f.n_records > 0 && vec)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, true>), grid, block, 0, s, X, x.stride, f,
-                  cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c, status);
+                  cfg, rec, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c, status);
     else if (f.n_records > 0)
         GS_LAUNCH("k_project_bwd_adam", (k_project_bwd_adam<D, PEN, MASK, false>), grid, block, 0, s, X, x.stride,
-                  f, cfg, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c, status);
+                  f, cfg, rec, M, pair_off, capacity, L, pg, Mo, m.stride, Vo, v.stride, Wd, sw, mask, c, status);
 }
 
 template <int D>
-static void project_bwd_adam_pen(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint4* M,
+static void project_bwd_adam_pen(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const float* rec,
+                                 const uint4* M,
                                  const uint32_t* po, uint64_t cap, const PartialLayout& L, const float* pg,
                                  gs_params& m, gs_params& v, const gs_params* w, const float* mask,
                                  const AdamConsts& c, uint32_t* st, hipStream_t s) {
-    if (w && mask) project_bwd_adam_launch<D, true, true>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s);
-    else if (w) project_bwd_adam_launch<D, true, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s);
-    else project_bwd_adam_launch<D, false, false>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s);
+    if (w && mask) project_bwd_adam_launch<D, true, true>(x, f, cfg, rec, M, po, cap, L, pg, m, v, w, mask, c, st, s);
+    else if (w) project_bwd_adam_launch<D, true, false>(x, f, cfg, rec, M, po, cap, L, pg, m, v, w, mask, c, st, s);
+    else project_bwd_adam_launch<D, false, false>(x, f, cfg, rec, M, po, cap, L, pg, m, v, w, mask, c, st, s);
 }
 
-hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const uint32_t* meta,
+hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_raster_cfg& cfg, const float* rec,
+                                   const uint32_t* meta,
                                    const gs_bins& bins, const float* pg, gs_params& m, gs_params& v,
                                    const gs_params* w, const float* mask, const gs_adam_cfg& acfg, hipStream_t s) {
     if (x.n == 0) return hipSuccess;
@@ -896,17 +928,17 @@ hipError_t launch_project_bwd_adam(gs_params& x, const gs_frame& f, const gs_ras
     const uint64_t cap = bins.capacity;
     uint32_t* st = bins.counters + GS_CTR_STATUS;
     switch (x.sh_degree) {
-        case 0: project_bwd_adam_pen<0>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
-        case 1: project_bwd_adam_pen<1>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
-        case 2: project_bwd_adam_pen<2>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
-        default: project_bwd_adam_pen<3>(x, f, cfg, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
+        case 0: project_bwd_adam_pen<0>(x, f, cfg, rec, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
+        case 1: project_bwd_adam_pen<1>(x, f, cfg, rec, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
+        case 2: project_bwd_adam_pen<2>(x, f, cfg, rec, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
+        default: project_bwd_adam_pen<3>(x, f, cfg, rec, M, po, cap, L, pg, m, v, w, mask, c, st, s); break;
     }
     return hipGetLastError();
 }
 
 template hipError_t launch_project<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, float*, uint32_t*, uint32_t*, hipStream_t);
 template hipError_t launch_project<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, double*, uint32_t*, uint32_t*, hipStream_t);
-template hipError_t launch_project_bwd<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const gs_bins&, const float*, gs_params&, hipStream_t);
-template hipError_t launch_project_bwd<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const uint32_t*, const gs_bins&, const double*, gs_params&, hipStream_t);
+template hipError_t launch_project_bwd<float>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const float*, const uint32_t*, const gs_bins&, const float*, gs_params&, hipStream_t);
+template hipError_t launch_project_bwd<double>(const gs_params&, const gs_frame&, const gs_raster_cfg&, const double*, const uint32_t*, const gs_bins&, const double*, gs_params&, hipStream_t);
 
 }  // namespace gs

@@ -28,8 +28,9 @@
 // at its emission index, where the projection backward adds each record's
 // pairs in a fixed order (deterministic, no float atomics).  The nine values
 // are, with ge = dL/dalpha * alpha summed over the pair's pixels and
-// (dx, dy) = pixel - mean:
-//   sum ge, sum ge dx, sum ge dy, sum ge dx^2, sum ge dx dy, sum ge dy^2,
+// (e1, e2) the offset pixel - mean in the footprint's axes (e1 along the
+// conic's narrow axis (c, s) that the record carries, e2 = (-s, c) across):
+//   sum ge, sum ge e1, sum ge e2, sum ge e1^2, sum ge e1 e2, sum ge e2^2,
 //   and dL/dcolour (r, g, b).
 // The geometric gradients follow from these moments in closed form.
 #include "gs_device.hpp"
@@ -41,7 +42,9 @@ constexpr int kRenderWaves = 4;
 constexpr int kBwdBatch = 48;   // records staged per backward batch (of the 64 lanes)
 
 // record words as produced by the projection
-enum { R_MX = 0, R_MY, R_QA, R_QB, R_QC, R_LO, R_CR, R_CG, R_CB, R_DEPTH, R_HX, R_HY };
+enum { R_MX = 0, R_MY, R_QA, R_QB, R_QC, R_LO, R_CR, R_CG, R_CB, R_AXIS, R_HX, R_HY };
+// LDS slots of a staged backward record past the first nine: the moment frame
+enum { S_AXC = 9, S_AXS = 10 };
 
 template <typename T>
 struct Rec {
@@ -241,11 +244,12 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
                 const bool live = !(done & (1u << k)) && al >= amin;
                 if (__ballot(live) == 0) continue;     // uniform: no pixel of the wave reached
                 const T a = Num<T>::min(al, amax);
-                const T tn = Tr[k] * (T(1) - a);
+                const T aT = a * Tr[k];
+                const T tn = Tr[k] - aT;
                 const bool stop = live && tn < tmin;
                 const bool keep = live && !stop;
                 done |= stop ? (1u << k) : 0u;
-                const T wgt = keep ? a * Tr[k] : T(0);
+                const T wgt = keep ? aT : T(0);
                 C[k][0] = Num<T>::fma(wgt, g.c[0], C[k][0]);
                 C[k][1] = Num<T>::fma(wgt, g.c[1], C[k][1]);
                 C[k][2] = Num<T>::fma(wgt, g.c[2], C[k][2]);
@@ -283,8 +287,9 @@ template <typename T, int QX, int QY, int NS>
 __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     gs_frame frame, gs_raster_cfg cfg, const T* __restrict__ rec, const uint4* __restrict__ meta,
     const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
-    const uint32_t* __restrict__ order, uint64_t capacity, const T* __restrict__ rgb, int mode,
-    const T* __restrict__ gin, T* __restrict__ loss_out, T* __restrict__ pg) {
+    const uint32_t* __restrict__ order, uint64_t capacity, const T* __restrict__ rgb,
+    const uint32_t* __restrict__ ncontrib, int mode, const T* __restrict__ gin, T* __restrict__ loss_out,
+    T* __restrict__ pg) {
     constexpr int PPL = QX * QY;
     // NS wavefronts per tile, wave `sub` owning the tile's sub-tile of QX x QY
     // quadrants and storing its own nine partials per pair (slot e NS + sub);
@@ -358,20 +363,24 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     const int64_t plane = int64_t(W) * H;
     const T inv = T(job.loss_weight) / T(3 * plane);
 
-    // per pixel: transmittance, dL/dC, D = sum_c dL/dC_c * C_final_c and the
-    // running S = sum_c dL/dC_c * C_accumulated_c
+    // per pixel: transmittance, dL/dC, D = sum_c dL/dC_c * C_final_c, the
+    // running S = sum_c dL/dC_c * C_accumulated_c, and the forward's count
+    // of list entries up to its last contributor (nc): a Gaussian is kept
+    // at a pixel exactly when alpha >= alpha_min and its list position is
+    // below nc, so the forward's stop rule needs no re-evaluation
     T Tr[PPL], gc[PPL][3], D[PPL], S[PPL];
-    uint32_t done = 0;
+    uint32_t nc[PPL];
     T loss = T(0);
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
         const bool in = x < W && y < H && (owned & (1u << k));
-        done |= in ? 0u : (1u << k);
         Tr[k] = T(1);
         D[k] = S[k] = T(0);
         gc[k][0] = gc[k][1] = gc[k][2] = T(0);
+        nc[k] = 0u;
         if (in) {
+            nc[k] = ncontrib[job.px0 + int64_t(y) * W + x];
             const int64_t o = 3 * job.px0 + int64_t(y) * W + x;
 #pragma unroll
             for (int ch = 0; ch < 3; ch++) {
@@ -396,21 +405,31 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     }
 
     const uint2 range = ranges[tile];
-    const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
+    const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max);
     const T lmin = Num<T>::log2(amin);
-    constexpr uint32_t all = (1u << PPL) - 1;
+    // per quadrant, the list entries any of its pixels still needs
+    uint32_t qend[PPL];
+    uint32_t wend = 0u;
+#pragma unroll
+    for (int k = 0; k < PPL; k++) {
+        qend[k] = uniform(wave_max_u32(nc[k]));
+        wend = qend[k] > wend ? qend[k] : wend;
+    }
     const int row = lane >> 4;
     for (uint32_t base = range.x; base < range.y; base += kBwdBatch) {
         const uint32_t cnt = min(uint32_t(kBwdBatch), range.y - base);
-        const bool any_alive = __ballot(done != all) != 0;
+        const uint32_t pos0 = base - range.x;   // list position of the batch's first entry
         uint32_t e_own = 0;   // pair this lane stores at the end of the batch
         T w[GS_REC_WORDS];
         uint32_t m = 0, r = 0;
         if (uint32_t(lane) < cnt) {
             r = vals[base + lane];
-            if (any_alive) {
+            const uint32_t pos = pos0 + uint32_t(lane);
+            if (pos < wend) {
                 load_rec(rec, r, w);
                 m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin) & owned;
+#pragma unroll
+                for (int k = 0; k < PPL; k++) m &= pos < qend[k] ? ~0u : ~(1u << k);
             }
             // emission index of pair (this tile, r): the record's pairs run
             // row by row over its tile rectangle
@@ -418,16 +437,16 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             const uint32_t x0 = mt.z & 0xffffu, y0 = mt.z >> 16, x1 = mt.w & 0xffffu;
             e_own = pair_off[r] + (uint32_t(ty) - y0) * (x1 - x0 + 1) + (uint32_t(tx) - x0);
         }
-        if (!any_alive) {
-            // every pixel of the tile has terminated: the rest of its pairs
-            // carry zero gradient
+        if (pos0 >= wend) {
+            // past every pixel's last contributor: the rest of the tile's
+            // pairs carry zero gradient
             if (uint32_t(lane) < cnt)
 #pragma unroll
                 for (int q = 0; q < 9; q++) pg[pslot(e_own) + q] = T(0);
             continue;
         }
-        // records that reach some quadrant are staged compacted; the others
-        // store zero partials below
+        // records that reach some quadrant are staged compacted, with their
+        // list position; the others store zero partials below
         const uint64_t staged = __ballot(m != 0);
         const uint32_t slot = __builtin_popcountll(staged & lanemask_lt());
         if (m != 0) {
@@ -437,52 +456,53 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             for (int q = 0; q < 6; q++) dst[q] = w[q];
 #pragma unroll
             for (int q = 6; q < 9; q++) dst[q] = src[q];
-            s_mask[wave][slot] = m;
+            narrow_axis(w[R_AXIS], dst[S_AXC], dst[S_AXS]);
+            s_mask[wave][slot] = m | (uint32_t(lane) << 8);
         }
         wave_lds_sync();
         const uint32_t n = __builtin_popcountll(staged);
         for (uint32_t i = 0; i < n; i++) {
-            const uint32_t qmask = uniform(s_mask[wave][i]);
+            const uint32_t word = uniform(s_mask[wave][i]);
+            const uint32_t qmask = word & 0xffu, pos = pos0 + (word >> 8);
             const Rec<T> g = lds_rec(s_rec[wave][i]);
+            const T axc = s_rec[wave][i][S_AXC], axs = s_rec[wave][i][S_AXS];
             T mo[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
             T dcol[3] = {T(0), T(0), T(0)};
-            bool hit = false;
+            bool hit = false;   // uniform: some lane kept the record
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
                 if (!(qmask & (1u << k))) continue;   // uniform: box misses quadrant k
                 const T dx = quad_centre(bx, k % QX) - g.mx, dy = quad_centre(by, k / QX) - g.my;
                 const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
-                const bool live = !(done & (1u << k)) && al >= amin;
-                if (__ballot(live) == 0) continue;     // uniform: no pixel of the wave reached
-                // the forward's operations, predicated the same way
+                const bool keep = al >= amin && pos < nc[k];
+                if (__ballot(keep) == 0) continue;     // uniform: no pixel of the wave keeps it
+                hit = true;
+                // the forward's operations on the kept pixels; zeros elsewhere
                 const T a = Num<T>::min(al, amax);
-                const T tn = Tr[k] * (T(1) - a);
-                const bool stop = live && tn < tmin;
-                const bool keep = live && !stop;
-                done |= stop ? (1u << k) : 0u;
-                const T wgt = keep ? a * Tr[k] : T(0);
+                const T ak = keep ? a : T(0);
+                const T wgt = ak * Tr[k];
                 const T gcc = Num<T>::fma(gc[k][2], g.c[2], Num<T>::fma(gc[k][1], g.c[1], gc[k][0] * g.c[0]));
                 S[k] = Num<T>::fma(wgt, gcc, S[k]);
                 // dL/dalpha = sum_c gc_c (c_c T - (C_final_c - C_acc_c) / (1 - alpha))
                 const T ga = Num<T>::fma(Tr[k], gcc, -(D[k] - S[k]) * recip(T(1) - a));
 #pragma unroll
                 for (int ch = 0; ch < 3; ch++) dcol[ch] = Num<T>::fma(gc[k][ch], wgt, dcol[ch]);
-                Tr[k] = keep ? tn : Tr[k];
-                hit = hit || keep;
+                Tr[k] -= wgt;
                 // alpha clamped at alpha_max: no gradient to the Gaussian's shape
-                const T ge = keep && al < amax ? ga * al : T(0);
-                const T t1 = ge * dx, t2 = ge * dy;
+                const T ge = (al < amax ? ak : T(0)) * ga;
+                const T e1 = Num<T>::fma(axc, dx, axs * dy), e2 = Num<T>::fma(axc, dy, -(axs * dx));
+                const T t1 = ge * e1, t2 = ge * e2;
                 mo[0] += ge;
                 mo[1] += t1;
                 mo[2] += t2;
-                mo[3] = Num<T>::fma(t1, dx, mo[3]);
-                mo[4] = Num<T>::fma(t1, dy, mo[4]);
-                mo[5] = Num<T>::fma(t2, dy, mo[5]);
+                mo[3] = Num<T>::fma(t1, e1, mo[3]);
+                mo[4] = Num<T>::fma(t1, e2, mo[4]);
+                mo[5] = Num<T>::fma(t2, e2, mo[5]);
             }
             // per-row partial sums (16 lanes), parked in LDS; the rows are
             // added and the pair stored once per batch, one lane per record
             T* rs = s_rows[wave][i][row];
-            if (__ballot(hit) != 0) {
+            if (hit) {
                 T v[9];
 #pragma unroll
                 for (int q = 0; q < 6; q++) v[q] = row_sum_last(mo[q]);
@@ -572,12 +592,13 @@ static void fwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec
 
 template <typename T, int QX, int QY, int NS>
 static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
-                       const gs_bins& b, const T* rgb, int mode, const T* gin, T* loss, T* pg, hipStream_t s) {
+                       const gs_bins& b, const T* rgb, const uint32_t* nc, int mode, const T* gin, T* loss, T* pg,
+                       hipStream_t s) {
     dim3 grid, block;
     compositing_grid<NS>(f, grid, block);
     GS_LAUNCH("k_render_bwd", (k_render_bwd<T, QX, QY, NS>), grid, block, 0, s, f, cfg, rec,
               reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals, reinterpret_cast<const uint2*>(b.ranges),
-              b.tile_order, b.capacity, rgb, mode, gin, loss, pg);
+              b.tile_order, b.capacity, rgb, nc, mode, gin, loss, pg);
 }
 
 // (binning tile, wavefronts per tile) -> quadrants per wavefront QX x QY:
@@ -617,16 +638,16 @@ hipError_t launch_render_fwd(const gs_frame& f, const gs_raster_cfg& cfg, const 
 
 template <typename T>
 hipError_t launch_render_bwd(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec, const uint32_t* meta,
-                             const gs_bins& bins, const T* rgb, gs_loss_mode mode, const T* gin, T* loss, T* pg,
-                             hipStream_t s) {
+                             const gs_bins& bins, const T* rgb, const uint32_t* nc, gs_loss_mode mode, const T* gin,
+                             T* loss, T* pg, hipStream_t s) {
     if (f.n_tiles == 0) return hipSuccess;
-    GS_TILE_DISPATCH(bwd_waves(cfg), bwd_launch, f, cfg, rec, meta, bins, rgb, int(mode), gin, loss, pg, s);
+    GS_TILE_DISPATCH(bwd_waves(cfg), bwd_launch, f, cfg, rec, meta, bins, rgb, nc, int(mode), gin, loss, pg, s);
     return hipGetLastError();
 }
 
 template hipError_t launch_render_fwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const gs_bins&, float*, float*, uint32_t*, unsigned long long*, hipStream_t);
 template hipError_t launch_render_fwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const gs_bins&, double*, double*, uint32_t*, unsigned long long*, hipStream_t);
-template hipError_t launch_render_bwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const uint32_t*, const gs_bins&, const float*, gs_loss_mode, const float*, float*, float*, hipStream_t);
-template hipError_t launch_render_bwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const uint32_t*, const gs_bins&, const double*, gs_loss_mode, const double*, double*, double*, hipStream_t);
+template hipError_t launch_render_bwd<float>(const gs_frame&, const gs_raster_cfg&, const float*, const uint32_t*, const gs_bins&, const float*, const uint32_t*, gs_loss_mode, const float*, float*, float*, hipStream_t);
+template hipError_t launch_render_bwd<double>(const gs_frame&, const gs_raster_cfg&, const double*, const uint32_t*, const gs_bins&, const double*, const uint32_t*, gs_loss_mode, const double*, double*, double*, hipStream_t);
 
 }  // namespace gs

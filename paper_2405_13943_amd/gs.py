@@ -65,6 +65,13 @@ class GsAdamCfg(ctypes.Structure):
                 ("reserved", c_i32), ("step", c_i64)]
 
 
+class GsTuneChoice(ctypes.Structure):
+    _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("fwd_waves", c_i32), ("bwd_waves", c_i32)]
+
+
+TUNE_STEP_FN = ctypes.CFUNCTYPE(c_i32, ctypes.POINTER(GsTuneChoice), c_vp)
+
+
 class GsError(RuntimeError):
     pass
 
@@ -91,14 +98,14 @@ def _load():
         "gs_render_fwd_f64": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_render_fwd_stats": ([P(GsFrame), P(GsRasterCfg), c_vp, P(GsBins), c_vp, c_vp, c_vp, c_vp, c_vp], c_i32),
         "gs_render_bwd_workspace_size": ([c_u64, c_i32], ctypes.c_size_t),
-        "gs_render_bwd": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_i32, c_vp, c_vp,
-                           P(GsParams), c_vp, ctypes.c_size_t, c_vp], c_i32),
-        "gs_render_bwd_f64": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_i32, c_vp,
-                               c_vp, P(GsParams), c_vp, ctypes.c_size_t, c_vp], c_i32),
+        "gs_render_bwd": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_vp, c_i32, c_vp,
+                           c_vp, P(GsParams), c_vp, ctypes.c_size_t, c_vp], c_i32),
+        "gs_render_bwd_f64": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_vp, c_i32,
+                               c_vp, c_vp, P(GsParams), c_vp, ctypes.c_size_t, c_vp], c_i32),
         "gs_adam_admm": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg),
                           c_vp, c_vp], c_i32),
-        "gs_render_bwd_adam": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_i32, c_vp,
-                                c_vp, P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg), c_vp,
+        "gs_render_bwd_adam": ([P(GsParams), P(GsFrame), P(GsRasterCfg), c_vp, c_vp, P(GsBins), c_vp, c_vp, c_i32,
+                                c_vp, c_vp, P(GsParams), P(GsParams), P(GsParams), c_vp, P(GsAdamCfg), c_vp,
                                 ctypes.c_size_t, c_vp], c_i32),
         "gs_consensus": ([P(GsParams), P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, c_f, c_vp, c_vp], c_i32),
         "gs_penalty_update": ([P(c_f), P(c_f), c_f, c_f, c_f, P(c_f)], c_i32),
@@ -109,6 +116,9 @@ def _load():
         "gs_ssim_loss_grad": ([P(GsFrame), P(GsRasterCfg), c_vp, c_vp, c_f, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp],
                               c_i32),
         "gs_dual_rescale": ([P(GsParams), P(GsParams), P(GsParams), c_vp, c_vp, P(c_f), c_vp], c_i32),
+        "gs_set_tune_cache": ([ctypes.c_char_p], c_i32),
+        "gs_autotune": ([ctypes.c_char_p, P(GsTuneChoice), c_i32, c_i32, TUNE_STEP_FN, c_vp, c_vp, P(GsTuneChoice),
+                         P(ctypes.c_double)], c_i32),
         "gs_profile_set": ([ctypes.c_char_p], c_i32),
         "gs_profile_get": ([ctypes.c_char_p, P(ctypes.c_double), P(c_i64)], c_i32),
     }
@@ -329,8 +339,8 @@ def render_bwd(params: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffer
     b = buf.bins
     fn = lib.gs_render_bwd_f64 if buf.f64 else lib.gs_render_bwd
     _check(fn(ctypes.byref(p), ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.rec), _ptr(buf.meta),
-              ctypes.byref(b), _ptr(buf.rgb), mode, _ptr(grad_in), _ptr(loss_out), ctypes.byref(g),
-              _ptr(buf.bwd_ws), buf.bwd_ws.numel(), _stream()), "gs_render_bwd")
+              ctypes.byref(b), _ptr(buf.rgb), _ptr(buf.ncontrib), mode, _ptr(grad_in), _ptr(loss_out),
+              ctypes.byref(g), _ptr(buf.bwd_ws), buf.bwd_ws.numel(), _stream()), "gs_render_bwd")
 
 
 def ssim_loss_grad(frame: Frame, cfg: GsRasterCfg, rgb: torch.Tensor, target: torch.Tensor, lam: float,
@@ -425,7 +435,8 @@ def render_bwd_adam(x: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffer
     pw = params_struct(w) if w is not None else None
     b = buf.bins
     _check(lib.gs_render_bwd_adam(ctypes.byref(px), ctypes.byref(frame.struct), ctypes.byref(cfg), _ptr(buf.rec),
-                                  _ptr(buf.meta), ctypes.byref(b), _ptr(buf.rgb), mode, _ptr(grad_in),
+                                  _ptr(buf.meta), ctypes.byref(b), _ptr(buf.rgb), _ptr(buf.ncontrib), mode,
+                                  _ptr(grad_in),
                                   _ptr(loss_out), ctypes.byref(pm), ctypes.byref(pv),
                                   ctypes.byref(pw) if pw is not None else None, _ptr(mask), ctypes.byref(acfg),
                                   _ptr(buf.bwd_ws), buf.bwd_ws.numel(), _stream()), "gs_render_bwd_adam")
@@ -480,6 +491,39 @@ def rasterize(params: torch.Tensor, frame: Frame, cfg: GsRasterCfg, buf: Buffers
         buf.grow(int(c["pairs"] * 1.25) + 1024)
     render_fwd(frame, cfg, buf)
     return buf
+
+
+def set_tune_cache(path):
+    """JSON file of the tuned launch shapes (None: in memory only)."""
+    _check(lib.gs_set_tune_cache(path.encode() if path else None), "gs_set_tune_cache")
+
+
+def autotune(key, candidates, run_step, reps=5):
+    """gs_autotune: the fastest of ``candidates`` ((tile_w, tile_h, fwd_waves,
+    bwd_waves) tuples) for workload ``key``, timed by the library over
+    ``run_step(choice_tuple)`` calls on the current stream (or taken from its
+    cache).  Returns (choice tuple, ms per step or -1 when cached without a
+    time)."""
+    cands = (GsTuneChoice * len(candidates))(*[GsTuneChoice(*map(int, c)) for c in candidates])
+    failure = []
+
+    def cb(choice, _user):
+        c = choice.contents
+        try:
+            run_step((c.tile_w, c.tile_h, c.fwd_waves, c.bwd_waves))
+            return 0
+        except Exception as e:          # reported through the status, re-raised below
+            failure.append(e)
+            return 1
+    fn = TUNE_STEP_FN(cb)
+    best, ms = GsTuneChoice(), ctypes.c_double(-1.0)
+    stream = _stream() if torch.cuda.is_available() else None   # a cached key needs no device
+    rc = lib.gs_autotune(key.encode(), cands, len(candidates), int(reps), fn, None, stream, ctypes.byref(best),
+                         ctypes.byref(ms))
+    if failure:
+        raise failure[0]
+    _check(rc, "gs_autotune")
+    return (best.tile_w, best.tile_h, best.fwd_waves, best.bwd_waves), ms.value
 
 
 def profile_set(names):

@@ -124,7 +124,7 @@ def test_invalid_arguments_rejected_without_launch(gs):
     # backward workspace too small
     bins = gs.GsBins(1, 1, 1, 1, 1000, 1)
     rc = gs.lib.gs_render_bwd(ctypes.byref(p10), ctypes.byref(gs.GsFrame(1, 1, 1, 1, 10, 10, 10, 1, 0)), ctypes.byref(cfg),
-                              1, 1, ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), 1, 8, None)
+                              1, 1, ctypes.byref(bins), 1, 1, 0, 1, None, ctypes.byref(p10), 1, 8, None)
     assert rc == gs.GS_E_CAPACITY
     # Adam with mismatched planes, bad step
     a = gs.GsParams(1, 10, 10, 0, 0)
@@ -142,16 +142,16 @@ def test_invalid_arguments_rejected_without_launch(gs):
     # fused backward + Adam: shared Gaussians unsupported, bad planes, small workspace
     fr_shared = gs.GsFrame(1, 1, 2, 2, 20, 20, 10, 0, 0)
     rc = gs.lib.gs_render_bwd_adam(ctypes.byref(p10), ctypes.byref(fr_shared), ctypes.byref(cfg), 1, 1,
-                                   ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), ctypes.byref(p10), None, None,
+                                   ctypes.byref(bins), 1, 1, 0, 1, None, ctypes.byref(p10), ctypes.byref(p10), None, None,
                                    ctypes.byref(acfg), 1, 1 << 20, None)
     assert rc == gs.GS_E_UNSUPPORTED and "share" in gs.lib.gs_last_error().decode()
     fr_disj = gs.GsFrame(1, 1, 1, 1, 10, 10, 10, 1, 0)
     rc = gs.lib.gs_render_bwd_adam(ctypes.byref(p10), ctypes.byref(fr_disj), ctypes.byref(cfg), 1, 1,
-                                   ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(b), ctypes.byref(p10), None, None,
+                                   ctypes.byref(bins), 1, 1, 0, 1, None, ctypes.byref(b), ctypes.byref(p10), None, None,
                                    ctypes.byref(acfg), 1, 1 << 20, None)
     assert rc == gs.GS_E_INVALID
     rc = gs.lib.gs_render_bwd_adam(ctypes.byref(p10), ctypes.byref(fr_disj), ctypes.byref(cfg), 1, 1,
-                                   ctypes.byref(bins), 1, 0, 1, None, ctypes.byref(p10), ctypes.byref(p10), None, None,
+                                   ctypes.byref(bins), 1, 1, 0, 1, None, ctypes.byref(p10), ctypes.byref(p10), None, None,
                                    ctypes.byref(acfg), 1, 8, None)
     assert rc == gs.GS_E_CAPACITY
 
@@ -170,6 +170,34 @@ def test_bin_sort_noalloc_size_limit_host_only(gs):
     assert rc == gs.GS_E_CAPACITY and "static scratch" in gs.lib.gs_last_error().decode()
     assert gs.lib.gs_bin_sort_noalloc(ctypes.byref(fr), ctypes.byref(cfg), None, ctypes.byref(big), None) == gs.GS_E_INVALID
     assert gs.lib.gs_bin_sort_noalloc(ctypes.byref(fr), ctypes.byref(cfg), 1, None, None) == gs.GS_E_INVALID
+
+
+def test_autotune_cache_host_only(gs, tmp_path):
+    """gs_autotune answers a cached workload key from the JSON cache without
+    calling the step (no device work), rejects invalid candidates and
+    arguments, and gs_set_tune_cache rejects a malformed file."""
+    import json
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"blocks-4": {"tile": [32, 8, -1, -1], "ms": {"32x8x-1x-1": 8.5, "16x16x-1x-1": 9.0},
+                                             "when": "x"},
+                                "other": {"tile": [8, 8, 1, 1], "ms": {}}}))
+    gs.set_tune_cache(str(path))
+    calls = []
+    cands = [(16, 16, -1, -1), (32, 8, -1, -1)]
+    best, ms = gs.autotune("blocks-4", cands, lambda t: calls.append(t), reps=2)
+    assert best == (32, 8, -1, -1) and ms == 8.5 and not calls
+    best, ms = gs.autotune("other", cands, lambda t: calls.append(t))
+    assert best == (8, 8, 1, 1) and ms == -1.0 and not calls
+    with pytest.raises(gs.GsError, match="not a valid launch shape"):
+        gs.autotune("blocks-4", [(12, 12, 1, 1)], lambda t: calls.append(t))
+    with pytest.raises(gs.GsError, match="at least one"):
+        gs.autotune("blocks-4", cands, lambda t: calls.append(t), reps=0)
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"k": {"tile": [16, 16]}}')
+    with pytest.raises(gs.GsError, match="malformed"):
+        gs.set_tune_cache(str(bad))
+    gs.set_tune_cache(None)
+    assert not calls
 
 
 def test_profile_registry_host_only(gs):

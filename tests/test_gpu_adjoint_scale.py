@@ -1,5 +1,5 @@
 """Adjoint at scale: 2M Gaussians (SH 3) in one 1920x1080 view, image and
-gradients of the HIP path against the FP64 oracle on two 256x256 crops.
+gradients of the HIP path against the FP64 oracle on four 256x256 crops.
 
 The loss is L = sum(W * C) with a seeded W ~ N(0, 1) on the crop's pixels and
 zero elsewhere (and zero at pixels the oracle flags as within rounding of a
@@ -32,7 +32,7 @@ def group_planes(A):
     return {**GROUPS, "f": list(range(11, A))}
 
 
-CROPS = ((832, 412), (200, 150))
+CROPS = ((832, 412), (200, 150), (1100, 40), (1400, 300))
 CROP = 256
 
 

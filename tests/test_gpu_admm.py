@@ -213,8 +213,10 @@ def test_adaptive_penalty_rounds_match_oracle():
 
 def test_autograd_function_fp64_against_finite_differences():
     """GaussianRasterize in FP64 (200 Gaussians, SH 3, 64x64): backward
-    through torch.autograd equals central differences of the forward on a
-    seeded subset of parameters."""
+    through torch.autograd equals central differences h = 1e-6 of the
+    forward on every one of the 11,800 parameters (coordinates whose
+    keep/stop decisions flip inside [-h, h] are left out)."""
+    from fd_batch import finite_differences
     s = scenes.config4a()
     cfg = gs.raster_cfg((16, 16))
     frame = gs.Frame(s.cams, [gs.JobSpec(0, 0, 200, 1.0)], cfg)
@@ -223,24 +225,12 @@ def test_autograd_function_fp64_against_finite_differences():
     out = raster.rasterize(p, frame, cfg)
     (W * out).sum().backward()
     g = p.grad.cpu().numpy()
-    rng = np.random.default_rng(4)
-    h = 1e-6
-    base_n = gs.rasterize(p.detach(), frame, cfg).ncontrib.clone()
-    checked = 0
-    for a, i in zip(rng.integers(0, 59, 150), rng.integers(0, 200, 150)):
-        vals, flip = [], False
-        for sgn in (1, -1):
-            q = p.detach().clone()
-            q[a, i] += sgn * h
-            b = gs.rasterize(q, frame, cfg)
-            flip |= not torch.equal(b.ncontrib, base_n)
-            vals.append(float((W * b.rgb).sum()))
-        if flip:
-            continue
-        checked += 1
-        fd = (vals[0] - vals[1]) / (2 * h)
-        assert abs(fd - g[a, i]) <= 1e-5 * abs(g[a, i]) + 2e-6, (a, i, fd, g[a, i])
-    assert checked > 120
+    coords = [(a, i) for a in range(59) for i in range(200)]
+    fd, noise, flipped = finite_differences(p.detach(), s.cams[0], W, coords, cfg)
+    ga = np.array([g[a, i] for a, i in coords])
+    bad = (np.abs(fd - ga) > 1e-5 * np.abs(ga) + 1e-9 * np.abs(g).max() + noise) & ~flipped
+    assert (~flipped).sum() >= 0.9 * len(coords)
+    assert not bad.any(), [(coords[k], fd[k], ga[k]) for k in np.nonzero(bad)[0][:10]]
 
 
 def test_autotuner_picks_a_candidate_and_caches(tmp_path):
@@ -257,6 +247,12 @@ def test_autotuner_picks_a_candidate_and_caches(tmp_path):
     path = str(tmp_path / "tune.json")
     best = admm.autotune_tile(run, "tiny-3blocks", path, reps=2)
     assert best in admm.TILES
+    # libgs timed every candidate and wrote them to the cache file
+    import json
+    ent = json.load(open(path))["tiny-3blocks"]
+    assert tuple(ent["tile"]) == best
+    assert len(ent["ms"]) == len(admm.TILES) and all(v > 0 for v in ent["ms"].values())
+    assert ent["ms"]["x".join(map(str, best))] == min(ent["ms"].values())
     assert admm.autotune_tile(lambda t: (_ for _ in ()).throw(AssertionError), "tiny-3blocks", path) == best
 
 
