@@ -33,7 +33,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-BWD_FLOPS = 46
+# VALU operations per (pixel, Gaussian) evaluation up to each pixel's
+# termination, and per visible Gaussian, that bound the compositing and
+# projection kernels from below (an exp counted as 4)
+FWD_OPS = 25
+BWD_OPS = 70
+PROJ_OPS = 150
+PROJ_BWD_OPS = 400
+ADAM_OPS = 15            # per parameter
 ORDER_STRANDS = 1024     # strands of the default training storage order (see setup)
 LR = (1.6e-4, 1e-3, 5e-3, 2.5e-3, 5e-2)       # mean, rotation, scale, SH, opacity
 RHO = (1e-3,) * 5
@@ -306,15 +313,17 @@ def run_gpu(args):
         torch.cuda.synchronize()
     # work of the timed views, counted after the timed region on the final
     # parameters: (pixel, Gaussian) contributions and tile pairs per view
-    kept = pairs = 0
+    kept = pairs = visible = 0
     nv = min(args.steps, len(frames))
     for t in range(args.warmup, args.warmup + nv):
         f = frames[t % len(frames)]
         gs.project(st["x"], f, cfg, buf)
         gs.bin_sort(f, cfg, buf)
         kept += gs.render_fwd_stats(f, cfg, buf)
-        pairs += gs.read_counters(buf)["pairs"]
-    kept, pairs = kept / nv, pairs / nv
+        c = gs.read_counters(buf)
+        pairs += c["pairs"]
+        visible += c["visible"]
+    kept, pairs, visible = kept / nv, pairs / nv, visible / nv
     status = gs.read_counters(buf)["status"]
     if status & gs.GS_STATUS_PAIR_OVERFLOW:
         raise SystemExit("pair capacity overflowed during the timed steps; rerun with more headroom")
@@ -333,10 +342,10 @@ def run_gpu(args):
     else:
         opt_kernel, opt_bytes = "k_project_bwd_adam", 28 * A * N + 20 * N + 36 * pairs
     opt_ms = kern[opt_kernel]
-    # ALU roofline of the compositing backward: BWD_FLOPS FP32 operations per
+    # ALU roofline of the compositing backward: BWD_OPS VALU operations per
     # (pixel, Gaussian) contribution (alpha recomputed, transmittance, colour
-    # behind, dL/dalpha, colour and moment accumulations; an FMA counts 2)
-    bwd_flops = BWD_FLOPS * kept
+    # behind, dL/dalpha, colour and moment accumulations)
+    bwd_flops = BWD_OPS * kept
     ssim = None
     if lam > 0:
         # algorithmic bytes of the two SSIM passes per colour value: the
@@ -353,8 +362,49 @@ def run_gpu(args):
     return dict(ms_per_step=ms / args.steps, steps=args.steps, stage_ms=stage, kernel_ms=kern, opt_kernel=opt_kernel,
                 ssim=ssim,
                 opt_bytes=opt_bytes, opt_gbs=opt_bytes / (opt_ms * 1e-3) / 1e9, pairs_max=pmax, pairs=pairs,
-                kept=kept, bwd_flops=bwd_flops, bwd_tflops=bwd_flops / (kern["k_render_bwd"] * 1e-3) / 1e12, N=N, A=A,
+                kept=kept, visible=visible, hw=args.width * args.height, bwd_flops=bwd_flops, bwd_tflops=bwd_flops / (kern["k_render_bwd"] * 1e-3) / 1e12, N=N, A=A,
                 scene=scene)
+
+
+def step_roofline(N, A, V, P, E, HW, ms_per_step, fused=True):
+    """Roofline of the whole training step: T_roof = sum over its kernels of
+    max(algorithmic HBM bytes / 8 TB/s, VALU operations / 157.3 TFLOP/s),
+    against the measured time per step.  Per kernel (V visible records, P
+    tile pairs, E (pixel, Gaussian) evaluations up to termination, HW
+    pixels):
+      project       12 N + 4 (A - 3) V + 52 V bytes      PROJ_OPS V
+      pair emission 8 V + 12 P
+      tile sort     24 P (one read and one write of the pairs)
+      ranges        8 P
+      forward       40 P + 20 HW                         FWD_OPS E
+      backward      76 P + 44 HW (records, partials)     BWD_OPS E
+      projection backward + Adam/ADMM, fused: x, m, v, w read and x, m, v
+      written (28 A N), meta and pair offset (20 N), nine partials per pair
+      (36 P)                                             PROJ_BWD_OPS V + ADAM_OPS A N
+    The two-call form counts the projection backward (4 A V + 36 V + 4 A N)
+    and the optimiser (32 A N: the gradient is written and read back)
+    separately."""
+    bw, alu = HBM_PEAK_GBS * 1e9, FP32_VECTOR_PEAK_TFLOPS * 1e12
+    rows = {
+        "project": (12 * N + 4 * (A - 3) * V + 52 * V, PROJ_OPS * V),
+        "emit": (8 * V + 12 * P, 0.0),
+        "sort": (24 * P, 0.0),
+        "ranges": (8 * P, 0.0),
+        "render_fwd": (40 * P + 20 * HW, FWD_OPS * E),
+        "render_bwd": (76 * P + 44 * HW, BWD_OPS * E),
+    }
+    if fused:
+        rows["project_bwd_adam"] = (28 * A * N + 20 * N + 36 * P, PROJ_BWD_OPS * V + ADAM_OPS * A * N)
+    else:
+        rows["project_bwd"] = (4 * A * V + 36 * V + 4 * A * N, PROJ_BWD_OPS * V)
+        rows["adam_admm"] = (32 * A * N, ADAM_OPS * A * N)
+    t = {k: max(b / bw, o / alu) for k, (b, o) in rows.items()}
+    t_roof = sum(t.values())
+    return {"t_roof_ms": round(t_roof * 1e3, 5), "t_measured_ms": round(ms_per_step, 5),
+            "frac": round(t_roof * 1e3 / ms_per_step, 4),
+            "per_kernel_roof_us": {k: round(v * 1e6, 2) for k, v in t.items()},
+            "bytes": int(sum(b for b, _ in rows.values())), "valu_ops": float(sum(o for _, o in rows.values())),
+            "counts": {"N": int(N), "A": int(A), "V": round(V), "P": round(P), "E": round(E), "HW": int(HW)}}
 
 
 def run_serve(args):
@@ -737,18 +787,33 @@ def run_blocks4(args):
     return out
 
 
-def cpu_baseline(scene, budget_s=12.0):
-    """The FP64 oracle on the host: fwd + bwd of one 1600x1066 view on a
-    seeded pixel sample (extrapolated by pixel count), plus the Adam + ADMM
-    oracle over all N."""
+def cpu_model():
+    """Model name of the host CPU (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, budget_s=8.0):
+    """The FP64 oracle on the host.  All threads: fwd + bwd of one 1600x1066
+    view on a seeded pixel sample sized to about budget_s (extrapolated by
+    pixel count) plus the Adam + ADMM oracle over all N: the step rate.  One
+    thread: the same on 32 and 160 pixels.  And one full step of the parity
+    scene (2,000 Gaussians, four 128x128 views, fwd + bwd + Adam/ADMM) on
+    all threads."""
     import oracle
-    cam = scene.cams[0]
-    target = None
     from paper_2405_13943_amd import scenes
+    lib = oracle.load_library()
+    cam = scene.cams[0]
     target = scenes.config2_targets(scene, [0])[0]
     rng = np.random.default_rng(5)
     npx_total = cam.width * cam.height
-    nthreads = oracle.load_library().orc_num_threads()
+    nthreads = lib.orc_num_threads()
 
     def fwd_bwd(npx):
         pix = rng.choice(npx_total, npx, replace=False)
@@ -759,24 +824,53 @@ def cpu_baseline(scene, budget_s=12.0):
         oracle.backward(scene.params, cam, dl, pixels=pix)
         return time.time() - t
 
-    # per-call time = fixed projection cost + per-pixel cost: two probes
-    # separate them, then the sample is sized to about budget_s
-    t64 = fwd_bwd(64)
-    t256 = fwd_bwd(256)
-    per_px = max((t256 - t64) / 192.0, 1e-6)
-    npx = int(min(npx_total, max(256, (budget_s - t64) / per_px)))
-    t_px = fwd_bwd(npx)
-    # the whole view: one fixed part plus every pixel at the sampled rate
-    t_img = t64 + (t_px - t64) * (npx_total - 64) / max(npx - 64, 1)
+    def view_seconds(budget):
+        # per-call time = fixed projection cost + per-pixel cost: two probes
+        # separate them, then the sample is sized to about `budget`
+        t64 = fwd_bwd(64)
+        t256 = fwd_bwd(256)
+        per_px = max((t256 - t64) / 192.0, 1e-6)
+        npx = int(min(npx_total, max(256, (budget - t64) / per_px)))
+        t_px = fwd_bwd(npx)
+        # the whole view: one fixed part plus every pixel at the sampled rate
+        return t64 + (t_px - t64) * (npx_total - 64) / max(npx - 64, 1), npx, t_px
+
     x = scene.params
     t = time.time()
     oracle.adam_admm(x, np.zeros_like(x), np.zeros_like(x), np.zeros_like(x), x, LR, RHO, 1)
     t_adam = time.time() - t
+    t_img, npx, t_px = view_seconds(budget_s)
     step_s = t_img + t_adam
+    # one thread: two sample sizes give the fixed and the per-pixel cost
+    lib.orc_set_threads(1)
+    try:
+        t_a = fwd_bwd(32)
+        npx1 = 160
+        t_px1 = fwd_bwd(npx1)
+    finally:
+        lib.orc_set_threads(nthreads)
+    t_img1 = t_a + max(t_px1 - t_a, 0.0) * (npx_total - 32) / (npx1 - 32)
+    # parity scene: a full step, every pixel of the four views
+    c1 = scenes.config1()
+    t = time.time()
+    g = np.zeros_like(c1.params, dtype=np.float64)
+    for v, c in enumerate(c1.cams):
+        r = oracle.render(c1.params, c)
+        dl = 0.25 * np.sign(r["rgb"] - c1.targets[v]) / r["rgb"].size
+        g += oracle.backward(c1.params, c, dl)
+    x1 = c1.params.astype(np.float64)
+    oracle.adam_admm(x1, g, np.zeros_like(x1), np.zeros_like(x1), x1, LR, RHO, 1)
+    t_c1 = time.time() - t
     return {"value": 1.0 / step_s, "unit": "steps/s", "cores": int(nthreads), "kind": "oracle",
             "sample": f"fwd+bwd on {npx} seeded pixels of one 1600x1066 view ({t_px:.1f}s, extrapolated to "
                       f"{npx_total} px: {t_img:.1f}s) + Adam/ADMM oracle over all {x.shape[1]} Gaussians "
-                      f"({t_adam:.1f}s)"}
+                      f"({t_adam:.1f}s)",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": 1.0 / (t_img1 + t_adam), "unit": "steps/s", "cores": 1,
+                              "sample": f"fwd+bwd on {npx1} seeded pixels ({t_px1:.1f}s, extrapolated: "
+                                        f"{t_img1:.1f}s) + the same Adam/ADMM time (all threads)"},
+            "parity_scene_step_s": round(t_c1, 3),
+            "parity_scene": "2,000 Gaussians SH0, 4 x 128x128 views, fwd+bwd+Adam/ADMM, every pixel, all threads"}
 
 
 def copy_probe(nbytes=1 << 30, reps=5):
@@ -909,7 +1003,9 @@ def main():
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(r["bwd_tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": measured_traffic("k_render_bwd", train_workload_label(args.order)),
-                     "work": f"{BWD_FLOPS} flops x {r['kept']:.4g} (pixel, Gaussian) contributions per launch"},
+                     "work": f"{BWD_OPS} VALU ops x {r['kept']:.4g} (pixel, Gaussian) contributions per launch"},
+        "roofline_step": step_roofline(r["N"], r["A"], r["visible"], r["pairs"], r["kept"], r["hw"],
+                                       r["ms_per_step"], fused=not args.unfused),
         "roofline_stream": {"bound": "hbm", "kernel": r["opt_kernel"], "achieved": round(r["opt_gbs"], 1),
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["opt_gbs"] / HBM_PEAK_GBS, 4),
                             "traffic": measured_traffic(r["opt_kernel"], train_workload_label(args.order)),

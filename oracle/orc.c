@@ -637,3 +637,6 @@ int orc_quat_rot(long n, const double *q, double *R) {
 }
 
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* threads of the following calls (timing of the oracle itself) */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -104,6 +104,8 @@ def load_library():
         lib.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp]
         lib.orc_quat_rot.argtypes = [ctypes.c_long, dp, dp]
         lib.orc_num_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         _lib = lib
     return _lib
 
