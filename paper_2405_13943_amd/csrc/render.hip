@@ -144,6 +144,60 @@ __device__ inline void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Stores the nine partials of two records' pairs (a at da, b at db; db may
+// be null), each summed over the wave's 64 lanes.  FP32: the two records are
+// reduced together; a swap of wave halves (v_permlane32_swap) and an add
+// leave record a's sums in lanes 0-31 and b's in lanes 32-63; a swap of
+// odd and even rows (v_permlane16_swap) between neighbouring partials and an
+// add leave in each row of 16 lanes five partials of one record (the even or
+// the odd ones); a row sum finishes them in the row's last lane, which
+// stores them.  A fixed sequence of operations: the sums are deterministic.
+__device__ inline float swap_add32(float a, float b) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ inline float swap_add16(float a, float b) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
+__device__ inline void store_pair_partials(const float (&va)[9], const float (&vb)[9], float* da, float* db) {
+    const int lane = lane_id();
+    float x[9], y[5];
+#pragma unroll
+    for (int q = 0; q < 9; q++) x[q] = swap_add32(va[q], vb[q]);
+#pragma unroll
+    for (int j = 0; j < 4; j++) y[j] = swap_add16(x[2 * j], x[2 * j + 1]);
+    y[4] = swap_add16(x[8], 0.f);
+#pragma unroll
+    for (int j = 0; j < 5; j++) y[j] = row_sum_last(y[j]);
+    if ((lane & 15) == 15) {
+        const int r = lane >> 4;
+        float* dst = r < 2 ? da : db;
+        const int par = r & 1;
+        if (dst)
+#pragma unroll
+            for (int j = 0; j < 5; j++)
+                if (2 * j + par < 9) dst[2 * j + par] = y[j];
+    }
+}
+
+__device__ inline void store_pair_partials(const double (&va)[9], const double (&vb)[9], double* da, double* db) {
+    double sa[9], sb[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+        sa[q] = wave_sum(va[q]);
+        sb[q] = wave_sum(vb[q]);
+    }
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            da[q] = sa[q];
+            if (db) db[q] = sb[q];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // forward
 
@@ -300,7 +354,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     constexpr int NSD = ADAPT ? 1 : NS;
     __shared__ T s_rec[kRenderWaves][kBwdBatch][GS_REC_WORDS];
     __shared__ uint32_t s_mask[kRenderWaves][kBwdBatch];
-    __shared__ T s_rows[kRenderWaves][kBwdBatch][4][9];
+    __shared__ uint32_t s_eown[kRenderWaves][kBwdBatch];   // emission index of each staged pair
     const int wave = threadIdx.x / kWave, lane = lane_id();
     int tile = 0, sub = 0, nwaves = NSD;
     uint32_t owned = (1u << PPL) - 1u;
@@ -415,7 +469,6 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
         qend[k] = uniform(wave_max_u32(nc[k]));
         wend = qend[k] > wend ? qend[k] : wend;
     }
-    const int row = lane >> 4;
     for (uint32_t base = range.x; base < range.y; base += kBwdBatch) {
         const uint32_t cnt = min(uint32_t(kBwdBatch), range.y - base);
         const uint32_t pos0 = base - range.x;   // list position of the batch's first entry
@@ -458,16 +511,25 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             for (int q = 6; q < 9; q++) dst[q] = src[q];
             narrow_axis(w[R_AXIS], dst[S_AXC], dst[S_AXS]);
             s_mask[wave][slot] = m | (uint32_t(lane) << 8);
+            s_eown[wave][slot] = e_own;
+        } else if (uint32_t(lane) < cnt) {
+            // reaches no quadrant this wave owns: zero partials
+#pragma unroll
+            for (int q = 0; q < 9; q++) pg[pslot(e_own) + q] = T(0);
         }
         wave_lds_sync();
         const uint32_t n = __builtin_popcountll(staged);
-        for (uint32_t i = 0; i < n; i++) {
+        // composites staged record i over the wave's quadrants, leaves its nine
+        // partials (per lane) in v; false when no pixel kept it
+        auto composite = [&](uint32_t i, T (&v)[9]) -> bool {
             const uint32_t word = uniform(s_mask[wave][i]);
             const uint32_t qmask = word & 0xffu, pos = pos0 + (word >> 8);
             const Rec<T> g = lds_rec(s_rec[wave][i]);
             const T axc = s_rec[wave][i][S_AXC], axs = s_rec[wave][i][S_AXS];
-            T mo[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-            T dcol[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < 9; q++) v[q] = T(0);
+            T* mo = v;
+            T* dcol = v + 6;
             bool hit = false;   // uniform: some lane kept the record
 #pragma unroll
             for (int k = 0; k < PPL; k++) {
@@ -499,30 +561,28 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
                 mo[4] = Num<T>::fma(t1, e2, mo[4]);
                 mo[5] = Num<T>::fma(t2, e2, mo[5]);
             }
-            // per-row partial sums (16 lanes), parked in LDS; the rows are
-            // added and the pair stored once per batch, one lane per record
-            T* rs = s_rows[wave][i][row];
-            if (hit) {
-                T v[9];
+            return hit;
+        };
+        // records in pairs: composited in list order, their partials summed
+        // over the wave together and stored
+        for (uint32_t i = 0; i < n; i += 2) {
+            T va[9], vb[9];
+            const bool ha = composite(i, va);
+            bool hb = false;
+            if (i + 1 < n) {
+                hb = composite(i + 1, vb);
+            } else {
 #pragma unroll
-                for (int q = 0; q < 6; q++) v[q] = row_sum_last(mo[q]);
-#pragma unroll
-                for (int q = 0; q < 3; q++) v[6 + q] = row_sum_last(dcol[q]);
-                if ((lane & 15) == 15)
-#pragma unroll
-                    for (int q = 0; q < 9; q++) rs[q] = v[q];
-            } else if ((lane & 15) == 15) {
-#pragma unroll
-                for (int q = 0; q < 9; q++) rs[q] = T(0);
+                for (int q = 0; q < 9; q++) vb[q] = T(0);
             }
-        }
-        wave_lds_sync();
-        if (uint32_t(lane) < cnt) {
-            const T(*rows)[9] = s_rows[wave][slot];
-            T* dst = pg + pslot(e_own);
-#pragma unroll
-            for (int q = 0; q < 9; q++)
-                dst[q] = m != 0 ? (rows[0][q] + rows[1][q]) + (rows[2][q] + rows[3][q]) : T(0);
+            T* da = pg + pslot(uniform(s_eown[wave][i]));
+            T* db = i + 1 < n ? pg + pslot(uniform(s_eown[wave][i + 1])) : nullptr;
+            if (ha || hb) {
+                store_pair_partials(va, vb, da, db);
+            } else if (lane < 9) {
+                da[lane] = T(0);
+                if (db) db[lane] = T(0);
+            }
         }
         __builtin_amdgcn_wave_barrier();
     }
