@@ -150,7 +150,7 @@ typedef struct {
 /* Tile bins produced by gs_bin_sort. */
 typedef struct {
     uint32_t *vals;          /* device [capacity]: record ids in (tile, depth, record) order */
-    uint32_t *ranges;        /* device [n_tiles][2]: [start, end) into vals */
+    uint32_t *ranges;        /* device [n_tiles][2]: [start, end) into vals; (0, 0) when empty */
     uint32_t *pair_off;      /* device [n_records]: first pair of each visible record */
     uint32_t *counters;      /* device [GS_N_COUNTERS] */
     uint64_t capacity;       /* pairs vals can hold */

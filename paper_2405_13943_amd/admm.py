@@ -378,3 +378,128 @@ def autotune_tile(run_step, key: str, cache_path=None, candidates=TILES, reps=5)
     gs.set_tune_cache(cache_path)
     best, _ = gs.autotune(key, candidates, run_step, reps)
     return tuple(best)
+
+
+# ---------------------------------------------------------------------------
+# blocks on concurrent streams
+
+def contiguous_groups(sizes, n_groups):
+    """Split blocks 0..K-1 into n_groups contiguous runs of similar total
+    size (the largest run as small as possible; exhaustive over the cut
+    points, K is small).  Returns [(k0, k1), ...]."""
+    import itertools
+    K = len(sizes)
+    n_groups = max(1, min(int(n_groups), K))
+    best, best_cost = None, None
+    for cuts in itertools.combinations(range(1, K), n_groups - 1):
+        edges = (0,) + cuts + (K,)
+        cost = max(sum(sizes[a:b]) for a, b in zip(edges[:-1], edges[1:]))
+        if best_cost is None or cost < best_cost:
+            best, best_cost = edges, cost
+    return [(a, b) for a, b in zip(best[:-1], best[1:])]
+
+
+class StreamedAdmmTrainer:
+    """Alg. 2 with the K blocks in contiguous groups, each group's local step
+    on a HIP stream of its own (one launch per stage per group), so that one
+    group's compositing (bound by vector ALU issue) and another group's
+    streaming optimiser (bound by HBM) run on the device at the same time.
+    The consensus runs on the calling stream after every group's stream has
+    reached it; the groups' next steps wait for it.  The parameter store,
+    optimiser state, duals and consensus targets are one set of tensors
+    (each group works on its columns); results are those of AdmmTrainer."""
+
+    def __init__(self, model: BlockModel, cams, targets, cfg: gs.GsRasterCfg, groups=2, capacity=None, **kw):
+        self.model = model
+        self.full = AdmmTrainer(model, cams, targets, cfg, capacity=capacity, **kw)
+        sizes = [model.block(k)[1] - model.block(k)[0] for k in range(model.K)]
+        self.parts = contiguous_groups(sizes, groups)
+        self.subs = []
+        for k0, k1 in self.parts:
+            lo, hi = model.offsets[k0], model.offsets[k1]
+            ends = model.ends if model.ends is not None else model.offsets[1:]
+            sub_model = BlockModel(model.sh_degree, model.z, model.x[:, lo:hi],
+                                   [o - lo for o in model.offsets[k0:k1 + 1]], model.holder_ptr, model.holder_idx,
+                                   model.local_gid[k0:k1], [e - lo for e in ends[k0:k1]], model.perm)
+            if callable(targets):
+                tg = (lambda f, a: (lambda k, v: f(k + a, v)))(targets, k0)
+            else:
+                tg = targets[k0:k1]
+            sub = AdmmTrainer(sub_model, cams[k0:k1], tg, cfg, capacity=capacity, **kw)
+            # the group's columns of the shared state
+            sub.m, sub.v = self.full.m[:, lo:hi], self.full.v[:, lo:hi]
+            sub.u, sub.w = self.full.u[:, lo:hi], self.full.w[:, lo:hi]
+            if sub.mask is not None:
+                sub.mask = self.full.mask[lo:hi]
+            sub.stream = torch.cuda.Stream(device=model.x.device)
+            self.subs.append(sub)
+        self.intv = self.full.intv
+        self.t = 0
+
+    @property
+    def cfg(self):
+        return self.full.cfg
+
+    @property
+    def capacity(self):
+        return max(s.capacity or 0 for s in self.subs)
+
+    def calibrate(self, headroom=1.3):
+        pm = []
+        for s in self.subs:
+            with torch.cuda.stream(s.stream):
+                pm.append(s.calibrate(headroom))
+        torch.cuda.synchronize()
+        return max(pm)
+
+    def local_step(self):
+        ev = torch.cuda.Event()
+        ev.record()
+        for s in self.subs:
+            s.stream.wait_event(ev)
+            s.t = self.t
+            s.rho = self.full.rho
+            with torch.cuda.stream(s.stream):
+                s.local_step()
+
+    def _join(self):
+        cur = torch.cuda.current_stream()
+        for s in self.subs:
+            ev = torch.cuda.Event()
+            ev.record(s.stream)
+            cur.wait_event(ev)
+
+    def consensus(self):
+        self._join()
+        self.full.t = self.t
+        self.full.consensus()
+
+    def check(self):
+        redone = 0
+        for s in self.subs:
+            with torch.cuda.stream(s.stream):
+                s.t = self.t
+                redone += s.check()
+        return redone
+
+    def step(self):
+        self.local_step()
+        if self.t % self.intv == 0:
+            self.check()
+            self.consensus()
+        self.t += 1
+
+    def synchronize(self):
+        self._join()
+
+    @property
+    def bufs(self):
+        return [s.buf for s in self.subs]
+
+    @property
+    def resid(self):
+        return self.full.resid
+
+    @property
+    def history(self):
+        return self.full.history

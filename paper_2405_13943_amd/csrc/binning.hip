@@ -144,8 +144,8 @@ __device__ inline void block_range(uint32_t n, int G, int b, uint32_t granule, u
 }
 
 // ---------------------------------------------------------------------------
-// reduce-then-scan over a sequence of n items (three launches: per-block
-// sums, a one-block scan of those, then each block's exclusive prefixes)
+// reduce-then-scan over a sequence of n items (two launches: per-block
+// sums, then each block's exclusive prefixes)
 
 struct RecordScan {       // item i: record i; output: compacted ids and first pairs
     using T = VisPairs;
@@ -193,33 +193,21 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, uint32_t n, typ
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// single block: exclusive scan of the G partials in place; the total goes to
-// F::finish
-template <typename F>
-__global__ __launch_bounds__(kScanBlock) void k_scan_spine(typename F::T* __restrict__ part, int G,
-                                                           uint32_t* __restrict__ counters, uint64_t capacity) {
-    using T = typename F::T;
-    __shared__ T s_wave[kScanBlock / kWave];
-    T carry{};
-    for (int base = 0; base < G; base += kScanBlock) {
-        const int i = base + threadIdx.x;
-        const T v = i < G ? part[i] : T{};
-        T tot;
-        const T ex = block_excl_scan(v, s_wave, tot);
-        if (i < G) part[i] = scan_add(carry, ex);
-        carry = scan_add(carry, tot);
-    }
-    if (threadIdx.x == 0) F::finish(carry, counters, capacity);
-}
-
+// Each workgroup's exclusive prefix is the sum of the partials before it (at
+// most kMaxGrid, read by the whole workgroup), then its items' prefixes; the
+// last workgroup also hands the total to F::finish.
 template <typename F>
 __global__ __launch_bounds__(kScanBlock) void k_scan_apply(F f, uint32_t n, const typename F::T* __restrict__ part,
-                                                           int G) {
+                                                           int G, uint32_t* __restrict__ counters, uint64_t capacity) {
     using T = typename F::T;
     __shared__ T s_wave[kScanBlock / kWave];
+    T before{};
+    for (int i = threadIdx.x; i < int(blockIdx.x); i += kScanBlock) before = scan_add(before, part[i]);
+    T carry;
+    block_excl_scan(before, s_wave, carry);
+    if (blockIdx.x == unsigned(G - 1) && threadIdx.x == 0) F::finish(scan_add(carry, part[G - 1]), counters, capacity);
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kScanBlock, lo, hi);
-    T carry = part[blockIdx.x];
     for (uint32_t base = lo; base < hi; base += kScanBlock) {
         const uint32_t i = base + threadIdx.x;
         const T v = i < hi ? f.value(i) : T{};
@@ -763,9 +751,8 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
         VisPairs* part = static_cast<VisPairs*>(w.part);
         GS_LAUNCH("k_scan_reduce", k_scan_reduce<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G,
                   bins.ranges, 2 * nt, w.longq);
-        GS_LAUNCH("k_scan_spine", k_scan_spine<RecordScan>, dim3(1), dim3(kScanBlock), 0, s, part, G, bins.counters,
-                  bins.capacity);
-        GS_LAUNCH("k_scan_apply", k_scan_apply<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G);
+        GS_LAUNCH("k_scan_apply", k_scan_apply<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G,
+                  bins.counters, bins.capacity);
     }
     // 2. emit (tile, record) pairs in record order, then sort them by tile id
     int bits = 0;

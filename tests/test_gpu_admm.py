@@ -233,6 +233,29 @@ def test_autograd_function_fp64_against_finite_differences():
     assert not bad.any(), [(coords[k], fd[k], ga[k]) for k in np.nonzero(bad)[0][:10]]
 
 
+@pytest.mark.parametrize("groups", [2, 3])
+def test_streamed_groups_equal_one_launch_per_stage(groups):
+    """Blocks in contiguous groups, each group's local steps on a stream of
+    its own, consensus after both: the store, optimiser state, duals,
+    targets and global model are bit-identical to one launch per stage over
+    all blocks, over five steps with two consensus rounds."""
+    bs = tiny_blocks()
+    ref = make_trainer(bs, intv=2)
+    model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
+    tr = admm.StreamedAdmmTrainer(model, bs.cams, targets_for(bs), gs.raster_cfg((16, 16)), groups=groups,
+                                  lr=(1e-3, 2e-3, 3e-3, 4e-3, 5e-3), rho=(1e-2,) * 5, intv=2, capacity=1 << 16)
+    assert len(tr.subs) == groups
+    for _ in range(5):
+        ref.step()
+        tr.step()
+    tr.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(ref.model.x, tr.model.x)
+    assert torch.equal(ref.m, tr.full.m) and torch.equal(ref.v, tr.full.v)
+    assert torch.equal(ref.u, tr.full.u) and torch.equal(ref.w, tr.full.w)
+    assert torch.equal(ref.model.z, tr.model.z)
+
+
 def test_autotuner_picks_a_candidate_and_caches(tmp_path):
     bs = tiny_blocks()
     model = admm.BlockModel.from_global(bs.params_global, bs.local_gid)
