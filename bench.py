@@ -9,11 +9,14 @@ Workload (one block): 500k Gaussians, SH degree 3, 64 ring cameras at
 
 with all inputs resident in HBM.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serve]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-serve] [--no-blocks4]
 
 The default line also carries a serving leg (``serve``): the 6M-Gaussian
 global model under Poisson requests at 200 req/s over mixed resolutions,
-p50/p99 latency and frames/s.  ``--workload blocks4`` instead prints the
+p50/p99 latency and frames/s, and 50 sampled requests rendered again alone
+(bit-equal to their images from the mix); and a short K = 4 block leg
+(``blocks4``): the batched step against the four blocks stepped one after
+another, with the images-equal check.  ``--workload blocks4`` instead prints the
 batched K = 4 block line (batched against sequential per-block steps) and
 ``--workload serve`` the serving leg alone.
 """
@@ -426,12 +429,23 @@ def run_serve(args):
     wcams = scenes.serve_requests(24, 55)
     srv.run_open_loop(wcams, np.zeros(len(wcams)))
     torch.cuda.synchronize()
-    # open loop at the offered rate; the first second is not counted
-    warm = 1.0
+    # open loop at the offered rate; the first seconds are not counted
+    warm = args.serve_warmup
     arr = scenes.poisson_arrivals(args.rate, args.serve_seconds + warm, 5005)
     cams = scenes.serve_requests(len(arr), 5006)
-    stats, _ = srv.run_open_loop(cams, arr, warmup=warm)
+    # a seeded sample of the measured requests keeps its image: each is
+    # rendered again alone afterwards and must match bit for bit
+    measured = np.nonzero(np.asarray(arr) >= warm)[0]
+    sample = np.random.default_rng(5008).choice(measured, min(50, len(measured)), replace=False)
+    stats, _ = srv.run_open_loop(cams, arr, warmup=warm, keep=[int(i) for i in sample])
     log(f"[serve] open loop {args.rate:.0f} req/s: {stats}")
+    n_equal, max_diff = 0, 0.0
+    for rid in sample:
+        alone = srv.render_alone(cams[int(rid)])
+        mixed = srv.kept[int(rid)]
+        n_equal += int(torch.equal(alone, mixed))
+        max_diff = max(max_diff, float((alone - mixed).abs().max()))
+    log(f"[serve] {n_equal} of {len(sample)} sampled requests equal alone and mixed (max diff {max_diff:.3g})")
     # saturation: a burst of requests all arriving at t = 0
     nb = int(args.rate * 2)
     bcams = scenes.serve_requests(nb, 5007)
@@ -444,14 +458,16 @@ def run_serve(args):
            "frames_per_s": round(stats["frames_per_s"], 1), "mpx_per_s": round(stats["mpx_per_s"], 1),
            "retries": stats["retries"], "max_batch": srv.max_batch, "slots": len(srv.slots),
            "saturated_frames_per_s": round(sat["frames_per_s"], 1), "saturated_mpx_per_s": round(sat["mpx_per_s"], 1),
-           "saturated_p50_ms": round(sat["p50_ms"], 2)}
+           "saturated_p50_ms": round(sat["p50_ms"], 2), "warmup_s": warm,
+           "largest_batch": stats["largest_batch"], "most_in_flight": stats["most_in_flight"],
+           "sampled_alone_equal": f"{n_equal}/{len(sample)}", "sampled_max_abs_diff": max_diff}
     del srv, params
     torch.cuda.empty_cache()
     return out
 
 
-KERNELS = ("k_project", "k_fill_u32", "k_scan_reduce", "k_scan_spine", "k_scan_apply", "k_emit", "k_rs_hist", "k_rs_colscan", "k_rs_scatter", "k_ranges",
-           "k_tile_sort", "k_tile_sort_long", "k_tile_plan", "k_render_fwd", "k_render_bwd", "k_project_bwd_rec",
+KERNELS = ("k_project", "k_fill_u32", "k_scan_reduce", "k_scan_apply", "k_tile_offsets", "k_scatter",
+           "k_tile_sort", "k_tile_sort_long", "k_render_fwd", "k_render_bwd", "k_project_bwd_rec",
            "k_zero_uncovered", "k_project_bwd_adam", "k_adam_uncovered", "k_adam_admm", "k_consensus")
 
 
@@ -691,14 +707,21 @@ def run_blocks4(args):
     # fresh state for the timed run
     model.x.copy_(x0)
     adaptive = admm.AdaptivePenalty() if args.adaptive else None
-    tr = admm.AdmmTrainer(model, bs.cams, target, gs.raster_cfg(tile), lr=LR, rho=RHO, intv=100,
-                          capacity=trainers[tile].capacity if tile in trainers else None, relax=args.relax,
-                          adaptive=adaptive)
-    trainers.clear()
-    if tr.capacity is None:
+    if args.block_groups > 1:
+        # contiguous groups of blocks, each on a stream of its own
+        tr = admm.StreamedAdmmTrainer(model, bs.cams, target, gs.raster_cfg(tile), groups=args.block_groups, lr=LR,
+                                      rho=RHO, intv=100, relax=args.relax, adaptive=adaptive)
+        trainers.clear()
         tr.calibrate()
     else:
-        tr._buffers(tr.frame([0] * K))
+        tr = admm.AdmmTrainer(model, bs.cams, target, gs.raster_cfg(tile), lr=LR, rho=RHO, intv=100,
+                              capacity=trainers[tile].capacity if tile in trainers else None, relax=args.relax,
+                              adaptive=adaptive)
+        trainers.clear()
+        if tr.capacity is None:
+            tr.calibrate()
+        else:
+            tr._buffers(tr.frame([0] * K))
     cfg = tr.cfg
     # sequential baseline: each block as its own plain single-block model
     seq = []
@@ -708,16 +731,19 @@ def run_blocks4(args):
                               intv=1 << 30)
         tk.calibrate()
         seq.append(tk)
-    # the batched frame renders every block exactly as its own plain render
-    views = [0] * K
-    f = tr.frame(views)
-    gs.rasterize(model.x, f, cfg, tr.buf)
+    # the batched frames render every block exactly as its own plain render
+    batched = [tr] if args.block_groups <= 1 else tr.subs
     same = True
-    for k in range(K):
-        fk = seq[k].frame([0])
-        gs.rasterize(seq[k].model.x, fk, cfg, seq[k].buf)
-        same &= bool(torch.equal(f.image(tr.buf.rgb, k), fk.image(seq[k].buf.rgb, 0)))
-    for b in [tr] + seq:
+    for bt in batched:
+        kb = bt.model.K
+        f = bt.frame([0] * kb)
+        gs.rasterize(bt.model.x, f, cfg, bt.buf)
+        k0 = 0 if bt is tr else tr.parts[tr.subs.index(bt)][0]
+        for k in range(kb):
+            fk = seq[k0 + k].frame([0])
+            gs.rasterize(seq[k0 + k].model.x, fk, cfg, seq[k0 + k].buf)
+            same &= bool(torch.equal(f.image(bt.buf.rgb, k), fk.image(seq[k0 + k].buf.rgb, 0)))
+    for b in batched + seq:
         b.buf.counters.zero_()
     log(f"[blocks4] batched images equal to per-block renders: {same}")
 
@@ -741,6 +767,8 @@ def run_blocks4(args):
     def batched_step():
         tr.local_step()
         if tr.t % tr.intv == 0:
+            if hasattr(tr, "join"):
+                tr.join()          # the groups' queued steps are not the consensus's time
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
             tr.consensus()
@@ -759,7 +787,7 @@ def run_blocks4(args):
     cons_kernels = {k: gs.profile_get(k) for k in ("k_consensus", "k_dual_rescale")}
     gs.profile_set(None)
     ms_s = timed(seq_step, steps)
-    ok = all(not gs.read_counters(b.buf)["status"] & gs.GS_STATUS_PAIR_OVERFLOW for b in [tr] + seq)
+    ok = all(not gs.read_counters(b.buf)["status"] & gs.GS_STATUS_PAIR_OVERFLOW for b in batched + seq)
     if not ok:
         raise SystemExit("pair capacity overflowed during the timed steps; rerun with more headroom")
     c_ms = [a.elapsed_time(b) for a, b in cons_ms]
@@ -778,7 +806,8 @@ def run_blocks4(args):
                                   f"({model.x.shape[1]} local slots), {args.block_cams} ring views per block at "
                                   "1600x1066, consensus every 100 steps",
                       "tile": "x".join(map(str, tile[:2])), "waves_per_tile_fwd_bwd": list(tile[2:]),
-                      "block_strands": args.block_strands},
+                      "block_strands": args.block_strands, "stream_groups": args.block_groups,
+                      "groups": [list(p) for p in tr.parts] if args.block_groups > 1 else [[0, K]]},
            "sequential_ms_per_step": ms_s / steps, "batched_speedup": ms_s / ms_b,
            "consensus_ms": c_ms, "consensus_calls": len(c_ms), "consensus_roofline": cons,
            "relax": args.relax, "adaptive_penalty": bool(args.adaptive), "images_equal_per_block": same,
@@ -912,16 +941,21 @@ def main():
                          "only; consensus: the consensus step alone on the K=4 block store; split4: K=4 blocks from "
                          "the scene by Alg. 1")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg of the train workload")
+    ap.add_argument("--no-blocks4", action="store_true", help="skip the K = 4 block leg of the train workload")
+    ap.add_argument("--blocks4-steps", type=int, default=100, help="timed steps of the K = 4 leg in the train line")
     ap.add_argument("--ssim", type=float, default=0.0,
                     help="train: weight lambda of the D-SSIM term of the loss (0: the L1 loss alone)")
     ap.add_argument("--serve-n", type=int, default=6_000_000)
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0, help="seconds of arrivals not counted (config: 5)")
     ap.add_argument("--serve-hbm", type=float, default=48.0, help="GB of transient serving buffers")
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-max-batch", type=int, default=8)
     ap.add_argument("--block-cams", type=int, default=32)
     ap.add_argument("--block-steps", type=int, default=200)
+    ap.add_argument("--block-groups", type=int, default=1,
+                    help="blocks4: contiguous groups of blocks, each on its own stream (1: one launch per stage)")
     ap.add_argument("--no-tile-auto", action="store_true", help="blocks4: use --tile instead of the autotuner")
     ap.add_argument("--relax", type=float, default=1.0, help="blocks4: over-relaxation alpha of the consensus")
     ap.add_argument("--adaptive", action="store_true", help="blocks4: residual-balancing penalty (until 2000)")
@@ -937,7 +971,7 @@ def main():
     ap.add_argument("--traffic-kernels", default=None,
                     help="with --record-traffic: comma-separated kernels to record (default: every measured kernel "
                          "with samples)")
-    ap.add_argument("--traffic-args", default="--steps 4 --warmup 2 --no-cpu-baseline --no-serve",
+    ap.add_argument("--traffic-args", default="--steps 4 --warmup 2 --no-cpu-baseline --no-serve --no-blocks4",
                     help="with --record-traffic: the bench arguments the counter runs used")
     ap.add_argument("--traffic-workload", default=None,
                     help="workload name stored with recorded traffic (default: the training workload and --order)")
@@ -974,6 +1008,21 @@ def main():
     srv = None
     if not args.no_serve:
         srv = run_serve(args)
+    b4 = None
+    if not args.no_blocks4:
+        # the K = 4 block leg, short: batched against the blocks one after another
+        import copy
+        a4 = copy.copy(args)
+        a4.block_steps, a4.warmup = args.blocks4_steps, 5
+        res = run_blocks4(a4)
+        b4 = {k: res[k] for k in ("ms_per_step", "sequential_ms_per_step", "batched_speedup", "images_equal_per_block")}
+        b4["workload"] = res["config"]["workload"]
+        b4["steps"] = a4.block_steps
+        b4["tile"] = res["config"]["tile"] + "/" + "/".join(map(str, res["config"]["waves_per_tile_fwd_bwd"]))
+        b4["stream_groups"] = res["config"]["stream_groups"]
+        b4["consensus_ms"] = [round(c, 3) for c in res["consensus_ms"]]
+        import torch
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
@@ -1012,6 +1061,7 @@ def main():
                             "bytes": int(r["opt_bytes"])},
         "cpu_baseline": cpu,
         "serve": srv,
+        "blocks4": b4,
     }
     if r["ssim"] is not None:
         out["roofline_ssim"] = r["ssim"]

@@ -462,7 +462,8 @@ class StreamedAdmmTrainer:
             with torch.cuda.stream(s.stream):
                 s.local_step()
 
-    def _join(self):
+    def join(self):
+        """The calling stream waits for every group's queued work."""
         cur = torch.cuda.current_stream()
         for s in self.subs:
             ev = torch.cuda.Event()
@@ -470,7 +471,7 @@ class StreamedAdmmTrainer:
             cur.wait_event(ev)
 
     def consensus(self):
-        self._join()
+        self.join()
         self.full.t = self.t
         self.full.consensus()
 
@@ -490,7 +491,7 @@ class StreamedAdmmTrainer:
         self.t += 1
 
     def synchronize(self):
-        self._join()
+        self.join()
 
     @property
     def bufs(self):
