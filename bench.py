@@ -812,6 +812,8 @@ def run_blocks4(args):
            "consensus_ms": c_ms, "consensus_calls": len(c_ms), "consensus_roofline": cons,
            "relax": args.relax, "adaptive_penalty": bool(args.adaptive), "images_equal_per_block": same,
            "kernel_ms_batched": kb, "kernel_ms_sequential": ks,
+           "kernel_ms_note": "per-kernel sums over all launches of a step; with stream groups the groups' "
+                             "launches overlap, so the batched sums exceed the step's elapsed time",
            "last_residuals": res}
     return out
 
@@ -902,6 +904,126 @@ def cpu_baseline(scene, budget_s=8.0):
             "parity_scene": "2,000 Gaussians SH0, 4 x 128x128 views, fwd+bwd+Adam/ADMM, every pixel, all threads"}
 
 
+def crop_subset(pr, x0, y0, size):
+    """Gaussians whose conservative footprint (the alpha_min ellipse's
+    bounding box from the oracle's projection, grown by 1% and 1 px) meets
+    the crop [x0, x0 + size) x [y0, y0 + size): every other Gaussian has
+    alpha < alpha_min at every crop pixel."""
+    o, S, m = pr["opacity"], pr["cov2d"], pr["mean2d"]
+    c = 2.0 * np.log(np.maximum(o * 255.0, 1.0))
+    hx = np.sqrt(c * S[:, 0]) * 1.01 + 1.0
+    hy = np.sqrt(c * S[:, 2]) * 1.01 + 1.0
+    sel = pr["valid"] & (o * 255.0 >= 1.0) & (m[:, 0] + hx >= x0) & (m[:, 0] - hx <= x0 + size) \
+        & (m[:, 1] + hy >= y0) & (m[:, 1] - hy <= y0 + size)
+    return np.nonzero(sel)[0]
+
+
+def run_oracle_timing(args):
+    """The FP64 oracle on this host, all threads and one thread: a full step
+    of the parity scene; fwd + bwd of the scale scene (500k, 1600x1066) and
+    of the 2M-Gaussian 1920x1080 scene on four seeded crops each (all
+    threads; one thread on a corner of the first crop), extrapolated by pixel
+    count to the whole view and labelled so; the Adam/ADMM oracle over all
+    500k Gaussians; the consensus oracle on a sample of the K = 4 store's
+    global ids, extrapolated to all of them."""
+    import oracle
+    from paper_2405_13943_amd import admm, scenes
+    lib = oracle.load_library()
+    nth = lib.orc_num_threads()
+
+    def at(n, fn):
+        lib.orc_set_threads(n)
+        try:
+            t = time.time()
+            fn()
+            return time.time() - t
+        finally:
+            lib.orc_set_threads(nth)
+
+    rows = []
+    c1 = scenes.config1()
+
+    def cfg1_step():
+        g = np.zeros_like(c1.params, dtype=np.float64)
+        for v, c in enumerate(c1.cams):
+            r = oracle.render(c1.params, c)
+            g += oracle.backward(c1.params, c, 0.25 * np.sign(r["rgb"] - c1.targets[v]) / r["rgb"].size)
+        x1 = c1.params.astype(np.float64)
+        oracle.adam_admm(x1, g, np.zeros_like(x1), np.zeros_like(x1), x1, LR, RHO, 1)
+    rows.append({"what": "parity scene step (2,000 Gaussians SH0, 4 x 128x128, fwd+bwd+Adam/ADMM, every pixel)",
+                 "all_threads_s": round(at(nth, cfg1_step), 3), "one_thread_s": round(at(1, cfg1_step), 3)})
+    log(f"[oracle] {rows[-1]}")
+    crop, crop1 = args.oracle_crop, max(8, args.oracle_crop // 4)
+    for name, scene in (("scale scene, 500k Gaussians SH3, one 1600x1066 view", scenes.config2(n=500_000, n_cams=1)),
+                        ("2M Gaussians SH3, one 1920x1080 view", scenes.config4b())):
+        cam = scene.cams[0]
+        W, H = cam.width, cam.height
+        target = scenes.rng(4242).random((3, H, W)).astype(np.float32)
+        t_proj = at(nth, lambda: oracle.project(scene.params, cam))
+        pr = oracle.project(scene.params, cam)
+        rng = np.random.default_rng(4343)
+        crops = [(int(rng.integers(0, W - crop)), int(rng.integers(0, H - crop))) for _ in range(4)]
+        per_px_all, per_px_one, n_sub = [], [], []
+        for i, (x0, y0) in enumerate(crops):
+            idx = crop_subset(pr, x0, y0, crop)
+            sub = np.ascontiguousarray(scene.params[:, idx])
+            ys, xs = np.mgrid[y0:y0 + crop, x0:x0 + crop]
+            pix = (ys * W + xs).ravel()
+
+            def fwd_bwd():
+                r = oracle.render(sub, cam, pixels=pix)
+                dl = np.sign(r["rgb"] - target.reshape(3, -1)[:, pix]) / (3 * W * H)
+                oracle.backward(sub, cam, dl, pixels=pix)
+            per_px_all.append(at(nth, fwd_bwd) / pix.size)
+            n_sub.append(int(len(idx)))
+            if i == 0:
+                # one thread: the same Gaussians, the crop's top-left
+                # crop1 x crop1 pixels
+                ys1, xs1 = np.mgrid[y0:y0 + crop1, x0:x0 + crop1]
+                pix1 = (ys1 * W + xs1).ravel()
+
+                def fwd_bwd1():
+                    r = oracle.render(sub, cam, pixels=pix1)
+                    dl = np.sign(r["rgb"] - target.reshape(3, -1)[:, pix1]) / (3 * W * H)
+                    oracle.backward(sub, cam, dl, pixels=pix1)
+                per_px_one.append(at(1, fwd_bwd1) / pix1.size)
+            log(f"[oracle] {name}: crop {i} at ({x0}, {y0}), {len(idx)} Gaussians reach it, "
+                f"{per_px_all[-1] * 1e3:.3f} ms/px all threads")
+        rows.append({"what": f"fwd+bwd, {name}, extrapolated from four {crop}x{crop} crops by pixel count",
+                     "oracle_input": "per crop, the Gaussians whose footprint box meets it (the selection the "
+                                     "crop parity tests give the oracle); the projection of all of them timed apart",
+                     "gaussians_per_crop": n_sub,
+                     "all_threads_s": round(t_proj + float(np.mean(per_px_all)) * W * H, 1),
+                     "one_thread_s": round(t_proj * nth + per_px_one[0] * float(np.mean(per_px_all)) / per_px_all[0]
+                                           * W * H, 1),
+                     "projection_all_threads_s": round(t_proj, 2),
+                     "ms_per_px_all_threads": [round(v * 1e3, 4) for v in per_px_all],
+                     "ms_per_px_one_thread": round(per_px_one[0] * 1e3, 4),
+                     "crops": crops,
+                     "one_thread_from": f"the first crop's Gaussians on its {crop1}x{crop1} top-left pixels, "
+                                        "scaled by the mean per-pixel time of the four crops over the first's; "
+                                        "projection time scaled by the thread count"})
+        log(f"[oracle] {rows[-1]}")
+    x = scenes.config2(n=500_000, n_cams=1).params
+    t = time.time()
+    oracle.adam_admm(x, np.zeros_like(x), np.zeros_like(x), np.zeros_like(x), x, LR, RHO, 1)
+    rows.append({"what": "Adam/ADMM oracle over all 500k Gaussians (NumPy)", "s": round(time.time() - t, 2)})
+    bs = scenes.block_scene(n_cams=1)
+    n_global = bs.params_global.shape[1]
+    ptr, idx = admm.holder_csr(bs.local_gid, n_global)
+    xl = bs.params_global[:, np.concatenate(bs.local_gid)].astype(np.float64)
+    sample = 50_000
+    sp = ptr[:sample + 1]
+    t = time.time()
+    oracle.consensus(xl, np.zeros_like(xl), sp, idx, sample)
+    t_s = time.time() - t
+    rows.append({"what": f"consensus oracle, {sample} of the K = 4 store's {n_global} global ids "
+                         f"({len(idx)} copies), extrapolated to all of them",
+                 "sample_s": round(t_s, 2), "extrapolated_s": round(t_s * n_global / sample, 1)})
+    log(f"[oracle] {rows[-1]}")
+    return {"workload": "oracle timing", "cpu_model": cpu_model(), "threads": int(nth), "rows": rows}
+
+
 def copy_probe(nbytes=1 << 30, reps=5):
     """Plain device-to-device copy of known size (reads and writes nbytes
     each), used to scale the HBM byte counters of rocprofv3."""
@@ -936,7 +1058,7 @@ def main():
                          "of the means in 16-Gaussian chunks over 1024 strands, plain Z-order, or as drawn")
     ap.add_argument("--inline-stage-timing", action="store_true",
                     help="record the per-stage events inside the timed loop (adds their cost to the step time)")
-    ap.add_argument("--workload", choices=("train", "blocks4", "serve", "consensus", "split4"), default="train",
+    ap.add_argument("--workload", choices=("train", "blocks4", "serve", "consensus", "split4", "oracle"), default="train",
                     help="train: single block at scale (+ serve leg); blocks4: batched K=4 blocks; serve: serving "
                          "only; consensus: the consensus step alone on the K=4 block store; split4: K=4 blocks from "
                          "the scene by Alg. 1")
@@ -954,8 +1076,9 @@ def main():
     ap.add_argument("--serve-max-batch", type=int, default=8)
     ap.add_argument("--block-cams", type=int, default=32)
     ap.add_argument("--block-steps", type=int, default=200)
-    ap.add_argument("--block-groups", type=int, default=1,
-                    help="blocks4: contiguous groups of blocks, each on its own stream (1: one launch per stage)")
+    ap.add_argument("--block-groups", type=int, default=2,
+                    help="blocks4: contiguous groups of blocks, each on its own stream between consensus rounds "
+                         "(1: one launch per stage over all blocks)")
     ap.add_argument("--no-tile-auto", action="store_true", help="blocks4: use --tile instead of the autotuner")
     ap.add_argument("--relax", type=float, default=1.0, help="blocks4: over-relaxation alpha of the consensus")
     ap.add_argument("--adaptive", action="store_true", help="blocks4: residual-balancing penalty (until 2000)")
@@ -964,6 +1087,7 @@ def main():
                     help="blocks4/split4: inside each holder group, Z-order of the means in 16-Gaussian chunks over "
                          "this many strands (0: the drawn order); a storage layout")
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--oracle-crop", type=int, default=256, help="oracle: side of the timed crops")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="host only: write profiles/hbm_traffic.json for the measured kernels from rocprofv3 --pmc "
@@ -992,6 +1116,9 @@ def main():
         print("bench.py measures one GPU: the path holds all K blocks in one GPU's HBM and this build has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "oracle":
+        print(json.dumps(run_oracle_timing(args)), flush=True)
+        return
     if args.workload == "blocks4":
         print(json.dumps(run_blocks4(args)), flush=True)
         return
