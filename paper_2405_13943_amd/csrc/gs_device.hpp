@@ -196,6 +196,12 @@ __device__ inline int lane_id() { return __lane_id(); }
 
 __device__ inline uint64_t lanemask_lt() { return (uint64_t(1) << lane_id()) - 1; }
 
+// lanes where b holds, as a wave-uniform 64-bit mask (every lane active)
+__device__ inline uint64_t lane_mask(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+// this lane's bit of a wave-uniform lane mask, read as a per-lane condition
+// without moving the mask into vector registers
+__device__ inline bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
 // Sum over the 64 lanes of a wave, returned to every lane.  FP32 uses DPP
 // (quad permutes, row rotations, then row broadcasts into lane 63); FP64
 // uses a butterfly of cross-lane shuffles.

@@ -648,48 +648,65 @@ __device__ inline float staged_grad(const float* geo, const float* Y, const floa
 }
 
 // phase 2 over contiguous, 16-byte aligned Gaussians g0 .. g0 + kFusedBlock - 1:
-// items (plane, 4 Gaussians), 16-byte accesses; m, v and w stream past the
-// caches (x stays cached: the chain rule has just read part of it)
+// each wavefront takes every fourth plane, its lanes 4 Gaussians each with
+// 16-byte accesses; the loads of kUnroll planes are issued before any of
+// them is used, so several lines per lane are in flight.  m, v and w stream
+// past the caches (x stays cached: the chain rule has just read part of it)
+constexpr int kUnroll = 3;
 template <int A, bool PEN, bool MASK>
 __device__ inline void adam_block_vec(float* __restrict__ X, int64_t sx, float* __restrict__ M, int64_t sm,
                                       float* __restrict__ V, int64_t sv, const float* __restrict__ Wp, int64_t sw,
                                       const float* __restrict__ mask, int64_t g0, const float* geo, const float* Y,
                                       const float* dc, const AdamConsts& c, float& fin) {
     constexpr int kCols = kFusedBlock / 4;
+    static_assert(kCols == kWave, "one plane per wavefront and step");
+    constexpr int kStep = kFusedBlock / kCols;
     const int t = threadIdx.x;
     const int col = t % kCols;
     const int i = 4 * col;
     const int64_t gv = g0 + i;
+    const int a_first = __builtin_amdgcn_readfirstlane(t / kCols);   // the wavefront's first plane
     float4 kv = make_float4(1.f, 1.f, 1.f, 1.f);
     if (MASK) kv = *reinterpret_cast<const float4*>(mask + gv);
-    for (int a = t / kCols; a < A; a += kFusedBlock / kCols) {
-        const int grp = plane_group(a);
-        const float lr = c.lr[grp], rho = c.rho[grp];
-        float4 xv = *reinterpret_cast<const float4*>(X + a * sx + gv);
-        float4 mv = load_stream4(M + a * sm + gv);
-        float4 vv = load_stream4(V + a * sv + gv);
-        float4 wv = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (PEN) wv = load_stream4(Wp + a * sw + gv);
-        // the four Gaussians' gradients of plane a: one 16-byte LDS read per array
-        float4 gq;
-        if (a < 11) {
-            gq = *reinterpret_cast<const float4*>(geo + a * kFusedBlock + i);
-        } else {
-            const float4 yq = *reinterpret_cast<const float4*>(Y + ((a - 11) / 3) * kFusedBlock + i);
-            const float4 dq = *reinterpret_cast<const float4*>(dc + ((a - 11) % 3) * kFusedBlock + i);
-            gq = make_float4(yq.x * dq.x, yq.y * dq.y, yq.z * dq.z, yq.w * dq.w);
+    for (int a0 = a_first; a0 < A; a0 += kUnroll * kStep) {
+        float4 xv[kUnroll], mv[kUnroll], vv[kUnroll], wv[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const int a = a0 + u * kStep;   // uniform
+            if (a >= A) break;
+            xv[u] = *reinterpret_cast<const float4*>(X + a * sx + gv);
+            mv[u] = load_stream4(M + a * sm + gv);
+            vv[u] = load_stream4(V + a * sv + gv);
+            wv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (PEN) wv[u] = load_stream4(Wp + a * sw + gv);
         }
-        adam_one(xv.x, gq.x, mv.x, vv.x, wv.x, PEN ? rho * kv.x : 0.f, lr, c);
-        adam_one(xv.y, gq.y, mv.y, vv.y, wv.y, PEN ? rho * kv.y : 0.f, lr, c);
-        adam_one(xv.z, gq.z, mv.z, vv.z, wv.z, PEN ? rho * kv.z : 0.f, lr, c);
-        adam_one(xv.w, gq.w, mv.w, vv.w, wv.w, PEN ? rho * kv.w : 0.f, lr, c);
-        *reinterpret_cast<float4*>(X + a * sx + gv) = xv;
-        store_stream4(M + a * sm + gv, mv);
-        store_stream4(V + a * sv + gv, vv);
-        adam_finite(fin, xv.x, vv.x);
-        adam_finite(fin, xv.y, vv.y);
-        adam_finite(fin, xv.z, vv.z);
-        adam_finite(fin, xv.w, vv.w);
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const int a = a0 + u * kStep;
+            if (a >= A) break;
+            const int grp = plane_group(a);
+            const float lr = c.lr[grp], rho = c.rho[grp];
+            // the four Gaussians' gradients of plane a: one 16-byte LDS read per array
+            float4 gq;
+            if (a < 11) {
+                gq = *reinterpret_cast<const float4*>(geo + a * kFusedBlock + i);
+            } else {
+                const float4 yq = *reinterpret_cast<const float4*>(Y + ((a - 11) / 3) * kFusedBlock + i);
+                const float4 dq = *reinterpret_cast<const float4*>(dc + ((a - 11) % 3) * kFusedBlock + i);
+                gq = make_float4(yq.x * dq.x, yq.y * dq.y, yq.z * dq.z, yq.w * dq.w);
+            }
+            adam_one(xv[u].x, gq.x, mv[u].x, vv[u].x, wv[u].x, PEN ? rho * kv.x : 0.f, lr, c);
+            adam_one(xv[u].y, gq.y, mv[u].y, vv[u].y, wv[u].y, PEN ? rho * kv.y : 0.f, lr, c);
+            adam_one(xv[u].z, gq.z, mv[u].z, vv[u].z, wv[u].z, PEN ? rho * kv.z : 0.f, lr, c);
+            adam_one(xv[u].w, gq.w, mv[u].w, vv[u].w, wv[u].w, PEN ? rho * kv.w : 0.f, lr, c);
+            *reinterpret_cast<float4*>(X + a * sx + gv) = xv[u];
+            store_stream4(M + a * sm + gv, mv[u]);
+            store_stream4(V + a * sv + gv, vv[u]);
+            adam_finite(fin, xv[u].x, vv[u].x);
+            adam_finite(fin, xv[u].y, vv[u].y);
+            adam_finite(fin, xv[u].z, vv[u].z);
+            adam_finite(fin, xv[u].w, vv[u].w);
+        }
     }
 }
 

@@ -61,6 +61,16 @@ __device__ inline T log2_alpha(const Rec<T>& g, T dx, T dy) {
     return N::fma(t, dx, N::fma(g.qc * dy, dy, g.lo));
 }
 
+// min(alpha, alpha_max) for alpha >= +0 or NaN: non-negative floats order
+// like their bit patterns, and a NaN's pattern lies above every finite one,
+// so the unsigned minimum equals fminf (NaN gives alpha_max) in one integer
+// instruction, without the NaN quieting fminf costs
+template <typename T> __device__ inline T clamp_alpha(T al, T amax);
+template <> __device__ inline float clamp_alpha<float>(float al, float amax) {
+    return __uint_as_float(min(__float_as_uint(al), __float_as_uint(amax)));
+}
+template <> __device__ inline double clamp_alpha<double>(double al, double amax) { return Num<double>::min(al, amax); }
+
 template <typename T> __device__ inline T recip(T x);
 template <> __device__ inline float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ inline double recip<double>(double x) { return 1.0 / x; }
@@ -245,24 +255,29 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
     // pixel centre of quadrant k: (bx + 8 (k % QX), by + 8 (k / QX))
     const T bx = T(tpx + lx) + T(0.5), by = T(tpy + ly) + T(0.5);
 
+    // per quadrant, the lanes whose pixel has stopped (or lies outside the
+    // image or the wavefront's quadrants): a wave-uniform lane mask, so the
+    // stop bookkeeping runs on the scalar unit
     T Tr[PPL], C[PPL][3];
-    uint32_t done = 0;
+    uint64_t stopm[PPL];
     uint32_t last[PPL];
     uint32_t n_kept = 0;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
         const int x = tpx + 8 * (k % QX) + lx, y = tpy + 8 * (k / QX) + ly;
-        done |= (x < W && y < H && (owned & (1u << k))) ? 0u : (1u << k);
+        stopm[k] = lane_mask(!(x < W && y < H && (owned & (1u << k))));
         Tr[k] = T(1);
         C[k][0] = C[k][1] = C[k][2] = T(0);
         last[k] = 0;
     }
     const uint2 range = ranges[tile];
     const T amin = T(cfg.alpha_min), amax = T(cfg.alpha_max), tmin = T(cfg.T_min);
-    constexpr uint32_t all = (1u << PPL) - 1;
     const T lmin = Num<T>::log2(amin);
     for (uint32_t base = range.x; base < range.y; base += kWave) {
-        if (__ballot(done != all) == 0) break;
+        uint64_t all_stopped = ~uint64_t(0);
+#pragma unroll
+        for (int k = 0; k < PPL; k++) all_stopped &= stopm[k];
+        if (all_stopped == ~uint64_t(0)) break;
         const uint32_t cnt = min(uint32_t(kWave), range.y - base);
         // stage the batch's records that reach some quadrant, compacted, each
         // with its quadrant mask and its position in the tile list
@@ -295,29 +310,27 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
                 if (!(qmask & (1u << k))) continue;   // uniform: box misses quadrant k
                 const T dx = quad_centre(bx, k % QX) - g.mx, dy = quad_centre(by, k / QX) - g.my;
                 const T al = Num<T>::exp2(log2_alpha(g, dx, dy));
-                const bool live = !(done & (1u << k)) && al >= amin;
-                if (__ballot(live) == 0) continue;     // uniform: no pixel of the wave reached
-                const T a = Num<T>::min(al, amax);
+                const uint64_t livem = lane_mask(al >= amin) & ~stopm[k];
+                if (livem == 0) continue;     // uniform: no pixel of the wave reached
+                const T a = clamp_alpha(al, amax);
                 const T aT = a * Tr[k];
                 const T tn = Tr[k] - aT;
-                const bool stop = live && tn < tmin;
-                const bool keep = live && !stop;
-                done |= stop ? (1u << k) : 0u;
+                const uint64_t stopb = lane_mask(tn < tmin) & livem;
+                stopm[k] |= stopb;
+                const uint64_t keepm = livem & ~stopb;
+                const bool keep = lane_in(keepm);
                 const T wgt = keep ? aT : T(0);
                 C[k][0] = Num<T>::fma(wgt, g.c[0], C[k][0]);
                 C[k][1] = Num<T>::fma(wgt, g.c[1], C[k][1]);
                 C[k][2] = Num<T>::fma(wgt, g.c[2], C[k][2]);
                 Tr[k] = keep ? tn : Tr[k];
                 last[k] = keep ? base - range.x + pos + 1 : last[k];
-                if (STATS) n_kept += keep ? 1u : 0u;
+                if (STATS) n_kept += uint32_t(__builtin_popcountll(keepm));   // uniform: the wave's count
             }
         }
         __builtin_amdgcn_wave_barrier();
     }
-    if (STATS) {
-        const uint32_t w = wave_sum_u32(n_kept);
-        if (lane == 0) atomicAdd(kept, static_cast<unsigned long long>(w));
-    }
+    if (STATS && lane == 0) atomicAdd(kept, static_cast<unsigned long long>(n_kept));
     const int64_t plane = int64_t(W) * H;
 #pragma unroll
     for (int k = 0; k < PPL; k++) {
@@ -527,7 +540,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             const Rec<T> g = lds_rec(s_rec[wave][i]);
             const T axc = s_rec[wave][i][S_AXC], axs = s_rec[wave][i][S_AXS];
 #pragma unroll
-            for (int q = 0; q < 9; q++) v[q] = T(0);
+            for (int q = 0; q < 9; q++) v[q] = -T(0);   // -0: the first x + v folds to x
             T* mo = v;
             T* dcol = v + 6;
             bool hit = false;   // uniform: some lane kept the record
@@ -540,7 +553,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
                 if (__ballot(keep) == 0) continue;     // uniform: no pixel of the wave keeps it
                 hit = true;
                 // the forward's operations on the kept pixels; zeros elsewhere
-                const T a = Num<T>::min(al, amax);
+                const T a = clamp_alpha(al, amax);
                 const T ak = keep ? a : T(0);
                 const T wgt = ak * Tr[k];
                 const T gcc = Num<T>::fma(gc[k][2], g.c[2], Num<T>::fma(gc[k][1], g.c[1], gc[k][0] * g.c[0]));
