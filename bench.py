@@ -285,7 +285,10 @@ def run_gpu(args):
 
     # timed region: HIP events bracket the whole loop; inside it the library
     # times the launches of the kernels the rooflines are taken on, with its
-    # own HIP events on the launch stream (fused calls hold several kernels).
+    # own HIP events on the launch stream (fused calls hold several kernels),
+    # on every PROFILE_STRIDE-th step: each event pair costs the stream a few
+    # microseconds, and a stride coprime to the 64 views samples a different
+    # view each time.
     # The per-stage split comes from a further untimed run of steps with
     # events between the calls (--inline-stage-timing puts those events in
     # the timed loop instead; each event costs the stream a few microseconds).
@@ -296,16 +299,21 @@ def run_gpu(args):
     gs.profile_set(kernels)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    stride = max(1, args.profile_stride)
     e0.record()
     for t in range(args.warmup, args.warmup + args.steps):
+        i = t - args.warmup
+        gs.profile_enable(i % stride == 0)
         step(t, timer if args.inline_stage_timing else None)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    kern = {}
+    gs.profile_enable(True)
+    kern, kern_n = {}, {}
     for k in kernels:
         tot, n = gs.profile_get(k)
         kern[k] = tot / max(n, 1)
+        kern_n[k] = n
     gs.profile_set(None)
     n_stage = args.steps
     if not args.inline_stage_timing:
@@ -362,7 +370,8 @@ def run_gpu(args):
                 "bytes": 44 * px, "ms": round(ssim_ms, 5), "lambda": lam}
         tf, tb = measured_traffic("k_ssim_fwd"), measured_traffic("k_ssim_bwd")
         ssim["traffic"] = tf + tb if tf is not None and tb is not None else None
-    return dict(ms_per_step=ms / args.steps, steps=args.steps, stage_ms=stage, kernel_ms=kern, opt_kernel=opt_kernel,
+    return dict(ms_per_step=ms / args.steps, steps=args.steps, stage_ms=stage, kernel_ms=kern, kernel_n=kern_n,
+                opt_kernel=opt_kernel,
                 ssim=ssim,
                 opt_bytes=opt_bytes, opt_gbs=opt_bytes / (opt_ms * 1e-3) / 1e9, pairs_max=pmax, pairs=pairs,
                 kept=kept, visible=visible, hw=args.width * args.height, bwd_flops=bwd_flops, bwd_tflops=bwd_flops / (kern["k_render_bwd"] * 1e-3) / 1e12, N=N, A=A,
@@ -1056,6 +1065,8 @@ def main():
     ap.add_argument("--order", choices=("z-strands", "z", "generator"), default="z-strands",
                     help="storage order of the training scene's Gaussians (a layout: the scene is the same): Z-order "
                          "of the means in 16-Gaussian chunks over 1024 strands, plain Z-order, or as drawn")
+    ap.add_argument("--profile-stride", type=int, default=9,
+                    help="time the roofline kernels' launches on every n-th timed step (1: all)")
     ap.add_argument("--inline-stage-timing", action="store_true",
                     help="record the per-stage events inside the timed loop (adds their cost to the step time)")
     ap.add_argument("--workload", choices=("train", "blocks4", "serve", "consensus", "split4", "oracle"), default="train",
@@ -1175,6 +1186,9 @@ def main():
                    "max_pairs": r["pairs_max"], "storage_order": args.order},
         "stage_ms": {k: round(v, 5) for k, v in r["stage_ms"].items()},
         "kernel_ms": {k: round(v, 5) for k, v in r["kernel_ms"].items()},
+        "kernel_ms_launches": r["kernel_n"],
+        "kernel_ms_note": f"HIP events on the launch stream around every {args.profile_stride}-th timed step's "
+                          "launch of each kernel",
         "roofline": {"bound": "alu", "kernel": "k_render_bwd", "achieved": round(r["bwd_tflops"], 3),
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(r["bwd_tflops"] / FP32_VECTOR_PEAK_TFLOPS, 4),

@@ -357,6 +357,12 @@ gs_status gs_render_bwd_adam(gs_params *x, const gs_frame *frame, const gs_raste
  * 0 for a kernel never launched). */
 gs_status gs_profile_set(const char *names);
 gs_status gs_profile_get(const char *name, double *total_ms, int64_t *launches);
+/* gs_profile_enable(on): on = 0 stops the selected kernels from recording
+ * events, keeping their totals and the selection; on != 0 resumes
+ * recording.  A caller can so time a sample of the launches of a long run
+ * without paying the event pairs on every launch.  gs_profile_set resumes
+ * recording as well.  Host-side only; never fails. */
+gs_status gs_profile_enable(int32_t on);
 
 /* Tile-shape autotuner (no counterpart in the paper: a choice of launch
  * shapes for the batched K-block step of Alg. 2, S1).  A candidate is a

@@ -553,6 +553,7 @@ namespace {
 struct ProfState {
     std::mutex mu;
     std::atomic<bool> on{false};
+    bool paused = false;
     bool all = false;
     std::set<std::string> names;
     struct Entry {
@@ -631,7 +632,17 @@ gs_status gs_profile_set(const char* names) {
         else if (!n.empty()) P.names.insert(n);
         a = b + 1;
     }
+    P.paused = false;
     P.on.store(P.all || !P.names.empty(), std::memory_order_relaxed);
+    g_err[0] = 0;
+    return GS_OK;
+}
+
+gs_status gs_profile_enable(int32_t on) {
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.paused = on == 0;
+    P.on.store(!P.paused && (P.all || !P.names.empty()), std::memory_order_relaxed);
     g_err[0] = 0;
     return GS_OK;
 }

@@ -344,10 +344,27 @@ __device__ inline void record_pair_sum(const T* __restrict__ pg, uint64_t p0, ui
     for (int i = 0; i < 9; i++) d[i] = T(0);
     const bool big = np > kCoop;
     if (!big) {
+        // four pairs per round trip: their loads are issued before any is
+        // added; past the last pair a lane reloads its last pair (in bounds)
+        // and adds -0 instead, which leaves every sum unchanged, so the sums
+        // are the one-pair-at-a-time sums bit for bit
         const T* src = pg + int64_t(p0) * 9;
-        for (uint64_t k = 0; k < np; k++)
+        for (uint64_t k = 0; k < np; k += 4) {
+            T t[4][9];
 #pragma unroll
-            for (int i = 0; i < 9; i++) d[i] += src[k * 9 + i];
+            for (int j = 0; j < 4; j++) {
+                const bool in = k + j < np;
+                const T* sj = src + (in ? k + j : np - 1) * 9;
+#pragma unroll
+                for (int i = 0; i < 9; i++) t[j][i] = sj[i];
+#pragma unroll
+                for (int i = 0; i < 9; i++) t[j][i] = in ? t[j][i] : -T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int i = 0; i < 9; i++) d[i] += t[j][i];
+        }
     }
     uint64_t bigmask = __ballot(big);
     while (bigmask) {

@@ -121,6 +121,7 @@ def _load():
                          P(ctypes.c_double)], c_i32),
         "gs_profile_set": ([ctypes.c_char_p], c_i32),
         "gs_profile_get": ([ctypes.c_char_p, P(ctypes.c_double), P(c_i64)], c_i32),
+        "gs_profile_enable": ([c_i32], c_i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -532,6 +533,12 @@ def profile_set(names):
     if names is not None and not isinstance(names, str):
         names = ",".join(names)
     _check(lib.gs_profile_set(names.encode() if names else None), "gs_profile_set")
+
+
+def profile_enable(on):
+    """Pause (False) or resume (True) event recording of the selected kernels,
+    keeping their totals: times a sample of the launches."""
+    _check(lib.gs_profile_enable(1 if on else 0), "gs_profile_enable")
 
 
 def profile_get(name):

@@ -209,6 +209,13 @@ def test_profile_registry_host_only(gs):
     gs.profile_set(None)
     assert gs.profile_get("k_emit") == (0.0, 0)
     assert gs.lib.gs_profile_get(None, None, None) == gs.GS_E_INVALID
+    # pausing keeps the selection; recording resumes on enable or on a new set
+    gs.profile_set(["k_render_bwd"])
+    gs.profile_enable(False)
+    gs.profile_enable(True)
+    assert gs.profile_get("k_render_bwd") == (0.0, 0)
+    gs.profile_enable(False)
+    gs.profile_set(None)
 
 
 def test_workspace_sizes_grow_with_inputs(gs):
