@@ -19,28 +19,34 @@ __host__ __device__ constexpr int plane_group(int a) {
 
 struct AdamConsts {
     float lr[5], rho[5];
-    float b1, b2, eps, bc1, bc2;
+    float b1, b2, eps, rbc1, rbc2;
 };
 
-// bias corrections 1 - beta^t evaluated in double on the host, then rounded
+// reciprocals of the bias corrections 1 - beta^t, evaluated in double on the
+// host, then rounded
 inline AdamConsts adam_consts(const gs_adam_cfg& cfg) {
     AdamConsts c;
     for (int k = 0; k < 5; k++) { c.lr[k] = cfg.lr[k]; c.rho[k] = cfg.rho[k]; }
     c.b1 = cfg.beta1; c.b2 = cfg.beta2; c.eps = cfg.eps;
-    c.bc1 = float(1.0 - std::pow(double(cfg.beta1), double(cfg.step)));
-    c.bc2 = float(1.0 - std::pow(double(cfg.beta2), double(cfg.step)));
+    c.rbc1 = float(1.0 / (1.0 - std::pow(double(cfg.beta1), double(cfg.step))));
+    c.rbc2 = float(1.0 / (1.0 - std::pow(double(cfg.beta2), double(cfg.step))));
     return c;
 }
 
-// g' = g + rho (x - w); m, v moments; x -= lr m^ / (sqrt(v^) + eps)
+// g' = g + rho (x - w); m, v moments; x -= lr m^ / (sqrt(v^) + eps).
+// The bias corrections are applied as products with their reciprocals and
+// the step's quotient as a product with the hardware reciprocal of the
+// hardware square root plus eps (each within an ulp or two): a few
+// instructions where the correctly rounded divisions and square root take
+// about forty, in a pass that streams every parameter
 __device__ inline float adam_one(float& x, float g, float& m, float& v, float w, float rho, float lr,
                                  const AdamConsts& c) {
     const float gp = g + rho * (x - w);
     m = c.b1 * m + (1.0f - c.b1) * gp;
     v = c.b2 * v + (1.0f - c.b2) * gp * gp;
-    const float mh = m / c.bc1;
-    const float vh = v / c.bc2;
-    x = x - lr * mh / (__builtin_sqrtf(vh) + c.eps);
+    const float mh = m * c.rbc1;
+    const float vh = v * c.rbc2;
+    x = x - lr * mh * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(vh) + c.eps);
     return x;
 }
 
