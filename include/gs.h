@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GS_ABI_VERSION 4
+#define GS_ABI_VERSION 5
 
 typedef enum {
     GS_OK = 0,
@@ -158,6 +158,13 @@ typedef struct {
                                 gs_bin_sort, needed when fwd_waves or bwd_waves is
                                 GS_WAVES_ADAPTIVE: [0..2] = tiles taking 4, 2 and 1 wavefronts,
                                 then the tile ids, those groups in that order */
+    uint8_t *qmask;          /* device [capacity] or NULL: per list entry (vals order), bit q set
+                                unless no pixel centre of 8x8 quadrant q of its tile (row-major
+                                over the tile's quadrants, at most 4) can reach alpha_min for
+                                its record.  Written by gs_render_fwd for the entries it walks,
+                                read by gs_render_bwd of the same frame and bins, which then
+                                need not recompute these conservative tests; with NULL the
+                                backward computes them itself (same results bit for bit). */
 } gs_bins;
 
 /* Adam with the ADMM penalty (Eq. 8a, supplementary Sec. C).  Groups in the

@@ -106,8 +106,8 @@ __device__ inline T clamp_to(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? h
 // what the box keeps only because it is axis-aligned (elongated, rotated
 // Gaussians); a skipped pixel would have had alpha < alpha_min, so images and
 // gradients are unchanged.
-template <typename T, int QX, int QY>
-__device__ inline uint32_t quad_mask(const T (&w)[GS_REC_WORDS], int px0, int py0, T lmin) {
+template <typename T>
+__device__ inline uint32_t quad_mask_n(const T (&w)[GS_REC_WORDS], int px0, int py0, int nqx, int nq, T lmin) {
     using N = Num<T>;
     const T mx = w[R_MX], my = w[R_MY], qa = w[R_QA], qb = w[R_QB], qc = w[R_QC], lo = w[R_LO];
     const T x0 = mx - w[R_HX], x1 = mx + w[R_HX];
@@ -119,8 +119,8 @@ __device__ inline uint32_t quad_mask(const T (&w)[GS_REC_WORDS], int px0, int py
     auto expo = [&](T dx, T dy) { return N::fma(N::fma(qa, dx, qb * dy), dx, qc * dy * dy); };
     uint32_t mask = 0;
 #pragma unroll 1
-    for (int k = 0; k < QX * QY; k++) {
-        const T qx = T(px0 + 8 * (k % QX)), qy = T(py0 + 8 * (k / QX));
+    for (int k = 0; k < nq; k++) {
+        const T qx = T(px0 + 8 * (k % nqx)), qy = T(py0 + 8 * (k / nqx));
         const bool box = x1 >= qx + T(0.5) && x0 <= qx + T(7.5) && y1 >= qy + T(0.5) && y0 <= qy + T(7.5);
         const T ax = qx + T(0.5) - mx, bx = qx + T(7.5) - mx;
         const T ay = qy + T(0.5) - my, by = qy + T(7.5) - my;
@@ -136,6 +136,12 @@ __device__ inline uint32_t quad_mask(const T (&w)[GS_REC_WORDS], int px0, int py
         mask |= box && ell ? (1u << k) : 0u;
     }
     return mask;
+}
+
+// the same over the QX x QY quadrants from pixel (px0, py0)
+template <typename T, int QX, int QY>
+__device__ inline uint32_t quad_mask(const T (&w)[GS_REC_WORDS], int px0, int py0, T lmin) {
+    return quad_mask_n(w, px0, py0, QX, QX * QY, lmin);
 }
 
 __device__ inline uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -221,7 +227,8 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
                                                                      T* __restrict__ rgb, T* __restrict__ Tout,
                                                                      uint32_t* __restrict__ ncontrib,
                                                                      unsigned long long* __restrict__ kept,
-                                                                     const uint32_t* __restrict__ order) {
+                                                                     const uint32_t* __restrict__ order,
+                                                                     uint8_t* __restrict__ qmask) {
     constexpr int PPL = QX * QY;
     // NS wavefronts per tile, wave `sub` owning the tile's sub-tile of QX x QY
     // quadrants; NS = 0: the plan's wavefronts, heavy tiles first, each owning
@@ -286,7 +293,19 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame fr
         if (uint32_t(lane) < cnt) {
             r = vals[base + lane];
             load_rec(rec, r, w);
-            m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin) & owned;
+            if (ADAPT || NSD == 1) {
+                // this wavefront's quadrants are the tile's: its mask is the tile mask
+                const uint32_t mt = quad_mask<T, QX, QY>(w, tpx, tpy, lmin);
+                if (qmask) qmask[base + lane] = uint8_t(mt);
+                m = mt & owned;
+            } else {
+                m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin) & owned;
+                if (qmask) {
+                    const int tx0 = (lt % job.tiles_x) * cfg.tile_w, ty0 = (lt / job.tiles_x) * cfg.tile_h;
+                    const int nqx = cfg.tile_w / 8;
+                    qmask[base + lane] = uint8_t(quad_mask_n(w, tx0, ty0, nqx, nqx * (cfg.tile_h / 8), lmin));
+                }
+            }
         }
         const uint64_t staged = __ballot(m != 0);
         if (m != 0) {
@@ -356,7 +375,7 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
     const uint32_t* __restrict__ pair_off, const uint32_t* __restrict__ vals, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ order, uint64_t capacity, const T* __restrict__ rgb,
     const uint32_t* __restrict__ ncontrib, int mode, const T* __restrict__ gin, T* __restrict__ loss_out,
-    T* __restrict__ pg) {
+    T* __restrict__ pg, const uint8_t* __restrict__ qmask) {
     constexpr int PPL = QX * QY;
     // NS wavefronts per tile, wave `sub` owning the tile's sub-tile of QX x QY
     // quadrants and storing its own nine partials per pair (slot e NS + sub);
@@ -493,7 +512,20 @@ __global__ __launch_bounds__(kWave * kRenderWaves) void k_render_bwd(
             const uint32_t pos = pos0 + uint32_t(lane);
             if (pos < wend) {
                 load_rec(rec, r, w);
-                m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin) & owned;
+                if (qmask == nullptr) {
+                    m = quad_mask<T, QX, QY>(w, tpx, tpy, lmin);
+                } else if (ADAPT || NSD == 1) {
+                    m = qmask[base + lane];   // the forward's tile mask: this wavefront's quadrants are the tile's
+                } else {
+                    // the forward's tile mask, bits of this wavefront's sub-tile
+                    const uint32_t mt = qmask[base + lane];
+                    const int nqx = cfg.tile_w / 8, qx0 = (sub % sxn) * QX, qy0 = (sub / sxn) * QY;
+                    m = 0;
+#pragma unroll
+                    for (int k = 0; k < PPL; k++)
+                        m |= ((mt >> ((qy0 + k / QX) * nqx + qx0 + k % QX)) & 1u) << k;
+                }
+                m &= owned;
 #pragma unroll
                 for (int k = 0; k < PPL; k++) m &= pos < qend[k] ? ~0u : ~(1u << k);
             }
@@ -657,10 +689,10 @@ static void fwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec
     compositing_grid<NS>(f, grid, block);
     if (kept)
         GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, true>), grid, block, 0, s, f, cfg, rec, b.vals,
-                  reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept, b.tile_order);
+                  reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept, b.tile_order, b.qmask);
     else
         GS_LAUNCH("k_render_fwd", (k_render_fwd<T, QX, QY, NS, false>), grid, block, 0, s, f, cfg, rec, b.vals,
-                  reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept, b.tile_order);
+                  reinterpret_cast<const uint2*>(b.ranges), rgb, Tfin, nc, kept, b.tile_order, b.qmask);
 }
 
 template <typename T, int QX, int QY, int NS>
@@ -671,7 +703,7 @@ static void bwd_launch(const gs_frame& f, const gs_raster_cfg& cfg, const T* rec
     compositing_grid<NS>(f, grid, block);
     GS_LAUNCH("k_render_bwd", (k_render_bwd<T, QX, QY, NS>), grid, block, 0, s, f, cfg, rec,
               reinterpret_cast<const uint4*>(meta), b.pair_off, b.vals, reinterpret_cast<const uint2*>(b.ranges),
-              b.tile_order, b.capacity, rgb, nc, mode, gin, loss, pg);
+              b.tile_order, b.capacity, rgb, nc, mode, gin, loss, pg, b.qmask);
 }
 
 // (binning tile, wavefronts per tile) -> quadrants per wavefront QX x QY:

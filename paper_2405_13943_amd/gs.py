@@ -57,7 +57,7 @@ class GsRasterCfg(ctypes.Structure):
 
 class GsBins(ctypes.Structure):
     _fields_ = [("vals", c_vp), ("ranges", c_vp), ("pair_off", c_vp), ("counters", c_vp), ("capacity", c_u64),
-                ("tile_order", c_vp)]
+                ("tile_order", c_vp), ("qmask", c_vp)]
 
 
 class GsAdamCfg(ctypes.Structure):
@@ -263,12 +263,14 @@ class Buffers:
         self.T = torch.empty(max(frame.n_pixels, 1), dtype=dtype, device=device)
         self.ncontrib = torch.empty(max(frame.n_pixels, 1), dtype=torch.int32, device=device)
         self.tile_order = torch.empty(max(frame.n_tiles, 1) + 4, dtype=torch.int32, device=device)
+        self.share_qmask = True    # the forward hands its quadrant masks to the backward
         self.frame = frame
         self._alloc_pairs(capacity, device)
 
     def _alloc_pairs(self, capacity, device="cuda"):
         self.capacity = int(max(capacity, 1))
         self.vals = torch.empty(self.capacity, dtype=torch.int32, device=device)
+        self.qmask = torch.empty(self.capacity, dtype=torch.uint8, device=device)
         nb = lib.gs_bin_sort_workspace_size(self.frame.n_records, self.capacity, self.frame.n_tiles)
         self.bin_ws = torch.empty(nb, dtype=torch.uint8, device=device)
         nw = lib.gs_render_bwd_workspace_size(self.capacity, 1 if self.f64 else 0)
@@ -280,7 +282,8 @@ class Buffers:
     @property
     def bins(self) -> GsBins:
         return GsBins(self.vals.data_ptr(), self.ranges.data_ptr(), self.pair_off.data_ptr(),
-                      self.counters.data_ptr(), self.capacity, self.tile_order.data_ptr())
+                      self.counters.data_ptr(), self.capacity, self.tile_order.data_ptr(),
+                      self.qmask.data_ptr() if self.share_qmask else None)
 
 
 # ---------------------------------------------------------------------------

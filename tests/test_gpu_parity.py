@@ -308,6 +308,33 @@ def test_render_bwd_sub_tile_waves_match_oracle(cfg1, ref1, tile):
     assert torch.equal(grad, grad2)
 
 
+@pytest.mark.parametrize("tile", [(16, 16, -1), (16, 16, 1), (16, 16, 2, 1), (16, 16, 1, 4), (16, 16, 4, 2),
+                                  (32, 8, 2, 4), (32, 8, -1, 1), (16, 8, 2, 1), (8, 8, 1), (16, 16, -1, 2)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_quadrant_masks_from_forward_equal_recomputed(cfg1, tile, dtype):
+    """The backward reading the forward's per-entry quadrant masks (bins.qmask)
+    gives the gradients it gives when it recomputes them, bit for bit, and the
+    same loss, whatever the forward's and the backward's wavefront splits."""
+    if dtype == torch.float64 and tile != (16, 16, 2, 1):
+        pytest.skip("FP64 on one split pair")
+    cfg = gs.raster_cfg(tile)
+    frame = make_frame(cfg1, cfg)
+    params = torch.from_numpy(cfg1.params).to("cuda", dtype)
+    buf = gs.rasterize(params, frame, cfg)
+    target = frame_target(frame, cfg1, range(4)).to(dtype)
+    out = []
+    for share in (True, False):
+        buf.share_qmask = share
+        g = torch.empty_like(params)
+        loss = torch.zeros(4, dtype=dtype, device="cuda")
+        gs.render_bwd(params, frame, cfg, buf, g, gs.LOSS_L1, target, loss)
+        out.append((g, loss))
+    buf.share_qmask = True
+    assert torch.equal(out[0][0], out[1][0]), tile
+    # the per-job loss is added with atomics in no fixed order
+    torch.testing.assert_close(out[0][1], out[1][1], rtol=1e-6, atol=0)
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (16, 16, -1), (32, 8, -1), (8, 8, -1)])
 def test_l1_loss_mode(cfg1, tile):
     """GS_LOSS_L1 equals the external mode fed the oracle's dL/dC of the
