@@ -374,10 +374,27 @@ __device__ inline void record_pair_sum(const T* __restrict__ pg, uint64_t p0, ui
         T part[9];
 #pragma unroll
         for (int i = 0; i < 9; i++) part[i] = T(0);
+        // four strided pairs per lane and round trip, added in the order of
+        // the one-at-a-time loop (past the end: the lane's first pair
+        // reloaded, -0 added)
         const T* src = pg + int64_t(bp0) * 9;
-        for (uint64_t k = lane; k < bnp; k += kWave)
+        for (uint64_t k0 = lane; k0 < bnp; k0 += 4 * kWave) {
+            T t[4][9];
 #pragma unroll
-            for (int i = 0; i < 9; i++) part[i] += src[k * 9 + i];
+            for (int j = 0; j < 4; j++) {
+                const uint64_t k = k0 + uint64_t(j) * kWave;
+                const bool in = k < bnp;
+                const T* sj = src + (in ? k : k0) * 9;
+#pragma unroll
+                for (int i = 0; i < 9; i++) t[j][i] = sj[i];
+#pragma unroll
+                for (int i = 0; i < 9; i++) t[j][i] = in ? t[j][i] : -T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int i = 0; i < 9; i++) part[i] += t[j][i];
+        }
 #pragma unroll
         for (int i = 0; i < 9; i++) {
             const T t = wave_sum(part[i]);
