@@ -33,7 +33,8 @@ template <> struct Num<float> {
     __device__ static inline float exp(float x) { return __expf(x); }
     __device__ static inline float log(float x) { return __logf(x); }
     __device__ static inline float sqrt(float x) { return __builtin_sqrtf(x); }
-    __device__ static inline float rsqrt(float x) { return 1.0f / __builtin_sqrtf(x); }
+    __device__ static inline float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }   // hardware, ~1 ulp
+    __device__ static inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }    // hardware, ~1 ulp
     __device__ static inline float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     __device__ static inline float max(float a, float b) { return __builtin_fmaxf(a, b); }
     __device__ static inline float min(float a, float b) { return __builtin_fminf(a, b); }
@@ -45,6 +46,7 @@ template <> struct Num<double> {
     __device__ static inline double log(double x) { return ::log(x); }
     __device__ static inline double sqrt(double x) { return ::sqrt(x); }
     __device__ static inline double rsqrt(double x) { return 1.0 / ::sqrt(x); }
+    __device__ static inline double rcp(double x) { return 1.0 / x; }
     __device__ static inline double fma(double a, double b, double c) { return ::fma(a, b, c); }
     __device__ static inline double max(double a, double b) { return ::fmax(a, b); }
     __device__ static inline double min(double a, double b) { return ::fmin(a, b); }

@@ -147,7 +147,7 @@ __device__ inline bool geometry(const T* __restrict__ P, int64_t stride, int64_t
     if (!(G.t[2] > T(cfg.near_z))) return false;
     const T logit = plane(P, stride, 10, g);
     if (fin) finite_acc(*fin, logit);
-    G.o = T(1) / (T(1) + N::exp(-logit));
+    G.o = N::rcp(T(1) + N::exp(-logit));
     if (G.o < T(cfg.alpha_min)) return false;
 
     T q[4];
@@ -183,9 +183,9 @@ __device__ inline bool geometry(const T* __restrict__ P, int64_t stride, int64_t
     G.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
 
     // Jacobian of the perspective map at the (clamped) mean
-    G.rz = T(1) / G.t[2];
-    const T limx = T(cfg.jac_clip) * T(0.5) * T(cam.W) / cam.fx;
-    const T limy = T(cfg.jac_clip) * T(0.5) * T(cam.H) / cam.fy;
+    G.rz = N::rcp(G.t[2]);
+    const T limx = T(cfg.jac_clip) * T(0.5) * T(cam.W) * N::rcp(cam.fx);
+    const T limy = T(cfg.jac_clip) * T(0.5) * T(cam.H) * N::rcp(cam.fy);
     const T ux = G.t[0] * G.rz, uy = G.t[1] * G.rz;
     G.clx = (ux < -limx) || (ux > limx);
     G.cly = (uy < -limy) || (uy > limy);
@@ -209,7 +209,7 @@ __device__ inline bool geometry(const T* __restrict__ P, int64_t stride, int64_t
     G.sxx = G.t0[0] * St0[0] + G.t0[1] * St0[1] + G.t0[2] * St0[2] + T(cfg.dilation);
     G.sxy = G.t0[0] * St1[0] + G.t0[1] * St1[1] + G.t0[2] * St1[2];
     G.syy = G.t1[0] * St1[0] + G.t1[1] * St1[1] + G.t1[2] * St1[2] + T(cfg.dilation);
-    const T rdet = T(1) / (G.sxx * G.syy - G.sxy * G.sxy);
+    const T rdet = N::rcp(G.sxx * G.syy - G.sxy * G.sxy);
     G.a = G.syy * rdet;
     G.b = -G.sxy * rdet;
     G.c = G.sxx * rdet;
