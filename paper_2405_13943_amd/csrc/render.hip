@@ -1,35 +1,38 @@
 // Per-tile front-to-back alpha compositing (Eq. 2) and its hand-written
 // backward.
 //
-// One wavefront owns one screen tile made of QX x QY quadrants of 8x8 pixels;
-// lane l holds pixel (l % 8, l / 8) of every quadrant, so PPL = QX * QY pixels
-// per lane.  The wave walks the tile's record list in (depth, record) order,
+// One wavefront owns one screen tile made of QX x QY quadrants of 8x8 pixels
+// (or, split per tile from the frame's plan, a run of its quadrants); lane l
+// holds pixel (l % 8, l / 8) of every quadrant, so PPL = QX * QY pixels per
+// lane.  The wave walks the tile's record list in (depth, record) order,
 // staging a batch of records at a time in a wave-private LDS slice (one record
-// per lane, read back as broadcasts): no workgroup barrier, and each wave stops
-// as soon as all its pixels have terminated.  While staging, each lane also
-// computes which quadrants its record can reach (pixel box and an exact,
-// conservative bound of alpha over the quadrant), only records that reach
-// one are staged (compacted with a ballot prefix), and the compositing loop
-// skips (uniformly, per quadrant) every Gaussian that cannot reach alpha_min
-// there.  Past that test the per-pixel work is
-// predicated (selects, not branches): a pixel that does not keep a Gaussian
-// adds an exact zero and keeps its transmittance, so divergence costs no
-// exec-mask bookkeeping.  Workgroups are remapped so that each XCD renders
-// one contiguous run of tiles (neighbouring tiles share records in that XCD's
-// L2).
+// per lane, read back as broadcasts): no workgroup barrier in the walk, and
+// each wave stops as soon as all its pixels have terminated.  While staging,
+// each lane also computes which quadrants its record can reach (pixel box and
+// an exact, conservative bound of alpha over the quadrant); only records that
+// reach one are staged (compacted with a ballot prefix), and the compositing
+// loop skips (uniformly, per quadrant) every Gaussian that cannot reach
+// alpha_min there.  The forward hands these quadrant masks to the backward,
+// one byte per list entry.  Past that test the per-pixel work is predicated
+// (selects, not branches): a pixel that does not keep a Gaussian adds an
+// exact zero and keeps its transmittance, and the forward keeps its per-pixel
+// stop flags as wave-wide lane masks, so their bookkeeping runs on the scalar
+// unit.  Workgroups are remapped so that each XCD renders one contiguous run
+// of tiles (neighbouring tiles share records in that XCD's L2).
 //
 // The backward runs front to back as well: it recomputes alpha, T and the
-// accumulated colour exactly as the forward did (same operations, same
-// order, hence the same keep/stop decisions) and gets the colour behind a
-// Gaussian as C_final - C_accumulated, so no per-pair transmittance is ever
-// stored.  Per (tile, record) pair it sums nine partials over each row of 16
-// lanes with DPP and parks the four row sums in LDS; once per batch of
-// records one lane per record adds the rows and stores the pair's nine values
-// at its emission index, where the projection backward adds each record's
-// pairs in a fixed order (deterministic, no float atomics).  The nine values
-// are, with ge = dL/dalpha * alpha summed over the pair's pixels and
-// (e1, e2) the offset pixel - mean in the footprint's axes (e1 along the
-// conic's narrow axis (c, s) that the record carries, e2 = (-s, c) across):
+// accumulated colour with the forward's operations, keeps a Gaussian at a
+// pixel exactly when alpha >= alpha_min and its list position is below the
+// forward's contributor count there, and gets the colour behind a Gaussian
+// as C_final - C_accumulated, so no per-pair transmittance is ever stored.
+// Per (tile, record) pair it forms nine partials per lane and reduces those
+// of two records at once with the gfx950 lane-swap instructions and a row
+// sum; a row's last lane stores them at the pair's emission index, where the
+// projection backward adds each record's pairs in a fixed order
+// (deterministic, no float atomics).  The nine values are, with
+// ge = dL/dalpha * alpha summed over the pair's pixels and (e1, e2) the
+// offset pixel - mean in the footprint's axes (e1 along the conic's narrow
+// axis (c, s) that the record carries, e2 = (-s, c) across):
 //   sum ge, sum ge e1, sum ge e2, sum ge e1^2, sum ge e1 e2, sum ge e2^2,
 //   and dL/dcolour (r, g, b).
 // The geometric gradients follow from these moments in closed form.
