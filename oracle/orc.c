@@ -200,6 +200,7 @@ typedef struct {
     double raw[3];       /* SH sum before offset and clamp */
     double col[3];
     double near_gap, clip_gap, col_gap;
+    double amin_win;  /* relative window of the alpha_min decision (see project_one) */
 } proj_t;
 
 static void project_one(int deg, const double *P, long stride, long i, const orc_cam *cam,
@@ -270,6 +271,21 @@ static void project_one(int deg, const double *P, long stride, long i, const orc
     g->A[1] = -g->S2[1] / det;
     g->A[2] = g->S2[0] / det;
 
+    /* Window of the alpha_min decision, relative to alpha_min.  An FP32
+     * evaluation places the mean to within the rounding of its pixel
+     * coordinates, about 2^-24 (|m_x| + |m_y|) each way; a shift d of the
+     * offset changes the exponent e = delta^T A delta by up to
+     * 2 sqrt(lambda_max e) |d|, hence alpha by sqrt(lambda_max e) |d|
+     * relative, at the alpha_min contour e = 2 ln(o / alpha_min).  Decisions
+     * within that (at least 1e-4) are within rounding of the threshold. */
+    {
+        const double lmax = 0.5 * (g->A[0] + g->A[2]) +
+                            sqrt(0.25 * (g->A[0] - g->A[2]) * (g->A[0] - g->A[2]) + g->A[1] * g->A[1]);
+        const double ethr = g->o > cfg->alpha_min ? 2.0 * log(g->o / cfg->alpha_min) : 0.0;
+        const double dm = 2.0 * 0x1p-24 * (fabs(g->m[0]) + fabs(g->m[1]));
+        g->amin_win = fmax(1e-4, sqrt(lmax * ethr) * dm);
+    }
+
     double cc[3];
     mat3_transpose(W, MT);
     for (int r = 0; r < 3; r++)
@@ -324,7 +340,7 @@ static int pixel_composite(const proj_t *g, long n, double px, double py, const 
         double Gv = exp(-0.5 * e);
         double araw = G->o * Gv;
         double a = araw < cfg->alpha_max ? araw : cfg->alpha_max;
-        if (fabs(a / cfg->alpha_min - 1.0) < 1e-4) fl |= F_ALPHA_MIN;
+        if (fabs(a / cfg->alpha_min - 1.0) < G->amin_win) fl |= F_ALPHA_MIN;
         if (a < cfg->alpha_min) continue;
         if (G->near_gap < 1e-6) fl |= F_NEAR;
         hits[nh].depth = G->t[2];
