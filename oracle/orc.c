@@ -200,7 +200,9 @@ typedef struct {
     double raw[3];       /* SH sum before offset and clamp */
     double col[3];
     double near_gap, clip_gap, col_gap;
-    double amin_win;  /* relative window of the alpha_min decision (see project_one) */
+    double lmax;      /* largest eigenvalue of the conic */
+    double dm;        /* bound on an FP32 evaluation's error in the pixel-space mean */
+    double cabs[3];   /* sum of |terms| of the colour (SH terms and the 0.5 offset) */
 } proj_t;
 
 static void project_one(int deg, const double *P, long stride, long i, const orc_cam *cam,
@@ -271,20 +273,12 @@ static void project_one(int deg, const double *P, long stride, long i, const orc
     g->A[1] = -g->S2[1] / det;
     g->A[2] = g->S2[0] / det;
 
-    /* Window of the alpha_min decision, relative to alpha_min.  An FP32
-     * evaluation places the mean to within the rounding of its pixel
-     * coordinates, about 2^-24 (|m_x| + |m_y|) each way; a shift d of the
-     * offset changes the exponent e = delta^T A delta by up to
-     * 2 sqrt(lambda_max e) |d|, hence alpha by sqrt(lambda_max e) |d|
-     * relative, at the alpha_min contour e = 2 ln(o / alpha_min).  Decisions
-     * within that (at least 1e-4) are within rounding of the threshold. */
-    {
-        const double lmax = 0.5 * (g->A[0] + g->A[2]) +
-                            sqrt(0.25 * (g->A[0] - g->A[2]) * (g->A[0] - g->A[2]) + g->A[1] * g->A[1]);
-        const double ethr = g->o > cfg->alpha_min ? 2.0 * log(g->o / cfg->alpha_min) : 0.0;
-        const double dm = 2.0 * 0x1p-24 * (fabs(g->m[0]) + fabs(g->m[1]));
-        g->amin_win = fmax(1e-4, sqrt(lmax * ethr) * dm);
-    }
+    /* Inputs of the rounding bounds (alpha_rel_err below): an FP32
+     * evaluation places the mean to within a few roundings of its pixel
+     * coordinates, taken as 2 * 2^-24 (|m_x| + |m_y|). */
+    g->lmax = 0.5 * (g->A[0] + g->A[2]) +
+              sqrt(0.25 * (g->A[0] - g->A[2]) * (g->A[0] - g->A[2]) + g->A[1] * g->A[1]);
+    g->dm = 2.0 * 0x1p-24 * (fabs(g->m[0]) + fabs(g->m[1]));
 
     double cc[3];
     mat3_transpose(W, MT);
@@ -297,9 +291,13 @@ static void project_one(int deg, const double *P, long stride, long i, const orc
     int nk = (deg + 1) * (deg + 1);
     g->col_gap = 1e300;
     for (int ch = 0; ch < 3; ch++) {
-        double s = 0;
-        for (int k = 0; k < nk; k++) s += g->Y[k] * P[(11 + 3 * k + ch) * stride + i];
+        double s = 0, sa = 0.5;
+        for (int k = 0; k < nk; k++) {
+            s += g->Y[k] * P[(11 + 3 * k + ch) * stride + i];
+            sa += fabs(g->Y[k] * P[(11 + 3 * k + ch) * stride + i]);
+        }
         g->raw[ch] = s;
+        g->cabs[ch] = sa;
         g->col[ch] = s + 0.5 > 0 ? s + 0.5 : 0.0;
         g->col_gap = fmin(g->col_gap, fabs(s + 0.5));
     }
@@ -308,7 +306,7 @@ static void project_one(int deg, const double *P, long stride, long i, const orc
 /* ------------------------------------------------------------------ */
 /* per-pixel compositing                                                */
 
-typedef struct { double depth; long idx; double alpha; double araw; double G; double dx, dy; } hit_t;
+typedef struct { double depth; long idx; double alpha; double araw; double G; double dx, dy, rerr; } hit_t;
 
 static int hit_cmp(const void *a, const void *b) {
     const hit_t *x = a, *y = b;
@@ -317,10 +315,30 @@ static int hit_cmp(const void *a, const void *b) {
     return (x->idx < y->idx) ? -1 : (x->idx > y->idx);
 }
 
-/* gather, sort and composite one pixel; returns number of contributors.
- * T_before[j] holds the transmittance in front of list entry j. */
+#define U32 0x1p-24   /* FP32 unit roundoff */
+
+/* First-order bound on the relative error of alpha = o exp(-e/2) at a pixel
+ * whose exponent is e, when it is evaluated in FP32.  The mean's pixel
+ * position is off by up to dm; a shift d of the offset changes
+ * e = delta^T A delta by up to 2 sqrt(lambda_max e) |d|, hence alpha by
+ * sqrt(lambda_max e) |d| relative.  The conic, the exponent, exp and the
+ * opacity add a few roundings each, relative to e and to 1. */
+static double alpha_rel_err(const proj_t *G, double e) {
+    return sqrt(G->lmax * e) * G->dm + U32 * (8.0 + 8.0 * e);
+}
+
+/* Gather, sort and composite one pixel; returns number of contributors.
+ * T_before[j] holds the transmittance in front of list entry j.
+ * err (optional, 4 doubles) receives first-order bounds on what an FP32
+ * evaluation of the same pixel may differ by: err[0] relative to the final
+ * T, err[1..3] absolute on the colour.  Each kept alpha carries
+ * alpha_rel_err (zero when alpha_max clamps it); 1 - alpha_j then carries
+ * alpha_j / (1 - alpha_j) times that, and each product and sum one more
+ * rounding.  The same bounds widen the windows of the threshold decisions,
+ * so that a decision an FP32 evaluation may take the other way is flagged. */
 static int pixel_composite(const proj_t *g, long n, double px, double py, const orc_cfg *cfg,
-                           hit_t *hits, double *T_before, double *rgb, double *T_out, int *flags) {
+                           hit_t *hits, double *T_before, double *rgb, double *T_out, int *flags,
+                           double *err) {
     long nh = 0;
     int fl = 0;
     for (long i = 0; i < n; i++) {
@@ -340,7 +358,7 @@ static int pixel_composite(const proj_t *g, long n, double px, double py, const 
         double Gv = exp(-0.5 * e);
         double araw = G->o * Gv;
         double a = araw < cfg->alpha_max ? araw : cfg->alpha_max;
-        if (fabs(a / cfg->alpha_min - 1.0) < G->amin_win) fl |= F_ALPHA_MIN;
+        if (fabs(a / cfg->alpha_min - 1.0) < fmax(1e-4, alpha_rel_err(G, e))) fl |= F_ALPHA_MIN;
         if (a < cfg->alpha_min) continue;
         if (G->near_gap < 1e-6) fl |= F_NEAR;
         hits[nh].depth = G->t[2];
@@ -350,30 +368,43 @@ static int pixel_composite(const proj_t *g, long n, double px, double py, const 
         hits[nh].G = Gv;
         hits[nh].dx = dx;
         hits[nh].dy = dy;
+        hits[nh].rerr = alpha_rel_err(G, e);
         nh++;
     }
     qsort(hits, nh, sizeof(hit_t), hit_cmp);
     double T = 1.0;
     double C[3] = {0, 0, 0};
+    double Trel = 0, Cerr[3] = {0, 0, 0};
     int nc = 0;
     for (long j = 0; j < nh; j++) {
         double a = hits[j].alpha;
         double Tn = T * (1 - a);
-        if (fabs(Tn / cfg->T_min - 1.0) < 1e-4) fl |= F_T_MIN;
+        const double ra = hits[j].araw < cfg->alpha_max ? hits[j].rerr : 0.0;
+        const double Tnrel = Trel + a / (1 - a) * ra + 2 * U32;
+        if (fabs(Tn / cfg->T_min - 1.0) < fmax(1e-4, Tnrel)) fl |= F_T_MIN;
         if (Tn < cfg->T_min) break;
         const proj_t *G = &g[hits[j].idx];
-        if (fabs(hits[j].araw / cfg->alpha_max - 1.0) < 1e-4) fl |= F_ALPHA_MAX;
+        if (fabs(hits[j].araw / cfg->alpha_max - 1.0) < fmax(1e-4, hits[j].rerr)) fl |= F_ALPHA_MAX;
         if (G->col_gap < 1e-6) fl |= F_COLOUR;
         if (G->clip_gap < 1e-6) fl |= F_CLIP;
         if (j > 0 && fabs(hits[j].depth - hits[j - 1].depth) < 1e-6 * hits[j].depth) fl |= F_DEPTH_TIE;
         T_before[j] = T;
-        for (int ch = 0; ch < 3; ch++) C[ch] += G->col[ch] * a * T;
+        for (int ch = 0; ch < 3; ch++) {
+            const double w = a * T;
+            C[ch] += G->col[ch] * w;
+            Cerr[ch] += w * (G->col[ch] * (ra + Trel + 3 * U32) + 8 * U32 * G->cabs[ch]) + U32 * C[ch];
+        }
         T = Tn;
+        Trel = Tnrel;
         nc++;
     }
     /* a tie between the last contributor and the next kept Gaussian matters too */
     if (nc < nh && nc > 0 && fabs(hits[nc].depth - hits[nc - 1].depth) < 1e-6 * hits[nc].depth) fl |= F_DEPTH_TIE;
     for (int ch = 0; ch < 3; ch++) rgb[ch] = C[ch] + T * cfg->bg[ch];
+    if (err) {
+        err[0] = Trel;
+        for (int ch = 0; ch < 3; ch++) err[1 + ch] = Cerr[ch] + T * fabs(cfg->bg[ch]) * (Trel + 2 * U32) + U32 * fabs(rgb[ch]);
+    }
     *T_out = T;
     *flags = fl;
     return nc;
@@ -415,7 +446,7 @@ int orc_project(int n, int deg, const double *P, long stride, const orc_cam *cam
 
 /* Render the listed pixels (linear index y*W + x; NULL = every pixel). */
 int orc_render(int n, int deg, const double *P, long stride, const orc_cam *cam, const orc_cfg *cfg,
-               const long *pix, long npix, double *rgb, double *T, int *ncontrib, int *flags) {
+               const long *pix, long npix, double *rgb, double *T, int *ncontrib, int *flags, double *err) {
     if (n < 0 || deg < 0 || deg > 3) return 1;
     long total = pix ? npix : (long)cam->W * cam->H;
     proj_t *g = project_all(n, deg, P, stride, cam, cfg);
@@ -428,7 +459,7 @@ int orc_render(int n, int deg, const double *P, long stride, const orc_cam *cam,
             long p = pix ? pix[k] : k;
             double px = (p % cam->W) + 0.5, py = (p / cam->W) + 0.5;
             int fl;
-            ncontrib[k] = pixel_composite(g, n, px, py, cfg, hits, Tb, rgb + 3 * k, T + k, &fl);
+            ncontrib[k] = pixel_composite(g, n, px, py, cfg, hits, Tb, rgb + 3 * k, T + k, &fl, err ? err + 4 * k : NULL);
             flags[k] = fl;
         }
         free(hits);
@@ -575,7 +606,7 @@ int orc_backward(int n, int deg, const double *P, long stride, const orc_cam *ca
             double px = (p % cam->W) + 0.5, py = (p / cam->W) + 0.5;
             double rgb[3], Tf;
             int fl;
-            int nc = pixel_composite(g, n, px, py, cfg, hits, Tb, rgb, &Tf, &fl);
+            int nc = pixel_composite(g, n, px, py, cfg, hits, Tb, rgb, &Tf, &fl, NULL);
             /* colour behind entry j, starting with the background */
             double S[3] = {Tf * cfg->bg[0], Tf * cfg->bg[1], Tf * cfg->bg[2]};
             for (int j = nc - 1; j >= 0; j--) {

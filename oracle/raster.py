@@ -98,7 +98,7 @@ def load_library():
         dp, ip, lp = P(ctypes.c_double), P(ctypes.c_int), P(ctypes.c_long)
         lib.orc_project.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_long, P(_Cam), P(_Cfg), dp]
         lib.orc_render.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_long, P(_Cam), P(_Cfg),
-                                   lp, ctypes.c_long, dp, dp, ip, ip]
+                                   lp, ctypes.c_long, dp, dp, ip, ip, dp]
         lib.orc_backward.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_long, P(_Cam), P(_Cfg),
                                      lp, ctypes.c_long, dp, dp, dp]
         lib.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_long, dp, dp, dp]
@@ -145,7 +145,9 @@ def render(params, cam, cfg=None, pixels=None) -> dict:
     """Eq. 2 at every pixel (or at the listed linear pixel indices y*W + x).
 
     Returns rgb [3][H][W] (or [3][npix]), final transmittance, contributor
-    count and per-pixel decision flags."""
+    count, per-pixel decision flags, and first-order bounds on what an FP32
+    evaluation of the same pixel may differ by: T_err relative to T, rgb_err
+    absolute per channel."""
     cfg = cfg or RasterConfig()
     p, n, deg = _planes(params)
     c = Camera.of(cam)
@@ -158,18 +160,20 @@ def render(params, cam, cfg=None, pixels=None) -> dict:
     T = np.zeros(max(npix, 1))
     nc = np.zeros(max(npix, 1), np.int32)
     fl = np.zeros(max(npix, 1), np.int32)
+    err = np.zeros((max(npix, 1), 4))
     lib = load_library()
     rc = lib.orc_render(n, deg, _ptr(p, ctypes.c_double), n, ctypes.byref(c._c()), ctypes.byref(cfg._c()),
                         _ptr(pix, ctypes.c_long), npix, _ptr(rgb, ctypes.c_double), _ptr(T, ctypes.c_double),
-                        _ptr(nc, ctypes.c_int), _ptr(fl, ctypes.c_int))
+                        _ptr(nc, ctypes.c_int), _ptr(fl, ctypes.c_int), _ptr(err, ctypes.c_double))
     if rc:
         raise ValueError("orc_render failed")
-    rgb, T, nc, fl = rgb[:npix], T[:npix], nc[:npix], fl[:npix]
+    rgb, T, nc, fl, err = rgb[:npix], T[:npix], nc[:npix], fl[:npix], err[:npix]
     if pixels is None:
         H, W = c.height, c.width
         return {"rgb": rgb.T.reshape(3, H, W).copy(), "T": T.reshape(H, W), "n": nc.reshape(H, W),
-                "flags": fl.reshape(H, W)}
-    return {"rgb": rgb.T.copy(), "T": T, "n": nc, "flags": fl}
+                "flags": fl.reshape(H, W), "T_err": err[:, 0].reshape(H, W).copy(),
+                "rgb_err": err[:, 1:].T.reshape(3, H, W).copy()}
+    return {"rgb": rgb.T.copy(), "T": T, "n": nc, "flags": fl, "T_err": err[:, 0].copy(), "rgb_err": err[:, 1:].T.copy()}
 
 
 def backward(params, cam, dLdC, cfg=None, pixels=None, screen=False):

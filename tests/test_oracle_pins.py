@@ -343,6 +343,49 @@ def test_listed_pixels_equal_full_render():
     np.testing.assert_array_equal(part["n"], full["n"].ravel()[pix])
 
 
+def test_rounding_bounds_cover_a_shift_of_the_means():
+    """The per-pixel bounds T_err / rgb_err (first-order propagation of an
+    error of up to 2^-23 (|m_x| + |m_y|) in each mean's pixel position,
+    through alpha, 1 - alpha and the products of Eq. 2) against brute force:
+    moving the principal point by delta moves every projected mean by exactly
+    delta and changes nothing else, so rendering with it is an evaluation
+    whose means are off by |delta|.  At 1600x1066, far from the origin, the
+    change of T exceeds 1e-4 relative (what a fixed tolerance would allow),
+    and stays within the bound at every pixel neither render flags.  Dropping
+    the alpha / (1 - alpha) factor, or halving the term of the mean's shift,
+    fails it."""
+    import dataclasses
+    s = scenes.config2(n=200_000, n_cams=1)
+    cam = s.cams[0]
+    P = np.ascontiguousarray(s.params.astype(np.float64))
+    pr = oracle.project(P, cam)
+    x0, y0, C = 1150, 600, 64
+    o, S, m = pr["opacity"], pr["cov2d"], pr["mean2d"]
+    c = 2.0 * np.log(np.maximum(o * 255.0, 1.0))
+    hx, hy = np.sqrt(c * S[:, 0]) * 1.01 + 1.01, np.sqrt(c * S[:, 2]) * 1.01 + 1.01
+    sel = pr["valid"] & (o * 255.0 >= 1.0) & (m[:, 0] + hx >= x0) & (m[:, 0] - hx <= x0 + C) \
+        & (m[:, 1] + hy >= y0) & (m[:, 1] - hy <= y0 + C)
+    sub = np.ascontiguousarray(P[:, sel])
+    # every shift below is within each mean's error allowance
+    assert 2.0 ** -23 * np.abs(m[sel]).sum(1).min() > 1.5e-4
+    ys, xs = np.mgrid[y0:y0 + C, x0:x0 + C]
+    pix = (ys * cam.width + xs).ravel()
+    r0 = oracle.render(sub, cam, pixels=pix)
+    assert r0["n"].mean() > 5 and (r0["T_err"] > 0).all()
+    worst = 0.0
+    for d in ((1e-4, 1e-4), (-1e-4, 1e-4), (1.4e-4, 0.0), (0.0, -1.4e-4)):
+        r1 = oracle.render(sub, dataclasses.replace(cam, cx=cam.cx + d[0], cy=cam.cy + d[1]), pixels=pix)
+        ok = (r0["flags"] == 0) & (r1["flags"] == 0)
+        assert ok.mean() > 0.99
+        dT = np.abs(r1["T"] - r0["T"])[ok]
+        assert (dT <= r0["T_err"][ok] * r0["T"][ok]).all(), d
+        assert (np.abs(r1["rgb"] - r0["rgb"])[:, ok] <= r0["rgb_err"][:, ok]).all(), d
+        worst = max(worst, (dT / r0["T"][ok]).max())
+    assert worst > 2e-4
+    # not vacuous the other way either: the bound is within a small factor of what a shift does
+    assert np.median(r0["T_err"]) < 5e-4
+
+
 def test_l1_loss_worked_example():
     """L1 part of Eq. 3 on a hand-worked 3 x 1 x 2 image: C - target =
     [[0.1, -0.2], [0, 0.3], [-0.5, 0]], so sum |d| = 1.1 over 3HW = 6 values:
