@@ -365,23 +365,37 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
 // ---------------------------------------------------------------------------
 // pair emission and tile ranges
 
-// Pair-parallel emission: block-sized chunks of the P pairs; each chunk finds
-// the visible records it spans by binary search over their first-pair
-// offsets (staged in LDS), so a Gaussian covering thousands of tiles is
-// spread over many threads instead of serialising one.
+// Pair-parallel emission: workgroup b of G takes the pairs that block b of
+// the first radix pass takes (block_range with the same G and granule), in
+// chunks of kEmitChunk; each chunk finds the visible records it spans by
+// binary search over their first-pair offsets (staged in LDS), so a
+// Gaussian covering thousands of tiles is spread over many threads instead
+// of serialising one.  With hist set, the workgroup also counts the first
+// radix digit (the low bits0 bits of the tile id) of its pairs and stores
+// the counts as that pass's histogram column, which saves the pass its
+// counting launch.
 constexpr int kEmitChunk = 1024;
+constexpr int kEmitBlock = 256;
 
-__global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ vis,
-                                              const uint32_t* __restrict__ poff, const uint32_t* __restrict__ counters,
-                                              gs_frame frame, uint64_t capacity, uint32_t* __restrict__ tkey,
-                                              uint32_t* __restrict__ tval) {
+__global__ __launch_bounds__(kEmitBlock) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ vis,
+                                                     const uint32_t* __restrict__ poff,
+                                                     const uint32_t* __restrict__ counters, gs_frame frame,
+                                                     uint64_t capacity, uint32_t* __restrict__ tkey,
+                                                     uint32_t* __restrict__ tval, int G, uint32_t granule, int bits0,
+                                                     uint32_t* __restrict__ hist) {
+    static_assert(kEmitBlock == 256, "one histogram bin per thread");
     __shared__ uint32_t s_off[kEmitChunk];
     __shared__ uint32_t s_rec[kEmitChunk];
     __shared__ uint32_t s_lo, s_hi;
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0u;
+    const uint32_t mask0 = (1u << bits0) - 1u;
     const uint32_t V = counters[GS_CTR_VISIBLE];
     const uint32_t P = uint32_t(min(uint64_t(counters[GS_CTR_PAIRS]), capacity));
-    for (uint32_t e0 = blockIdx.x * kEmitChunk; e0 < P; e0 += gridDim.x * kEmitChunk) {
-        const uint32_t e1 = min(P, e0 + kEmitChunk);
+    uint32_t lo_e, hi_e;
+    block_range(P, G, blockIdx.x, granule, lo_e, hi_e);
+    for (uint32_t e0 = lo_e; e0 < hi_e; e0 += kEmitChunk) {
+        const uint32_t e1 = min(hi_e, e0 + kEmitChunk);
         if (threadIdx.x < 2) {
             // last visible rank whose first pair is <= target (ranks with zero
             // pairs do not exist: every visible record covers a tile)
@@ -411,10 +425,16 @@ __global__ __launch_bounds__(256) void k_emit(const uint4* __restrict__ meta, co
             const int j = job_of_record(frame.jobs, frame.n_jobs, r);
             const uint32_t x0 = m.z & 0xffffu, y0 = m.z >> 16, x1 = m.w & 0xffffu;
             const uint32_t w = x1 - x0 + 1;
-            tkey[e] = uint32_t(frame.jobs[j].tile0) + (y0 + k / w) * uint32_t(frame.jobs[j].tiles_x) + x0 + k % w;
+            const uint32_t t = uint32_t(frame.jobs[j].tile0) + (y0 + k / w) * uint32_t(frame.jobs[j].tiles_x) + x0 + k % w;
+            tkey[e] = t;
             tval[e] = r;
+            if (hist != nullptr) atomicAdd(&h[t & mask0], 1u);
         }
         __syncthreads();
+    }
+    if (hist != nullptr) {
+        __syncthreads();
+        hist[threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
     }
 }
 
@@ -543,11 +563,93 @@ __device__ void block_merge_sort(uint64_t* sk, uint32_t n) {
     }
 }
 
+// Compositing plan for adaptive wavefronts: every tile's wavefront count
+// (adaptive_waves of its list length) and the tiles grouped by it, 4-wave
+// tiles first (one workgroup each, and the longest lists start first), then
+// 2-wave, then 1-wave tiles.  One workgroup (of any multiple of the
+// wavefront); the order inside a group is whatever the LDS atomics give,
+// which changes no result (each tile is composited on its own).  The first
+// pass counts the groups in registers and keeps each tile's group in
+// `cache` (LDS, when n_tiles <= cache_cap) for the second, which places the
+// tiles.
+__device__ void tile_plan(const uint2* __restrict__ ranges, const uint32_t* __restrict__ counters, int n_tiles,
+                          int quads, uint32_t* __restrict__ order, uint8_t* cache, int cache_cap) {
+    constexpr int kMaxWaves = 1024 / kWave;
+    __shared__ uint32_t cnt[3][kMaxWaves], cur[3];
+    const bool cached = cache != nullptr && n_tiles <= cache_cap;
+    const uint32_t pairs = counters[GS_CTR_PAIRS];
+    const int lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    auto group = [&](int t) {
+        if (t >= n_tiles) return -1;
+        const uint2 rg = ranges[t];
+        const int w = adaptive_waves(rg.y - rg.x, pairs, n_tiles, quads);
+        return w == 4 ? 0 : (w == 2 ? 1 : 2);
+    };
+    // counts: per thread in registers, then per wavefront
+    uint32_t c[3] = {0u, 0u, 0u};
+    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+        const int gr = group(t);
+        if (cached) cache[t] = uint8_t(gr);
+        c[0] += gr == 0 ? 1u : 0u;
+        c[1] += gr == 1 ? 1u : 0u;
+        c[2] += gr == 2 ? 1u : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        uint32_t v = c[k];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+        if (lane == 0) cnt[k][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot[3] = {0u, 0u, 0u};
+        for (int k = 0; k < 3; k++)
+            for (int w = 0; w < nw; w++) tot[k] += cnt[k][w];
+        cur[0] = 0u;
+        cur[1] = tot[0];
+        cur[2] = tot[0] + tot[1];
+        order[0] = tot[0];
+        order[1] = tot[1];
+        order[2] = tot[2];
+    }
+    __syncthreads();
+    // scatter: a wavefront reserves a run per group, lanes rank inside it
+    const int n_round = (n_tiles + int(blockDim.x) - 1) / int(blockDim.x) * int(blockDim.x);
+    for (int t = threadIdx.x; t < n_round; t += blockDim.x) {
+        const int gr = cached ? (t < n_tiles ? int(cache[t]) : -1) : group(t);
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const uint64_t b = __ballot(gr == k);
+            uint32_t base = 0u;
+            if (lane == 0 && b) base = atomicAdd(&cur[k], uint32_t(__builtin_popcountll(b)));
+            base = __shfl(base, 0, kWave);
+            if (gr == k) order[4 + base + __builtin_popcountll(b & lanemask_lt())] = uint32_t(t);
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_tile_plan(const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ counters, int n_tiles, int quads,
+                                                    uint32_t* __restrict__ order) {
+    tile_plan(ranges, counters, n_tiles, quads, order, nullptr, 0);
+}
+
+// With order set, workgroup 0 makes the compositing plan (tile_plan) and the
+// others sort; the plan only reads the ranges, so it runs beside the sorts.
 __global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restrict__ meta,
                                                           const uint2* __restrict__ ranges, int n_tiles,
-                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ longq) {
+                                                          uint32_t* __restrict__ vals, uint32_t* __restrict__ longq,
+                                                          const uint32_t* __restrict__ counters, int quads,
+                                                          uint32_t* __restrict__ order) {
     __shared__ uint64_t sk[kSortChunk];
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int first = order != nullptr ? 1 : 0;
+    if (int(blockIdx.x) < first) {
+        tile_plan(ranges, counters, n_tiles, quads, order, reinterpret_cast<uint8_t*>(sk), int(sizeof(sk)));
+        return;
+    }
+    const int nsort = int(gridDim.x) - first;
+    for (int tile = int(blockIdx.x) - first; tile < n_tiles; tile += nsort) {
         const uint2 rg = ranges[tile];
         const uint32_t n = rg.y - rg.x;
         if (n < 2) continue;                                   // uniform per workgroup
@@ -628,59 +730,6 @@ __global__ __launch_bounds__(kLongBlock) void k_tile_sort_long(const uint4* __re
     }
 }
 
-// Compositing plan for adaptive wavefronts: every tile's wavefront count
-// (adaptive_waves of its list length) and the tiles grouped by it, 4-wave
-// tiles first (one workgroup each, and the longest lists start first), then
-// 2-wave, then 1-wave tiles.  One workgroup; the order inside a group is
-// whatever the LDS atomics give, which changes no result (each tile is
-// composited on its own).
-__global__ __launch_bounds__(1024) void k_tile_plan(const uint2* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ counters, int n_tiles, int quads,
-                                                    uint32_t* __restrict__ order) {
-    __shared__ uint32_t cnt[3], cur[3];
-    if (threadIdx.x < 3) cnt[threadIdx.x] = 0u;
-    __syncthreads();
-    const uint32_t pairs = counters[GS_CTR_PAIRS];
-    const int lane = lane_id();
-    auto group = [&](int t) {
-        if (t >= n_tiles) return -1;
-        const uint2 rg = ranges[t];
-        const int w = adaptive_waves(rg.y - rg.x, pairs, n_tiles, quads);
-        return w == 4 ? 0 : (w == 2 ? 1 : 2);
-    };
-    // counts: one LDS atomic per group and wavefront
-    const int n_round = (n_tiles + int(blockDim.x) - 1) / int(blockDim.x) * int(blockDim.x);
-    for (int t = threadIdx.x; t < n_round; t += blockDim.x) {
-        const int gr = group(t);
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const uint64_t b = __ballot(gr == k);
-            if (lane == 0 && b) atomicAdd(&cnt[k], uint32_t(__builtin_popcountll(b)));
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        cur[0] = 0u;
-        cur[1] = cnt[0];
-        cur[2] = cnt[0] + cnt[1];
-    }
-    if (threadIdx.x < 3) order[threadIdx.x] = cnt[threadIdx.x];
-    __syncthreads();
-    // scatter: a wavefront reserves a run per group, lanes rank inside it
-    for (int t = threadIdx.x; t < n_round; t += blockDim.x) {
-        const int gr = group(t);
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const uint64_t b = __ballot(gr == k);
-            uint32_t base = 0u;
-            if (lane == 0 && b) base = atomicAdd(&cur[k], uint32_t(__builtin_popcountll(b)));
-            base = __shfl(base, 0, kWave);
-            if (gr == k) order[4 + base + __builtin_popcountll(b & lanemask_lt())] = uint32_t(t);
-        }
-    }
-}
-
-
 // ---------------------------------------------------------------------------
 
 static int grid_for(uint64_t n_max, int per_block) {
@@ -690,18 +739,44 @@ static int grid_for(uint64_t n_max, int per_block) {
     return int(g);
 }
 
-// sorts by the low `bits` bits of the keys in passes of at most 8 bits;
-// returns (in k_final) the buffer that holds the sorted keys
-static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
-                             uint32_t n_max, int bits, uint32_t** k_final, hipStream_t s, BinWs& w) {
+// Grid and keys per workgroup of the radix passes over at most n_max keys.
+struct RadixShape {
+    bool small;
+    uint32_t tile;
+    int G;
+};
+static RadixShape radix_shape(uint32_t n_max) {
     const bool small = n_max <= kRsSmallMax;
     const uint32_t tile = kRsBlock * (small ? kRsItemsSmall : kRsItemsLarge);
-    const int G = grid_for(n_max, int(tile));
-    const int passes = (bits + 7) / 8;
+    return {small, tile, grid_for(n_max, int(tile))};
+}
+static int radix_passes(int bits) { return (bits + 7) / 8; }
+// width of pass p's digit: near-equal widths over the passes
+static int radix_digit(int bits, int p) {
+    const int passes = radix_passes(bits);
+    int shift = 0;
+    for (int q = 0; q < p; q++) shift += (bits - shift) / (passes - q);
+    return (bits - shift) / (passes - p);
+}
+
+// sorts by the low `bits` bits of the keys in passes of at most 8 bits;
+// returns (in k_final) the buffer that holds the sorted keys.  With
+// first_hist_done the first pass's histogram is already in w.hist (k_emit
+// counted it).
+static hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, const uint32_t* n_dev,
+                             uint32_t n_max, int bits, bool first_hist_done, uint32_t** k_final, hipStream_t s,
+                             BinWs& w) {
+    const RadixShape rs = radix_shape(n_max);
+    const bool small = rs.small;
+    const uint32_t tile = rs.tile;
+    const int G = rs.G;
+    const int passes = radix_passes(bits);
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     for (int p = 0, shift = 0; p < passes; p++) {
-        const int b = (bits - shift) / (passes - p);          // near-equal digit widths
-        GS_LAUNCH("k_rs_hist", k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, b, w.hist, G, tile);
+        const int b = radix_digit(bits, p);
+        if (p > 0 || !first_hist_done)
+            GS_LAUNCH("k_rs_hist", k_rs_hist, dim3(G), dim3(kRsBlock), 0, s, ki, n_dev, n_max, shift, b, w.hist, G,
+                      tile);
         GS_LAUNCH("k_rs_colscan", k_rs_colscan, dim3(256), dim3(kRsBlock), 0, s, w.hist, G, w.coltot);
         if (small)
             GS_LAUNCH("k_rs_scatter", k_rs_scatter<kRsItemsSmall>, dim3(G), dim3(kRsBlock), 0, s, ki, vi, ko, vo, n_dev,
@@ -728,10 +803,12 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     // counts restart every call (the record scan writes them); the status
     // bits are sticky until the caller clears them
     const int64_t nt = f.n_tiles;
+    const bool want_plan = bins.tile_order && (fwd_waves(cfg) == 0 || bwd_waves(cfg) == 0);
+    const int quads = (cfg.tile_w / 8) * (cfg.tile_h / 8);
     auto plan = [&]() {
-        if (bins.tile_order && (fwd_waves(cfg) == 0 || bwd_waves(cfg) == 0))
-            GS_LAUNCH("k_tile_plan", k_tile_plan, dim3(1), dim3(1024), 0, s, ranges, bins.counters, f.n_tiles,
-                      (cfg.tile_w / 8) * (cfg.tile_h / 8), bins.tile_order);
+        if (want_plan)
+            GS_LAUNCH("k_tile_plan", k_tile_plan, dim3(1), dim3(1024), 0, s, ranges, bins.counters, f.n_tiles, quads,
+                      bins.tile_order);
     };
     if (nrec == 0) {
         GS_LAUNCH("k_counters_empty", k_counters_empty, dim3(1), dim3(64), 0, s, bins.counters);
@@ -755,31 +832,41 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
                   bins.counters, bins.capacity);
     }
     // 2. emit (tile, record) pairs in record order, then sort them by tile id
+    //    (the emission counts the first radix digit)
     int bits = 0;
     while ((1ll << bits) < nt) bits++;
-    const int passes = (bits + 7) / 8;
+    const int passes = radix_passes(bits);
     uint32_t* emit_val = (passes & 1) ? w.tval : bins.vals;
     uint32_t* other_val = (passes & 1) ? bins.vals : w.tval;
-    GS_LAUNCH("k_emit", k_emit, dim3(unsigned(grid_for(bins.capacity, kEmitChunk))), dim3(256), 0, s, meta, w.vis,
-              w.poff, bins.counters, f, bins.capacity, w.tkey[0], emit_val);
     const uint32_t pmax = uint32_t(std::min<uint64_t>(bins.capacity, 0xffffffffull));
+    if (passes > 0) {
+        const RadixShape rs = radix_shape(pmax);
+        GS_LAUNCH("k_emit", k_emit, dim3(rs.G), dim3(kEmitBlock), 0, s, meta, w.vis, w.poff, bins.counters, f,
+                  bins.capacity, w.tkey[0], emit_val, rs.G, rs.tile, radix_digit(bits, 0), w.hist);
+    } else {
+        const int G = grid_for(pmax, kEmitChunk);
+        GS_LAUNCH("k_emit", k_emit, dim3(G), dim3(kEmitBlock), 0, s, meta, w.vis, w.poff, bins.counters, f,
+                  bins.capacity, w.tkey[0], emit_val, G, uint32_t(kEmitChunk), 0, static_cast<uint32_t*>(nullptr));
+    }
     uint32_t* tk_final = w.tkey[0];
     if (passes > 0) {
         const hipError_t e = radix_sort(w.tkey[0], emit_val, w.tkey[1], other_val, bins.counters + GS_CTR_PAIRS, pmax,
-                                        bits, &tk_final, s, w);
+                                        bits, true, &tk_final, s, w);
         if (e != hipSuccess) return e;
     }
     // 3. per-tile [start, end)
     GS_LAUNCH("k_ranges", k_ranges, dim3(2048), dim3(256), 0, s, tk_final, bins.counters, bins.capacity, ranges);
-    // 4. each tile's list in (depth bits, record) order
+    // 4. each tile's list in (depth bits, record) order, and (5.) beside it
+    //    the compositing plan, when a pass splits tiles adaptively
     if (nt > 0) {
-        GS_LAUNCH("k_tile_sort", k_tile_sort, dim3(unsigned(std::min<int64_t>(nt, 4096))), dim3(kSortBlock), 0, s, meta,
-                  ranges, f.n_tiles, bins.vals, w.longq);
+        uint32_t* order = want_plan ? bins.tile_order : nullptr;
+        GS_LAUNCH("k_tile_sort", k_tile_sort, dim3(unsigned(std::min<int64_t>(nt, 4096) + (want_plan ? 1 : 0))),
+                  dim3(kSortBlock), 0, s, meta, ranges, f.n_tiles, bins.vals, w.longq, bins.counters, quads, order);
         GS_LAUNCH("k_tile_sort_long", k_tile_sort_long, dim3(unsigned(std::min<int64_t>(nt, 256))), dim3(kLongBlock), 0,
                   s, meta, ranges, w.longq, bins.vals, w.key[0], w.key[1]);
+    } else {
+        plan();
     }
-    // 5. compositing plan, when a pass splits tiles adaptively
-    plan();
     return hipGetLastError();
 }
 
