@@ -475,9 +475,9 @@ def run_serve(args):
     return out
 
 
-KERNELS = ("k_project", "k_fill_u32", "k_scan_reduce", "k_scan_apply", "k_tile_offsets", "k_scatter",
-           "k_tile_sort", "k_tile_sort_long", "k_render_fwd", "k_render_bwd", "k_project_bwd_rec",
-           "k_zero_uncovered", "k_project_bwd_adam", "k_adam_uncovered", "k_adam_admm", "k_consensus")
+KERNELS = ("k_project", "k_fill_u32", "k_scan_reduce", "k_scan_apply", "k_emit", "k_rs_hist", "k_rs_colscan",
+           "k_rs_scatter", "k_ranges", "k_tile_sort", "k_tile_sort_long", "k_tile_plan", "k_render_fwd",
+           "k_render_bwd", "k_project_bwd_rec", "k_zero_uncovered", "k_project_bwd_adam", "k_adam_uncovered", "k_adam_admm", "k_consensus")
 
 
 def kernel_breakdown(gs, torch, fn, steps):
