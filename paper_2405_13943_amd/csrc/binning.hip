@@ -565,67 +565,56 @@ __device__ void block_merge_sort(uint64_t* sk, uint32_t n) {
 
 // Compositing plan for adaptive wavefronts: every tile's wavefront count
 // (adaptive_waves of its list length) and the tiles grouped by it, 4-wave
-// tiles first (one workgroup each, and the longest lists start first), then
-// 2-wave, then 1-wave tiles.  One workgroup (of any multiple of the
-// wavefront); the order inside a group is whatever the LDS atomics give,
+// tiles first (one workgroup each), then 2-wave, then 1-wave tiles; inside
+// a group the longer lists first, by buckets of half the frame's mean list
+// length (the last bucket open-ended), so that the heaviest tiles of each
+// group do not start last.  One workgroup (of any multiple of the
+// wavefront); the order inside a bucket is whatever the LDS atomics give,
 // which changes no result (each tile is composited on its own).  The first
-// pass counts the groups in registers and keeps each tile's group in
-// `cache` (LDS, when n_tiles <= cache_cap) for the second, which places the
-// tiles.
+// pass counts the buckets and keeps each tile's bucket in `cache` (LDS, when
+// n_tiles <= cache_cap) for the second, which places the tiles.
+constexpr int kPlanBuckets = 16;
+
 __device__ void tile_plan(const uint2* __restrict__ ranges, const uint32_t* __restrict__ counters, int n_tiles,
                           int quads, uint32_t* __restrict__ order, uint8_t* cache, int cache_cap) {
-    constexpr int kMaxWaves = 1024 / kWave;
-    __shared__ uint32_t cnt[3][kMaxWaves], cur[3];
+    constexpr int NB = 3 * kPlanBuckets;
+    static_assert(NB <= 256, "a tile's bin fits a byte");
+    __shared__ uint32_t cnt[NB];
     const bool cached = cache != nullptr && n_tiles <= cache_cap;
-    const uint32_t pairs = counters[GS_CTR_PAIRS];
-    const int lane = lane_id(), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
-    auto group = [&](int t) {
-        if (t >= n_tiles) return -1;
-        const uint2 rg = ranges[t];
-        const int w = adaptive_waves(rg.y - rg.x, pairs, n_tiles, quads);
-        return w == 4 ? 0 : (w == 2 ? 1 : 2);
+    const uint64_t pairs = counters[GS_CTR_PAIRS];
+    for (int k = threadIdx.x; k < NB; k += blockDim.x) cnt[k] = 0u;
+    __syncthreads();
+    // bin: group (4, 2, 1 wavefronts) major, then the length bucket, longest first
+    auto bin = [&](int t) {
+        const uint32_t n = ranges[t].y - ranges[t].x;
+        const int w = adaptive_waves(n, uint32_t(pairs), n_tiles, quads);
+        const int grp = w == 4 ? 0 : (w == 2 ? 1 : 2);
+        const uint64_t q = pairs ? (2ull * n * uint64_t(n_tiles)) / pairs : 0ull;   // n / (mean / 2)
+        const int bucket = q < uint64_t(kPlanBuckets - 1) ? int(q) : kPlanBuckets - 1;
+        return grp * kPlanBuckets + (kPlanBuckets - 1 - bucket);
     };
-    // counts: per thread in registers, then per wavefront
-    uint32_t c[3] = {0u, 0u, 0u};
     for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-        const int gr = group(t);
-        if (cached) cache[t] = uint8_t(gr);
-        c[0] += gr == 0 ? 1u : 0u;
-        c[1] += gr == 1 ? 1u : 0u;
-        c[2] += gr == 2 ? 1u : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        uint32_t v = c[k];
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-        if (lane == 0) cnt[k][wave] = v;
+        const int b = bin(t);
+        if (cached) cache[t] = uint8_t(b);
+        atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t tot[3] = {0u, 0u, 0u};
-        for (int k = 0; k < 3; k++)
-            for (int w = 0; w < nw; w++) tot[k] += cnt[k][w];
-        cur[0] = 0u;
-        cur[1] = tot[0];
-        cur[2] = tot[0] + tot[1];
+        uint32_t run = 0u, tot[3] = {0u, 0u, 0u};
+        for (int k = 0; k < NB; k++) {
+            const uint32_t c = cnt[k];
+            cnt[k] = run;                  // first place of the bin
+            run += c;
+            tot[k / kPlanBuckets] += c;
+        }
         order[0] = tot[0];
         order[1] = tot[1];
         order[2] = tot[2];
     }
     __syncthreads();
-    // scatter: a wavefront reserves a run per group, lanes rank inside it
-    const int n_round = (n_tiles + int(blockDim.x) - 1) / int(blockDim.x) * int(blockDim.x);
-    for (int t = threadIdx.x; t < n_round; t += blockDim.x) {
-        const int gr = cached ? (t < n_tiles ? int(cache[t]) : -1) : group(t);
-#pragma unroll
-        for (int k = 0; k < 3; k++) {
-            const uint64_t b = __ballot(gr == k);
-            uint32_t base = 0u;
-            if (lane == 0 && b) base = atomicAdd(&cur[k], uint32_t(__builtin_popcountll(b)));
-            base = __shfl(base, 0, kWave);
-            if (gr == k) order[4 + base + __builtin_popcountll(b & lanemask_lt())] = uint32_t(t);
-        }
+    for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+        const int b = cached ? int(cache[t]) : bin(t);
+        order[4 + atomicAdd(&cnt[b], 1u)] = uint32_t(t);
     }
 }
 

@@ -138,6 +138,40 @@ def test_bins_bit_exact(gpu1):
     _bins_check(frame, buf)
 
 
+def plan_check(frame, cfg, buf):
+    """The compositing plan: a permutation of the tiles grouped by their
+    wavefront count (4 above 4x the mean list length, 2 above 1.25x, never
+    more than the tile's quadrants), the counts in front; inside a group the
+    lists by bucket of half the mean length, longest first (last bucket
+    open-ended).  Which of several tiles of one bucket comes first is free."""
+    nt = frame.n_tiles
+    order = buf.tile_order.cpu().numpy().view(np.uint32)
+    rg = buf.ranges.view(-1, 2).cpu().numpy().view(np.uint32).astype(np.int64)
+    n = rg[:nt, 1] - rg[:nt, 0]
+    pairs = int(gs.read_counters(buf)["pairs"])
+    quads = (cfg.tile_w // 8) * (cfg.tile_h // 8)
+    a = 4 * n * nt
+    waves = np.minimum(np.where(a > 16 * pairs, 4, np.where(a > 5 * pairs, 2, 1)), quads)
+    n4, n2, n1 = (int(v) for v in order[:3])
+    assert (n4, n2, n1) == tuple(int((waves == w).sum()) for w in (4, 2, 1))
+    lst = order[4:4 + nt].astype(np.int64)
+    assert np.array_equal(np.sort(lst), np.arange(nt))
+    bucket = np.minimum(2 * n * nt // max(pairs, 1), 15)
+    for lo, hi, w in ((0, n4, 4), (n4, n4 + n2, 2), (n4 + n2, nt, 1)):
+        part = lst[lo:hi]
+        assert (waves[part] == w).all()
+        assert (np.diff(bucket[part]) <= 0).all()
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 8), (16, 8)])
+def test_compositing_plan(cfg1, tile):
+    cfg = gs.raster_cfg((*tile, -1, -1))
+    frame = make_frame(cfg1, cfg)
+    buf = gs.rasterize(torch.from_numpy(cfg1.params).cuda(), frame, cfg)
+    plan_check(frame, cfg, buf)
+    assert int(buf.tile_order[0]) + int(buf.tile_order[1]) > 0      # some tiles split
+
+
 @pytest.mark.parametrize("n", [300, 1500, 6000, 9000])
 def test_bins_bit_exact_long_tile_lists(n):
     """Large Gaussians in front of a small view put n entries in every tile

@@ -56,6 +56,14 @@ def crop_subset(pr, x0, y0):
     return np.nonzero(sel)[0]
 
 
+def test_compositing_plan_at_scale(step):
+    """The plan the timed step composites with: tiles grouped by wavefront
+    count and longest list first inside each group."""
+    from test_gpu_parity import plan_check
+    params_np, cam, cfg, params, frame, buf, pr = step
+    plan_check(frame, cfg, buf)
+
+
 @pytest.mark.parametrize("crop", CROPS)
 def test_image_and_gradient_on_crop(step, crop):
     params_np, cam, cfg, params, frame, buf, pr = step
