@@ -454,7 +454,8 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tke
 // list per workgroup at a time) takes lists of up to kSortChunk entries: up
 // to one workgroup's width a rank sort in LDS (each thread counts the keys
 // below its own), longer ones a merge sort in LDS (4 keys per thread up to
-// 1024 entries, 16 beyond).  k_tile_sort_long takes
+// 1024 entries, 8 beyond; 16 KB of LDS per workgroup, so that many
+// workgroups are resident).  k_tile_sort_long takes
 // the longer lists (dense views), one large workgroup each.
 //
 // The merge sort: every thread sorts E consecutive keys in registers (a
@@ -465,9 +466,9 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tke
 // work is O(n log n) with one LDS read and write per key and round.
 
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortItemsShort = 4;                      // lists up to 1024: more threads, shorter merges
-constexpr int kSortChunk = kSortBlock * kSortItems;     // 4096
+constexpr int kSortChunk = kSortBlock * kSortItems;     // 2048
 constexpr int kLongBlock = 1024;
 constexpr int kLongItems = 8;
 constexpr int kLongChunk = kLongBlock * kLongItems;     // 8192

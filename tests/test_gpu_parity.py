@@ -172,11 +172,11 @@ def test_compositing_plan(cfg1, tile):
     assert int(buf.tile_order[0]) + int(buf.tile_order[1]) > 0      # some tiles split
 
 
-@pytest.mark.parametrize("n", [300, 1500, 6000, 9000])
+@pytest.mark.parametrize("n", [300, 1500, 3000, 6000, 9000])
 def test_bins_bit_exact_long_tile_lists(n):
     """Large Gaussians in front of a small view put n entries in every tile
-    (above 256: the in-LDS merge sort, 4 keys per thread up to 1024 and 16
-    beyond; above 4096: the long-list kernel; above 8192: its chunks and
+    (above 256: the in-LDS merge sort, 4 keys per thread up to 1024 and 8
+    beyond; above 2048: the long-list kernel; above 8192: its chunks and
     merges), with many equal depths (ties ordered by record), against the
     reference."""
     p = scenes.gaussians(n, 0, 4100 + n, [-0.3, -0.3, -0.3], [0.3, 0.3, 0.3], 0.0, 0.1)
