@@ -221,17 +221,15 @@ __device__ inline void store_pair_partials(const double (&va)[9], const double (
 // forward
 
 // STATS: also add the number of (pixel, Gaussian) contributions of the
-// launch to *kept (one 64-bit atomic per wave).
+// launch to *kept (one 64-bit atomic per wave).  At least kFwdWavesPerSimd
+// wavefronts per SIMD: the FP32 forward then fits in 72 registers without
+// spilling, against 80 (6 per SIMD) left to itself.
+constexpr int kFwdWavesPerSimd = 7;
 template <typename T, int QX, int QY, int NS, bool STATS>
-__global__ __launch_bounds__(kWave * kRenderWaves) void k_render_fwd(gs_frame frame, gs_raster_cfg cfg,
-                                                                     const T* __restrict__ rec,
-                                                                     const uint32_t* __restrict__ vals,
-                                                                     const uint2* __restrict__ ranges,
-                                                                     T* __restrict__ rgb, T* __restrict__ Tout,
-                                                                     uint32_t* __restrict__ ncontrib,
-                                                                     unsigned long long* __restrict__ kept,
-                                                                     const uint32_t* __restrict__ order,
-                                                                     uint8_t* __restrict__ qmask) {
+__global__ __launch_bounds__(kWave * kRenderWaves, kFwdWavesPerSimd) void k_render_fwd(
+    gs_frame frame, gs_raster_cfg cfg, const T* __restrict__ rec, const uint32_t* __restrict__ vals,
+    const uint2* __restrict__ ranges, T* __restrict__ rgb, T* __restrict__ Tout, uint32_t* __restrict__ ncontrib,
+    unsigned long long* __restrict__ kept, const uint32_t* __restrict__ order, uint8_t* __restrict__ qmask) {
     constexpr int PPL = QX * QY;
     // NS wavefronts per tile, wave `sub` owning the tile's sub-tile of QX x QY
     // quadrants; NS = 0: the plan's wavefronts, heavy tiles first, each owning
