@@ -450,13 +450,14 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tke
 
 // ---------------------------------------------------------------------------
 // per-tile depth order: each tile's list (record ids, any order) sorted by the
-// unique key (depth bits, record id).  k_tile_sort (persistent grid, one
-// list per workgroup at a time) takes lists of up to kSortChunk entries: up
-// to one workgroup's width a rank sort in LDS (each thread counts the keys
-// below its own), longer ones a merge sort in LDS (4 keys per thread up to
-// 1024 entries, 8 beyond; 16 KB of LDS per workgroup, so that many
-// workgroups are resident).  k_tile_sort_long takes
-// the longer lists (dense views), one large workgroup each.
+// unique key (depth bits, record id).  k_tile_sort<ITEMS> (persistent grid,
+// one list per workgroup at a time) takes lists of up to kSortBlock * ITEMS
+// entries: up to one workgroup's width a rank sort in LDS (each thread
+// counts the keys below its own), longer ones a merge sort in LDS (4 keys
+// per thread up to 1024 entries, ITEMS beyond).  ITEMS is 8 (16 KB of LDS
+// per workgroup, twice as many workgroups resident) unless the frame's
+// lists are long on average (ITEMS 16, lists up to 4096 on chip).
+// k_tile_sort_long takes the longer lists, one large workgroup each.
 //
 // The merge sort: every thread sorts E consecutive keys in registers (a
 // sorting network), then rounds of pairwise merges double the sorted runs;
@@ -466,9 +467,10 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ tke
 // work is O(n log n) with one LDS read and write per key and round.
 
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 8;
+constexpr int kSortItems = 8;                           // lists up to 2048 on chip
+constexpr int kSortItemsDense = 16;                     // lists up to 4096 on chip
+constexpr uint64_t kDenseList = 1024;                   // mean list length (capacity / tiles) above which: dense
 constexpr int kSortItemsShort = 4;                      // lists up to 1024: more threads, shorter merges
-constexpr int kSortChunk = kSortBlock * kSortItems;     // 2048
 constexpr int kLongBlock = 1024;
 constexpr int kLongItems = 8;
 constexpr int kLongChunk = kLongBlock * kLongItems;     // 8192
@@ -627,11 +629,13 @@ __global__ __launch_bounds__(1024) void k_tile_plan(const uint2* __restrict__ ra
 
 // With order set, workgroup 0 makes the compositing plan (tile_plan) and the
 // others sort; the plan only reads the ranges, so it runs beside the sorts.
+template <int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restrict__ meta,
                                                           const uint2* __restrict__ ranges, int n_tiles,
                                                           uint32_t* __restrict__ vals, uint32_t* __restrict__ longq,
                                                           const uint32_t* __restrict__ counters, int quads,
                                                           uint32_t* __restrict__ order) {
+    constexpr int kSortChunk = kSortBlock * ITEMS;
     __shared__ uint64_t sk[kSortChunk];
     const int first = order != nullptr ? 1 : 0;
     if (int(blockIdx.x) < first) {
@@ -664,13 +668,13 @@ __global__ __launch_bounds__(kSortBlock) void k_tile_sort(const uint4* __restric
         for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) sk[i] = depth_key(meta, v[i]);
         __syncthreads();
         if (n <= kSortBlock * kSortItemsShort) block_merge_sort<kSortBlock, kSortItemsShort>(sk, n);
-        else block_merge_sort<kSortBlock, kSortItems>(sk, n);
+        else block_merge_sort<kSortBlock, ITEMS>(sk, n);
         for (uint32_t i = threadIdx.x; i < n; i += kSortBlock) v[i] = uint32_t(sk[i]);
         __syncthreads();
     }
 }
 
-// Lists longer than kSortChunk (queued by k_tile_sort, in any order): one
+// Lists longer than k_tile_sort takes (queued by it, in any order): one
 // workgroup of kLongBlock threads per list,
 // chunks of kLongChunk keys merge-sorted in LDS, then (lists longer than a
 // chunk) pairwise merges of sorted runs through two scratch ranges (each
@@ -850,8 +854,13 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     //    the compositing plan, when a pass splits tiles adaptively
     if (nt > 0) {
         uint32_t* order = want_plan ? bins.tile_order : nullptr;
-        GS_LAUNCH("k_tile_sort", k_tile_sort, dim3(unsigned(std::min<int64_t>(nt, 4096) + (want_plan ? 1 : 0))),
-                  dim3(kSortBlock), 0, s, meta, ranges, f.n_tiles, bins.vals, w.longq, bins.counters, quads, order);
+        const dim3 grid(unsigned(std::min<int64_t>(nt, 4096) + (want_plan ? 1 : 0)));
+        if (bins.capacity > uint64_t(nt) * kDenseList)
+            GS_LAUNCH("k_tile_sort", k_tile_sort<kSortItemsDense>, grid, dim3(kSortBlock), 0, s, meta, ranges,
+                      f.n_tiles, bins.vals, w.longq, bins.counters, quads, order);
+        else
+            GS_LAUNCH("k_tile_sort", k_tile_sort<kSortItems>, grid, dim3(kSortBlock), 0, s, meta, ranges, f.n_tiles,
+                      bins.vals, w.longq, bins.counters, quads, order);
         GS_LAUNCH("k_tile_sort_long", k_tile_sort_long, dim3(unsigned(std::min<int64_t>(nt, 256))), dim3(kLongBlock), 0,
                   s, meta, ranges, w.longq, bins.vals, w.key[0], w.key[1]);
     } else {

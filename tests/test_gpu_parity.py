@@ -175,10 +175,10 @@ def test_compositing_plan(cfg1, tile):
 @pytest.mark.parametrize("n", [300, 1500, 3000, 6000, 9000])
 def test_bins_bit_exact_long_tile_lists(n):
     """Large Gaussians in front of a small view put n entries in every tile
-    (above 256: the in-LDS merge sort, 4 keys per thread up to 1024 and 8
-    beyond; above 2048: the long-list kernel; above 8192: its chunks and
-    merges), with many equal depths (ties ordered by record), against the
-    reference."""
+    (above 256: the in-LDS merge sort, 4 keys per thread up to 1024 and 16
+    beyond, the capacity making the frame dense; above 4096: the long-list
+    kernel; above 8192: its chunks and merges), with many equal depths (ties
+    ordered by record), against the reference."""
     p = scenes.gaussians(n, 0, 4100 + n, [-0.3, -0.3, -0.3], [0.3, 0.3, 0.3], 0.0, 0.1)
     p[scenes.MEAN + 2, ::3] = 0.25                  # every third Gaussian at the same depth
     params = torch.from_numpy(p).cuda()
@@ -190,6 +190,25 @@ def test_bins_bit_exact_long_tile_lists(n):
         lens = np.diff(buf.ranges.view(-1, 2).cpu().numpy().view(np.uint32), axis=1)
         assert lens.max() > min(n - 10, 256)
         _bins_check(frame, buf)
+
+
+@pytest.mark.parametrize("n", [1500, 3000])
+def test_bins_bit_exact_long_lists_in_sparse_frame(n):
+    """A cluster of n small Gaussians in a 1600x1066 view: a few tiles hold
+    about n entries while the mean list stays short, so the tile sort keeps
+    its small form (8 keys per thread, lists up to 2048 on chip) and sends
+    the longer lists to the long-list kernel; bins against the reference."""
+    p = scenes.gaussians(n, 0, 4400 + n, [-0.01, -0.01, -0.3], [0.01, 0.01, 0.3], -5.0, 0.3)
+    p[scenes.MEAN + 2, ::4] = 0.1                   # every fourth Gaussian at the same depth
+    params = torch.from_numpy(p).cuda()
+    cam = scenes.look_at([0.0, 0.0, 3.0], [0, 0, 0], 1600, 1066, 1200.0, 1200.0)
+    cfg = gs.raster_cfg((16, 16))
+    frame = gs.Frame([cam], [gs.JobSpec(0, 0, n, 1.0)], cfg)
+    buf = gs.rasterize(params, frame, cfg, capacity=64 * n + 1024)
+    assert buf.capacity <= frame.n_tiles * 1024        # the sparse form of the tile sort
+    lens = np.diff(buf.ranges.view(-1, 2).cpu().numpy().view(np.uint32), axis=1)
+    assert lens.max() > min(n - 100, 2048) and lens.mean() < 64
+    _bins_check(frame, buf)
 
 
 @pytest.mark.parametrize("size", [(16, 16), (17, 16), (48, 16), (200, 16)])
