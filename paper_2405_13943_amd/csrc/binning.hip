@@ -108,9 +108,10 @@ __device__ inline VisPairs shfl_up_v(VisPairs x, int off) {
     return {__shfl_up(x.v, off, kWave), __shfl_up(x.p, off, kWave)};
 }
 
-// exclusive scan of one value per thread over a kScanBlock-thread block;
-// total = the block's sum.  Only the (associative) scan_add is used.
-template <typename T>
+// exclusive scan of one value per thread over a B-thread block (s_wave
+// holds B / kWave values); total = the block's sum.  Only the
+// (associative) scan_add is used.
+template <int B = kScanBlock, typename T>
 __device__ inline T block_excl_scan(T v, T* s_wave, T& total) {
     const int lane = lane_id(), wave = threadIdx.x / kWave;
     T inc = v;
@@ -126,7 +127,7 @@ __device__ inline T block_excl_scan(T v, T* s_wave, T& total) {
     T before{};
     total = T{};
 #pragma unroll
-    for (int w = 0; w < kScanBlock / kWave; w++) {
+    for (int w = 0; w < B / kWave; w++) {
         const T s = s_wave[w];
         if (w < wave) before = scan_add(before, s);
         total = scan_add(total, s);
@@ -194,25 +195,29 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, uint32_t n, typ
 }
 
 // Each workgroup's exclusive prefix is the sum of the partials before it (at
-// most kMaxGrid, read by the whole workgroup), then its items' prefixes; the
-// last workgroup also hands the total to F::finish.
+// most kMaxGrid, read by the whole workgroup), then its items' prefixes in
+// chunks of kApplyBlock (the reduce's ranges, kApplyBlock threads: fewer
+// rounds of the block scan); the last workgroup also hands the total to
+// F::finish.
+constexpr int kApplyBlock = 1024;
 template <typename F>
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(F f, uint32_t n, const typename F::T* __restrict__ part,
-                                                           int G, uint32_t* __restrict__ counters, uint64_t capacity) {
+__global__ __launch_bounds__(kApplyBlock) void k_scan_apply(F f, uint32_t n, const typename F::T* __restrict__ part,
+                                                            int G, uint32_t* __restrict__ counters,
+                                                            uint64_t capacity) {
     using T = typename F::T;
-    __shared__ T s_wave[kScanBlock / kWave];
+    __shared__ T s_wave[kApplyBlock / kWave];
     T before{};
-    for (int i = threadIdx.x; i < int(blockIdx.x); i += kScanBlock) before = scan_add(before, part[i]);
+    for (int i = threadIdx.x; i < int(blockIdx.x); i += kApplyBlock) before = scan_add(before, part[i]);
     T carry;
-    block_excl_scan(before, s_wave, carry);
+    block_excl_scan<kApplyBlock>(before, s_wave, carry);
     if (blockIdx.x == unsigned(G - 1) && threadIdx.x == 0) F::finish(scan_add(carry, part[G - 1]), counters, capacity);
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kScanBlock, lo, hi);
-    for (uint32_t base = lo; base < hi; base += kScanBlock) {
+    for (uint32_t base = lo; base < hi; base += kApplyBlock) {
         const uint32_t i = base + threadIdx.x;
         const T v = i < hi ? f.value(i) : T{};
         T tot;
-        const T ex = block_excl_scan(v, s_wave, tot);
+        const T ex = block_excl_scan<kApplyBlock>(v, s_wave, tot);
         if (i < hi) f.emit(i, scan_add(carry, ex), v);
         carry = scan_add(carry, tot);
     }
@@ -822,7 +827,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
         VisPairs* part = static_cast<VisPairs*>(w.part);
         GS_LAUNCH("k_scan_reduce", k_scan_reduce<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G,
                   bins.ranges, 2 * nt, w.longq);
-        GS_LAUNCH("k_scan_apply", k_scan_apply<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G,
+        GS_LAUNCH("k_scan_apply", k_scan_apply<RecordScan>, dim3(G), dim3(kApplyBlock), 0, s, rs, nrec, part, G,
                   bins.counters, bins.capacity);
     }
     // 2. emit (tile, record) pairs in record order, then sort them by tile id
