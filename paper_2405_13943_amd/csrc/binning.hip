@@ -24,6 +24,7 @@
 namespace gs {
 
 constexpr int kScanBlock = 256;
+constexpr int kEmitChunk = 1024;                 // pairs per emission chunk
 constexpr int kRsBlock = 256;
 constexpr int kRsItemsLarge = 16;                // keys per thread and iteration of a radix pass: large
 constexpr int kRsItemsSmall = 4;                 // and small sorts (more workgroups)
@@ -35,6 +36,7 @@ __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_
 struct BinWs {
     uint32_t* vis;        // visible record ids in record order, [n_records]
     uint32_t* poff;       // first pair of each visible record in that order, [n_records]
+    uint32_t* cfirst;     // visible rank holding pair c * kEmitChunk, [capacity / kEmitChunk + 1]
     uint32_t* tkey[2];    // tile keys, [capacity] each
     uint32_t* tval;       // alternate record-id buffer, [capacity]
     uint64_t* key[2];     // sort keys of tile lists longer than one LDS chunk, [capacity] each
@@ -55,6 +57,7 @@ static BinWs carve(void* base, int64_t n_records, uint64_t capacity, int32_t n_t
     const size_t nr = size_t(n_records > 0 ? n_records : 1) * 4, nc = size_t(capacity > 0 ? capacity : 1);
     w.vis = reinterpret_cast<uint32_t*>(take(nr));
     w.poff = reinterpret_cast<uint32_t*>(take(nr));
+    w.cfirst = reinterpret_cast<uint32_t*>(take((nc / kEmitChunk + 1) * 4));
     char* a = take(nc * 8);
     char* b = take(nc * 8);
     w.key[0] = reinterpret_cast<uint64_t*>(a);
@@ -154,6 +157,8 @@ struct RecordScan {       // item i: record i; output: compacted ids and first p
     uint32_t* vis;
     uint32_t* pair_off;       // by record
     uint32_t* poff;           // by visible rank
+    uint32_t* cfirst;         // by emission chunk: the visible rank holding its first pair
+    uint64_t capacity;
     __device__ T value(uint32_t i) const {
         const uint32_t n = meta_tiles(meta[i].y);
         return {n > 0 ? 1u : 0u, n};
@@ -163,6 +168,9 @@ struct RecordScan {       // item i: record i; output: compacted ids and first p
             vis[pre.v] = i;
             poff[pre.v] = pre.p;
             pair_off[i] = pre.p;
+            // the emission chunks whose first pair is one of this record's
+            const uint64_t p0 = pre.p, p1 = min(p0 + v.p, capacity);
+            for (uint64_t c = (p0 + kEmitChunk - 1) / kEmitChunk; c * kEmitChunk < p1; c++) cfirst[c] = pre.v;
         }
     }
     __device__ static void finish(T total, uint32_t* counters, uint64_t capacity) {
@@ -378,20 +386,21 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
 // of serialising one.  With hist set, the workgroup also counts the first
 // radix digit (the low bits0 bits of the tile id) of its pairs and stores
 // the counts as that pass's histogram column, which saves the pass its
-// counting launch.
-constexpr int kEmitChunk = 1024;
+// counting launch.  A chunk's first and last records come from cfirst
+// (written by the record scan) instead of binary searches over all visible
+// records.
 constexpr int kEmitBlock = 256;
 
 __global__ __launch_bounds__(kEmitBlock) void k_emit(const uint4* __restrict__ meta, const uint32_t* __restrict__ vis,
                                                      const uint32_t* __restrict__ poff,
+                                                     const uint32_t* __restrict__ cfirst,
                                                      const uint32_t* __restrict__ counters, gs_frame frame,
                                                      uint64_t capacity, uint32_t* __restrict__ tkey,
                                                      uint32_t* __restrict__ tval, int G, uint32_t granule, int bits0,
                                                      uint32_t* __restrict__ hist) {
     static_assert(kEmitBlock == 256, "one histogram bin per thread");
-    __shared__ uint32_t s_off[kEmitChunk];
-    __shared__ uint32_t s_rec[kEmitChunk];
-    __shared__ uint32_t s_lo, s_hi;
+    __shared__ uint32_t s_off[kEmitChunk + 1];
+    __shared__ uint32_t s_rec[kEmitChunk + 1];
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0u;
     const uint32_t mask0 = (1u << bits0) - 1u;
@@ -401,19 +410,12 @@ __global__ __launch_bounds__(kEmitBlock) void k_emit(const uint4* __restrict__ m
     block_range(P, G, blockIdx.x, granule, lo_e, hi_e);
     for (uint32_t e0 = lo_e; e0 < hi_e; e0 += kEmitChunk) {
         const uint32_t e1 = min(hi_e, e0 + kEmitChunk);
-        if (threadIdx.x < 2) {
-            // last visible rank whose first pair is <= target (ranks with zero
-            // pairs do not exist: every visible record covers a tile)
-            const uint32_t target = threadIdx.x == 0 ? e0 : e1 - 1;
-            uint32_t lo = 0, hi = V - 1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi + 1) >> 1;
-                if (poff[mid] <= target) lo = mid; else hi = mid - 1;
-            }
-            if (threadIdx.x == 0) s_lo = lo; else s_hi = lo;
-        }
-        __syncthreads();
-        const uint32_t lo = s_lo, n = s_hi - s_lo + 1;
+        // the ranks holding pairs e0 and e1 (both multiples of kEmitChunk
+        // unless e1 = P), at most kEmitChunk + 1 of them: the searches below
+        // never pick the last one when its first pair is e1
+        const uint32_t lo = cfirst[e0 / kEmitChunk];
+        const uint32_t hi = e1 < P ? cfirst[e1 / kEmitChunk] : V - 1;
+        const uint32_t n = min(uint32_t(kEmitChunk + 1), hi - lo + 1);
         for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
             s_off[i] = poff[lo + i];
             s_rec[i] = vis[lo + i];
@@ -823,7 +825,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     static_assert(sizeof(uint2) == 8, "ranges are pairs of 32-bit words");
     {
         const int G = grid_for(nrec, kScanBlock * 8);
-        RecordScan rs{meta, w.vis, bins.pair_off, w.poff};
+        RecordScan rs{meta, w.vis, bins.pair_off, w.poff, w.cfirst, bins.capacity};
         VisPairs* part = static_cast<VisPairs*>(w.part);
         GS_LAUNCH("k_scan_reduce", k_scan_reduce<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G,
                   bins.ranges, 2 * nt, w.longq);
@@ -840,11 +842,11 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
     const uint32_t pmax = uint32_t(std::min<uint64_t>(bins.capacity, 0xffffffffull));
     if (passes > 0) {
         const RadixShape rs = radix_shape(pmax);
-        GS_LAUNCH("k_emit", k_emit, dim3(rs.G), dim3(kEmitBlock), 0, s, meta, w.vis, w.poff, bins.counters, f,
+        GS_LAUNCH("k_emit", k_emit, dim3(rs.G), dim3(kEmitBlock), 0, s, meta, w.vis, w.poff, w.cfirst, bins.counters, f,
                   bins.capacity, w.tkey[0], emit_val, rs.G, rs.tile, radix_digit(bits, 0), w.hist);
     } else {
         const int G = grid_for(pmax, kEmitChunk);
-        GS_LAUNCH("k_emit", k_emit, dim3(G), dim3(kEmitBlock), 0, s, meta, w.vis, w.poff, bins.counters, f,
+        GS_LAUNCH("k_emit", k_emit, dim3(G), dim3(kEmitBlock), 0, s, meta, w.vis, w.poff, w.cfirst, bins.counters, f,
                   bins.capacity, w.tkey[0], emit_val, G, uint32_t(kEmitChunk), 0, static_cast<uint32_t*>(nullptr));
     }
     uint32_t* tk_final = w.tkey[0];
