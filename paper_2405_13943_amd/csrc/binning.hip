@@ -183,22 +183,24 @@ struct RecordScan {       // item i: record i; output: compacted ids and first p
 
 // The reduce also zeroes `clear[0, n_clear)` (grid-stride) and the word
 // `*clear1` (when not null), for buffers the later steps fill in part or
-// count into: it saves launches.
+// count into: it saves launches.  kReduceBlock threads per workgroup over
+// the ranges of kScanBlock granules.
+constexpr int kReduceBlock = 1024;
 template <typename F>
-__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(F f, uint32_t n, typename F::T* __restrict__ part, int G,
-                                                            uint32_t* __restrict__ clear, int64_t n_clear,
-                                                            uint32_t* __restrict__ clear1) {
+__global__ __launch_bounds__(kReduceBlock) void k_scan_reduce(F f, uint32_t n, typename F::T* __restrict__ part,
+                                                              int G, uint32_t* __restrict__ clear, int64_t n_clear,
+                                                              uint32_t* __restrict__ clear1) {
     using T = typename F::T;
-    __shared__ T s_wave[kScanBlock / kWave];
-    for (int64_t i = int64_t(blockIdx.x) * kScanBlock + threadIdx.x; i < n_clear; i += int64_t(G) * kScanBlock)
+    __shared__ T s_wave[kReduceBlock / kWave];
+    for (int64_t i = int64_t(blockIdx.x) * kReduceBlock + threadIdx.x; i < n_clear; i += int64_t(G) * kReduceBlock)
         clear[i] = 0u;
     if (clear1 != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *clear1 = 0u;
     uint32_t lo, hi;
     block_range(n, G, blockIdx.x, kScanBlock, lo, hi);
     T acc{};
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kScanBlock) acc = scan_add(acc, f.value(i));
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kReduceBlock) acc = scan_add(acc, f.value(i));
     T tot;
-    block_excl_scan(acc, s_wave, tot);
+    block_excl_scan<kReduceBlock>(acc, s_wave, tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
@@ -827,7 +829,7 @@ hipError_t launch_bin_sort(const gs_frame& f, const gs_raster_cfg& cfg, const ui
         const int G = grid_for(nrec, kScanBlock * 8);
         RecordScan rs{meta, w.vis, bins.pair_off, w.poff, w.cfirst, bins.capacity};
         VisPairs* part = static_cast<VisPairs*>(w.part);
-        GS_LAUNCH("k_scan_reduce", k_scan_reduce<RecordScan>, dim3(G), dim3(kScanBlock), 0, s, rs, nrec, part, G,
+        GS_LAUNCH("k_scan_reduce", k_scan_reduce<RecordScan>, dim3(G), dim3(kReduceBlock), 0, s, rs, nrec, part, G,
                   bins.ranges, 2 * nt, w.longq);
         GS_LAUNCH("k_scan_apply", k_scan_apply<RecordScan>, dim3(G), dim3(kApplyBlock), 0, s, rs, nrec, part, G,
                   bins.counters, bins.capacity);
